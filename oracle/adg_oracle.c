@@ -1,0 +1,1033 @@
+/*
+ * adg_oracle.c -- plain, slow, FP64 CPU oracle of one ADER-DG time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  The GPU library never
+ * links, includes or calls it, and the two share no code, headers or tables.
+ *
+ * What it computes follows the ExaHyPE paper (Reinarz et al., "ExaHyPE: An
+ * Engine for Parallel Dynamically Adaptive Simulations of Wave Problems"):
+ *   - the balance law with flux, non-conservative product, source and point
+ *     sources: Sec. 2, Eq. (1);
+ *   - the element-local space-time predictor, a fixed-point (Picard) iteration
+ *     on the weak form Eq. (5), tensor-product Lagrange basis on Gauss-Legendre
+ *     points: Sec. 3.3;
+ *   - the three phases of a step (predictor, Rusanov face flux, corrector
+ *     Eq. (6) with a diagonal mass matrix): Sec. 3.3;
+ *   - the time step restriction Eq. (7): Sec. 3.4;
+ *   - the admissibility check of the a-posteriori limiter: Sec. 3.5;
+ *   - the PDEs: compressible Euler, Eqs. (8) and (10) (Sec. 6.1) and linear
+ *     elasticity in velocity-stress form (Sec. 2.1).
+ * Readings of silent or ambiguous passages are marked READING below.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
+ * No FMA contraction, IEEE binary64, round to nearest.
+ *
+ * Data contract (the same one the GPU library documents for its callers):
+ *   Q      : [cell][nvar][node]   node = kx + n*(ky + n*kz), x fastest
+ *   params : [cell][nparam]       material parameters, constant per cell
+ *   cell   = cx + Cx*(cy + Cy*cz)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXN 8   /* n = N+1 <= 8 */
+#define ORC_MAXQ 16  /* evolved + parameter slots per point */
+#define ORC_MAXSRC 8
+
+enum { ORC_EULER = 1, ORC_ELASTIC = 2, ORC_ADVECTION = 3 };
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -3 };
+
+/* Problem description.  Mirrored field by field by a ctypes Structure. */
+typedef struct {
+  int dim, order, pde, nvar, nparam, picard_iters;
+  int cells[3];
+  double lo[3], hi[3];
+  double cfl;
+  double gamma;  /* Euler: ratio of specific heats */
+  double adv[3]; /* advection: velocity a */
+  double kappa;  /* advection: linear decay source S(q) = -kappa q */
+  int nsrc;
+  int pad_;
+  double src_x[ORC_MAXSRC][3];
+  double src_w[ORC_MAXSRC][ORC_MAXQ]; /* which variables a source drives */
+  double src_f0[ORC_MAXSRC], src_t0[ORC_MAXSRC], src_amp[ORC_MAXSRC];
+} orc_problem;
+
+/* ------------------------------------------------------------------------
+ * 1. One-dimensional tables on the reference interval [0,1].
+ *    Gauss-Legendre nodes xi_i and weights w_i (sum w = 1), the Lagrange
+ *    basis phi_i through the nodes, D_ij = phi_j'(xi_i), the boundary values
+ *    l0_i = phi_i(0), l1_i = phi_i(1), and the time matrix of the predictor
+ *    K1_ij = phi_i(1) phi_j(1) - int_0^1 phi_i'(tau) phi_j(tau) dtau
+ *          = l1_i l1_j - w_j D_ji         (exact under Gauss quadrature)
+ *    which comes from integrating the time derivative of Eq. (5) by parts
+ *    with the old solution taken as the upwind value at the start of the
+ *    step (Sec. 3.3).  Everything is formed in long double, then rounded.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int n;
+  double xi[ORC_MAXN], w[ORC_MAXN];
+  double D[ORC_MAXN][ORC_MAXN];
+  double l0[ORC_MAXN], l1[ORC_MAXN];
+  double K1[ORC_MAXN][ORC_MAXN], K1inv[ORC_MAXN][ORC_MAXN];
+} tables;
+
+/* Legendre polynomial P_n(x) and its derivative, three-term recurrence. */
+static void legendre(int n, long double x, long double *p, long double *dp) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) { *p = 1.0L; *dp = 0.0L; return; }
+  for (int k = 2; k <= n; ++k) {
+    long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *p = p1;
+  *dp = n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+/* Lagrange basis phi_i(x) on nodes xs[0..n-1], straight from the product. */
+static long double lagrange_ld(int n, const long double *xs, int i, long double x) {
+  long double v = 1.0L;
+  for (int m = 0; m < n; ++m)
+    if (m != i) v *= (x - xs[m]) / (xs[i] - xs[m]);
+  return v;
+}
+
+/* phi_j'(x_i) from the product rule written out. */
+static long double lagrange_deriv_at_node(int n, const long double *xs, int j, int i) {
+  if (i == j) {
+    long double s = 0.0L;
+    for (int m = 0; m < n; ++m)
+      if (m != j) s += 1.0L / (xs[j] - xs[m]);
+    return s;
+  }
+  long double num = 1.0L, den = 1.0L;
+  for (int m = 0; m < n; ++m) {
+    if (m != j) den *= (xs[j] - xs[m]);
+    if (m != j && m != i) num *= (xs[i] - xs[m]);
+  }
+  return num / den;
+}
+
+static int make_tables(int n, tables *T) {
+  if (n < 1 || n > ORC_MAXN) return ORC_EINVAL;
+  long double x[ORC_MAXN], w[ORC_MAXN];
+  /* Newton on P_n from the Chebyshev-like first guess, on [-1,1]. */
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      long double p, dp;
+      legendre(n, z, &p, &dp);
+      long double dz = p / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-30L) break;
+    }
+    long double p, dp;
+    legendre(n, z, &p, &dp);
+    /* map to [0,1]: xi = (1 + z)/2 ascending, weight 2/((1-z^2) P'^2) halved */
+    x[n - 1 - i] = 0.5L * (1.0L + z);
+    w[n - 1 - i] = 1.0L / ((1.0L - z * z) * dp * dp);
+  }
+  long double D[ORC_MAXN][ORC_MAXN], l0[ORC_MAXN], l1[ORC_MAXN];
+  for (int i = 0; i < n; ++i) {
+    l0[i] = lagrange_ld(n, x, i, 0.0L);
+    l1[i] = lagrange_ld(n, x, i, 1.0L);
+    for (int j = 0; j < n; ++j) D[i][j] = lagrange_deriv_at_node(n, x, j, i);
+  }
+  long double K[ORC_MAXN][2 * ORC_MAXN];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      K[i][j] = l1[i] * l1[j] - w[j] * D[j][i];
+      K[i][n + j] = (i == j) ? 1.0L : 0.0L;
+    }
+  T->n = n;
+  for (int i = 0; i < n; ++i) {
+    T->xi[i] = (double)x[i];
+    T->w[i] = (double)w[i];
+    T->l0[i] = (double)l0[i];
+    T->l1[i] = (double)l1[i];
+    for (int j = 0; j < n; ++j) {
+      T->D[i][j] = (double)D[i][j];
+      T->K1[i][j] = (double)K[i][j];
+    }
+  }
+  /* Gauss-Jordan elimination with partial pivoting for K1^{-1}. */
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(K[r][col]) > fabsl(K[piv][col])) piv = r;
+    if (piv != col)
+      for (int c = 0; c < 2 * n; ++c) {
+        long double tmp = K[col][c];
+        K[col][c] = K[piv][c];
+        K[piv][c] = tmp;
+      }
+    long double d = K[col][col];
+    for (int c = 0; c < 2 * n; ++c) K[col][c] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      long double f = K[r][col];
+      for (int c = 0; c < 2 * n; ++c) K[r][c] -= f * K[col][c];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T->K1inv[i][j] = (double)K[i][n + j];
+  return ORC_OK;
+}
+
+/* phi_i(x) in double for interpolation at arbitrary reference points. */
+static double lagrange(const tables *T, int i, double x) {
+  double v = 1.0;
+  for (int m = 0; m < T->n; ++m)
+    if (m != i) v *= (x - T->xi[m]) / (T->xi[i] - T->xi[m]);
+  return v;
+}
+
+/* ------------------------------------------------------------------------
+ * 2. The PDE terms of Eq. (1), pointwise, in the (Q, direction, out)
+ *    convention of the paper's user functions (Table 2, Sec. 4.1).
+ *    Q holds the nvar evolved quantities followed by the nparam material
+ *    parameters (Sec. 6.2 keeps the material in the state vector).
+ * ------------------------------------------------------------------------ */
+
+/* Euler pressure, Eq. (10): p = (gamma-1) (E - |j|^2 / (2 rho)). */
+static double euler_pressure(const orc_problem *P, const double *Q) {
+  double jj = 0.0;
+  for (int a = 0; a < P->dim; ++a) jj += Q[1 + a] * Q[1 + a];
+  return (P->gamma - 1.0) * (Q[P->dim + 1] - 0.5 * jj / Q[0]);
+}
+
+/* Stress index of the symmetric pair (i, d): xx yy zz xy xz yz. */
+static int sym_index(int i, int d) {
+  if (i == d) return i;
+  int a = i < d ? i : d, b = i < d ? d : i;
+  if (a == 0 && b == 1) return 3;
+  if (a == 0 && b == 2) return 4;
+  return 5;
+}
+
+/* Flux F_d(Q) (the d-th column of the flux tensor). */
+static void pde_flux(const orc_problem *P, const double *Q, int d, double *F) {
+  switch (P->pde) {
+    case ORC_EULER: {
+      /* Eq. (8): F_d = (j_d, j_d j / rho + p e_d, j_d (E + p) / rho) */
+      int E = P->dim + 1;
+      double p = euler_pressure(P, Q);
+      double ud = Q[1 + d] / Q[0];
+      F[0] = Q[1 + d];
+      for (int a = 0; a < P->dim; ++a) F[1 + a] = ud * Q[1 + a];
+      F[1 + d] += p;
+      F[E] = ud * (Q[E] + p);
+      break;
+    }
+    case ORC_ELASTIC: {
+      /* Sec. 2.1: F = (0, sigma) -- the momentum rows carry sigma_{i d}. */
+      for (int v = 0; v < 6; ++v) F[v] = 0.0;
+      for (int i = 0; i < 3; ++i) F[6 + i] = Q[sym_index(i, d)];
+      break;
+    }
+    case ORC_ADVECTION:
+      F[0] = P->adv[d] * Q[0];
+      break;
+  }
+}
+
+/* Non-conservative product B(Q) . grad Q; gradQ is [dim][nq]. */
+static void pde_ncp(const orc_problem *P, const double *Q, const double *gradQ, double *BgradQ) {
+  int nq = P->nvar + P->nparam;
+  for (int v = 0; v < P->nvar; ++v) BgradQ[v] = 0.0;
+  if (P->pde != ORC_ELASTIC) return;
+  /* Sec. 2.1: the stress rows carry E(lambda, mu) . grad v with v = (rho v)/rho.
+   * lambda = rho (cp^2 - 2 cs^2), mu = rho cs^2 (READING: the Lame constants
+   * "can be derived" from Table 3's rho, cp, cs). */
+  double rho = Q[9], cp = Q[10], cs = Q[11];
+  double mu = rho * cs * cs;
+  double lam = rho * cp * cp - 2.0 * mu;
+  double g[3][3]; /* g[i][d] = d v_i / d x_d */
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) g[i][d] = gradQ[d * nq + 6 + i] / rho;
+  double divv = g[0][0] + g[1][1] + g[2][2];
+  BgradQ[0] = 2.0 * mu * g[0][0] + lam * divv;
+  BgradQ[1] = 2.0 * mu * g[1][1] + lam * divv;
+  BgradQ[2] = 2.0 * mu * g[2][2] + lam * divv;
+  BgradQ[3] = mu * (g[0][1] + g[1][0]);
+  BgradQ[4] = mu * (g[0][2] + g[2][0]);
+  BgradQ[5] = mu * (g[1][2] + g[2][1]);
+}
+
+/* Smooth source S(Q, x, t).  Only the advection test PDE has one. */
+static void pde_source(const orc_problem *P, const double *Q, const double *x, double t, double *S) {
+  (void)x;
+  (void)t;
+  for (int v = 0; v < P->nvar; ++v) S[v] = 0.0;
+  if (P->pde == ORC_ADVECTION) S[0] = -P->kappa * Q[0];
+}
+
+/* Largest absolute eigenvalue of the flux Jacobian in direction d (Sec. 4.1's
+ * eigenvalues hook; the kernel only needs the maximum). */
+static double pde_max_eigen(const orc_problem *P, const double *Q, int d) {
+  switch (P->pde) {
+    case ORC_EULER: {
+      /* textbook: u_d - c, u_d, u_d + c, c = sqrt(gamma p / rho) */
+      double c = sqrt(P->gamma * euler_pressure(P, Q) / Q[0]);
+      return fabs(Q[1 + d] / Q[0]) + c;
+    }
+    case ORC_ELASTIC:
+      return Q[10]; /* +-cp, +-cs (twice), 0 (three times) */
+    case ORC_ADVECTION:
+      return fabs(P->adv[d]);
+  }
+  return 0.0;
+}
+
+/* Physical admissibility (Sec. 3.5, criterion 1) plus finiteness. */
+static int pde_admissible(const orc_problem *P, const double *Q) {
+  int nq = P->nvar + P->nparam;
+  for (int v = 0; v < nq; ++v)
+    if (!isfinite(Q[v])) return 0;
+  if (P->pde == ORC_EULER) {
+    if (!(Q[0] > 0.0)) return 0;
+    if (!(euler_pressure(P, Q) > 0.0)) return 0;
+  }
+  return 1;
+}
+
+/* Ricker wavelet s(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2). */
+static double ricker(const orc_problem *P, int s, double t) {
+  const double pi = 3.14159265358979323846;
+  double a = pi * P->src_f0[s] * (t - P->src_t0[s]);
+  a = a * a;
+  return P->src_amp[s] * (1.0 - 2.0 * a) * exp(-a);
+}
+
+/* ------------------------------------------------------------------------
+ * 3. Mesh helpers: uniform Cartesian cells, periodic in every direction.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int n, S, F, nv, nq, dim;
+  long C;
+  double h[3];
+  int stride[3]; /* node stride along each axis: 1, n, n^2 */
+} mesh;
+
+static int make_mesh(const orc_problem *P, mesh *M) {
+  if (P->dim < 2 || P->dim > 3) return ORC_EINVAL;
+  if (P->order < 1 || P->order + 1 > ORC_MAXN) return ORC_EINVAL;
+  if (P->nvar < 1 || P->nvar + P->nparam > ORC_MAXQ || P->nparam < 0) return ORC_EINVAL;
+  M->dim = P->dim;
+  M->n = P->order + 1;
+  M->S = 1;
+  M->F = 1;
+  M->C = 1;
+  for (int d = 0; d < P->dim; ++d) {
+    if (P->cells[d] < 1) return ORC_EINVAL;
+    M->S *= M->n;
+    if (d > 0) M->F *= M->n;
+    M->C *= P->cells[d];
+    M->h[d] = (P->hi[d] - P->lo[d]) / P->cells[d];
+    M->stride[d] = d == 0 ? 1 : M->stride[d - 1] * M->n;
+  }
+  M->nv = P->nvar;
+  M->nq = P->nvar + P->nparam;
+  return ORC_OK;
+}
+
+static void cell_coords(const orc_problem *P, long c, int cc[3]) {
+  cc[0] = (int)(c % P->cells[0]);
+  long r = c / P->cells[0];
+  cc[1] = (int)(P->dim > 1 ? r % P->cells[1] : 0);
+  cc[2] = (int)(P->dim > 2 ? r / P->cells[1] : 0);
+}
+
+static long cell_index(const orc_problem *P, const int cc[3]) {
+  long c = cc[0];
+  if (P->dim > 1) c += (long)P->cells[0] * cc[1];
+  if (P->dim > 2) c += (long)P->cells[0] * P->cells[1] * cc[2];
+  return c;
+}
+
+/* neighbour across the face with normal e_d on side s (-1 or +1), periodic */
+static long neighbour(const orc_problem *P, long c, int d, int s) {
+  int cc[3];
+  cell_coords(P, c, cc);
+  cc[d] = (cc[d] + s + P->cells[d]) % P->cells[d];
+  return cell_index(P, cc);
+}
+
+/* node multi-index */
+static void node_index(const mesh *M, int k, int kk[3]) {
+  kk[0] = k % M->n;
+  kk[1] = (k / M->n) % M->n;
+  kk[2] = k / (M->n * M->n);
+  if (M->dim == 2) kk[2] = 0;
+}
+
+/* index of the face node k_perp for a face with normal d: the remaining axes
+ * in increasing order, the lower one fastest. */
+static int face_node(const mesh *M, int d, const int kk[3]) {
+  int f = 0, mul = 1;
+  for (int a = 0; a < M->dim; ++a) {
+    if (a == d) continue;
+    f += kk[a] * mul;
+    mul *= M->n;
+  }
+  return f;
+}
+
+/* ------------------------------------------------------------------------
+ * 4. Space-time predictor for one cell (Sec. 3.3, phase 1).
+ *
+ *    q_h(x, tau) = sum_{j,k} theta_j(tau) phi_k(x) q_{j,k}, tau in [0,1],
+ *    t = t^n + tau dt.  Testing Eq. (1) with theta_i phi_k over the cell and
+ *    the step, integrating the time derivative by parts with u^n upwind at
+ *    tau = 0, and using Gauss-Legendre quadrature collocated with the nodes:
+ *       sum_j K1_ij q_{j,k} = l0_i u^n_k + dt w_i R(q)_{i,k},
+ *       R = - div F(q_h) - B(q_h) . grad q_h + S(q_h) + point sources,
+ *    with spatial derivatives of the nodal interpolants.  This is solved by
+ *    the fixed-point iteration the paper uses for non-linear PDEs:
+ *       q^0_j = u^n,   q^{r+1}_i = sum_j K1inv_ij (l0_j u^n + dt w_j R(q^r)_j).
+ *    READING: the iteration count is fixed (picard_iters, default N+1), no
+ *    tolerance test, and the initial guess is u^n at every time node.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double *u;      /* [S][nq]          u^n with the parameters appended */
+  double *q;      /* [n][S][nq]       current iterate */
+  double *qn;     /* [n][S][nq]       next iterate */
+  double *F;      /* [dim][n][S][nv]  flux at every space-time node */
+  double *grad;   /* [n][S][dim][nq]  spatial gradient of q */
+  double *R;      /* [n][S][nv]       right-hand side of the predictor */
+  double *ncp;    /* [n][S][nv] */
+  double *src;    /* [n][S][nv] */
+  /* outputs of the predictor, at the final iterate */
+  double *qbar;   /* [S][nv]          time average of q */
+  double *Fbar;   /* [dim][S][nv]     time average of F_d(q) */
+  double *Nbar;   /* [S][nv]          time average of B(q) grad q */
+  double *Sbar;   /* [S][nv]          time average of the sources */
+} work;
+
+static int work_alloc(const mesh *M, work *W) {
+  size_t S = M->S, n = M->n, nq = M->nq, nv = M->nv, d = M->dim;
+  W->u = calloc(S * nq, sizeof(double));
+  W->q = calloc(n * S * nq, sizeof(double));
+  W->qn = calloc(n * S * nq, sizeof(double));
+  W->F = calloc(d * n * S * nv, sizeof(double));
+  W->grad = calloc(n * S * d * nq, sizeof(double));
+  W->R = calloc(n * S * nv, sizeof(double));
+  W->ncp = calloc(n * S * nv, sizeof(double));
+  W->src = calloc(n * S * nv, sizeof(double));
+  W->qbar = calloc(S * nv, sizeof(double));
+  W->Fbar = calloc(d * S * nv, sizeof(double));
+  W->Nbar = calloc(S * nv, sizeof(double));
+  W->Sbar = calloc(S * nv, sizeof(double));
+  if (!W->u || !W->q || !W->qn || !W->F || !W->grad || !W->R || !W->ncp || !W->src ||
+      !W->qbar || !W->Fbar || !W->Nbar || !W->Sbar)
+    return ORC_ENOMEM;
+  return ORC_OK;
+}
+
+static void work_free(work *W) {
+  free(W->u); free(W->q); free(W->qn); free(W->F); free(W->grad); free(W->R);
+  free(W->ncp); free(W->src); free(W->qbar); free(W->Fbar); free(W->Nbar); free(W->Sbar);
+}
+
+/* Evaluate F, grad q, B grad q, S and R = -div F - B grad q + S at every
+ * space-time node of the iterate W->q. */
+static void eval_terms(const orc_problem *P, const mesh *M, const tables *T, long c,
+                       const double *xlo, double dt, double t, work *W) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv, dim = M->dim;
+  /* fluxes */
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < S; ++k)
+      for (int d = 0; d < dim; ++d)
+        pde_flux(P, &W->q[((size_t)j * S + k) * nq], d,
+                 &W->F[(((size_t)d * n + j) * S + k) * nv]);
+  for (int j = 0; j < n; ++j) {
+    double tj = t + T->xi[j] * dt; /* time nodes share the spatial nodes */
+    for (int k = 0; k < S; ++k) {
+      int kk[3];
+      node_index(M, k, kk);
+      const double *qk = &W->q[((size_t)j * S + k) * nq];
+      double *g = &W->grad[((size_t)j * S + k) * dim * nq];
+      double divF[ORC_MAXQ];
+      for (int v = 0; v < nv; ++v) divF[v] = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        for (int v = 0; v < nq; ++v) g[d * nq + v] = 0.0;
+        for (int m = 0; m < n; ++m) {
+          int km = k + (m - kk[d]) * M->stride[d]; /* node with k_d <- m */
+          double Dkm = T->D[kk[d]][m];
+          const double *qm = &W->q[((size_t)j * S + km) * nq];
+          const double *Fm = &W->F[(((size_t)d * n + j) * S + km) * nv];
+          for (int v = 0; v < nv; ++v) {
+            g[d * nq + v] += Dkm * qm[v];
+            divF[v] += Dkm * Fm[v] / M->h[d];
+          }
+        }
+        for (int v = 0; v < nv; ++v) g[d * nq + v] /= M->h[d];
+        /* material parameters are constant inside the cell: zero gradient */
+      }
+      double *B = &W->ncp[((size_t)j * S + k) * nv];
+      pde_ncp(P, qk, g, B);
+      double x[3] = {0.0, 0.0, 0.0};
+      for (int d = 0; d < dim; ++d) x[d] = xlo[d] + M->h[d] * T->xi[kk[d]];
+      double *Sv = &W->src[((size_t)j * S + k) * nv];
+      pde_source(P, qk, x, tj, Sv);
+      /* point sources, Eq. (1): the test function integrates a Dirac delta
+       * to phi_k(x_s); dividing by the diagonal mass |T| W_k gives the nodal
+       * value.  READING: a point lying on a face belongs to the cell whose
+       * half-open interval [x_lo, x_lo + h) contains it. */
+      for (int s = 0; s < P->nsrc; ++s) {
+        int sc[3] = {0, 0, 0};
+        double xs[3];
+        for (int d = 0; d < dim; ++d) {
+          sc[d] = (int)floor((P->src_x[s][d] - P->lo[d]) / M->h[d]);
+          xs[d] = (P->src_x[s][d] - P->lo[d]) / M->h[d] - sc[d];
+        }
+        if (cell_index(P, sc) != c) continue;
+        double phi = 1.0, mass = 1.0;
+        for (int d = 0; d < dim; ++d) {
+          phi *= lagrange(T, kk[d], xs[d]);
+          mass *= M->h[d] * T->w[kk[d]];
+        }
+        double amp = ricker(P, s, tj) * phi / mass;
+        for (int v = 0; v < nv; ++v) Sv[v] += amp * P->src_w[s][v];
+      }
+      double *R = &W->R[((size_t)j * S + k) * nv];
+      for (int v = 0; v < nv; ++v) R[v] = -divF[v] - B[v] + Sv[v];
+    }
+  }
+}
+
+static void predictor_cell(const orc_problem *P, const mesh *M, const tables *T, long c,
+                           const double *Q, const double *params, double dt, double t,
+                           int iters, work *W) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv, dim = M->dim;
+  int cc[3];
+  cell_coords(P, c, cc);
+  double xlo[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < dim; ++d) xlo[d] = P->lo[d] + cc[d] * M->h[d];
+  /* gather u^n (evolved quantities, then the cell's parameters) */
+  for (int k = 0; k < S; ++k) {
+    for (int v = 0; v < nv; ++v) W->u[(size_t)k * nq + v] = Q[((size_t)c * nv + v) * S + k];
+    for (int p = 0; p < P->nparam; ++p)
+      W->u[(size_t)k * nq + nv + p] = params[(size_t)c * P->nparam + p];
+  }
+  /* initial guess q^0_j = u^n */
+  for (int j = 0; j < n; ++j)
+    memcpy(&W->q[(size_t)j * S * nq], W->u, sizeof(double) * S * nq);
+  for (int r = 0; r < iters; ++r) {
+    eval_terms(P, M, T, c, xlo, dt, t, W);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < S; ++k) {
+        double *qi = &W->qn[((size_t)i * S + k) * nq];
+        for (int v = 0; v < nv; ++v) {
+          double acc = 0.0;
+          for (int j = 0; j < n; ++j)
+            acc += T->K1inv[i][j] *
+                   (T->l0[j] * W->u[(size_t)k * nq + v] + dt * T->w[j] * W->R[((size_t)j * S + k) * nv + v]);
+          qi[v] = acc;
+        }
+        for (int p = 0; p < P->nparam; ++p) qi[nv + p] = W->u[(size_t)k * nq + nv + p];
+      }
+    double *tmp = W->q;
+    W->q = W->qn;
+    W->qn = tmp;
+  }
+  /* READING: the averaged terms are evaluated at the final iterate q^I. */
+  eval_terms(P, M, T, c, xlo, dt, t, W);
+  for (int k = 0; k < S; ++k)
+    for (int v = 0; v < nv; ++v) {
+      double a = 0.0, b = 0.0, s = 0.0;
+      for (int j = 0; j < n; ++j) {
+        a += T->w[j] * W->q[((size_t)j * S + k) * nq + v];
+        b += T->w[j] * W->ncp[((size_t)j * S + k) * nv + v];
+        s += T->w[j] * W->src[((size_t)j * S + k) * nv + v];
+      }
+      W->qbar[(size_t)k * nv + v] = a;
+      W->Nbar[(size_t)k * nv + v] = b;
+      W->Sbar[(size_t)k * nv + v] = s;
+      for (int d = 0; d < dim; ++d) {
+        double f = 0.0;
+        for (int j = 0; j < n; ++j) f += T->w[j] * W->F[(((size_t)d * n + j) * S + k) * nv + v];
+        W->Fbar[((size_t)d * S + k) * nv + v] = f;
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * 5. Projection of the prediction onto the faces (Sec. 5.1, step fusion;
+ *    Sec. 3.3 phase 2 needs q_h and F(q_h) on both sides of every face).
+ *    READING: the time-averaged state and the time-averaged normal flux are
+ *    both extrapolated with l0 / l1.
+ *    Per cell: qhat, Fhat [2*dim faces][F face nodes][nv], face = 2d + side.
+ * ------------------------------------------------------------------------ */
+static void project_to_faces(const mesh *M, const tables *T, const work *W, double *qhat, double *Fhat) {
+  const int S = M->S, nv = M->nv, F = M->F;
+  size_t face_sz = (size_t)F * nv;
+  memset(qhat, 0, sizeof(double) * 2 * M->dim * face_sz);
+  memset(Fhat, 0, sizeof(double) * 2 * M->dim * face_sz);
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    for (int d = 0; d < M->dim; ++d) {
+      int f = face_node(M, d, kk);
+      for (int side = 0; side < 2; ++side) {
+        double l = side ? T->l1[kk[d]] : T->l0[kk[d]];
+        double *qh = &qhat[(2 * d + side) * face_sz + (size_t)f * nv];
+        double *Fh = &Fhat[(2 * d + side) * face_sz + (size_t)f * nv];
+        for (int v = 0; v < nv; ++v) {
+          qh[v] += l * W->qbar[(size_t)k * nv + v];
+          Fh[v] += l * W->Fbar[((size_t)d * S + k) * nv + v];
+        }
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * 6. Rusanov flux with a path-conservative non-conservative part
+ *    (Sec. 3.3 phase 2; the default Riemann solver of Table 1).
+ *    The face has normal +e_d; L is the cell on its low side.
+ *       s = max(lambda*(qL), lambda*(qR))            READING: pointwise
+ *       G = (FL + FR)/2 - s (qR - qL)/2
+ *       Bmid = B_d((qL + qR)/2) (qR - qL) / 2       READING: straight path,
+ *                                                    midpoint rule
+ *    The fluctuation entering cell L through its high face is G - FL + Bmid,
+ *    the one entering cell R through its low face is FR - G + Bmid.
+ * ------------------------------------------------------------------------ */
+static void rusanov(const orc_problem *P, int d, const double *qL, const double *FL,
+                    const double *qR, const double *FR, double *flL, double *flR) {
+  int nv = P->nvar, nq = P->nvar + P->nparam;
+  double s = fmax(pde_max_eigen(P, qL, d), pde_max_eigen(P, qR, d));
+  double qm[ORC_MAXQ], grad[3 * ORC_MAXQ], Bm[ORC_MAXQ];
+  for (int v = 0; v < nq; ++v) qm[v] = 0.5 * (qL[v] + qR[v]);
+  for (int a = 0; a < 3 * ORC_MAXQ; ++a) grad[a] = 0.0;
+  for (int v = 0; v < nv; ++v) grad[d * nq + v] = qR[v] - qL[v];
+  pde_ncp(P, qm, grad, Bm);
+  for (int v = 0; v < nv; ++v) {
+    double G = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (qR[v] - qL[v]);
+    double Bmid = 0.5 * Bm[v];
+    flL[v] = G - FL[v] + Bmid;
+    flR[v] = FR[v] - G + Bmid;
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * 7. Corrector (Sec. 3.3 phase 3, Eq. (6)) with the diagonal GL mass matrix.
+ *    READING: Eq. (6) as printed has the sign of the volume term flipped;
+ *    the standard weak form is used,
+ *       int_T phi_k dq = dt [ int_T grad phi_k . Fbar - int_dT phi_k G.n ]
+ *                       - dt int_T phi_k Nbar + dt int_T phi_k Sbar
+ *                       - (path-conservative jump terms of the NCP),
+ *    evaluated in the equivalent strong form (summation by parts on GL):
+ *       dq_k = dt (-div Fbar - Nbar + Sbar)_k
+ *              - dt sum_d [l1_{k_d} flL(high face) + l0_{k_d} flR(low face)]
+ *                          / (h_d w_{k_d}).
+ *    The weak form itself is also evaluated for conservative PDEs so the
+ *    tests can check that the two agree.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double *vol;  /* [C][S][nv]         dt (-div Fbar - Nbar + Sbar) */
+  double *weak; /* [C][S][nv]         weak-form volume part dt sum w D Fbar + dt Sbar */
+  double *qhat; /* [C][2 dim][F][nv] */
+  double *Fhat; /* [C][2 dim][F][nv] */
+} cellside;
+
+/* Predict cell c and store its volume increment and face traces. */
+static void predict_and_project(const orc_problem *P, const mesh *M, const tables *T, long c,
+                                const double *Q, const double *params, double dt, double t,
+                                work *W, double *vol, double *weak, double *qhat, double *Fhat) {
+  const int S = M->S, nv = M->nv, n = M->n;
+  predictor_cell(P, M, T, c, Q, params, dt, t, P->picard_iters, W);
+  project_to_faces(M, T, W, qhat, Fhat);
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    for (int v = 0; v < nv; ++v) {
+      double divF = 0.0, wk = 0.0;
+      for (int d = 0; d < M->dim; ++d) {
+        double a = 0.0, b = 0.0;
+        for (int m = 0; m < n; ++m) {
+          int km = k + (m - kk[d]) * M->stride[d];
+          double f = W->Fbar[((size_t)d * S + km) * nv + v];
+          a += T->D[kk[d]][m] * f;
+          b += T->w[m] * T->D[m][kk[d]] * f; /* int phi_k' F over the cell */
+        }
+        divF += a / M->h[d];
+        wk += b / (M->h[d] * T->w[kk[d]]);
+      }
+      vol[(size_t)k * nv + v] = dt * (-divF - W->Nbar[(size_t)k * nv + v] + W->Sbar[(size_t)k * nv + v]);
+      if (weak) weak[(size_t)k * nv + v] = dt * (wk + W->Sbar[(size_t)k * nv + v]);
+    }
+  }
+}
+
+/* Assemble u^{n+1} of cell c from its own traces and its neighbours'. */
+static void correct_cell(const orc_problem *P, const mesh *M, const tables *T, long c,
+                         const double *Q, const double *params, double dt, const double *vol,
+                         const double *weak, double *const *qhat_of, double *const *Fhat_of,
+                         const long *nb /*[dim][2]: low, high neighbour*/, double *out,
+                         double *weak_out) {
+  const int S = M->S, nv = M->nv, F = M->F, nq = M->nq;
+  size_t face_sz = (size_t)F * nv;
+  /* fluctuations on the faces of this cell, [2 dim][F][nv] */
+  double *fl = malloc(sizeof(double) * 2 * M->dim * face_sz);
+  double *G = malloc(sizeof(double) * 2 * M->dim * face_sz);
+  double qL[ORC_MAXQ], qR[ORC_MAXQ], flL[ORC_MAXQ], flR[ORC_MAXQ];
+  for (int d = 0; d < M->dim; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      /* side 1: this cell is L, the neighbour above is R; side 0: reverse */
+      long cl = side ? c : nb[2 * d + 0];
+      long cr = side ? nb[2 * d + 1] : c;
+      const double *qhL = qhat_of[side ? 0 : 1 + 2 * d] + (size_t)(2 * d + 1) * face_sz;
+      const double *FhL = Fhat_of[side ? 0 : 1 + 2 * d] + (size_t)(2 * d + 1) * face_sz;
+      const double *qhR = qhat_of[side ? 2 + 2 * d : 0] + (size_t)(2 * d + 0) * face_sz;
+      const double *FhR = Fhat_of[side ? 2 + 2 * d : 0] + (size_t)(2 * d + 0) * face_sz;
+      for (int f = 0; f < F; ++f) {
+        for (int v = 0; v < nv; ++v) {
+          qL[v] = qhL[(size_t)f * nv + v];
+          qR[v] = qhR[(size_t)f * nv + v];
+        }
+        for (int p = 0; p < P->nparam; ++p) {
+          qL[nv + p] = params[(size_t)cl * P->nparam + p];
+          qR[nv + p] = params[(size_t)cr * P->nparam + p];
+        }
+        rusanov(P, d, qL, &FhL[(size_t)f * nv], qR, &FhR[(size_t)f * nv], flL, flR);
+        for (int v = 0; v < nv; ++v) {
+          fl[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] : flR[v];
+          /* G itself, for the weak-form check */
+          G[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] + FhL[(size_t)f * nv + v]
+                                                                  : FhR[(size_t)f * nv + v] - flR[v];
+        }
+      }
+    }
+  }
+  (void)nq;
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    for (int v = 0; v < nv; ++v) {
+      double surf = 0.0, wsurf = 0.0;
+      for (int d = 0; d < M->dim; ++d) {
+        int f = face_node(M, d, kk);
+        double hi = fl[(2 * d + 1) * face_sz + (size_t)f * nv + v];
+        double lo = fl[(2 * d + 0) * face_sz + (size_t)f * nv + v];
+        surf += (T->l1[kk[d]] * hi + T->l0[kk[d]] * lo) / (M->h[d] * T->w[kk[d]]);
+        double Ghi = G[(2 * d + 1) * face_sz + (size_t)f * nv + v];
+        double Glo = G[(2 * d + 0) * face_sz + (size_t)f * nv + v];
+        wsurf += (T->l1[kk[d]] * Ghi - T->l0[kk[d]] * Glo) / (M->h[d] * T->w[kk[d]]);
+      }
+      double u = Q[((size_t)c * nv + v) * S + k];
+      out[(size_t)v * S + k] = u + (vol[(size_t)k * nv + v] - dt * surf);
+      if (weak_out) weak_out[(size_t)v * S + k] = u + (weak[(size_t)k * nv + v] - dt * wsurf);
+    }
+  }
+  free(fl);
+  free(G);
+}
+
+/* ------------------------------------------------------------------------
+ * 8. Exported entry points.
+ * ------------------------------------------------------------------------ */
+int orc_tables(int n, double *xi, double *w, double *D, double *l0, double *l1, double *K1,
+               double *K1inv) {
+  tables T;
+  int st = make_tables(n, &T);
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    if (xi) xi[i] = T.xi[i];
+    if (w) w[i] = T.w[i];
+    if (l0) l0[i] = T.l0[i];
+    if (l1) l1[i] = T.l1[i];
+    for (int j = 0; j < n; ++j) {
+      if (D) D[i * n + j] = T.D[i][j];
+      if (K1) K1[i * n + j] = T.K1[i][j];
+      if (K1inv) K1inv[i * n + j] = T.K1inv[i][j];
+    }
+  }
+  return ORC_OK;
+}
+
+/* Lagrange basis values phi_i(x), i < n, at one reference point. */
+int orc_basis_eval(int n, double x, double *phi) {
+  tables T;
+  int st = make_tables(n, &T);
+  if (st) return st;
+  for (int i = 0; i < n; ++i) phi[i] = lagrange(&T, i, x);
+  return ORC_OK;
+}
+
+int orc_set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+/* Physical coordinates of every node, [C][S][dim]. */
+int orc_node_coords(const orc_problem *P, double *xyz) {
+  mesh M;
+  tables T;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  for (long c = 0; c < M.C; ++c) {
+    int cc[3];
+    cell_coords(P, c, cc);
+    for (int k = 0; k < M.S; ++k) {
+      int kk[3];
+      node_index(&M, k, kk);
+      for (int d = 0; d < M.dim; ++d)
+        xyz[((size_t)c * M.S + k) * M.dim + d] = P->lo[d] + (cc[d] + T.xi[kk[d]]) * M.h[d];
+    }
+  }
+  return ORC_OK;
+}
+
+/* Pointwise terms, exported for unit tests. */
+int orc_pointwise(const orc_problem *P, const double *Q, int d, double *flux, double *max_eigen,
+                  int *admissible) {
+  if (flux) pde_flux(P, Q, d, flux);
+  if (max_eigen) *max_eigen = pde_max_eigen(P, Q, d);
+  if (admissible) *admissible = pde_admissible(P, Q);
+  return ORC_OK;
+}
+
+int orc_ncp(const orc_problem *P, const double *Q, const double *gradQ, double *BgradQ) {
+  pde_ncp(P, Q, gradQ, BgradQ);
+  return ORC_OK;
+}
+
+int orc_rusanov(const orc_problem *P, int d, const double *qL, const double *FL, const double *qR,
+                const double *FR, double *flL, double *flR) {
+  rusanov(P, d, qL, FL, qR, FR, flL, flR);
+  return ORC_OK;
+}
+
+/* Eq. (7): dt = CFL / (d (2N+1)) * h / |lambda_max|.
+ * READING: h = min_d h_d, lambda_max = max over cells, nodes and directions
+ * of the largest absolute eigenvalue, evaluated on u^n. */
+int orc_stable_dt(const orc_problem *P, const double *Q, const double *params, double *dt,
+                  double *lambda_max) {
+  mesh M;
+  if (make_mesh(P, &M)) return ORC_EINVAL;
+  double lam = 0.0;
+  for (long c = 0; c < M.C; ++c)
+    for (int k = 0; k < M.S; ++k) {
+      double q[ORC_MAXQ];
+      for (int v = 0; v < M.nv; ++v) q[v] = Q[((size_t)c * M.nv + v) * M.S + k];
+      for (int p = 0; p < P->nparam; ++p) q[M.nv + p] = params[(size_t)c * P->nparam + p];
+      for (int d = 0; d < M.dim; ++d) lam = fmax(lam, pde_max_eigen(P, q, d));
+    }
+  double h = M.h[0];
+  for (int d = 1; d < M.dim; ++d) h = fmin(h, M.h[d]);
+  if (lambda_max) *lambda_max = lam;
+  *dt = P->cfl / (M.dim * (2.0 * P->order + 1.0)) * h / lam;
+  return ORC_OK;
+}
+
+/* Space-time predictor of one cell, [n][S][nq] (unit tests). */
+int orc_predictor(const orc_problem *P, long cell, const double *Q, const double *params, double dt,
+                  double t, int iters, double *qst, double *qbar, double *Fbar) {
+  mesh M;
+  tables T;
+  work W;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  if (work_alloc(&M, &W)) { work_free(&W); return ORC_ENOMEM; }
+  predictor_cell(P, &M, &T, cell, Q, params, dt, t, iters, &W);
+  if (qst) memcpy(qst, W.q, sizeof(double) * M.n * M.S * M.nq);
+  if (qbar) memcpy(qbar, W.qbar, sizeof(double) * M.S * M.nv);
+  if (Fbar) memcpy(Fbar, W.Fbar, sizeof(double) * M.dim * M.S * M.nv);
+  work_free(&W);
+  return ORC_OK;
+}
+
+/* Face traces (qhat, Fhat) and volume increment of every cell. */
+static int predict_all(const orc_problem *P, const mesh *M, const tables *T, const double *Q,
+                       const double *params, double dt, double t, const long *cells, long ncells,
+                       cellside *CS) {
+  size_t face_all = (size_t)2 * M->dim * M->F * M->nv;
+  int fail = 0;
+#pragma omp parallel
+  {
+    work W;
+    int ok = work_alloc(M, &W) == ORC_OK;
+    if (!ok) {
+#pragma omp atomic write
+      fail = 1;
+    }
+#pragma omp for schedule(dynamic, 4)
+    for (long i = 0; i < ncells; ++i) {
+      if (!ok) continue;
+      long c = cells ? cells[i] : i;
+      predict_and_project(P, M, T, c, Q, params, dt, t, &W, &CS->vol[(size_t)i * M->S * M->nv],
+                          CS->weak ? &CS->weak[(size_t)i * M->S * M->nv] : NULL,
+                          &CS->qhat[i * face_all], &CS->Fhat[i * face_all]);
+    }
+    work_free(&W);
+  }
+  return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* One full step in place: Q <- u^{n+1}.  If weak_out is not NULL it receives
+ * u^{n+1} assembled with the weak form of Eq. (6) (conservative PDEs only). */
+int orc_step(const orc_problem *P, double *Q, const double *params, double dt, double t,
+             double *weak_out) {
+  mesh M;
+  tables T;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  size_t face_all = (size_t)2 * M.dim * M.F * M.nv;
+  cellside CS;
+  CS.vol = malloc(sizeof(double) * M.C * M.S * M.nv);
+  CS.weak = weak_out ? malloc(sizeof(double) * M.C * M.S * M.nv) : NULL;
+  CS.qhat = malloc(sizeof(double) * M.C * face_all);
+  CS.Fhat = malloc(sizeof(double) * M.C * face_all);
+  double *out = malloc(sizeof(double) * M.C * M.S * M.nv);
+  int st = ORC_ENOMEM;
+  if (CS.vol && CS.qhat && CS.Fhat && out && (!weak_out || CS.weak)) {
+    st = predict_all(P, &M, &T, Q, params, dt, t, NULL, M.C, &CS);
+    if (st == ORC_OK) {
+#pragma omp parallel for schedule(dynamic, 8)
+      for (long c = 0; c < M.C; ++c) {
+        long nb[6];
+        double *qh[7], *Fh[7];
+        qh[0] = &CS.qhat[c * face_all];
+        Fh[0] = &CS.Fhat[c * face_all];
+        for (int d = 0; d < M.dim; ++d)
+          for (int s = 0; s < 2; ++s) {
+            nb[2 * d + s] = neighbour(P, c, d, s ? 1 : -1);
+            qh[1 + 2 * d + s] = &CS.qhat[nb[2 * d + s] * face_all];
+            Fh[1 + 2 * d + s] = &CS.Fhat[nb[2 * d + s] * face_all];
+          }
+        correct_cell(P, &M, &T, c, Q, params, dt, &CS.vol[(size_t)c * M.S * M.nv],
+                     CS.weak ? &CS.weak[(size_t)c * M.S * M.nv] : NULL, qh, Fh, nb,
+                     &out[(size_t)c * M.nv * M.S],
+                     weak_out ? &weak_out[(size_t)c * M.nv * M.S] : NULL);
+      }
+      memcpy(Q, out, sizeof(double) * M.C * M.S * M.nv);
+    }
+  }
+  free(CS.vol); free(CS.weak); free(CS.qhat); free(CS.Fhat); free(out);
+  return st;
+}
+
+/* u^{n+1} of a chosen set of cells only (out: [ncs][nv][S]).  Each chosen
+ * cell needs its own prediction and those of its 2 dim face neighbours. */
+int orc_step_cells(const orc_problem *P, const double *Q, const double *params, double dt,
+                   double t, long ncs, const long *cells, double *out) {
+  mesh M;
+  tables T;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  size_t face_all = (size_t)2 * M.dim * M.F * M.nv;
+  long per = 1 + 2 * M.dim;
+  long nall = ncs * per;
+  long *list = malloc(sizeof(long) * nall);
+  cellside CS;
+  CS.vol = malloc(sizeof(double) * nall * M.S * M.nv);
+  CS.weak = NULL;
+  CS.qhat = malloc(sizeof(double) * nall * face_all);
+  CS.Fhat = malloc(sizeof(double) * nall * face_all);
+  int st = ORC_ENOMEM;
+  if (list && CS.vol && CS.qhat && CS.Fhat) {
+    for (long i = 0; i < ncs; ++i) {
+      list[i * per] = cells[i];
+      for (int d = 0; d < M.dim; ++d)
+        for (int s = 0; s < 2; ++s) list[i * per + 1 + 2 * d + s] = neighbour(P, cells[i], d, s ? 1 : -1);
+    }
+    st = predict_all(P, &M, &T, Q, params, dt, t, list, nall, &CS);
+    if (st == ORC_OK) {
+#pragma omp parallel for
+      for (long i = 0; i < ncs; ++i) {
+        long nb[6];
+        double *qh[7], *Fh[7];
+        for (int a = 0; a < per; ++a) {
+          qh[a] = &CS.qhat[(i * per + a) * face_all];
+          Fh[a] = &CS.Fhat[(i * per + a) * face_all];
+          if (a > 0) nb[a - 1] = list[i * per + a];
+        }
+        correct_cell(P, &M, &T, cells[i], Q, params, dt, &CS.vol[(size_t)(i * per) * M.S * M.nv],
+                     NULL, qh, Fh, nb, &out[(size_t)i * M.nv * M.S], NULL);
+      }
+    }
+  }
+  free(list); free(CS.vol); free(CS.qhat); free(CS.Fhat);
+  return st;
+}
+
+/* Face traces of one cell: qhat and Fhat, each [2 dim][F][nv] (unit tests and
+ * parity of the projection step). */
+int orc_cell_traces(const orc_problem *P, long cell, const double *Q, const double *params,
+                    double dt, double t, double *qhat, double *Fhat, double *vol) {
+  mesh M;
+  tables T;
+  work W;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  if (work_alloc(&M, &W)) { work_free(&W); return ORC_ENOMEM; }
+  double *v = malloc(sizeof(double) * M.S * M.nv);
+  predict_and_project(P, &M, &T, cell, Q, params, dt, t, &W, v, NULL, qhat, Fhat);
+  if (vol) memcpy(vol, v, sizeof(double) * M.S * M.nv);
+  free(v);
+  work_free(&W);
+  return ORC_OK;
+}
+
+/* Receivers: u(x_r) = sum_k Phi_k(xi_r) u_k in the cell holding x_r
+ * (half-open cell intervals).  out: [nrec][nv]. */
+int orc_sample_receivers(const orc_problem *P, int nrec, const double *xyz, const double *Q,
+                         double *out) {
+  mesh M;
+  tables T;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  for (int r = 0; r < nrec; ++r) {
+    int cc[3] = {0, 0, 0};
+    double xs[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < M.dim; ++d) {
+      double s = (xyz[r * 3 + d] - P->lo[d]) / M.h[d];
+      cc[d] = (int)floor(s);
+      if (cc[d] < 0 || cc[d] >= P->cells[d]) return ORC_EINVAL;
+      xs[d] = s - cc[d];
+    }
+    long c = cell_index(P, cc);
+    for (int v = 0; v < M.nv; ++v) {
+      double acc = 0.0;
+      for (int k = 0; k < M.S; ++k) {
+        int kk[3];
+        node_index(&M, k, kk);
+        double phi = 1.0;
+        for (int d = 0; d < M.dim; ++d) phi *= lagrange(&T, kk[d], xs[d]);
+        acc += phi * Q[((size_t)c * M.nv + v) * M.S + k];
+      }
+      out[r * M.nv + v] = acc;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Admissibility of every cell (Sec. 3.5, physical criterion plus finiteness):
+ * flags[c] = 1 if any node of c fails; *count = number of flagged cells. */
+int orc_check_admissible(const orc_problem *P, const double *Q, const double *params,
+                         unsigned char *flags, int *count) {
+  mesh M;
+  if (make_mesh(P, &M)) return ORC_EINVAL;
+  int cnt = 0;
+  for (long c = 0; c < M.C; ++c) {
+    int bad = 0;
+    for (int k = 0; k < M.S && !bad; ++k) {
+      double q[ORC_MAXQ];
+      for (int v = 0; v < M.nv; ++v) q[v] = Q[((size_t)c * M.nv + v) * M.S + k];
+      for (int p = 0; p < P->nparam; ++p) q[M.nv + p] = params[(size_t)c * P->nparam + p];
+      bad = !pde_admissible(P, q);
+    }
+    flags[c] = (unsigned char)bad;
+    cnt += bad;
+  }
+  *count = cnt;
+  return ORC_OK;
+}

@@ -1,0 +1,544 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own formulas: textbook
+tables, numpy's own Gauss-Legendre / polynomial routines, closed-form
+solutions of the PDEs, conservation and free-stream invariants, and a dense
+solve of the element-local space-time system assembled from exact polynomial
+integrals.  No test here needs a GPU.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- 1-D tables
+def _leggauss01(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _lagrange_polys(nodes):
+    """Lagrange basis as numpy Legendre series on the domain [0, 1] (well
+    conditioned, unlike power series at n = 8)."""
+    polys = []
+    for i, xi in enumerate(nodes):
+        L = np.polynomial.Legendre.fromroots(np.delete(nodes, i), domain=[0.0, 1.0])
+        polys.append(L / L(xi))
+    return polys
+
+
+def _integ01(L):
+    Li = L.integ()
+    return Li(1.0) - Li(0.0)
+
+
+def test_gauss_legendre_abramowitz_stegun():
+    """GL abscissae/weights against Abramowitz & Stegun Table 25.4 (15 digits)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "gauss_legendre_as_25_4.txt"))
+    for n in (2, 3, 4, 5):
+        T = O.tables(n)
+        z = 2.0 * T["xi"] - 1.0  # back to [-1, 1]
+        wz = 2.0 * T["w"]
+        for _, a, wt in rows[rows[:, 0] == n]:
+            hit = np.where(np.abs(np.abs(z) - a) < 1e-12)[0]
+            assert len(hit) == (1 if a == 0.0 else 2), (n, a)
+            np.testing.assert_allclose(wz[hit], wt, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_gauss_legendre_vs_numpy(n):
+    T = O.tables(n)
+    x, w = _leggauss01(n)
+    # numpy's own rule is itself accurate to a few ulp, not correctly rounded
+    np.testing.assert_allclose(T["xi"], x, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(T["w"], w, rtol=0, atol=1e-15)
+    assert abs(T["w"].sum() - 1.0) < 4e-16
+    np.testing.assert_allclose(T["xi"], 1.0 - T["xi"][::-1], atol=4e-16)
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_quadrature_degree(n):
+    """n-point GL integrates x^k exactly on [0,1] for k <= 2n-1, not for 2n."""
+    T = O.tables(n)
+    for k in range(2 * n):
+        assert abs(np.dot(T["w"], T["xi"] ** k) - 1.0 / (k + 1)) < 2e-15, k
+    assert abs(np.dot(T["w"], T["xi"] ** (2 * n)) - 1.0 / (2 * n + 1)) > 1e-12
+
+
+@pytest.mark.parametrize("n", range(2, 9))
+def test_derivative_matrix_and_boundary_values(n):
+    T = O.tables(n)
+    xi = T["xi"]
+    # D differentiates every polynomial of degree <= N = n-1 exactly
+    for k in range(n):
+        exact = k * xi ** (k - 1) if k else np.zeros(n)
+        np.testing.assert_allclose(T["D"] @ xi ** k, exact, atol=5e-12 * max(1, k))
+    # l0 / l1 evaluate the interpolant at 0 and 1
+    for k in range(n):
+        assert abs(T["l0"] @ xi ** k - (1.0 if k == 0 else 0.0)) < 1e-13
+        assert abs(T["l1"] @ xi ** k - 1.0) < 1e-13
+    # independent construction: numpy polynomials through numpy's GL nodes
+    x, _ = _leggauss01(n)
+    polys = _lagrange_polys(x)
+    for j, c in enumerate(polys):
+        np.testing.assert_allclose(T["D"][:, j], c.deriv()(x), atol=1e-13 * n * n)
+        assert abs(T["l0"][j] - c(0.0)) < 1e-13
+        assert abs(T["l1"][j] - c(1.0)) < 1e-13
+    np.testing.assert_allclose(O.basis_eval(n, 0.37), [c(0.37) for c in polys], atol=1e-13)
+
+
+@pytest.mark.parametrize("n", range(2, 9))
+def test_summation_by_parts_and_time_matrix(n):
+    T = O.tables(n)
+    W = np.diag(T["w"])
+    D = T["D"]
+    sbp = W @ D + D.T @ W
+    np.testing.assert_allclose(sbp, np.outer(T["l1"], T["l1"]) - np.outer(T["l0"], T["l0"]),
+                               atol=1e-11 * n)
+    # K1 . 1 = l0, and K1 K1^{-1} = I
+    np.testing.assert_allclose(T["K1"] @ np.ones(n), T["l0"], atol=1e-12)
+    np.testing.assert_allclose(T["K1"] @ T["K1inv"], np.eye(n), atol=1e-12 * n)
+    # K1_ij = phi_i(1) phi_j(1) - int_0^1 phi_i' phi_j from exact polynomial integrals
+    x, _ = _leggauss01(n)
+    polys = _lagrange_polys(x)
+    K = np.zeros((n, n))
+    for i, ci in enumerate(polys):
+        for j, cj in enumerate(polys):
+            K[i, j] = ci(1.0) * cj(1.0) - _integ01(ci.deriv() * cj)
+    np.testing.assert_allclose(T["K1"], K, atol=1e-13 * n * n)
+
+
+# ---------------------------------------------------------------- PDE terms
+def _num_jacobian(fun, q, nv):
+    J = np.zeros((nv, nv))
+    h = 1e-6
+    for v in range(nv):
+        e = np.zeros_like(q)
+        e[v] = h * max(1.0, abs(q[v]))
+        J[:, v] = (fun(q + e) - fun(q - e)) / (2 * e[v])
+    return J
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_euler_eigenvalues_match_flux_jacobian(dim):
+    """The eigenvalue hook agrees with the spectrum of the flux Jacobian."""
+    P = O.problem(dim, 2, O.EULER, [2] * dim)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        rho = rng.uniform(0.5, 2.0)
+        u = rng.uniform(-1, 1, dim)
+        p = rng.uniform(0.5, 2.0)
+        q = np.concatenate([[rho], rho * u, [p / 0.4 + 0.5 * rho * u @ u]])
+        for d in range(dim):
+            J = _num_jacobian(lambda s: O.pointwise(P, s, d)[0], q, dim + 2)
+            ev = np.sort(np.linalg.eigvals(J).real)
+            c = np.sqrt(1.4 * p / rho)
+            np.testing.assert_allclose(ev, np.sort([u[d] - c] + [u[d]] * dim + [u[d] + c]), atol=1e-6)
+            assert abs(O.pointwise(P, q, d)[1] - np.abs(ev).max()) < 1e-6
+
+
+def _elastic_state(rng, rho=2.7, cp=6.0, cs=3.464):
+    return np.concatenate([rng.normal(size=9), [rho, cp, cs]])
+
+
+def _elastic_matrix(P, q, d):
+    """A_d = dF_d/dQ + B_d (linear system, so central differences are exact)."""
+    def total(qv):
+        F = O.pointwise(P, qv, d)[0]
+        return F
+
+    def ncp_dir(qv_evolved):
+        g = np.zeros((3, 12))
+        g[d, :9] = qv_evolved
+        return O.ncp(P, q, g)
+
+    A = _num_jacobian(lambda s: total(np.concatenate([s, q[9:]])), q[:9], 9)
+    B = np.column_stack([ncp_dir(np.eye(9)[v]) for v in range(9)])
+    return A + B
+
+
+def test_elastic_wave_speeds():
+    """Spectrum of the elastic system in every direction: +-cp, +-cs (x2), 0 (x3)."""
+    P = O.problem(3, 2, O.ELASTIC, [2, 2, 2])
+    rng = np.random.default_rng(2)
+    for rho, cp, cs in [(2600.0, 4000.0, 2000.0), (2700.0, 6000.0, 3464.0), (1.0, 2.0, 1.0)]:
+        q = _elastic_state(rng, rho, cp, cs)
+        for d in range(3):
+            ev = np.sort(np.linalg.eigvals(_elastic_matrix(P, q, d)).real)
+            np.testing.assert_allclose(ev, np.sort([-cp, -cs, -cs, 0, 0, 0, cs, cs, cp]), atol=1e-6 * cp)
+            assert O.pointwise(P, q, d)[1] == cp
+
+
+def test_rusanov_properties():
+    P = O.problem(3, 2, O.EULER, [2, 2, 2])
+    rng = np.random.default_rng(3)
+    q = np.array([1.2, 0.1, -0.2, 0.3, 3.0])
+    for d in range(3):
+        F = O.pointwise(P, q, d)[0]
+        flL, flR = O.rusanov(P, d, q, F, q, F)
+        assert np.abs(flL).max() == 0 and np.abs(flR).max() == 0  # consistency
+    # scalar advection: Rusanov is exact upwinding
+    Pa = O.problem(2, 2, O.ADVECTION, [2, 2], adv=(0.7, -1.3))
+    for d, a in enumerate((0.7, -1.3)):
+        qL, qR = rng.normal(), rng.normal()
+        flL, flR = O.rusanov(Pa, d, [qL], [a * qL], [qR], [a * qR])
+        G = a * (qL if a > 0 else qR)
+        np.testing.assert_allclose(flL, [G - a * qL], atol=1e-15)
+        np.testing.assert_allclose(flR, [a * qR - G], atol=1e-15)
+    # elastic, homogeneous material: path-conservative consistency flL + flR = A_d (qR - qL)
+    Pe = O.problem(3, 2, O.ELASTIC, [2, 2, 2])
+    for d in range(3):
+        qL, qR = _elastic_state(rng), _elastic_state(rng)
+        FL = O.pointwise(Pe, qL, d)[0]
+        FR = O.pointwise(Pe, qR, d)[0]
+        flL, flR = O.rusanov(Pe, d, qL, FL, qR, FR)
+        np.testing.assert_allclose(flL + flR, _elastic_matrix(Pe, qL, d) @ (qR[:9] - qL[:9]), atol=1e-8)
+
+
+def test_cfl_closed_form():
+    for dim, N in ((2, 3), (3, 5)):
+        P = O.problem(dim, N, O.EULER, [4, 3, 2][:dim], hi=[1.0, 0.5, 2.0][:dim], cfl=0.9)
+        rho, u, p = 1.3, np.array([0.4, -0.9, 0.2])[:dim], 2.0
+        Q = np.zeros((P.ncells, dim + 2, P.S))
+        Q[:, 0], Q[:, 1:dim + 1], Q[:, -1] = rho, (rho * u)[None, :, None], p / 0.4 + 0.5 * rho * u @ u
+        dt, lam = O.stable_dt(P, Q)
+        lam_exact = np.abs(u).max() + np.sqrt(1.4 * p / rho)
+        h = min(P.h)
+        assert abs(lam - lam_exact) < 1e-14 * lam_exact
+        assert abs(dt - 0.9 / (dim * (2 * N + 1)) * h / lam_exact) < 1e-15 * dt
+
+
+# ---------------------------------------------------------------- predictor
+def _dense_predictor(P, u_cell, dt, A_list, kappa=0.0):
+    """Solve the element-local space-time system exactly.
+
+    Unknowns q[(j,k), v]; test functions theta_i(tau) phi_k(x); all integrals
+    are exact polynomial integrals of numpy Lagrange polynomials (no GL
+    quadrature), so this is the Galerkin system of the weak form with the
+    time derivative integrated by parts and u^n upwind at tau = 0:
+      sum [theta_i(1) theta_j(1) - int theta_i' theta_j] M q_j
+        + dt int theta_i theta_j [sum_d A_d Dx_d + kappa M] q_j = theta_i(0) M u.
+    A_list[d] is the (constant) nv x nv matrix multiplying d/dx_d.
+    """
+    n, dim = P.n, P.dim
+    nv = A_list[0].shape[0]
+    x, _ = _leggauss01(n)
+    polys = _lagrange_polys(x)
+    M1 = np.array([[_integ01(a * b) for b in polys] for a in polys])
+    C1 = np.array([[_integ01(a * b.deriv()) for b in polys] for a in polys])
+    Tt = np.array([[a(1.0) * b(1.0) - _integ01(a.deriv() * b) for b in polys] for a in polys])
+    th0 = np.array([a(0.0) for a in polys])
+    h = P.h
+    # spatial operators on the tensor space, node index k = kx + n ky (+ n^2 kz)
+    def kron_dims(mats):
+        out = np.array([[1.0]])
+        for m in reversed(mats):
+            out = np.kron(out, m)
+        return out
+    Mx = kron_dims([M1 * h[d] for d in range(dim)])
+    Dx = []
+    for d in range(dim):
+        # int phi_k d/dx_d phi_k' over the cell = prod_{a != d} (h_a M1) * C1 (the h_d cancels)
+        mats = [M1 * h[a] if a != d else C1 for a in range(dim)]
+        Dx.append(kron_dims(mats))
+    S = n ** dim
+    Asp = sum(np.kron(Dx[d], A_list[d]) for d in range(dim)) + kappa * np.kron(Mx, np.eye(nv))
+    Mxv = np.kron(Mx, np.eye(nv))
+    big = np.kron(Tt, Mxv) + dt * np.kron(M1, Asp)
+    rhs = np.kron(th0, Mxv @ u_cell.reshape(-1))
+    sol = np.linalg.solve(big, rhs)
+    return sol.reshape(n, S, nv)
+
+
+def test_predictor_constant_state_is_fixed_point():
+    P = O.problem(3, 3, O.EULER, [2, 2, 2])
+    Q = np.zeros((P.ncells, 5, P.S))
+    Q[:, :] = np.array([1.1, 0.3, -0.2, 0.1, 2.7])[None, :, None]
+    qst, qbar, _ = O.predictor(P, 3, Q, None, 1e-2)
+    np.testing.assert_allclose(qst[..., :5], np.broadcast_to(Q[3].T, qst[..., :5].shape), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("dim,N", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_predictor_advection_equals_dense_solve(dim, N):
+    """Linear advection: Picard with I = dN+1 iterations is exact (nilpotent
+    iteration) and equals the dense solve of the element system."""
+    a = (0.8, -0.5, 0.3)[:dim]
+    P = O.problem(dim, N, O.ADVECTION, [3] * dim, adv=a, hi=[1.0, 0.7, 1.3][:dim])
+    rng = np.random.default_rng(10 + dim + N)
+    Q = rng.normal(size=(P.ncells, 1, P.S))
+    c = 4
+    dt = 0.05
+    qst, _, _ = O.predictor(P, c, Q, None, dt, iters=dim * N + 1)
+    ref = _dense_predictor(P, Q[c].T, dt, [np.array([[ad]]) for ad in a])
+    np.testing.assert_allclose(qst[..., 0], ref[..., 0], atol=2e-13 * np.abs(ref).max())
+
+
+def test_predictor_advection_polynomial_closed_form():
+    """Polynomial data of degree <= N in each variable is transported exactly:
+    q(x, t^n + tau dt) = p(x - a tau dt) at every space-time node."""
+    dim, N = 2, 3
+    a = np.array([0.6, -0.4])
+    P = O.problem(dim, N, O.ADVECTION, [2, 2], adv=tuple(a))
+    X = O.node_coords(P)
+
+    def p(x, y):
+        return 1.0 + 0.3 * x - 0.2 * y + 0.5 * x * x * y - 0.7 * x ** 3 * y ** 2 + 0.1 * y ** 3
+
+    Q = p(X[..., 0], X[..., 1])[:, None, :]
+    dt = 0.07
+    qst, _, _ = O.predictor(P, 1, Q, None, dt, iters=dim * N + 1)
+    tau = O.tables(N + 1)["xi"]
+    for j in range(N + 1):
+        s = tau[j] * dt
+        exact = p(X[1, :, 0] - a[0] * s, X[1, :, 1] - a[1] * s)
+        np.testing.assert_allclose(qst[j, :, 0], exact, atol=1e-13)
+
+
+def test_predictor_decay_source_converges_to_dense_solve():
+    P = O.problem(2, 2, O.ADVECTION, [2, 2], adv=(0.5, 0.25), kappa=3.0)
+    rng = np.random.default_rng(7)
+    Q = rng.normal(size=(P.ncells, 1, P.S))
+    dt = 0.05
+    qst, _, _ = O.predictor(P, 2, Q, None, dt, iters=60)
+    ref = _dense_predictor(P, Q[2].T, dt, [np.array([[0.5]]), np.array([[0.25]])], kappa=3.0)
+    np.testing.assert_allclose(qst[..., 0], ref[..., 0], atol=1e-13)
+
+
+def test_predictor_elastic_equals_dense_solve():
+    """Elastic (linear, flux + non-conservative product): Picard with dN+1
+    iterations equals the dense solve built from the system matrices."""
+    P = O.problem(3, 1, O.ELASTIC, [2, 2, 2], hi=[3.0, 3.0, 3.0])
+    rng = np.random.default_rng(8)
+    params = np.tile([2.0, 3.0, 1.5], (P.ncells, 1))
+    Q = rng.normal(size=(P.ncells, 9, P.S))
+    q0 = np.concatenate([np.zeros(9), params[0]])
+    A = [_elastic_matrix(P, q0, d) for d in range(3)]
+    dt = 0.04
+    qst, _, _ = O.predictor(P, 5, Q, params, dt, iters=3 * 1 + 1)
+    ref = _dense_predictor(P, Q[5].T, dt, A)
+    np.testing.assert_allclose(qst[..., :9], ref, atol=1e-12 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- full step
+def _euler_state(rho, u, p, gamma=1.4):
+    """(rho, rho u, E) with E = p/(gamma-1) + rho |u|^2 / 2 (Eq. 10)."""
+    u = np.asarray(u)
+    return np.concatenate([[rho], rho * u, [p / (gamma - 1) + 0.5 * rho * u @ u]])
+
+
+def _c1_state(P, t):
+    X = O.node_coords(P)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * (X[..., 0] + X[..., 1] - 2.0 * t))
+    return np.stack([rho, rho, rho, 2.5 + rho], axis=1)
+
+
+def _run_to(P, Q, T, params=None):
+    t = 0.0
+    while t < T - 1e-15:
+        dt = min(O.stable_dt(P, Q, params)[0], T - t)
+        Q = O.step(P, Q, params, dt, t)
+        t += dt
+    return Q
+
+
+def _rel_l2(P, A, B):
+    Tn = O.tables(P.n)
+    W = Tn["w"]
+    Wk = W
+    for _ in range(P.dim - 1):
+        Wk = np.kron(W, Wk)
+    diff = ((A - B) ** 2 * Wk).sum()
+    return np.sqrt(diff / ((B ** 2) * Wk).sum())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_free_stream(dim):
+    P = O.problem(dim, 3, O.EULER, [3, 4, 2][:dim])
+    q = _euler_state(1.3, [0.4, -0.7, 0.2][:dim], 0.9)
+    Q = np.broadcast_to(q[None, :, None], (P.ncells, dim + 2, P.S)).copy()
+    Qn = O.run(P, Q, steps=5)[0]
+    np.testing.assert_allclose(Qn, Q, rtol=1e-14, atol=0)
+
+
+def test_free_stream_elastic_with_material_jumps():
+    P = O.problem(3, 2, O.ELASTIC, [3, 3, 3], hi=[3000.0] * 3)
+    rng = np.random.default_rng(4)
+    params = np.column_stack([rng.uniform(2000, 3000, P.ncells), rng.uniform(5000, 7000, P.ncells),
+                              rng.uniform(2500, 3400, P.ncells)])
+    # physically scaled constant state: sigma ~ rho cp v, rho v ~ rho v
+    scale = np.array([2700.0 * 6000.0] * 6 + [2700.0] * 3)
+    Q = np.broadcast_to((scale * rng.normal(size=9))[None, :, None], (P.ncells, 9, P.S)).copy()
+    Qn = O.run(P, Q, params, steps=4)[0]
+    np.testing.assert_allclose(Qn, Q, rtol=0, atol=1e-14 * 2700.0 * 6000.0)
+    np.testing.assert_allclose(Qn[:, 6:], Q[:, 6:], rtol=0, atol=1e-14 * 2700.0)
+
+
+def _smooth_euler(P, seed):
+    X = O.node_coords(P)
+    rng = np.random.default_rng(seed)
+    def f():
+        k = rng.integers(-2, 3, size=(4, P.dim))
+        k[np.all(k == 0, axis=1)] = 1
+        ph = rng.uniform(0, 2 * np.pi, 4)
+        return sum(np.sin(2 * np.pi * X @ k[m] + ph[m]) for m in range(4)) / 4
+    rho = 1.0 + 0.2 * f()
+    u = [0.3 * f() for _ in range(P.dim)]
+    p = 1.0 + 0.2 * f()
+    E = p / 0.4 + 0.5 * rho * sum(ui * ui for ui in u)
+    return np.stack([rho] + [rho * ui for ui in u] + [E], axis=1)
+
+
+@pytest.mark.parametrize("dim,N,cells", [(2, 3, [6, 5]), (3, 2, [3, 4, 3])])
+def test_conservation_periodic(dim, N, cells):
+    P = O.problem(dim, N, O.EULER, cells, hi=[1.0, 0.8, 1.2][:dim])
+    Q = _smooth_euler(P, 11)
+    Tn = O.tables(P.n)
+    Wk = Tn["w"]
+    for _ in range(dim - 1):
+        Wk = np.kron(Tn["w"], Wk)
+    vol = np.prod(P.h)
+    tot0 = (Q * Wk).sum(axis=(0, 2)) * vol
+    Qn = O.run(P, Q, steps=5)[0]
+    tot1 = (Qn * Wk).sum(axis=(0, 2)) * vol
+    np.testing.assert_allclose(tot1, tot0, rtol=0, atol=1e-14 * 5 * np.abs(tot0).max())
+
+
+def test_weak_and_strong_form_agree():
+    P = O.problem(3, 3, O.EULER, [3, 3, 2])
+    Q = _smooth_euler(P, 12)
+    dt = O.stable_dt(P, Q)[0]
+    strong, weak = O.step(P, Q, None, dt, 0.0, weak=True)
+    np.testing.assert_allclose(strong, weak, rtol=0, atol=2e-14 * np.abs(Q).max())
+
+
+def test_c1_closed_form_and_order():
+    """The advected density wave of the 2-D Euler config is an exact solution;
+    h-refinement converges at order >= N+1 - 0.3 (Sec. 6, N+1 expected)."""
+    errs = {}
+    for N in (2, 3):
+        errs[N] = []
+        for m in (4, 8, 16):
+            P = O.problem(2, N, O.EULER, [m, m])
+            Q = _run_to(P, _c1_state(P, 0.0), 0.05)
+            errs[N].append(_rel_l2(P, Q, _c1_state(P, 0.05)))
+        rates = np.log2(np.array(errs[N][:-1]) / np.array(errs[N][1:]))
+        assert rates[-1] >= N + 1 - 0.3, (N, errs[N], rates)
+    # the config itself: 16x16 cells, N = 3, 10 steps
+    P = O.problem(2, 3, O.EULER, [16, 16])
+    Q, t = O.run(P, _c1_state(P, 0.0), steps=10)
+    assert _rel_l2(P, Q, _c1_state(P, t)) < 1e-6
+
+
+def test_advection_decay_closed_form_order():
+    """q(x,t) = q0(x - a t) exp(-kappa t): exercises the smooth source term."""
+    a, kappa = (1.0, 0.5), 2.0
+    errs = []
+    for m in (4, 8, 16):
+        P = O.problem(2, 2, O.ADVECTION, [m, m], adv=a, kappa=kappa)
+        X = O.node_coords(P)
+        f = lambda t: (np.sin(2 * np.pi * (X[..., 0] - a[0] * t)) * np.cos(2 * np.pi * (X[..., 1] - a[1] * t))
+                       * np.exp(-kappa * t) + 2.0 * np.exp(-kappa * t))[:, None, :]
+        Q = _run_to(P, f(0.0), 0.1)
+        errs.append(_rel_l2(P, Q, f(0.1)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] >= 3 - 0.3, (errs, rates)
+
+
+def _plane_wave(P, X, t, kind, mvec, A=1e-3):
+    """Plane waves of the elastic system in the paper's variables (sigma, rho v).
+    P-wave: v = A n sin(k.x - cp|k|t), sigma = (A/cp)(lam I + 2 mu n n^T) sin(.)
+    S-wave: v = A s sin(k.x - cs|k|t), sigma = (A mu/cs)(s n^T + n s^T) sin(.)"""
+    rho, cp, cs = 1.0, 2.0, 1.0
+    mu, lam = rho * cs * cs, rho * cp * cp - 2 * rho * cs * cs
+    k = 2 * np.pi * np.asarray(mvec, float)
+    nrm = k / np.linalg.norm(k)
+    c = cp if kind == "P" else cs
+    phase = np.sin(X @ k - c * np.linalg.norm(k) * t)
+    if kind == "P":
+        pol = nrm
+        sig = (A / cp) * (lam * np.eye(3) + 2 * mu * np.outer(nrm, nrm))
+    else:
+        pol = np.cross(nrm, [0.0, 0.0, 1.0]) if abs(nrm[2]) < 0.9 else np.cross(nrm, [1.0, 0.0, 0.0])
+        pol /= np.linalg.norm(pol)
+        sig = (A * mu / cs) * (np.outer(pol, nrm) + np.outer(nrm, pol))
+    comp = [sig[0, 0], sig[1, 1], sig[2, 2], sig[0, 1], sig[0, 2], sig[1, 2]]
+    fields = [s * phase for s in comp] + [rho * A * pol[i] * phase for i in range(3)]
+    return np.stack(fields, axis=1), np.tile([rho, cp, cs], (X.shape[0], 1))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["P", "S"])
+def test_elastic_plane_wave_order(kind):
+    errs = []
+    N = 3
+    for m in (4, 8):
+        P = O.problem(3, N, O.ELASTIC, [m, m, m])
+        X = O.node_coords(P)
+        Q, params = _plane_wave(P, X, 0.0, kind, (1, 1, 0))
+        Qn = _run_to(P, Q, 0.1, params)
+        errs.append(_rel_l2(P, Qn, _plane_wave(P, X, 0.1, kind, (1, 1, 0))[0]))
+    rate = np.log2(errs[0] / errs[1])
+    assert rate >= N + 1 - 0.3, (errs, rate)
+
+
+# ---------------------------------------------------------------- sources, receivers, checks
+def test_point_source_reproduces_dirac_on_polynomials():
+    """A point source added over one step acts on every test polynomial p of
+    degree <= N as p(x_s) * int s dt (the weak form of a Dirac delta), and its
+    time integral is the Gauss rule of the Ricker wavelet (accurate to the
+    quadrature error, far below the tolerance at this dt)."""
+    from scipy.integrate import quad
+    N = 3
+    xs = (0.41, 0.63, 0.27)
+    src = dict(x=xs, w=[1.0], f0=5.0, t0=0.2, amp=1.0)
+    P = O.problem(3, N, O.ADVECTION, [3, 3, 3], adv=(0.0, 0.0, 0.0), sources=[src])
+    Q = np.zeros((P.ncells, 1, P.S))
+    dt, t = 2e-3, 0.17
+    Qn = O.step(P, Q, None, dt, t)
+    dq = Qn[:, 0, :]
+    X = O.node_coords(P)
+    Tn = O.tables(P.n)
+    Wk = np.kron(Tn["w"], np.kron(Tn["w"], Tn["w"]))
+    vol = np.prod(P.h)
+    pi2f2 = (np.pi * 5.0) ** 2
+    s_int = quad(lambda tt: (1 - 2 * pi2f2 * (tt - 0.2) ** 2) * np.exp(-pi2f2 * (tt - 0.2) ** 2), t, t + dt,
+                 epsabs=1e-15, epsrel=1e-14)[0]
+    for coeffs in [(1, 0, 0, 0), (0, 1, 0, 0), (0.3, -0.2, 0.5, 0.1)]:
+        pfun = lambda x: coeffs[0] + coeffs[1] * x[..., 0] + coeffs[2] * x[..., 1] ** 2 * x[..., 2] \
+            + coeffs[3] * x[..., 0] ** 3 * x[..., 1] ** 2
+        lhs = (pfun(X) * dq * Wk).sum() * vol
+        rhs = pfun(np.array(xs)) * s_int
+        assert abs(lhs - rhs) < 1e-12 * abs(s_int), (coeffs, lhs, rhs)
+
+
+def test_receivers_interpolate():
+    N = 3
+    P = O.problem(3, N, O.ADVECTION, [2, 3, 2], hi=[2.0, 3.0, 2.0])
+    X = O.node_coords(P)
+    p = lambda x: 1 + x[..., 0] ** 3 - 2 * x[..., 1] ** 2 * x[..., 2] + 0.5 * x[..., 0] * x[..., 1] * x[..., 2] ** 3
+    Q = p(X)[:, None, :]
+    rng = np.random.default_rng(5)
+    pts = rng.uniform([0, 0, 0], [2, 3, 2], size=(20, 3))
+    np.testing.assert_allclose(O.sample_receivers(P, pts, Q)[:, 0], p(pts), rtol=1e-13, atol=1e-12)
+    # a receiver sitting exactly on a node returns that nodal value
+    node = X[7, 13]
+    assert O.sample_receivers(P, node[None, :], Q)[0, 0] == pytest.approx(Q[7, 0, 13], abs=1e-13)
+
+
+def test_admissibility_flags_planted_cells():
+    P = O.problem(3, 2, O.EULER, [4, 3, 2])
+    q = _euler_state(1.0, [0.1, 0.2, 0.0], 1.0)
+    Q = np.broadcast_to(q[None, :, None], (P.ncells, 5, P.S)).copy()
+    Q[3, 2, 5] = np.nan
+    Q[7, 0, 0] = -0.1                        # negative density
+    Q[11, 4, 9] = 0.5 * Q[11, 1, 9] ** 2     # E below kinetic energy: negative pressure
+    Q[11, 4, 9] = 0.001
+    Q[17, 1, 3] = np.inf
+    flags, count = O.check_admissible(P, Q)
+    assert count == 4
+    assert set(np.nonzero(flags)[0]) == {3, 7, 11, 17}
