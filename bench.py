@@ -1,0 +1,213 @@
+"""Throughput of the ADER-DG step on one MI355X.
+
+Workload (default): 3-D compressible Euler, order N = 5 (6^3 Gauss-Legendre
+nodes per cell, 5 quantities), 64^3 periodic cells, seeded smooth Fourier
+initial state, FP64.  One timed step is the whole hot path: the predictor
+kernel (space-time predictor, time averages, volume integral, face
+projection) and the corrector kernel (Rusanov, surface integral, update,
+and the Eq. (7) maximum for the next step's dt).  The first dt comes from the
+stand-alone reduction during warm-up.
+
+Prints one JSON line.  value = DoFs per step * steps / timed seconds, with
+DoFs = cells * (N+1)^3 * 5.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ADER-DG DoF-updates/s per step, FP64 vs mixed at stated L2 error; adjoint s/grad"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (= FP64 matrix) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def predictor_flops_per_cell(dim: int, N: int, nvar: int, iters: int, flux_flops: int) -> int:
+    """Algorithmic FLOPs of the predictor kernel per cell and step (I Picard
+    iterations of: pointwise flux, 1-D derivative contractions of every flux
+    component along its direction, the K1^{-1} W time operator and the
+    update; then the averages at the final iterate, the volume divergence and
+    the extrapolation of qbar and Fbar_d to both faces of every line)."""
+    n = N + 1
+    S = n ** dim
+    P = n * S                      # space-time nodes
+    deriv = dim * nvar * 2 * n     # per space-time node
+    timeop = nvar * 2 * n
+    update = nvar * 2
+    per_iter = P * (flux_flops + deriv + timeop + update)
+    final = P * (flux_flops + 2 * dim * nvar + 2 * nvar)
+    volume = S * dim * nvar * 2 * n
+    traces = 2 * dim * (S // n) * 2 * nvar * 2 * n
+    return iters * per_iter + final + volume + traces
+
+
+def euler_flux_flops(dim: int) -> int:
+    # 1/rho (1), |j|^2 (2 dim - 1), p (4), E + p (1); per direction: u_d (1),
+    # u_d j (dim), + p (1), u_d (E + p) (1)
+    return 1 + (2 * dim - 1) + 4 + 1 + dim * (3 + dim)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "pde.hpp"):
+        with open(os.path.join(ROOT, "paper_1905_07987_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per predictor launch measured with rocprofv3 counters, if the
+    recorded kernel-source hash matches the current sources."""
+    path = os.path.join(ROOT, "profiles", f"predict_kernel_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cells: int, N: int):
+    """The oracle, as it stands, timed on the host cores for one step of the
+    same per-cell work on a smaller periodic mesh."""
+    import oracle as O
+    from paper_1905_07987_amd import inputs
+    threads = O.set_threads(min(os.cpu_count() or 1, 16))
+    P = O.problem(3, N, O.EULER, [cells] * 3)
+    Q = inputs.c2_state(O.node_coords(P))
+    t0 = time.perf_counter()
+    dt, _ = O.stable_dt(P, Q)
+    O.step(P, Q, None, dt, 0.0)
+    el = time.perf_counter() - t0
+    dofs = P.ncells * 5 * (N + 1) ** 3
+    return {"value": dofs / el, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step (dt reduction + predictor + corrector) of the same 3-D Euler N={N} "
+                      f"workload on {cells}^3 periodic cells, {el:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--order", type=int, default=5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cells", type=int, default=32)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                                   "design note, not an implemented path"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1905_07987_amd import adg, inputs
+
+    N, m = args.order, args.cells
+    nvar = 5
+    dofs = m ** 3 * (N + 1) ** 3 * nvar
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    log(f"workload c2: 3-D Euler N={N}, {m}^3 cells, {dofs} DoFs")
+    s = adg.Solver(3, N, "euler", [m, m, m], precision=args.precision)
+    xyz = s.node_coords()
+    Q0 = inputs.c2_state(xyz)
+    del xyz
+    Q0d = torch.as_tensor(Q0, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(solver, steps, warmup, time_kernels=True):
+        Q = Q0d.clone()
+        clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+        solver.stable_dt(Q, None, clock)
+        for _ in range(warmup):
+            solver.step(Q, None, clock, next_dt=True)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        t0 = time.perf_counter()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for i in range(steps):
+            ev[2 * i].record(stream)
+            solver.predict(Q, None, clock, Q)         # kernel A
+            ev[2 * i + 1].record(stream)
+            solver.correct(Q, None, clock, next_dt=True)  # kernel B
+        ev[2 * steps].record(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        total_ms = start.elapsed_time(stop)
+        pred = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
+        corr = [ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(steps)]
+        return Q, clock, total_ms, wall, float(np.mean(pred)), float(np.mean(corr))
+
+    Q64, clock64, total_ms, wall, pred_ms, corr_ms = run(s, args.steps, args.warmup)
+    ms_per_step = total_ms / args.steps
+    value = dofs / (ms_per_step * 1e-3)
+    log(f"fp64: {ms_per_step:.3f} ms/step (predict {pred_ms:.3f}, correct {corr_ms:.3f}), "
+        f"wall {wall:.2f} s, {value:.3e} DoF/s")
+
+    flops_cell = predictor_flops_per_cell(3, N, nvar, N + 1, euler_flux_flops(3))
+    flops_launch = flops_cell * m ** 3
+    achieved = flops_launch / (pred_ms * 1e-3) / 1e12
+    traffic = read_traffic("c2")
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": traffic, "kernel": "predict_kernel<Euler<3>,5,double>",
+                "flops_per_launch": flops_launch, "ms_per_launch": round(pred_ms, 4)}
+
+    variants = {"correct_kernel_ms": round(corr_ms, 4)}
+    if not args.no_mixed and args.precision == "fp64":
+        s32 = adg.Solver(3, N, "euler", [m, m, m], precision="fp32")
+        Q32, clock32, t32, _, p32, c32 = run(s32, args.steps, args.warmup)
+        err = float(torch.linalg.vector_norm(Q32 - Q64) / torch.linalg.vector_norm(Q64))
+        v32 = dofs / (t32 / args.steps * 1e-3)
+        variants["mixed_fp32"] = {"value": v32, "ms_per_step": round(t32 / args.steps, 4),
+                                  "predict_ms": round(p32, 4),
+                                  "rel_l2_vs_fp64_after_steps": err,
+                                  "steps_compared": args.warmup + args.steps}
+        log(f"mixed fp32: {t32 / args.steps:.3f} ms/step, {v32:.3e} DoF/s, rel L2 vs fp64 {err:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args.cpu_cells, N)
+        log(f"cpu baseline {cpu['value']:.3e} DoF/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "DoF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-predictor/f64-update",
+        "data": "synthetic",
+        "config": {"workload": f"c2: 3-D Euler, N={N}, {m}^3 periodic cells, seeded 8-mode Fourier "
+                               f"state, CFL 0.9, {args.precision}",
+                   "dofs_per_step": dofs, "picard_iters": N + 1},
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

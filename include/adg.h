@@ -1,0 +1,213 @@
+/*
+ * adg.h -- C ABI of libadg, an ADER-DG step engine for AMD Instinct MI355X
+ * (gfx950).  The operations follow the ExaHyPE paper (Reinarz et al.,
+ * "ExaHyPE: An Engine for Parallel Dynamically Adaptive Simulations of Wave
+ * Problems"), Sec. 2-3: the balance law of Eq. (1) with flux,
+ * non-conservative product, source and point sources, discretised by
+ * ADER-DG (Sec. 3.3: element-local space-time predictor solved by a Picard
+ * iteration, Rusanov face flux, corrector Eq. (6) with a diagonal mass
+ * matrix) under the time step restriction of Eq. (7) (Sec. 3.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Mesh: uniform Cartesian, dim = 2 or 3, cells[d] cells on [lo[d], hi[d]],
+ *    periodic in every direction.  Cell index c = cx + Cx*(cy + Cy*cz).
+ *  - Basis: tensor-product Lagrange polynomials of degree N on the n = N+1
+ *    Gauss-Legendre points of each axis (Sec. 3.3).  Node index
+ *    k = kx + n*(ky + n*kz), x fastest; S = n^dim nodes per cell.
+ *  - State Q: float64 device array [C][nvar][S] (per-cell structure of
+ *    arrays).  Material parameters: float64 device array [C][nparam]
+ *    (constant per cell; may be NULL when nparam == 0).
+ *  - Clock: float64 device array of 2 entries {t, dt}.  Entry points read
+ *    and write it on the device, so a sequence of steps needs no host
+ *    synchronisation.
+ *  - Ownership: every Q / params / clock / flags / output pointer belongs to
+ *    the caller, must be device memory of the current HIP device, and is not
+ *    retained after the call returns.  The context owns its tables, source
+ *    and receiver descriptors and its workspace (face traces, reduction
+ *    slots).
+ *  - Streams: every device entry point only enqueues work on `stream` (a
+ *    hipStream_t; NULL is the null stream) and returns without waiting.
+ *    Calls on one context must be ordered (one context per concurrent
+ *    stream): the context's workspace is shared by its calls.
+ *  - Errors: every entry point returns adg_status.  Arguments are checked
+ *    before anything is enqueued; on error nothing is enqueued and
+ *    adg_last_error() (thread-local) describes the problem.  Nothing aborts
+ *    or throws across the ABI.  Device-side faults surface as ADG_ERR_HIP
+ *    from a later call, as with any HIP work.
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int adg_status;
+#define ADG_OK 0
+#define ADG_ERR_INVALID_ARG (-1) /* bad pointer, size or configuration value */
+#define ADG_ERR_HIP (-2)         /* a HIP runtime call failed (message has the hipError_t) */
+#define ADG_ERR_NOMEM (-3)       /* device or host allocation failed */
+#define ADG_ERR_UNSUPPORTED (-4) /* valid but not built: order, PDE/dim pair, precision */
+#define ADG_ERR_STATE (-6)       /* call out of order, e.g. sampling with no receivers set */
+
+/* Built-in PDEs (Sec. 2 and Sec. 6).  Their pointwise terms follow the
+ * paper's user-function convention (Sec. 4.1, Table 2): flux(Q, direction),
+ * nonConservativeProduct(Q, gradQ), source(Q, x, t), eigenvalues(Q,
+ * direction) (the kernels use the largest absolute value) and
+ * isPhysicallyAdmissible(Q).
+ *  ADG_PDE_EULER      compressible Euler, Eqs. (8) and (10):
+ *                     Q = (rho, j_1..j_dim, E), nvar = dim + 2, nparam = 0,
+ *                     p = (gamma - 1)(E - |j|^2 / (2 rho)); admissible iff
+ *                     rho > 0, p > 0 and finite.
+ *  ADG_PDE_ELASTIC    linear elasticity in velocity-stress form (Sec. 2.1),
+ *                     dim = 3 only: Q = (sxx, syy, szz, sxy, sxz, syz,
+ *                     rho vx, rho vy, rho vz), nvar = 9; params per cell
+ *                     (rho, cp, cs), nparam = 3; flux F = (0, sigma),
+ *                     non-conservative product E(lambda, mu) grad v with
+ *                     lambda = rho (cp^2 - 2 cs^2), mu = rho cs^2.
+ *  ADG_PDE_ADVECTION  scalar test PDE: F_d = a_d q, S(q) = -kappa q,
+ *                     nvar = 1, nparam = 0. */
+#define ADG_PDE_EULER 1
+#define ADG_PDE_ELASTIC 2
+#define ADG_PDE_ADVECTION 3
+
+/* Arithmetic of the predictor (space-time predictor, time averages, face
+ * projection and volume integral).  The time step, the Rusanov face flux,
+ * the surface integral and the solution update are always float64, and the
+ * state, traces and clock are always stored in float64. */
+#define ADG_FP64 0
+#define ADG_MIXED_FP32 1
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int order;        /* polynomial degree N >= 1 (built range: adg_max_order) */
+  int pde;          /* ADG_PDE_* */
+  int precision;    /* ADG_FP64 or ADG_MIXED_FP32 */
+  int cells[3];     /* cells per axis (cells[2] ignored for dim 2) */
+  double lo[3];     /* domain lower corner */
+  double hi[3];     /* domain upper corner */
+  double cfl;       /* CFL_N of Eq. (7), 0 < cfl; the paper requires < 1 */
+  int picard_iters; /* fixed number of Picard iterations; 0 selects N+1 */
+  int reserved;
+  double gamma;     /* Euler ratio of specific heats (> 1) */
+  double adv[3];    /* advection velocity */
+  double kappa;     /* advection decay rate */
+} adg_config;
+
+/* Sizes derived from a configuration (adg_query). */
+typedef struct {
+  int nvar, nparam;
+  int nodes_per_cell;    /* S = n^dim */
+  int face_nodes;        /* n^(dim-1) */
+  long long ncells;      /* C */
+  long long state_elems; /* C * nvar * S */
+  size_t workspace_bytes;
+  size_t trace_elems;    /* C * 2 dim * 2 * nvar * face_nodes */
+} adg_info;
+
+/* A point source of Eq. (1): delta(x - x_s) * s(t) * weight[v], with s the
+ * Ricker wavelet s(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2).
+ * The source belongs to the cell whose half-open box [lo, lo + h) holds x. */
+typedef struct {
+  double x[3];
+  double weight[16]; /* per evolved quantity (first nvar entries used) */
+  double f0, t0, amp;
+} adg_point_source;
+
+typedef struct adg_ctx adg_ctx;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* adg_last_error(void);
+
+/* Largest polynomial degree N built for a (pde, dim) pair, 0 if none. */
+int adg_max_order(int pde, int dim);
+
+/* Host-only: the one-dimensional tables on [0, 1] for n = order + 1 points:
+ * Gauss-Legendre nodes xi[n] and weights w[n] (sum 1), D[n*n] with
+ * D[i*n + j] = phi_j'(xi_i), boundary values l0[n] = phi(0), l1[n] = phi(1),
+ * and K1inv[n*n], the inverse of the predictor's time matrix
+ * K1_ij = phi_i(1) phi_j(1) - int_0^1 phi_i' phi_j (Sec. 3.3, Eq. (5)
+ * integrated by parts in time with upwinding from the old time level).
+ * Any output pointer may be NULL.  Needs no GPU. */
+adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double* l0,
+                            double* l1, double* K1inv);
+
+/* Validate cfg, build the tables, and allocate the workspace on the current
+ * HIP device.  *out receives a context owned by the caller, released with
+ * adg_destroy.  Errors: INVALID_ARG (bad values), UNSUPPORTED (order or
+ * PDE/dim not built), NOMEM, HIP. */
+adg_status adg_create(const adg_config* cfg, adg_ctx** out);
+
+/* Release the context and its device memory (waits for the device). */
+adg_status adg_destroy(adg_ctx* ctx);
+
+/* Sizes of a context's problem. */
+adg_status adg_query(const adg_ctx* ctx, adg_info* info);
+
+/* Host-only: physical coordinates of every node, xyz[C][S][dim] (host
+ * memory, float64), for pointwise initial data as the paper's
+ * adjustPointSolution (Table 2). */
+adg_status adg_node_coords(const adg_ctx* ctx, double* xyz);
+
+/* Eq. (7): clock[1] <- cfl / (dim (2N + 1)) * min_d h_d / lambda_max, with
+ * lambda_max the largest absolute eigenvalue over all cells, nodes and
+ * directions of Q.  clock[0] is not touched.  A NaN anywhere makes dt NaN. */
+adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, double* clock,
+                         void* stream);
+
+/* One ADER-DG step (Sec. 3.3, three phases) in place: Q <- u^{n+1} with
+ * dt = clock[1] and t^n = clock[0]; afterwards clock[0] <- t^n + dt.
+ * flags: ADG_STEP_NEXT_DT also evaluates Eq. (7) on u^{n+1} during the
+ * update and stores it in clock[1] (bitwise the value adg_stable_dt would
+ * give); without it clock[1] is left unchanged (a frozen step size).
+ * Does not test for non-finite values: that is adg_check_admissible. */
+#define ADG_STEP_NEXT_DT 1
+adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                    void* stream);
+
+/* The predictor phase alone (Sec. 3.3 phase 1 with the projection onto the
+ * faces of Sec. 5.1): Qvol <- u^n + dt (-div Fbar - Nbar + Sbar) per node
+ * ([C][nvar][S], may equal Q) and, if traces is not NULL, the face traces
+ * traces[C][2 dim][2][nvar][F] with face = 2 d + side (side 0 at the low
+ * end of axis d), [0] = time-averaged state, [1] = time-averaged normal
+ * flux.  For tests and instrumentation; adg_step is the production path. */
+adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, const double* clock,
+                       double* Qvol, double* traces, void* stream);
+
+/* The corrector phase alone (Sec. 3.3 phases 2 and 3): Rusanov fluxes from
+ * the face traces the last adg_predict call on this context left in its
+ * workspace, then Q <- Q - dt * (surface integral) and the clock update of
+ * adg_step (same flags).  adg_predict(ctx, Q, params, clock, Q, NULL, s)
+ * followed by adg_correct(ctx, Q, params, clock, flags, s) is exactly
+ * adg_step; the split lets callers time or interleave the two kernels.
+ * STATE error if no adg_predict with workspace traces preceded it. */
+adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                       void* stream);
+
+/* A-posteriori physical admissibility (Sec. 3.5): troubled[c] <- 1 if any
+ * node of cell c is non-finite or fails the PDE's admissibility test, else
+ * 0; *count <- number of troubled cells (device int32). */
+adg_status adg_check_admissible(adg_ctx* ctx, const double* Q, const double* params,
+                                uint8_t* troubled, int32_t* count, void* stream);
+
+/* Replace the context's point sources (host array of n <= 16 entries;
+ * n = 0 clears).  Synchronous upload. */
+adg_status adg_set_point_sources(adg_ctx* ctx, int n, const adg_point_source* src);
+
+/* Replace the receiver set: n points xyz[n][3] (host), each inside the
+ * domain.  Synchronous upload of per-receiver interpolation weights. */
+adg_status adg_set_receivers(adg_ctx* ctx, int n, const double* xyz);
+
+/* out[r][v] <- sum_k Phi_k(xi_r) Q[c_r][v][k]: the degree-N polynomial of
+ * the receiver's cell evaluated at the receiver (device output [n][nvar]). */
+adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H */

@@ -1,0 +1,248 @@
+"""ctypes binding of libadg (include/adg.h).
+
+Argument marshalling only: every step of the ADER-DG path runs in the HIP
+kernels of ``libadg.so``.  Device arrays are torch tensors (float64,
+contiguous, on the context's GPU); their raw pointers and torch's current HIP
+stream are handed to the C ABI.  There is no CPU fallback: if the library is
+missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadg.so")
+
+PDE_EULER, PDE_ELASTIC, PDE_ADVECTION = 1, 2, 3
+FP64, MIXED_FP32 = 0, 1
+STEP_NEXT_DT = 1
+
+_PDE_NAMES = {"euler": PDE_EULER, "elastic": PDE_ELASTIC, "advection": PDE_ADVECTION}
+_PREC_NAMES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32}
+
+
+class AdgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libadg status {status}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("order", C.c_int), ("pde", C.c_int), ("precision", C.c_int),
+        ("cells", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("cfl", C.c_double), ("picard_iters", C.c_int), ("reserved", C.c_int),
+        ("gamma", C.c_double), ("adv", C.c_double * 3), ("kappa", C.c_double),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("nvar", C.c_int), ("nparam", C.c_int), ("nodes_per_cell", C.c_int), ("face_nodes", C.c_int),
+        ("ncells", C.c_longlong), ("state_elems", C.c_longlong), ("workspace_bytes", C.c_size_t),
+        ("trace_elems", C.c_size_t),
+    ]
+
+
+class PointSource(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("weight", C.c_double * 16), ("f0", C.c_double),
+                ("t0", C.c_double), ("amp", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libadg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.adg_last_error.restype = C.c_char_p
+        L.adg_max_order.argtypes = [C.c_int, C.c_int]
+        L.adg_basis_tables.argtypes = [C.c_int] + [dp] * 6
+        L.adg_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.adg_destroy.argtypes = [vp]
+        L.adg_query.argtypes = [vp, C.POINTER(Info)]
+        L.adg_node_coords.argtypes = [vp, dp]
+        L.adg_stable_dt.argtypes = [vp, vp, vp, vp, vp]
+        L.adg_step.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.adg_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.adg_correct.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.adg_check_admissible.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.adg_set_point_sources.argtypes = [vp, C.c_int, C.POINTER(PointSource)]
+        L.adg_set_receivers.argtypes = [vp, C.c_int, dp]
+        L.adg_sample_receivers.argtypes = [vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_destroy",
+            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_step", "adg_predict", "adg_correct",
+            "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
+            "adg_sample_receivers")
+
+
+def _check(st: int):
+    if st != 0:
+        raise AdgError(st, lib().adg_last_error().decode())
+
+
+def max_order(pde: str | int, dim: int) -> int:
+    return lib().adg_max_order(_PDE_NAMES.get(pde, pde), dim)
+
+
+def basis_tables(order: int) -> dict:
+    """Host-side tables of the library (no GPU needed)."""
+    n = order + 1
+    xi, w, l0, l1 = (np.zeros(n) for _ in range(4))
+    D, Ki = np.zeros((n, n)), np.zeros((n, n))
+    p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    _check(lib().adg_basis_tables(order, p(xi), p(w), p(D), p(l0), p(l1), p(Ki)))
+    return dict(xi=xi, w=w, D=D, l0=l0, l1=l1, K1inv=Ki)
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One ADER-DG problem on the current GPU (a libadg context)."""
+
+    def __init__(self, dim: int, order: int, pde="euler", cells=(16, 16, 1), lo=(0.0, 0.0, 0.0),
+                 hi=(1.0, 1.0, 1.0), cfl: float = 0.9, picard_iters: int = 0, precision="fp64",
+                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0):
+        cfg = Config()
+        cfg.dim, cfg.order = dim, order
+        cfg.pde = _PDE_NAMES.get(pde, pde)
+        cfg.precision = _PREC_NAMES.get(precision, precision)
+        cells = list(cells) + [1] * (3 - len(cells))
+        lo = list(lo) + [0.0] * (3 - len(lo))
+        hi = list(hi) + [1.0] * (3 - len(hi))
+        adv = list(adv) + [0.0] * (3 - len(adv))
+        for d in range(3):
+            cfg.cells[d], cfg.lo[d], cfg.hi[d], cfg.adv[d] = cells[d], lo[d], hi[d], adv[d]
+        cfg.cfl, cfg.picard_iters, cfg.gamma, cfg.kappa = cfl, picard_iters, gamma, kappa
+        self.cfg = cfg
+        self._ctx = C.c_void_p()
+        _check(lib().adg_create(C.byref(cfg), C.byref(self._ctx)))
+        info = Info()
+        _check(lib().adg_query(self._ctx, C.byref(info)))
+        self.info = info
+        self.dim, self.order, self.n = dim, order, order + 1
+        self.nvar, self.nparam = info.nvar, info.nparam
+        self.S, self.F, self.ncells = info.nodes_per_cell, info.face_nodes, info.ncells
+        self.nrec = 0
+
+    def close(self):
+        if self._ctx:
+            lib().adg_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- helpers
+    @property
+    def state_shape(self):
+        return (self.ncells, self.nvar, self.S)
+
+    @property
+    def trace_shape(self):
+        return (self.ncells, 2 * self.dim, 2, self.nvar, self.F)
+
+    def _dev(self, t, shape=None, dtype=None, name="array"):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name} must have dtype {dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def _params(self, params):
+        import torch
+        if self.nparam == 0:
+            return C.c_void_p()
+        if params is None:
+            raise ValueError("this PDE needs material parameters [ncells, nparam]")
+        return self._dev(params, (self.ncells, self.nparam), torch.float64, "params")
+
+    # ---------------------------------------------------------------- API
+    def node_coords(self) -> np.ndarray:
+        xyz = np.zeros((self.ncells, self.S, self.dim))
+        _check(lib().adg_node_coords(self._ctx, xyz.ctypes.data_as(C.POINTER(C.c_double))))
+        return xyz
+
+    def stable_dt(self, Q, params, clock, stream=None):
+        import torch
+        _check(lib().adg_stable_dt(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                   self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
+                                   _stream(stream)))
+
+    def step(self, Q, params, clock, next_dt: bool = True, stream=None):
+        import torch
+        _check(lib().adg_step(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                              self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
+                              STEP_NEXT_DT if next_dt else 0, _stream(stream)))
+
+    def predict(self, Q, params, clock, Qvol, traces=None, stream=None):
+        import torch
+        tr = C.c_void_p() if traces is None else self._dev(traces, self.trace_shape, torch.float64,
+                                                           "traces")
+        _check(lib().adg_predict(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                 self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
+                                 self._dev(Qvol, self.state_shape, torch.float64, "Qvol"), tr,
+                                 _stream(stream)))
+
+    def correct(self, Q, params, clock, next_dt: bool = True, stream=None):
+        import torch
+        _check(lib().adg_correct(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                 self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
+                                 STEP_NEXT_DT if next_dt else 0, _stream(stream)))
+
+    def check_admissible(self, Q, params, troubled, count, stream=None):
+        import torch
+        _check(lib().adg_check_admissible(
+            self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"), self._params(params),
+            self._dev(troubled, (self.ncells,), torch.uint8, "troubled"),
+            self._dev(count, (1,), torch.int32, "count"), _stream(stream)))
+
+    def set_point_sources(self, sources):
+        """sources: list of dicts with x (3), weight (nvar), f0, t0, amp."""
+        arr = (PointSource * max(1, len(sources)))()
+        for i, s in enumerate(sources):
+            for d in range(3):
+                arr[i].x[d] = s["x"][d] if d < len(s["x"]) else 0.0
+            for v, wv in enumerate(s["weight"]):
+                arr[i].weight[v] = wv
+            arr[i].f0, arr[i].t0, arr[i].amp = s["f0"], s["t0"], s["amp"]
+        _check(lib().adg_set_point_sources(self._ctx, len(sources), arr))
+
+    def set_receivers(self, xyz):
+        xyz = np.asarray(xyz, dtype=np.float64).reshape(len(xyz), -1)
+        if xyz.shape[1] < 3:
+            xyz = np.pad(xyz, ((0, 0), (0, 3 - xyz.shape[1])))
+        xyz = np.ascontiguousarray(xyz)
+        _check(lib().adg_set_receivers(self._ctx, len(xyz), xyz.ctypes.data_as(C.POINTER(C.c_double))))
+        self.nrec = len(xyz)
+
+    def sample_receivers(self, Q, out, stream=None):
+        import torch
+        _check(lib().adg_sample_receivers(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                          self._dev(out, (self.nrec, self.nvar), torch.float64, "out"),
+                                          _stream(stream)))

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host API and the kernel translation
+// units of libadg.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/adg.h"
+
+namespace adg {
+
+constexpr int kMaxN = 8;       // n = N + 1 points per axis
+constexpr int kMaxSources = 16;
+constexpr int kMaxVar = 16;
+
+// One-dimensional tables on [0, 1] (see adg_basis_tables).  KW = K1^{-1} W is
+// the time operator of the Picard update, invw = 1 / w.
+template <class R>
+struct Tables {
+  R xi[kMaxN], w[kMaxN], invw[kMaxN], l0[kMaxN], l1[kMaxN];
+  R D[kMaxN][kMaxN];   // D[i][j] = phi_j'(xi_i)
+  R KW[kMaxN][kMaxN];  // (K1^{-1})_ij w_j
+};
+
+struct PdeConsts {
+  double gamma;
+  double adv[3];
+  double kappa;
+};
+
+// Point source as the kernels see it: the owning cell, the Ricker
+// parameters and the nodal weights phi_k(xi_s) / (|T| W_k) * weight[v] live in
+// a device table of [nsrc][S][nvar] doubles.
+struct SourceDev {
+  long long cell;
+  double f0, t0, amp;
+};
+
+// Everything a kernel needs besides the data pointers; passed by value.
+struct KArgs {
+  int cells[3];
+  int picard_iters;
+  long long ncells;
+  double h[3], inv_h[3];
+  double dt_factor;  // cfl / (dim (2N+1)) * min_d h_d
+  PdeConsts pde;
+  Tables<double> t64;
+  Tables<float> t32;
+  int nsrc;
+  int nblocks;  // grid size of the cell kernels (for the block -> cell map)
+  const SourceDev* src;
+  const double* src_w;  // [nsrc][S][nvar]
+  // reduction slots in the workspace
+  unsigned long long* red_max;  // ordered bits of a non-negative double
+  unsigned int* red_count;
+  int* red_sum;
+};
+
+// Kernel entry points of one (PDE, dim, order) instantiation set.
+struct KernelSet {
+  int block;  // threads per block of the cell kernels
+  int cells_per_block;
+  hipError_t (*predict)(const KArgs&, int precision, const double* Q, const double* params,
+                        const double* clock, double* Qout, double* traces, hipStream_t);
+  hipError_t (*correct)(const KArgs&, double* Q, const double* params, double* clock,
+                        const double* traces, int next_dt, hipStream_t);
+  hipError_t (*stable_dt)(const KArgs&, const double* Q, const double* params, double* clock,
+                          hipStream_t);
+  hipError_t (*admissible)(const KArgs&, const double* Q, const double* params,
+                           uint8_t* troubled, int32_t* count, hipStream_t);
+};
+
+// Registries implemented by the per-PDE translation units; return nullptr if
+// the order is not built.
+const KernelSet* kernels_euler2(int order);
+const KernelSet* kernels_euler3(int order);
+const KernelSet* kernels_elastic3(int order);
+const KernelSet* kernels_advection2(int order);
+const KernelSet* kernels_advection3(int order);
+int max_order_euler2();
+int max_order_euler3();
+int max_order_elastic3();
+int max_order_advection2();
+int max_order_advection3();
+
+// Host tables (basis.cpp).
+int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1, double* K1inv);
+
+}  // namespace adg

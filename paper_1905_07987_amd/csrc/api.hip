@@ -1,0 +1,480 @@
+// C ABI of libadg (declared in include/adg.h): argument checking, context
+// set-up, and the launch sequence of one step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "adg_internal.hpp"
+
+using namespace adg;
+
+struct adg_ctx {
+  adg_config cfg;
+  int n = 0, S = 0, F = 0, nv = 0, np = 0, dim = 0;
+  long long C = 0;
+  int device = 0;
+  const KernelSet* ks = nullptr;
+  KArgs args{};
+  double* traces = nullptr;  // [C][2 dim][2][nv][F]
+  size_t trace_elems = 0;
+  void* red = nullptr;       // reduction slots
+  SourceDev* d_src = nullptr;
+  double* d_src_w = nullptr;
+  int nsrc = 0;
+  long long* d_rec_cell = nullptr;
+  double* d_rec_w = nullptr;  // [nrec][S]
+  int nrec = 0;
+  bool traces_ready = false;  // workspace holds traces of a predict call
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+adg_status fail(adg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+adg_status hip_fail(hipError_t e, const char* what) {
+  return fail(ADG_ERR_HIP, std::string(what) + ": " + hipGetErrorName(e) + " (" +
+                               hipGetErrorString(e) + ")");
+}
+
+#define ADG_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+const KernelSet* find_kernels(int pde, int dim, int order) {
+  if (pde == ADG_PDE_EULER && dim == 2) return kernels_euler2(order);
+  if (pde == ADG_PDE_EULER && dim == 3) return kernels_euler3(order);
+  if (pde == ADG_PDE_ELASTIC && dim == 3) return kernels_elastic3(order);
+  if (pde == ADG_PDE_ADVECTION && dim == 2) return kernels_advection2(order);
+  if (pde == ADG_PDE_ADVECTION && dim == 3) return kernels_advection3(order);
+  return nullptr;
+}
+
+int pde_nvar(int pde, int dim) {
+  if (pde == ADG_PDE_EULER) return dim + 2;
+  if (pde == ADG_PDE_ELASTIC) return 9;
+  if (pde == ADG_PDE_ADVECTION) return 1;
+  return 0;
+}
+
+int pde_nparam(int pde) { return pde == ADG_PDE_ELASTIC ? 3 : 0; }
+
+// phi_i(x) of the Lagrange basis through the GL nodes.
+double lagrange(const double* xi, int n, int i, double x) {
+  double v = 1.0;
+  for (int m = 0; m < n; ++m)
+    if (m != i) v *= (x - xi[m]) / (xi[i] - xi[m]);
+  return v;
+}
+
+// Cell and reference coordinates of a physical point (half-open cells).
+bool locate(const adg_ctx* c, const double* x, long long* cell, double* ref) {
+  long long idx = 0, mul = 1;
+  for (int d = 0; d < c->dim; ++d) {
+    const double h = (c->cfg.hi[d] - c->cfg.lo[d]) / c->cfg.cells[d];
+    const double s = (x[d] - c->cfg.lo[d]) / h;
+    const double fl = std::floor(s);
+    if (!(fl >= 0.0 && fl < c->cfg.cells[d])) return false;
+    ref[d] = s - fl;
+    idx += (long long)fl * mul;
+    mul *= c->cfg.cells[d];
+  }
+  *cell = idx;
+  return true;
+}
+
+__global__ void sample_kernel(const double* __restrict__ Q, const long long* __restrict__ rcell,
+                              const double* __restrict__ rw, double* __restrict__ out, int nv,
+                              int S) {
+  const int r = blockIdx.x;
+  const long long c = rcell[r];
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < S; k += 64) acc += rw[(long long)r * S + k] * Q[(c * nv + v) * S + k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (threadIdx.x == 0) out[(long long)r * nv + v] = acc;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* adg_last_error(void) { return g_err.c_str(); }
+
+int adg_max_order(int pde, int dim) {
+  if (pde == ADG_PDE_EULER && dim == 2) return max_order_euler2();
+  if (pde == ADG_PDE_EULER && dim == 3) return max_order_euler3();
+  if (pde == ADG_PDE_ELASTIC && dim == 3) return max_order_elastic3();
+  if (pde == ADG_PDE_ADVECTION && dim == 2) return max_order_advection2();
+  if (pde == ADG_PDE_ADVECTION && dim == 3) return max_order_advection3();
+  return 0;
+}
+
+adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double* l0, double* l1,
+                            double* K1inv) {
+  if (order < 0 || order + 1 > kMaxN) return fail(ADG_ERR_INVALID_ARG, "order out of range 0..7");
+  if (basis_tables(order + 1, xi, w, D, l0, l1, K1inv) != 0)
+    return fail(ADG_ERR_INVALID_ARG, "basis construction failed");
+  return ADG_OK;
+}
+
+adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
+  if (!cfg || !out) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const adg_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return fail(ADG_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (c.order < 1) return fail(ADG_ERR_INVALID_ARG, "order must be >= 1");
+  if (pde_nvar(c.pde, c.dim) == 0) return fail(ADG_ERR_INVALID_ARG, "unknown pde");
+  if (c.precision != ADG_FP64 && c.precision != ADG_MIXED_FP32)
+    return fail(ADG_ERR_INVALID_ARG, "unknown precision");
+  if (!(c.cfl > 0.0) || !std::isfinite(c.cfl)) return fail(ADG_ERR_INVALID_ARG, "cfl must be > 0");
+  if (c.picard_iters < 0 || c.picard_iters > 64)
+    return fail(ADG_ERR_INVALID_ARG, "picard_iters must be in 0..64");
+  if (c.pde == ADG_PDE_EULER && !(c.gamma > 1.0)) return fail(ADG_ERR_INVALID_ARG, "gamma must be > 1");
+  long long C = 1;
+  for (int d = 0; d < c.dim; ++d) {
+    if (c.cells[d] < 1) return fail(ADG_ERR_INVALID_ARG, "cells must be >= 1");
+    if (!(c.hi[d] > c.lo[d])) return fail(ADG_ERR_INVALID_ARG, "hi must exceed lo");
+    C *= c.cells[d];
+  }
+  const KernelSet* ks = find_kernels(c.pde, c.dim, c.order);
+  if (!ks) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "order %d not built for pde %d in %dD (max %d)", c.order, c.pde,
+             c.dim, adg_max_order(c.pde, c.dim));
+    return fail(ADG_ERR_UNSUPPORTED, buf);
+  }
+  if ((C + ks->cells_per_block - 1) / ks->cells_per_block > 0x7fffffffLL)
+    return fail(ADG_ERR_UNSUPPORTED, "too many cells for one launch");
+
+  adg_ctx* x = new (std::nothrow) adg_ctx;
+  if (!x) return fail(ADG_ERR_NOMEM, "host allocation failed");
+  x->cfg = c;
+  x->dim = c.dim;
+  x->n = c.order + 1;
+  x->S = c.dim == 2 ? x->n * x->n : x->n * x->n * x->n;
+  x->F = x->S / x->n;
+  x->nv = pde_nvar(c.pde, c.dim);
+  x->np = pde_nparam(c.pde);
+  x->C = C;
+  x->ks = ks;
+  hipError_t e = hipGetDevice(&x->device);
+  if (e != hipSuccess) {
+    delete x;
+    return hip_fail(e, "hipGetDevice");
+  }
+
+  KArgs& a = x->args;
+  for (int d = 0; d < 3; ++d) {
+    a.cells[d] = d < c.dim ? c.cells[d] : 1;
+    a.h[d] = d < c.dim ? (c.hi[d] - c.lo[d]) / c.cells[d] : 1.0;
+    a.inv_h[d] = 1.0 / a.h[d];
+  }
+  a.ncells = C;
+  a.picard_iters = c.picard_iters ? c.picard_iters : c.order + 1;
+  double hmin = a.h[0];
+  for (int d = 1; d < c.dim; ++d) hmin = std::fmin(hmin, a.h[d]);
+  a.dt_factor = c.cfl / (c.dim * (2.0 * c.order + 1.0)) * hmin;
+  a.pde.gamma = c.gamma;
+  for (int d = 0; d < 3; ++d) a.pde.adv[d] = c.adv[d];
+  a.pde.kappa = c.kappa;
+  {
+    const int n = x->n;
+    double xi[kMaxN], w[kMaxN], D[kMaxN * kMaxN], l0[kMaxN], l1[kMaxN], Ki[kMaxN * kMaxN];
+    basis_tables(n, xi, w, D, l0, l1, Ki);
+    std::memset(&a.t64, 0, sizeof a.t64);
+    std::memset(&a.t32, 0, sizeof a.t32);
+    for (int i = 0; i < n; ++i) {
+      a.t64.xi[i] = xi[i];
+      a.t64.w[i] = w[i];
+      a.t64.invw[i] = 1.0 / w[i];
+      a.t64.l0[i] = l0[i];
+      a.t64.l1[i] = l1[i];
+      for (int j = 0; j < n; ++j) {
+        a.t64.D[i][j] = D[i * n + j];
+        a.t64.KW[i][j] = Ki[i * n + j] * w[j];
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      a.t32.xi[i] = (float)a.t64.xi[i];
+      a.t32.w[i] = (float)a.t64.w[i];
+      a.t32.invw[i] = (float)a.t64.invw[i];
+      a.t32.l0[i] = (float)a.t64.l0[i];
+      a.t32.l1[i] = (float)a.t64.l1[i];
+      for (int j = 0; j < n; ++j) {
+        a.t32.D[i][j] = (float)a.t64.D[i][j];
+        a.t32.KW[i][j] = (float)a.t64.KW[i][j];
+      }
+    }
+  }
+  x->trace_elems = (size_t)C * 2 * c.dim * 2 * x->nv * x->F;
+  e = hipMalloc((void**)&x->traces, x->trace_elems * sizeof(double));
+  if (e != hipSuccess) {
+    delete x;
+    return fail(ADG_ERR_NOMEM, std::string("trace workspace: ") + hipGetErrorString(e));
+  }
+  e = hipMalloc(&x->red, 64);
+  if (e == hipSuccess) e = hipMemset(x->red, 0, 64);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(x->traces);
+    delete x;
+    return hip_fail(e, "reduction slots");
+  }
+  a.red_max = (unsigned long long*)x->red;
+  a.red_count = (unsigned int*)((char*)x->red + 8);
+  a.red_sum = (int*)((char*)x->red + 16);
+  a.nsrc = 0;
+  a.src = nullptr;
+  a.src_w = nullptr;
+  *out = x;
+  return ADG_OK;
+}
+
+adg_status adg_destroy(adg_ctx* ctx) {
+  if (!ctx) return ADG_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->traces);
+  (void)hipFree(ctx->red);
+  (void)hipFree(ctx->d_src);
+  (void)hipFree(ctx->d_src_w);
+  (void)hipFree(ctx->d_rec_cell);
+  (void)hipFree(ctx->d_rec_w);
+  (void)hipSetDevice(dev);
+  delete ctx;
+  return ADG_OK;
+}
+
+adg_status adg_query(const adg_ctx* ctx, adg_info* info) {
+  if (!ctx || !info) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  info->nvar = ctx->nv;
+  info->nparam = ctx->np;
+  info->nodes_per_cell = ctx->S;
+  info->face_nodes = ctx->F;
+  info->ncells = ctx->C;
+  info->state_elems = ctx->C * ctx->nv * ctx->S;
+  info->trace_elems = ctx->trace_elems;
+  info->workspace_bytes = ctx->trace_elems * sizeof(double) + 64;
+  return ADG_OK;
+}
+
+adg_status adg_node_coords(const adg_ctx* ctx, double* xyz) {
+  if (!ctx || !xyz) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  const int n = ctx->n, dim = ctx->dim;
+  for (long long c = 0; c < ctx->C; ++c) {
+    long long cc[3] = {c % ctx->cfg.cells[0], (c / ctx->cfg.cells[0]) % (dim > 1 ? ctx->cfg.cells[1] : 1),
+                       dim == 3 ? c / ((long long)ctx->cfg.cells[0] * ctx->cfg.cells[1]) : 0};
+    for (int k = 0; k < ctx->S; ++k) {
+      int kk[3] = {k % n, (k / n) % n, k / (n * n)};
+      for (int d = 0; d < dim; ++d)
+        xyz[((size_t)c * ctx->S + k) * dim + d] =
+            ctx->cfg.lo[d] + (cc[d] + ctx->args.t64.xi[kk[d]]) * ctx->args.h[d];
+    }
+  }
+  return ADG_OK;
+}
+
+static adg_status check_state(adg_ctx* ctx, const void* Q, const void* params) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  if (!Q) return fail(ADG_ERR_INVALID_ARG, "null state");
+  if (ctx->np > 0 && !params) return fail(ADG_ERR_INVALID_ARG, "this PDE needs material parameters");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+    return fail(ADG_ERR_STATE, "current HIP device differs from the context's device");
+  return ADG_OK;
+}
+
+adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, double* clock,
+                         void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  hipError_t e = ctx->ks->stable_dt(ctx->args, Q, params, clock, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stable_dt launch");
+  return ADG_OK;
+}
+
+adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, const double* clock,
+                       double* Qvol, double* traces, void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock || !Qvol) return fail(ADG_ERR_INVALID_ARG, "null clock or output");
+  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Qvol,
+                                  traces ? traces : ctx->traces, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "predict launch");
+  if (!traces) ctx->traces_ready = true;
+  return ADG_OK;
+}
+
+adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                       void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  if (!ctx->traces_ready) return fail(ADG_ERR_STATE, "adg_correct needs a preceding adg_predict");
+  hipError_t e = ctx->ks->correct(ctx->args, Q, params, clock, ctx->traces,
+                                  (flags & ADG_STEP_NEXT_DT) ? 1 : 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "correct launch");
+  return ADG_OK;
+}
+
+adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                    void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, s);
+  if (e != hipSuccess) return hip_fail(e, "predict launch");
+  ctx->traces_ready = true;
+  e = ctx->ks->correct(ctx->args, Q, params, clock, ctx->traces, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
+  if (e != hipSuccess) return hip_fail(e, "correct launch");
+  return ADG_OK;
+}
+
+adg_status adg_check_admissible(adg_ctx* ctx, const double* Q, const double* params,
+                                uint8_t* troubled, int32_t* count, void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!troubled || !count) return fail(ADG_ERR_INVALID_ARG, "null output");
+  hipError_t e = ctx->ks->admissible(ctx->args, Q, params, troubled, count, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "admissible launch");
+  return ADG_OK;
+}
+
+adg_status adg_set_point_sources(adg_ctx* ctx, int n, const adg_point_source* src) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  if (n < 0 || n > kMaxSources) return fail(ADG_ERR_INVALID_ARG, "0 <= n <= 16 sources");
+  if (n > 0 && !src) return fail(ADG_ERR_INVALID_ARG, "null sources");
+  const int S = ctx->S, nv = ctx->nv, nd = ctx->n;
+  SourceDev hs[kMaxSources];
+  double* hw = new (std::nothrow) double[(size_t)(n > 0 ? n : 1) * S * nv];
+  if (!hw) return fail(ADG_ERR_NOMEM, "host allocation failed");
+  const double* xi = ctx->args.t64.xi;
+  const double* w = ctx->args.t64.w;
+  double vol = 1.0;
+  for (int d = 0; d < ctx->dim; ++d) vol *= ctx->args.h[d];
+  for (int s = 0; s < n; ++s) {
+    long long cell;
+    double ref[3] = {0, 0, 0};
+    if (!locate(ctx, src[s].x, &cell, ref)) {
+      delete[] hw;
+      return fail(ADG_ERR_INVALID_ARG, "point source outside the domain");
+    }
+    hs[s] = SourceDev{cell, src[s].f0, src[s].t0, src[s].amp};
+    for (int k = 0; k < S; ++k) {
+      int kk[3] = {k % nd, (k / nd) % nd, k / (nd * nd)};
+      double phi = 1.0, mass = vol;
+      for (int d = 0; d < ctx->dim; ++d) {
+        phi *= lagrange(xi, nd, kk[d], ref[d]);
+        mass *= w[kk[d]];
+      }
+      for (int v = 0; v < nv; ++v) hw[((size_t)s * S + k) * nv + v] = phi / mass * src[s].weight[v];
+    }
+  }
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->d_src);
+  (void)hipFree(ctx->d_src_w);
+  ctx->d_src = nullptr;
+  ctx->d_src_w = nullptr;
+  ctx->nsrc = 0;
+  ctx->args.nsrc = 0;
+  ctx->args.src = nullptr;
+  ctx->args.src_w = nullptr;
+  if (n > 0) {
+    hipError_t e = hipMalloc((void**)&ctx->d_src, sizeof(SourceDev) * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_src_w, sizeof(double) * n * S * nv);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_src, hs, sizeof(SourceDev) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(ctx->d_src_w, hw, sizeof(double) * n * S * nv, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete[] hw;
+      return hip_fail(e, "source upload");
+    }
+    ctx->nsrc = n;
+    ctx->args.nsrc = n;
+    ctx->args.src = ctx->d_src;
+    ctx->args.src_w = ctx->d_src_w;
+  }
+  delete[] hw;
+  return ADG_OK;
+}
+
+adg_status adg_set_receivers(adg_ctx* ctx, int n, const double* xyz) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  if (n < 0 || (n > 0 && !xyz)) return fail(ADG_ERR_INVALID_ARG, "bad receiver list");
+  const int S = ctx->S, nd = ctx->n;
+  long long* hc = new (std::nothrow) long long[n > 0 ? n : 1];
+  double* hw = new (std::nothrow) double[(size_t)(n > 0 ? n : 1) * S];
+  if (!hc || !hw) {
+    delete[] hc;
+    delete[] hw;
+    return fail(ADG_ERR_NOMEM, "host allocation failed");
+  }
+  for (int r = 0; r < n; ++r) {
+    double ref[3] = {0, 0, 0};
+    if (!locate(ctx, xyz + 3 * r, &hc[r], ref)) {
+      delete[] hc;
+      delete[] hw;
+      return fail(ADG_ERR_INVALID_ARG, "receiver outside the domain");
+    }
+    for (int k = 0; k < S; ++k) {
+      int kk[3] = {k % nd, (k / nd) % nd, k / (nd * nd)};
+      double phi = 1.0;
+      for (int d = 0; d < ctx->dim; ++d) phi *= lagrange(ctx->args.t64.xi, nd, kk[d], ref[d]);
+      hw[(size_t)r * S + k] = phi;
+    }
+  }
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->d_rec_cell);
+  (void)hipFree(ctx->d_rec_w);
+  ctx->d_rec_cell = nullptr;
+  ctx->d_rec_w = nullptr;
+  ctx->nrec = 0;
+  if (n > 0) {
+    hipError_t e = hipMalloc((void**)&ctx->d_rec_cell, sizeof(long long) * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_rec_w, sizeof(double) * n * S);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_rec_cell, hc, sizeof(long long) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_rec_w, hw, sizeof(double) * n * S, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete[] hc;
+      delete[] hw;
+      return hip_fail(e, "receiver upload");
+    }
+    ctx->nrec = n;
+  }
+  delete[] hc;
+  delete[] hw;
+  return ADG_OK;
+}
+
+adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void* stream) {
+  adg_status st = check_state(ctx, Q, (const void*)1);
+  if (st) return st;
+  if (!out) return fail(ADG_ERR_INVALID_ARG, "null output");
+  if (ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
+  hipLaunchKernelGGL(sample_kernel, dim3(ctx->nrec), dim3(64), 0, (hipStream_t)stream, Q,
+                     ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nv, ctx->S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return ADG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,19 @@
+// Kernel instantiations for Elastic3, orders 1..5.
+#include "kernels.hpp"
+
+namespace adg {
+
+const KernelSet* kernels_elastic3(int order) {
+  switch (order) {
+    case 1: return Launch<Elastic3, 1>::set();
+    case 2: return Launch<Elastic3, 2>::set();
+    case 3: return Launch<Elastic3, 3>::set();
+    case 4: return Launch<Elastic3, 4>::set();
+    case 5: return Launch<Elastic3, 5>::set();
+    default: return nullptr;
+  }
+}
+
+int max_order_elastic3() { return 5; }
+
+}  // namespace adg

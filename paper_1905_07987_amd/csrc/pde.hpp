@@ -1,0 +1,204 @@
+// Pointwise PDE terms of Eq. (1) of the ExaHyPE paper for the built-in
+// systems, written as device functors templated on the arithmetic type.
+//
+// Each PDE type provides
+//   DIM, NV (evolved quantities), NP (material parameters)
+//   flux_nonzero(d, v)  compile-time sparsity of F_d (which components the
+//                       kernels must differentiate)
+//   grad_needed(v)      which evolved quantities the non-conservative
+//                       product reads the gradient of
+//   kHasNcp, kHasSource
+//   fluxes(Q, P, F)     all directions at once, F[d][v] (only nonzero ones
+//                       are read)
+//   ncp(Q, P, g, B)     B(Q) . grad Q with g[d][v] = dQ_v/dx_d
+//   source(Q, P, S)     smooth source term S(Q)
+//   max_eigen(Q, P, d)  largest |eigenvalue| of the direction-d system
+//   admissible(Q, P)    physical admissibility (Sec. 3.5) incl. finiteness
+// Q points to NV evolved values, P to NP parameter values.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "adg_internal.hpp"
+
+namespace adg {
+
+template <class R>
+__device__ __forceinline__ R rdiv(R a, R b) {
+  return a / b;
+}
+
+template <class R>
+__device__ __forceinline__ bool finite_val(R x) {
+  return __builtin_isfinite(x);
+}
+
+// Compressible Euler, Eqs. (8) and (10): Q = (rho, j, E).
+template <int DIM_>
+struct Euler {
+  static constexpr int DIM = DIM_, NV = DIM_ + 2, NP = 0;
+  static constexpr bool kHasNcp = false, kHasSource = false;
+  static constexpr bool flux_nonzero(int, int) { return true; }
+  static constexpr bool grad_needed(int) { return false; }
+
+  template <class R>
+  __device__ static __forceinline__ void fluxes(const R* Q, const R*, const PdeConsts& pc,
+                                                R (*F)[NV]) {
+    const R gm1 = R(pc.gamma) - R(1);
+    const R irho = R(1) / Q[0];
+    R jj = R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) jj += Q[1 + a] * Q[1 + a];
+    const R p = gm1 * (Q[DIM + 1] - R(0.5) * jj * irho);
+    const R Ep = Q[DIM + 1] + p;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const R ud = Q[1 + d] * irho;
+      F[d][0] = Q[1 + d];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) F[d][1 + a] = ud * Q[1 + a];
+      F[d][1 + d] += p;
+      F[d][DIM + 1] = ud * Ep;
+    }
+  }
+
+  template <class R>
+  __device__ static __forceinline__ void ncp(const R*, const R*, const PdeConsts&,
+                                             const R (*)[NV], R* B) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) B[v] = R(0);
+  }
+
+  template <class R>
+  __device__ static __forceinline__ void source(const R*, const R*, const PdeConsts&, R* S) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[v] = R(0);
+  }
+
+  template <class R>
+  __device__ static __forceinline__ R pressure(const R* Q, const PdeConsts& pc) {
+    R jj = R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) jj += Q[1 + a] * Q[1 + a];
+    return (R(pc.gamma) - R(1)) * (Q[DIM + 1] - R(0.5) * jj / Q[0]);
+  }
+
+  // u_d -+ c and u_d: the largest modulus is |u_d| + c, c = sqrt(gamma p / rho)
+  template <class R>
+  __device__ static __forceinline__ R max_eigen(const R* Q, const R*, const PdeConsts& pc, int d) {
+    const R c = sqrt(R(pc.gamma) * pressure(Q, pc) / Q[0]);
+    return fabs(Q[1 + d] / Q[0]) + c;
+  }
+
+  template <class R>
+  __device__ static __forceinline__ bool admissible(const R* Q, const R*, const PdeConsts& pc) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ok = ok && finite_val(Q[v]);
+    return ok && Q[0] > R(0) && pressure(Q, pc) > R(0);
+  }
+};
+
+// Linear elasticity, velocity-stress form of Sec. 2.1:
+//   Q = (sxx, syy, szz, sxy, sxz, syz, rho vx, rho vy, rho vz), params (rho, cp, cs)
+//   d/dt sigma + E(lambda, mu) grad v = 0,   d/dt (rho v) + div sigma = 0.
+struct Elastic3 {
+  static constexpr int DIM = 3, NV = 9, NP = 3;
+  static constexpr bool kHasNcp = true, kHasSource = false;
+  static constexpr bool flux_nonzero(int, int v) { return v >= 6; }
+  static constexpr bool grad_needed(int v) { return v >= 6; }
+  static constexpr int sym(int i, int d) {
+    return i == d ? i : ((i + d == 1) ? 3 : ((i + d == 2) ? 4 : 5));
+  }
+
+  template <class R>
+  __device__ static __forceinline__ void fluxes(const R* Q, const R*, const PdeConsts&,
+                                                R (*F)[NV]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) F[d][v] = R(0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) F[d][6 + i] = Q[sym(i, d)];
+    }
+  }
+
+  template <class R>
+  __device__ static __forceinline__ void ncp(const R*, const R* P, const PdeConsts&,
+                                             const R (*g)[NV], R* B) {
+    const R rho = P[0], cp = P[1], cs = P[2];
+    const R mu = rho * cs * cs;
+    const R lam = rho * cp * cp - R(2) * mu;
+    const R ir = R(1) / rho;
+    R gv[3][3];  // gv[i][d] = d v_i / d x_d
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gv[i][d] = g[d][6 + i] * ir;
+    const R divv = gv[0][0] + gv[1][1] + gv[2][2];
+    B[0] = R(2) * mu * gv[0][0] + lam * divv;
+    B[1] = R(2) * mu * gv[1][1] + lam * divv;
+    B[2] = R(2) * mu * gv[2][2] + lam * divv;
+    B[3] = mu * (gv[0][1] + gv[1][0]);
+    B[4] = mu * (gv[0][2] + gv[2][0]);
+    B[5] = mu * (gv[1][2] + gv[2][1]);
+    B[6] = B[7] = B[8] = R(0);
+  }
+
+  template <class R>
+  __device__ static __forceinline__ void source(const R*, const R*, const PdeConsts&, R* S) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[v] = R(0);
+  }
+
+  // +-cp, +-cs (twice), 0 (three times)
+  template <class R>
+  __device__ static __forceinline__ R max_eigen(const R*, const R* P, const PdeConsts&, int) {
+    return P[1];
+  }
+
+  template <class R>
+  __device__ static __forceinline__ bool admissible(const R* Q, const R* P, const PdeConsts&) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ok = ok && finite_val(Q[v]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) ok = ok && finite_val(P[p]);
+    return ok;
+  }
+};
+
+// Scalar advection with linear decay (a test PDE with a closed-form solution).
+template <int DIM_>
+struct Advection {
+  static constexpr int DIM = DIM_, NV = 1, NP = 0;
+  static constexpr bool kHasNcp = false, kHasSource = true;
+  static constexpr bool flux_nonzero(int, int) { return true; }
+  static constexpr bool grad_needed(int) { return false; }
+
+  template <class R>
+  __device__ static __forceinline__ void fluxes(const R* Q, const R*, const PdeConsts& pc,
+                                                R (*F)[NV]) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) F[d][0] = R(pc.adv[d]) * Q[0];
+  }
+  template <class R>
+  __device__ static __forceinline__ void ncp(const R*, const R*, const PdeConsts&,
+                                             const R (*)[NV], R* B) {
+    B[0] = R(0);
+  }
+  template <class R>
+  __device__ static __forceinline__ void source(const R* Q, const R*, const PdeConsts& pc, R* S) {
+    S[0] = -R(pc.kappa) * Q[0];
+  }
+  template <class R>
+  __device__ static __forceinline__ R max_eigen(const R*, const R*, const PdeConsts& pc, int d) {
+    return fabs(R(pc.adv[d]));
+  }
+  template <class R>
+  __device__ static __forceinline__ bool admissible(const R* Q, const R*, const PdeConsts&) {
+    return finite_val(Q[0]);
+  }
+};
+
+}  // namespace adg
