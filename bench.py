@@ -88,7 +88,7 @@ def cpu_baseline(cells: int, N: int):
     import oracle as O
     from paper_1905_07987_amd import inputs
     threads = O.set_threads(min(os.cpu_count() or 1, 16))
-    P = O.problem(3, N, O.EULER, [cells] * 3)
+    P = O.problem(3, N, O.EULER, [cells] * 3, cfl=0.5)
     Q = inputs.c2_state(O.node_coords(P))
     t0 = time.perf_counter()
     dt, _ = O.stable_dt(P, Q)
@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=32)
+    ap.add_argument("--cfl", type=float, default=0.5,
+                    help="CFL_N of Eq. (7); 0.5 = 0.9 x the linear stability limit at N = 5")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,7 +131,7 @@ def main():
         print("[bench]", *a, file=sys.stderr, flush=True)
 
     log(f"workload c2: 3-D Euler N={N}, {m}^3 cells, {dofs} DoFs")
-    s = adg.Solver(3, N, "euler", [m, m, m], precision=args.precision)
+    s = adg.Solver(3, N, "euler", [m, m, m], precision=args.precision, cfl=args.cfl)
     xyz = s.node_coords()
     Q0 = inputs.c2_state(xyz)
     del xyz
@@ -179,7 +181,7 @@ def main():
 
     variants = {"correct_kernel_ms": round(corr_ms, 4)}
     if not args.no_mixed and args.precision == "fp64":
-        s32 = adg.Solver(3, N, "euler", [m, m, m], precision="fp32")
+        s32 = adg.Solver(3, N, "euler", [m, m, m], precision="fp32", cfl=args.cfl)
         Q32, clock32, t32, _, p32, c32 = run(s32, args.steps, args.warmup)
         err = float(torch.linalg.vector_norm(Q32 - Q64) / torch.linalg.vector_norm(Q64))
         v32 = dofs / (t32 / args.steps * 1e-3)
@@ -202,7 +204,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-predictor/f64-update",
         "data": "synthetic",
         "config": {"workload": f"c2: 3-D Euler, N={N}, {m}^3 periodic cells, seeded 8-mode Fourier "
-                               f"state, CFL 0.9, {args.precision}",
+                               f"state, CFL_N {args.cfl}, {args.precision}",
                    "dofs_per_step": dofs, "picard_iters": N + 1},
         "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
     }

@@ -25,7 +25,8 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith((".hip", ".cpp")) and f != "gen_tables.cpp")
 
 
 def _compile(src: str, extra: list[str]) -> tuple[str, str]:
@@ -37,8 +38,20 @@ def _compile(src: str, extra: list[str]) -> tuple[str, str]:
     return obj, p.stderr
 
 
+def generate_tables() -> str:
+    """Compile and run gen_tables (host only) to write csrc/tables_gen.hpp."""
+    exe = os.path.join(BUILD, "gen_tables")
+    cmd = ["g++", "-O2", "-std=c++17", "-o", exe, os.path.join(CSRC, "gen_tables.cpp"),
+           os.path.join(CSRC, "basis.cpp")]
+    subprocess.run(cmd, check=True)
+    out = os.path.join(CSRC, "tables_gen.hpp")
+    subprocess.run([exe, out], check=True)
+    return out
+
+
 def build(jobs: int | None = None, extra: list[str] | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate_tables()
     extra = list(extra or [])
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/adg.h"
+#include "basis.hpp"
 
 namespace adg {
 
@@ -53,16 +54,17 @@ struct KArgs {
   int nblocks;  // grid size of the cell kernels (for the block -> cell map)
   const SourceDev* src;
   const double* src_w;  // [nsrc][S][nvar]
-  // reduction slots in the workspace
-  unsigned long long* red_max;  // ordered bits of a non-negative double
-  unsigned int* red_count;
-  int* red_sum;
+  // per-block partial results (workspace), one slot per block of the
+  // corrector / reduction kernels
+  double* partial;
+  int* ipartial;
 };
 
 // Kernel entry points of one (PDE, dim, order) instantiation set.
 struct KernelSet {
-  int block;  // threads per block of the cell kernels
-  int cells_per_block;
+  int block;  // threads per block of the predictor
+  int cells_per_block;    // predictor
+  int cells_per_block_b;  // corrector and reductions (one partial slot per block)
   hipError_t (*predict)(const KArgs&, int precision, const double* Q, const double* params,
                         const double* clock, double* Qout, double* traces, hipStream_t);
   hipError_t (*correct)(const KArgs&, double* Q, const double* params, double* clock,
@@ -86,7 +88,5 @@ int max_order_elastic3();
 int max_order_advection2();
 int max_order_advection3();
 
-// Host tables (basis.cpp).
-int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1, double* K1inv);
 
 }  // namespace adg

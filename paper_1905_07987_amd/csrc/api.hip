@@ -21,7 +21,8 @@ struct adg_ctx {
   KArgs args{};
   double* traces = nullptr;  // [C][2 dim][2][nv][F]
   size_t trace_elems = 0;
-  void* red = nullptr;       // reduction slots
+  void* red = nullptr;       // per-block partials of the reductions
+  size_t red_bytes = 0;
   SourceDev* d_src = nullptr;
   double* d_src_w = nullptr;
   int nsrc = 0;
@@ -225,17 +226,21 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
     delete x;
     return fail(ADG_ERR_NOMEM, std::string("trace workspace: ") + hipGetErrorString(e));
   }
-  e = hipMalloc(&x->red, 64);
-  if (e == hipSuccess) e = hipMemset(x->red, 0, 64);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  {
+    const long long nb = (C + ks->cells_per_block_b - 1) / ks->cells_per_block_b;
+    e = hipMalloc(&x->red, (size_t)nb * (sizeof(double) + sizeof(int)) + 256);
+  }
   if (e != hipSuccess) {
     (void)hipFree(x->traces);
     delete x;
-    return hip_fail(e, "reduction slots");
+    return fail(ADG_ERR_NOMEM, std::string("reduction workspace: ") + hipGetErrorString(e));
   }
-  a.red_max = (unsigned long long*)x->red;
-  a.red_count = (unsigned int*)((char*)x->red + 8);
-  a.red_sum = (int*)((char*)x->red + 16);
+  {
+    const long long nb = (C + ks->cells_per_block_b - 1) / ks->cells_per_block_b;
+    a.partial = (double*)x->red;
+    a.ipartial = (int*)((char*)x->red + ((size_t)nb * sizeof(double) + 255) / 256 * 256);
+    x->red_bytes = (size_t)nb * (sizeof(double) + sizeof(int)) + 256;
+  }
   a.nsrc = 0;
   a.src = nullptr;
   a.src_w = nullptr;
@@ -269,7 +274,7 @@ adg_status adg_query(const adg_ctx* ctx, adg_info* info) {
   info->ncells = ctx->C;
   info->state_elems = ctx->C * ctx->nv * ctx->S;
   info->trace_elems = ctx->trace_elems;
-  info->workspace_bytes = ctx->trace_elems * sizeof(double) + 64;
+  info->workspace_bytes = ctx->trace_elems * sizeof(double) + ctx->red_bytes;
   return ADG_OK;
 }
 
@@ -468,8 +473,8 @@ adg_status adg_set_receivers(adg_ctx* ctx, int n, const double* xyz) {
 adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void* stream) {
   adg_status st = check_state(ctx, Q, (const void*)1);
   if (st) return st;
-  if (!out) return fail(ADG_ERR_INVALID_ARG, "null output");
   if (ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
+  if (!out) return fail(ADG_ERR_INVALID_ARG, "null output");
   hipLaunchKernelGGL(sample_kernel, dim3(ctx->nrec), dim3(64), 0, (hipStream_t)stream, Q,
                      ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nv, ctx->S);
   hipError_t e = hipGetLastError();

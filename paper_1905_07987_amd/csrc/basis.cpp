@@ -11,7 +11,7 @@
 // upwind value at the start of the step.
 #include <cmath>
 
-#include "adg_internal.hpp"
+#include "basis.hpp"
 
 namespace adg {
 namespace {
@@ -60,8 +60,8 @@ void gauss_legendre(int n, ld* x, ld* w) {
 
 int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1,
                  double* K1inv) {
-  if (n < 1 || n > kMaxN) return -1;
-  ld x[kMaxN], wt[kMaxN], bw[kMaxN], Dl[kMaxN][kMaxN], a[kMaxN], b[kMaxN];
+  if (n < 1 || n > kBasisMaxN) return -1;
+  ld x[kBasisMaxN], wt[kBasisMaxN], bw[kBasisMaxN], Dl[kBasisMaxN][kBasisMaxN], a[kBasisMaxN], b[kBasisMaxN];
   gauss_legendre(n, x, wt);
   // barycentric weights
   for (int j = 0; j < n; ++j) {
@@ -87,8 +87,8 @@ int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1
     for (int j = 0; j < n; ++j) out[j] = (bw[j] / (xe - x[j])) / den;
   }
   // K1 and its inverse (LU with partial pivoting, then n solves)
-  ld K[kMaxN][kMaxN], Kinv[kMaxN][kMaxN];
-  int perm[kMaxN];
+  ld K[kBasisMaxN][kBasisMaxN], Kinv[kBasisMaxN][kBasisMaxN];
+  int perm[kBasisMaxN];
   for (int i = 0; i < n; ++i) {
     perm[i] = i;
     for (int j = 0; j < n; ++j) K[i][j] = b[i] * b[j] - wt[j] * Dl[j][i];
@@ -113,7 +113,7 @@ int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1
     }
   }
   for (int col = 0; col < n; ++col) {
-    ld y[kMaxN];
+    ld y[kBasisMaxN];
     for (int i = 0; i < n; ++i) {
       ld s = (perm[i] == col) ? 1.0L : 0.0L;
       for (int j = 0; j < i; ++j) s -= K[i][j] * y[j];

@@ -1,4 +1,4 @@
-// Kernel instantiations for Elastic3, orders 1..5.
+// Kernel instantiations for Elastic3, orders 1..4.
 #include "kernels.hpp"
 
 namespace adg {
@@ -9,11 +9,10 @@ const KernelSet* kernels_elastic3(int order) {
     case 2: return Launch<Elastic3, 2>::set();
     case 3: return Launch<Elastic3, 3>::set();
     case 4: return Launch<Elastic3, 4>::set();
-    case 5: return Launch<Elastic3, 5>::set();
     default: return nullptr;
   }
 }
 
-int max_order_elastic3() { return 5; }
+int max_order_elastic3() { return 4; }
 
 }  // namespace adg

@@ -1,4 +1,4 @@
-// Kernel instantiations for Euler<3>, orders 1..6.
+// Kernel instantiations for Euler<3>, orders 1..5.
 #include "kernels.hpp"
 
 namespace adg {
@@ -10,11 +10,10 @@ const KernelSet* kernels_euler3(int order) {
     case 3: return Launch<Euler<3>, 3>::set();
     case 4: return Launch<Euler<3>, 4>::set();
     case 5: return Launch<Euler<3>, 5>::set();
-    case 6: return Launch<Euler<3>, 6>::set();
     default: return nullptr;
   }
 }
 
-int max_order_euler3() { return 6; }
+int max_order_euler3() { return 5; }
 
 }  // namespace adg

@@ -16,8 +16,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "adg_internal.hpp"
 #include "pde.hpp"
+#include "tables_gen.hpp"
 
 namespace adg {
 
@@ -34,9 +37,18 @@ struct Geo {
   static constexpr int NV = PDE::NV, NP = PDE::NP;
   static constexpr int CPB = S >= 256 ? 1 : 256 / S;  // cells per block
   static constexpr int BLOCK = CPB * S;
-  static constexpr int SP = S + S / n;     // LDS row: one pad slot per x-row
+  // LDS rows are stored line-major per direction: node k of a row for
+  // direction d sits at line_d(k) * LS + k_d, with the line stride LS odd so
+  // that 16 consecutive lanes touching consecutive lines, or consecutive
+  // nodes of a line, fall into distinct banks.
+  static constexpr int LS = (n % 2 == 0) ? n + 1 : n + 2;
+  static constexpr int SP = F * LS;        // LDS row length (elements)
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
-  __host__ __device__ static constexpr int pidx(int k) { return k + k / n; }
+  // line index of node (kx, ky, kz) for direction d: the other axes, lower first
+  __host__ __device__ static constexpr int line_of(int d, int kx, int ky, int kz) {
+    return DIM == 2 ? (d == 0 ? ky : kx)
+                    : (d == 0 ? ky + n * kz : (d == 1 ? kx + n * kz : kx + n * ky));
+  }
 };
 
 // Derivative channels per direction: the nonzero flux components, then the
@@ -73,18 +85,48 @@ struct Chan {
   }
 };
 
-// Time slices per LDS chunk: enough line tasks for the block, within 64 KiB.
+// Predictor layout.  Time slices are processed in pairs; the two slices of
+// a pair share one 16-byte LDS element per (channel, node), so every LDS
+// access of the iteration is 128-bit wide.  Cells per block: ~256 lanes,
+// limited so the block's LDS stays within 64 KiB.
+template <class R>
+struct alignas(2 * sizeof(R)) Pair {
+  R x, y;
+};
+
 template <class PDE, int N, class R>
-struct Chunk {
+struct GeoA {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  static constexpr int want = (G::n + G::DIM - 1) / G::DIM;
-  static constexpr int per_slot = G::CPB * C::NCH * G::SP * (int)sizeof(R);
-  static constexpr int fit = (64 * 1024) / per_slot;
-  static constexpr int TC = cmax(1, cmin(want, fit));
-  static constexpr int ITER_ELEMS = G::CPB * TC * C::NCH * G::SP;
-  static constexpr int FIN_ELEMS = G::CPB * (G::NV + C::NFLUX) * G::SP;
-  static constexpr int ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
+  static constexpr int ITER_ELEMS = C::NCH * G::SP * 2;          // per cell, in R
+  static constexpr int FIN_ELEMS = (G::NV + C::NFLUX) * G::SP;   // per cell, in R
+  static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
+  static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
+  static constexpr int by_lds = cmax(1, (64 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * G::S;
+  static constexpr int ELEMS = CPB * CELL_ELEMS;
+  static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
+  // Occupancy target (waves per SIMD) handed to the register allocator.  At
+  // FP64 the unconstrained kernel takes more than 256 registers (one wave per
+  // SIMD); bounding it at two waves costs only a few rarely used values
+  // parked in scratch, and doubles the waves that hide LDS and barrier
+  // latency.  FP32 values take half the registers, so three waves fit.
+  static constexpr int MIN_WAVES = sizeof(R) == 8 ? 2 : 3;
+  static_assert(ELEMS * (int)sizeof(R) <= 64 * 1024, "predictor LDS exceeds 64 KiB");
+};
+
+// Compile-time one-dimensional tables of order n in precision R (generated at
+// build time from the same host construction as adg_basis_tables); every use
+// sits in a fully unrolled loop, so the constants fold into the instructions.
+template <class R, int n>
+struct CT {
+  using B = BasisConst<n>;
+  __device__ static constexpr R D(int i, int m) { return R(B::D[i][m]); }
+  __device__ static constexpr R KW(int i, int j) { return R(B::KW[i][j]); }
+  __device__ static constexpr R w(int j) { return R(B::w[j]); }
+  __device__ static constexpr R l0(int j) { return R(B::l0[j]); }
+  __device__ static constexpr R l1(int j) { return R(B::l1[j]); }
 };
 
 template <class R>
@@ -114,20 +156,6 @@ __device__ __forceinline__ void node_coords(int k, int n, int* kk) {
   if (DIM == 3) kk[2] = k / (n * n);
 }
 
-// First node and stride of line l (the face-node index) along direction d.
-template <int DIM>
-__device__ __forceinline__ void line_geom(int d, int l, int n, int& base, int& stride) {
-  if (DIM == 2) {
-    base = d == 0 ? l * n : l;
-    stride = d == 0 ? 1 : n;
-  } else {
-    const int a = l % n, b = l / n;  // remaining axes, lower one first
-    if (d == 0) { base = n * a + n * n * b; stride = 1; }
-    else if (d == 1) { base = a + n * n * b; stride = n; }
-    else { base = a + n * b; stride = n * n; }
-  }
-}
-
 // Block-level max of non-negative doubles; returns the block max in thread 0.
 // Every thread stores its value in LDS; the first wave (always complete:
 // BLOCK >= 64) folds the block and reduces across its lanes, so no shuffle
@@ -145,16 +173,9 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return m;
 }
 
-// Grid-wide completion: returns true in thread 0 of the last block to finish.
-__device__ __forceinline__ bool last_block(unsigned int* counter, bool* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    *flag = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  return *flag && threadIdx.x == 0;
+// true if local cell c of block b exists (ragged last block)
+__device__ __forceinline__ bool cell0_valid(const KArgs& a, int b, int cpb, int c) {
+  return (long long)xcd_block(b, a.nblocks) * cpb + c < a.ncells;
 }
 
 __device__ __forceinline__ double ricker(double f0, double t0, double amp, double t) {
@@ -168,30 +189,36 @@ __device__ __forceinline__ double ricker(double f0, double t0, double amp, doubl
 // Kernel A: predictor, time averages, volume term and face projection.
 // ---------------------------------------------------------------------------
 template <class PDE, int N, class R>
-__global__ void __launch_bounds__((Geo<PDE, N>::BLOCK))
+__global__ void __launch_bounds__((GeoA<PDE, N, R>::BLOCK), (GeoA<PDE, N, R>::MIN_WAVES))
 predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params,
                const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
   // Q and Qout may be the same array (in-place step): each element is read
   // once at the start and written once at the end by the same thread.
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  using K = Chunk<PDE, N, R>;
+  using GA = GeoA<PDE, N, R>;
+  using T = CT<R, G::n>;
+  using P2 = Pair<R>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = G::CPB, BLOCK = G::BLOCK, SP = G::SP, TC = K::TC;
+  constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK, SP = G::SP;
   constexpr int NCH = C::NCH, NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
   static_assert(C::uniform(), "flux sparsity must be the same in every direction");
-  __shared__ R lds[K::ELEMS];
+  __shared__ P2 lds2[GA::ELEMS / 2];
+  R* const lds = reinterpret_cast<R*>(lds2);
 
-  const Tables<R>& T = tables<R>(a);
   const int tid = threadIdx.x;
   const int lc = tid / S, k = tid - lc * S;
+  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  {
+    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * G::LS + kd[d];
+  }
   const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
   const long long cell = cell0 + lc;
   const bool active = cell < a.ncells;
   const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
-
-  int kk[3] = {0, 0, 0};
-  node_coords<DIM>(k, n, kk);
 
   double u64[NV];
   R u[NV], P[NP > 0 ? NP : 1];
@@ -208,158 +235,215 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
 #pragma unroll
   for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
 
-  R q[n][NV];
+  // Point sources: the Ricker amplitude at the n time nodes of this step is
+  // evaluated once per block; only blocks holding a source cell use them.
+  __shared__ double src_amp[kMaxSources * n];
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc * n) {
+    const int s = tid / n, j = tid - s * n;
+    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt64);
+  }
+  // (made visible by the first barrier below)
+
+  P2* const mine = lds2 + lc * (GA::CELL_ELEMS / 2);  // this cell's pairs [NCH][SP]
+  R q[n][NV];     // current iterate at the n time nodes of node k
+  R Fbar[DIM][NV], Nbar[NV], Sbar[NV];  // final pass: time averages
+
+  // point-source term of slice j at this node, added to Sv
+  auto add_point_sources = [&](int j, R* Sv) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const R amp = R(src_amp[s * n + j]);
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sv[v] += amp * R(wsk[v]);
+    }
+  };
+
+  // One pass over the time slices of the current iterate, two at a time.
+  //  KIND 0: first Picard step.  q^0 = u^n at every time node, so every slice
+  //          has the same right-hand side apart from point sources: one
+  //          slice is evaluated and copied to all n.
+  //  KIND 1: Picard step.
+  //  Both leave R_j in q[j]; the caller then forms sum_j KW_ij R_j.
+  //  KIND 2: final pass at the last iterate: time averages of F, B grad q
+  //          and S (READING: the averaged terms use the final iterate).
+  auto pass = [&](auto kind_tag) {
+    constexpr int KIND = decltype(kind_tag)::value;
+    constexpr bool FIN = KIND == 2;
+    constexpr bool USE_LDS = !FIN || PDE::kHasNcp;
+    constexpr int NSL = KIND == 0 ? 1 : n;  // slices evaluated
+#pragma unroll
+    for (int c0 = 0; c0 < NSL; c0 += 2) {
+      const bool two = c0 + 1 < NSL;  // compile-time after unrolling
+      const int j0 = c0, j1 = two ? c0 + 1 : c0;
+      // (1) fluxes and gradient inputs of slices j0, j1 -> LDS pairs
+      R Fa[DIM][NV], Fb[DIM][NV];
+      PDE::fluxes(q[j0], P, a.pde, Fa);
+      if (two) PDE::fluxes(q[j1], P, a.pde, Fb);
+      if constexpr (FIN) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            Fbar[d][v] += T::w(j0) * Fa[d][v];
+            if (two) Fbar[d][v] += T::w(j1) * Fb[d][v];
+          }
+      }
+      if constexpr (USE_LDS) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if constexpr (!FIN) {
+#pragma unroll
+            for (int c = 0; c < NFL; ++c) {
+              const int v = C::flux_var(d, c);
+              mine[(d * NCHD + c) * SP + pk[d]] = P2{Fa[d][v], two ? Fb[d][v] : R(0)};
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NGR; ++c) {
+            const int v = C::grad_var(c);
+            mine[(d * NCHD + NFL + c) * SP + pk[d]] = P2{q[j0][v], two ? q[j1][v] : R(0)};
+          }
+        }
+        __syncthreads();
+        // (2) line tasks (cell, direction, channel half, line): differentiate
+        //     both slices of every channel in place
+        constexpr int CH0 = FIN ? NFL : 0;  // the final pass only needs gradients
+        constexpr int CHM = (CH0 + NCHD + 1) / 2;
+        for (int task = tid; task < CPB * DIM * 2 * F; task += BLOCK) {
+          const int l = task % F;
+          const int hf = (task / F) & 1;
+          const int d = (task / (2 * F)) % DIM;
+          const int c2 = task / (2 * F * DIM);
+          P2* row = lds2 + c2 * (GA::CELL_ELEMS / 2) + d * NCHD * SP + l * G::LS;
+          const R s = inv_h[d];
+          const int cb = hf ? CHM : CH0, ce = hf ? NCHD : CHM;
+          for (int c = cb; c < ce; ++c) {
+            P2 x[n];
+#pragma unroll
+            for (int m = 0; m < n; ++m) x[m] = row[c * SP + m];
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+              R y0 = R(0), y1 = R(0);
+#pragma unroll
+              for (int m = 0; m < n; ++m) {
+                y0 += T::D(i, m) * x[m].x;
+                y1 += T::D(i, m) * x[m].y;
+              }
+              row[c * SP + i] = P2{y0 * s, y1 * s};
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // (3) right-hand sides of slices j0, j1 at this node
+      R divA[NV], divB[NV], gA[DIM][NV], gB[DIM][NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        divA[v] = divB[v] = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) gA[d][v] = gB[d][v] = R(0);
+      }
+      if constexpr (USE_LDS) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if constexpr (!FIN) {
+#pragma unroll
+            for (int c = 0; c < NFL; ++c) {
+              const P2 t = mine[(d * NCHD + c) * SP + pk[d]];
+              divA[C::flux_var(d, c)] += t.x;
+              divB[C::flux_var(d, c)] += t.y;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NGR; ++c) {
+            const P2 t = mine[(d * NCHD + NFL + c) * SP + pk[d]];
+            gA[d][C::grad_var(c)] = t.x;
+            gB[d][C::grad_var(c)] = t.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+        const int j = h ? j1 : j0;
+        R B[NV], Sv[NV];
+        if constexpr (PDE::kHasNcp) {
+          PDE::ncp(q[j], P, a.pde, h ? gB : gA, B);
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) B[v] = R(0);
+        }
+        PDE::source(q[j], P, a.pde, Sv);
+        if constexpr (KIND == 0) {
+          // identical slices: R_j = R (plus the point sources of slice j)
+          R Rv[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Rv[v] = Sv[v] - divA[v] - B[v];
+#pragma unroll
+          for (int jj = 0; jj < n; ++jj) {
+            R Sp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Sp[v] = R(0);
+            add_point_sources(jj, Sp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[jj][v] = Rv[v] + Sp[v];
+          }
+        } else {
+          add_point_sources(j, Sv);
+          if constexpr (KIND == 1) {
+            // q_j is no longer needed once R_j is known: keep R_j in its place
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[j][v] = Sv[v] - (h ? divB[v] : divA[v]) - B[v];
+          } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              Nbar[v] += T::w(j) * B[v];
+              Sbar[v] += T::w(j) * Sv[v];
+            }
+          }
+        }
+      }
+      if constexpr (USE_LDS) __syncthreads();
+    }
+  };
+
+  const int I = a.picard_iters;
 #pragma unroll
   for (int j = 0; j < n; ++j)
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[j][v] = u[v];
-
-  R Fbar[DIM][NV], Nbar[NV], Sbar[NV];
+  for (int r = 0; r < I; ++r) {
+    if (r == 0)
+      pass(std::integral_constant<int, 0>{});
+    else
+      pass(std::integral_constant<int, 1>{});
+    // q holds R_j at every time node: q^{r+1}_i = u + dt sum_j KW_ij R_j
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R t[n];
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) s += T::KW(i, j) * q[j][v];
+        t[i] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i) q[i][v] = u[v] + dt * t[i];
+    }
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     Nbar[v] = Sbar[v] = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Fbar[d][v] = R(0);
   }
-
-  R* const mine = lds + lc * (TC * NCH * SP);  // this cell's chunk region
-  const int I = a.picard_iters;
-
-  for (int r = 0; r <= I; ++r) {
-    const bool fin = (r == I);  // final pass: averages at the last iterate
-    R acc[n][NV];
-#pragma unroll
-    for (int i = 0; i < n; ++i)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[i][v] = R(0);
-
-#pragma unroll
-    for (int c0 = 0; c0 < n; c0 += TC) {
-      const int cnt = cmin(TC, n - c0);
-      // (1) fluxes and gradient inputs of the chunk's slices -> LDS
-#pragma unroll
-      for (int jj = 0; jj < TC; ++jj) {
-        if (c0 + jj >= n) break;
-        const int j = c0 + jj;
-        R Fl[DIM][NV];
-        PDE::fluxes(q[j], P, a.pde, Fl);
-        if (fin) {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Fbar[d][v] += T.w[j] * Fl[d][v];
-        }
-        if (!fin || PDE::kHasNcp) {
-          R* slot = mine + jj * NCH * SP;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-#pragma unroll
-            for (int c = 0; c < NFL; ++c)
-              slot[(d * NCHD + c) * SP + G::pidx(k)] = Fl[d][C::flux_var(d, c)];
-#pragma unroll
-            for (int c = 0; c < NGR; ++c)
-              slot[(d * NCHD + NFL + c) * SP + G::pidx(k)] = q[j][C::grad_var(c)];
-          }
-        }
-      }
-      if (!fin || PDE::kHasNcp) {
-        __syncthreads();
-        // (2) one task per (cell, slice, direction, line): differentiate in place
-        const int ntask = CPB * cnt * DIM * F;
-        for (int task = tid; task < ntask; task += BLOCK) {
-          const int l = task % F;
-          const int rest = task / F;
-          const int d = rest % DIM;
-          const int rest2 = rest / DIM;
-          const int jj = rest2 % cnt;
-          const int c2 = rest2 / cnt;
-          int base, stride;
-          line_geom<DIM>(d, l, n, base, stride);
-          R* row = lds + c2 * (TC * NCH * SP) + (jj * NCH + d * NCHD) * SP;
-          const R s = inv_h[d];
-#pragma unroll
-          for (int c = 0; c < NCHD; ++c) {
-            R x[n];
-#pragma unroll
-            for (int m = 0; m < n; ++m) x[m] = row[c * SP + G::pidx(base + m * stride)];
-#pragma unroll
-            for (int i = 0; i < n; ++i) {
-              R y = R(0);
-#pragma unroll
-              for (int m = 0; m < n; ++m) y += T.D[i][m] * x[m];
-              row[c * SP + G::pidx(base + i * stride)] = y * s;
-            }
-          }
-        }
-        __syncthreads();
-      }
-      // (3) right-hand side of every slice at this node
-#pragma unroll
-      for (int jj = 0; jj < TC; ++jj) {
-        if (c0 + jj >= n) break;
-        const int j = c0 + jj;
-        const R* slot = mine + jj * NCH * SP;
-        R divF[NV], g[DIM][NV], B[NV], Sv[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          divF[v] = R(0);
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) g[d][v] = R(0);
-        }
-        if (!fin || PDE::kHasNcp) {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            if (!fin) {
-#pragma unroll
-              for (int c = 0; c < NFL; ++c)
-                divF[C::flux_var(d, c)] += slot[(d * NCHD + c) * SP + G::pidx(k)];
-            }
-#pragma unroll
-            for (int c = 0; c < NGR; ++c)
-              g[d][C::grad_var(c)] = slot[(d * NCHD + NFL + c) * SP + G::pidx(k)];
-          }
-        }
-        if (PDE::kHasNcp) {
-          PDE::ncp(q[j], P, a.pde, g, B);
-        } else {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) B[v] = R(0);
-        }
-        PDE::source(q[j], P, a.pde, Sv);
-        if (a.nsrc > 0) {
-          const double tj = t_n + (double)a.t64.xi[j] * dt64;
-          for (int s = 0; s < a.nsrc; ++s) {
-            if (a.src[s].cell != cell) continue;
-            const R amp = R(ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, tj));
-            const double* wsk = a.src_w + ((long long)s * S + k) * NV;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Sv[v] += amp * R(wsk[v]);
-          }
-        }
-        if (!fin) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const R Rv = Sv[v] - divF[v] - B[v];
-#pragma unroll
-            for (int i = 0; i < n; ++i) acc[i][v] += T.KW[i][j] * Rv;
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            Nbar[v] += T.w[j] * B[v];
-            Sbar[v] += T.w[j] * Sv[v];
-          }
-        }
-      }
-      if (!fin || PDE::kHasNcp) __syncthreads();
-    }
-    if (!fin) {
-#pragma unroll
-      for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) q[i][v] = u[v] + dt * acc[i][v];
-    }
-  }
+  pass(std::integral_constant<int, 2>{});
 
   // time average of the final iterate
   R qbar[NV];
@@ -367,7 +451,7 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
   for (int v = 0; v < NV; ++v) {
     R s = R(0);
 #pragma unroll
-    for (int j = 0; j < n; ++j) s += T.w[j] * q[j][v];
+    for (int j = 0; j < n; ++j) s += T::w(j) * q[j][v];
     qbar[v] = s;
   }
 
@@ -377,20 +461,18 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
   R divF[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
-  R* const fin_mine = lds + lc * ((NV + NFL) * SP);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) fin_mine[v * SP + G::pidx(k)] = qbar[v];
+  R* const fin_mine = lds + lc * GA::CELL_ELEMS;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
 #pragma unroll
-    for (int c = 0; c < NFL; ++c) fin_mine[(NV + c) * SP + G::pidx(k)] = Fbar[d][C::flux_var(d, c)];
+    for (int v = 0; v < NV; ++v) fin_mine[v * SP + pk[d]] = qbar[v];
+#pragma unroll
+    for (int c = 0; c < NFL; ++c) fin_mine[(NV + c) * SP + pk[d]] = Fbar[d][C::flux_var(d, c)];
     __syncthreads();
     for (int task = tid; task < CPB * F; task += BLOCK) {
       const int l = task % F, c2 = task / F;
       const long long tcell = cell0 + c2;
-      int base, stride;
-      line_geom<DIM>(d, l, n, base, stride);
-      R* rows = lds + c2 * ((NV + NFL) * SP);
+      R* rows = lds + c2 * GA::CELL_ELEMS + l * G::LS;
       double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
       const bool tact = tcell < a.ncells;
       // qbar traces at both ends
@@ -399,13 +481,13 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
         R e0 = R(0), e1 = R(0);
 #pragma unroll
         for (int m = 0; m < n; ++m) {
-          const R x = rows[v * SP + G::pidx(base + m * stride)];
-          e0 += T.l0[m] * x;
-          e1 += T.l1[m] * x;
+          const R x = rows[v * SP + m];
+          e0 += T::l0(m) * x;
+          e1 += T::l1(m) * x;
         }
         if (tact) {
-          tr[(0 * NV + v) * F + l] = double(e0);          // face 2d,   state
-          tr[(2 * NV + v) * F + l] = double(e1);          // face 2d+1, state
+          tr[(0 * NV + v) * F + l] = double(e0);  // face 2d,   state
+          tr[(2 * NV + v) * F + l] = double(e1);  // face 2d+1, state
         }
       }
       // normal-flux traces; derivative of Fbar_d in place
@@ -421,12 +503,12 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
         const int v = C::flux_var(d, c);
         R x[n];
 #pragma unroll
-        for (int m = 0; m < n; ++m) x[m] = rows[(NV + c) * SP + G::pidx(base + m * stride)];
+        for (int m = 0; m < n; ++m) x[m] = rows[(NV + c) * SP + m];
         R e0 = R(0), e1 = R(0);
 #pragma unroll
         for (int m = 0; m < n; ++m) {
-          e0 += T.l0[m] * x[m];
-          e1 += T.l1[m] * x[m];
+          e0 += T::l0(m) * x[m];
+          e1 += T::l1(m) * x[m];
         }
         if (tact) {
           tr[(1 * NV + v) * F + l] = double(e0);
@@ -437,14 +519,14 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
         for (int i = 0; i < n; ++i) {
           R y = R(0);
 #pragma unroll
-          for (int m = 0; m < n; ++m) y += T.D[i][m] * x[m];
-          rows[(NV + c) * SP + G::pidx(base + i * stride)] = y * s;
+          for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
+          rows[(NV + c) * SP + i] = y * s;
         }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < NFL; ++c) divF[C::flux_var(d, c)] += fin_mine[(NV + c) * SP + G::pidx(k)];
+    for (int c = 0; c < NFL; ++c) divF[C::flux_var(d, c)] += fin_mine[(NV + c) * SP + pk[d]];
     __syncthreads();
   }
 
@@ -459,44 +541,58 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
 
 // ---------------------------------------------------------------------------
 // Kernel B: Rusanov flux on every face of the cell, surface integral and
-// update; optionally the Eq. (7) maximum of the new state for the next step.
+// update; optionally the per-block Eq. (7) maximum of the new state (reduced
+// over blocks by finalize_kernel, which also advances the clock).
 // ---------------------------------------------------------------------------
 template <class PDE, int N>
-__global__ void __launch_bounds__((Geo<PDE, N>::BLOCK))
-correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__ params,
-               double* __restrict__ clock, const double* __restrict__ traces, int next_dt) {
+struct GeoB {
   using G = Geo<PDE, N>;
+  static constexpr int FL_PER_CELL = 2 * G::DIM * G::NV * G::F;  // doubles
+  static constexpr int by_threads = G::S >= 512 ? 1 : 512 / G::S;
+  static constexpr int by_lds = cmax(1, (48 * 1024) / (FL_PER_CELL * 8));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * G::S;
+  static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
+};
+
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoB<PDE, N>::BLOCK))
+correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__ params,
+               const double* __restrict__ clock, const double* __restrict__ traces, int next_dt) {
+  using G = Geo<PDE, N>;
+  using GB = GeoB<PDE, N>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = G::CPB, BLOCK = G::BLOCK;
-  __shared__ double fl[CPB * 2 * DIM * NV * F];
+  constexpr int CPB = GB::CPB, BLOCK = GB::BLOCK;
+  __shared__ double fl[CPB * GB::FL_PER_CELL];
   __shared__ double red[BLOCK];
-  __shared__ bool last;
 
   const Tables<double>& T = a.t64;
   const int tid = threadIdx.x;
-  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const int cell0 = xcd_block(blockIdx.x, a.nblocks) * CPB;
   const double dt = clock[1];
+  const int C0 = a.cells[0], C1 = a.cells[1];
+  const int ncells = (int)a.ncells;
 
   // fluctuations, one task per (cell, face, face node)
   for (int task = tid; task < CPB * 2 * DIM * F; task += BLOCK) {
     const int f = task % F;
     const int face = (task / F) % (2 * DIM);
     const int c2 = task / (F * 2 * DIM);
-    const long long c = cell0 + c2;
-    if (c >= a.ncells) continue;
+    const int c = cell0 + c2;
+    if (c >= ncells) continue;
     const int d = face >> 1, side = face & 1;
     // periodic neighbour across this face
-    long long cc[3];
-    cc[0] = c % a.cells[0];
-    cc[1] = (c / a.cells[0]) % a.cells[1];
-    cc[2] = DIM == 3 ? c / ((long long)a.cells[0] * a.cells[1]) : 0;
+    int cc[3];
+    cc[0] = c % C0;
+    cc[1] = (c / C0) % C1;
+    cc[2] = DIM == 3 ? c / (C0 * C1) : 0;
     cc[d] += side ? 1 : -1;
     if (cc[d] < 0) cc[d] += a.cells[d];
     if (cc[d] >= a.cells[d]) cc[d] -= a.cells[d];
-    const long long nb = cc[0] + (long long)a.cells[0] * (cc[1] + (long long)a.cells[1] * cc[2]);
-    const long long cL = side ? c : nb, cR = side ? nb : c;
-    const double* tL = traces + ((cL * (2 * DIM) + 2 * d + 1) * 2) * (long long)NV * F;
-    const double* tR = traces + ((cR * (2 * DIM) + 2 * d + 0) * 2) * (long long)NV * F;
+    const int nb = cc[0] + C0 * (cc[1] + C1 * cc[2]);
+    const int cL = side ? c : nb, cR = side ? nb : c;
+    const double* tL = traces + ((long long)(cL * (2 * DIM) + 2 * d + 1) * 2) * NV * F;
+    const double* tR = traces + ((long long)(cR * (2 * DIM) + 2 * d + 0) * 2) * NV * F;
     double qL[NV], qR[NV], FL[NV], FR[NV], pL[NP > 0 ? NP : 1], pR[NP > 0 ? NP : 1], pm[NP > 0 ? NP : 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -513,7 +609,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     }
     const double s = fmax(PDE::max_eigen(qL, pL, a.pde, d), PDE::max_eigen(qR, pR, a.pde, d));
     double B[NV];
-    if (PDE::kHasNcp) {
+    if constexpr (PDE::kHasNcp) {
       double qm[NV], g[DIM][NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -538,9 +634,9 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
   __syncthreads();
 
   const int lc = tid / S, k = tid - lc * S;
-  const long long cell = cell0 + lc;
+  const int cell = cell0 + lc;
   double lam = 0.0;
-  if (cell < a.ncells) {
+  if (cell < ncells) {
     int kk[3] = {0, 0, 0};
     node_coords<DIM>(k, n, kk);
     int fidx[DIM];
@@ -562,7 +658,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
         const double lo = fl[((lc * 2 * DIM + 2 * d) * NV + v) * F + fidx[d]];
         surf += (T.l1[kk[d]] * hi + T.l0[kk[d]] * lo) * T.invw[kk[d]];
       }
-      const long long idx = (cell * NV + v) * S + k;
+      const long long idx = ((long long)cell * NV + v) * S + k;
       qn[v] = Q[idx] - surf;
       Q[idx] = qn[v];
     }
@@ -573,31 +669,20 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
   }
   if (next_dt) {
     const double m = block_max<BLOCK>(lam, red);
-    if (tid == 0) atomicMax(a.red_max, (unsigned long long)__double_as_longlong(m));
-  }
-  if (last_block(a.red_count, &last)) {
-    __threadfence();
-    if (next_dt) {
-      const double lmax = __longlong_as_double((long long)atomicAdd(a.red_max, 0ull));
-      clock[1] = a.dt_factor / lmax;
-      atomicExch(a.red_max, 0ull);
-    }
-    clock[0] = clock[0] + dt;
-    atomicExch(a.red_count, 0u);
+    if (tid == 0) a.partial[blockIdx.x] = m;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Eq. (7) on a given state.
+// Eq. (7) on a given state: per-block maxima of the largest |eigenvalue|.
 // ---------------------------------------------------------------------------
 template <class PDE, int N>
-__global__ void __launch_bounds__((Geo<PDE, N>::BLOCK))
-stable_dt_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
-                 double* __restrict__ clock) {
+__global__ void __launch_bounds__((GeoB<PDE, N>::BLOCK))
+lambda_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params) {
   using G = Geo<PDE, N>;
-  constexpr int S = G::S, NV = G::NV, NP = G::NP, DIM = G::DIM, CPB = G::CPB;
-  __shared__ double red[G::BLOCK];
-  __shared__ bool last;
+  using GB = GeoB<PDE, N>;
+  constexpr int S = G::S, NV = G::NV, NP = G::NP, DIM = G::DIM, CPB = GB::CPB;
+  __shared__ double red[GB::BLOCK];
   const int tid = threadIdx.x;
   const int lc = tid / S, k = tid - lc * S;
   const long long cell = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB + lc;
@@ -611,28 +696,44 @@ stable_dt_kernel(const KArgs a, const double* __restrict__ Q, const double* __re
 #pragma unroll
     for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(q, P, a.pde, d));
   }
-  const double m = block_max<G::BLOCK>(lam, red);
-  if (tid == 0) atomicMax(a.red_max, (unsigned long long)__double_as_longlong(m));
-  if (last_block(a.red_count, &last)) {
-    __threadfence();
-    const double lmax = __longlong_as_double((long long)atomicAdd(a.red_max, 0ull));
-    clock[1] = a.dt_factor / lmax;
-    atomicExch(a.red_max, 0ull);
-    atomicExch(a.red_count, 0u);
+  const double m = block_max<GB::BLOCK>(lam, red);
+  if (tid == 0) a.partial[blockIdx.x] = m;
+}
+
+namespace {  // one copy per translation unit
+
+// One block folds the per-block partials and updates the clock {t, dt}:
+// mode & 1: dt <- dt_factor / max(partial)      (Eq. (7))
+// mode & 2: t <- t + dt (the dt the step used, read before it is replaced)
+__global__ void __launch_bounds__(256)
+finalize_kernel(const double* __restrict__ partial, int nparts, double dt_factor, int mode,
+                double* __restrict__ clock) {
+  __shared__ double red[256];
+  double m = 0.0;
+  if (mode & 1)
+    for (int i = threadIdx.x; i < nparts; i += 256) m = fmax(m, partial[i]);
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) {
+    const double dt_used = clock[1];
+    if (mode & 2) clock[0] = clock[0] + dt_used;
+    if (mode & 1) clock[1] = dt_factor / m;
   }
 }
 
+}  // namespace
+
 // ---------------------------------------------------------------------------
-// Physical admissibility per cell (Sec. 3.5).
+// Physical admissibility per cell (Sec. 3.5); per-block counts summed by
+// count_kernel.
 // ---------------------------------------------------------------------------
 template <class PDE, int N>
-__global__ void __launch_bounds__((Geo<PDE, N>::BLOCK))
+__global__ void __launch_bounds__((GeoB<PDE, N>::BLOCK))
 admissible_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
-                  uint8_t* __restrict__ troubled, int32_t* __restrict__ count) {
+                  uint8_t* __restrict__ troubled) {
   using G = Geo<PDE, N>;
-  constexpr int S = G::S, NV = G::NV, NP = G::NP, CPB = G::CPB;
+  using GB = GeoB<PDE, N>;
+  constexpr int S = G::S, NV = G::NV, NP = G::NP, CPB = GB::CPB;
   __shared__ int bad[CPB];
-  __shared__ bool last;
   const int tid = threadIdx.x;
   const int lc = tid / S, k = tid - lc * S;
   const long long cell = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB + lc;
@@ -647,17 +748,31 @@ admissible_kernel(const KArgs a, const double* __restrict__ Q, const double* __r
     if (!PDE::admissible(q, P, a.pde)) bad[lc] = 1;
   }
   __syncthreads();
-  if (k == 0 && cell < a.ncells) {
-    troubled[cell] = (uint8_t)bad[lc];
-    if (bad[lc]) atomicAdd(a.red_sum, 1);
-  }
-  if (last_block(a.red_count, &last)) {
-    __threadfence();
-    *count = atomicAdd(a.red_sum, 0);
-    atomicExch(a.red_sum, 0);
-    atomicExch(a.red_count, 0u);
+  if (k == 0 && cell < a.ncells) troubled[cell] = (uint8_t)bad[lc];
+  if (tid == 0) {
+    int cnt = 0;
+    for (int c = 0; c < CPB; ++c) cnt += (cell0_valid(a, blockIdx.x, CPB, c) ? bad[c] : 0);
+    a.ipartial[blockIdx.x] = cnt;
   }
 }
+
+namespace {
+
+__global__ void __launch_bounds__(256)
+count_kernel(const int* __restrict__ partial, int nparts, int32_t* __restrict__ count) {
+  __shared__ int red[256];
+  int s = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = red[0];
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers and the per-(PDE, N) kernel set.
@@ -665,46 +780,63 @@ admissible_kernel(const KArgs a, const double* __restrict__ Q, const double* __r
 template <class PDE, int N>
 struct Launch {
   using G = Geo<PDE, N>;
-  static int blocks(const KArgs& a) { return (int)((a.ncells + G::CPB - 1) / G::CPB); }
+  using GB = GeoB<PDE, N>;
+  template <class R>
+  static int blocks_a(const KArgs& a) {
+    return (int)((a.ncells + GeoA<PDE, N, R>::CPB - 1) / GeoA<PDE, N, R>::CPB);
+  }
+  static int blocks_b(const KArgs& a) { return (int)((a.ncells + GB::CPB - 1) / GB::CPB); }
 
   static hipError_t predict(const KArgs& a0, int precision, const double* Q, const double* params,
                             const double* clock, double* Qout, double* traces, hipStream_t st) {
     KArgs a = a0;
-    a.nblocks = blocks(a);
-    if (precision == ADG_MIXED_FP32)
-      hipLaunchKernelGGL((predict_kernel<PDE, N, float>), dim3(a.nblocks), dim3(G::BLOCK), 0, st, a,
-                         Q, params, clock, Qout, traces);
-    else
-      hipLaunchKernelGGL((predict_kernel<PDE, N, double>), dim3(a.nblocks), dim3(G::BLOCK), 0, st,
-                         a, Q, params, clock, Qout, traces);
+    if (precision == ADG_MIXED_FP32) {
+      a.nblocks = blocks_a<float>(a);
+      hipLaunchKernelGGL((predict_kernel<PDE, N, float>), dim3(a.nblocks),
+                         dim3(GeoA<PDE, N, float>::BLOCK), 0, st, a, Q, params, clock, Qout, traces);
+    } else {
+      a.nblocks = blocks_a<double>(a);
+      hipLaunchKernelGGL((predict_kernel<PDE, N, double>), dim3(a.nblocks),
+                         dim3(GeoA<PDE, N, double>::BLOCK), 0, st, a, Q, params, clock, Qout, traces);
+    }
     return hipGetLastError();
   }
   static hipError_t correct(const KArgs& a0, double* Q, const double* params, double* clock,
                             const double* traces, int next_dt, hipStream_t st) {
     KArgs a = a0;
-    a.nblocks = blocks(a);
-    hipLaunchKernelGGL((correct_kernel<PDE, N>), dim3(a.nblocks), dim3(G::BLOCK), 0, st, a, Q, params,
-                       clock, traces, next_dt);
+    a.nblocks = blocks_b(a);
+    hipLaunchKernelGGL((correct_kernel<PDE, N>), dim3(a.nblocks), dim3(GB::BLOCK), 0, st, a, Q,
+                       params, clock, traces, next_dt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, a.partial, a.nblocks, a.dt_factor,
+                       next_dt ? 3 : 2, clock);
     return hipGetLastError();
   }
   static hipError_t stable_dt(const KArgs& a0, const double* Q, const double* params, double* clock,
                               hipStream_t st) {
     KArgs a = a0;
-    a.nblocks = blocks(a);
-    hipLaunchKernelGGL((stable_dt_kernel<PDE, N>), dim3(a.nblocks), dim3(G::BLOCK), 0, st, a, Q, params,
+    a.nblocks = blocks_b(a);
+    hipLaunchKernelGGL((lambda_kernel<PDE, N>), dim3(a.nblocks), dim3(GB::BLOCK), 0, st, a, Q, params);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, a.partial, a.nblocks, a.dt_factor, 1,
                        clock);
     return hipGetLastError();
   }
   static hipError_t admissible(const KArgs& a0, const double* Q, const double* params,
                                uint8_t* troubled, int32_t* count, hipStream_t st) {
     KArgs a = a0;
-    a.nblocks = blocks(a);
-    hipLaunchKernelGGL((admissible_kernel<PDE, N>), dim3(a.nblocks), dim3(G::BLOCK), 0, st, a, Q,
-                       params, troubled, count);
+    a.nblocks = blocks_b(a);
+    hipLaunchKernelGGL((admissible_kernel<PDE, N>), dim3(a.nblocks), dim3(GB::BLOCK), 0, st, a, Q,
+                       params, troubled);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, a.ipartial, a.nblocks, count);
     return hipGetLastError();
   }
   static const KernelSet* set() {
-    static const KernelSet ks = {G::BLOCK, G::CPB, &predict, &correct, &stable_dt, &admissible};
+    static const KernelSet ks = {GeoA<PDE, N, double>::BLOCK, GeoA<PDE, N, double>::CPB, GB::CPB, &predict, &correct, &stable_dt, &admissible};
     return &ks;
   }
 };
