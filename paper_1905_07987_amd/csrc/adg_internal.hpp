@@ -16,6 +16,8 @@ namespace adg {
 constexpr int kMaxN = 8;       // n = N + 1 points per axis
 constexpr int kMaxSources = 16;
 constexpr int kMaxVar = 16;
+constexpr int kSlots = 256;       // reduction slots
+constexpr int kSlotStride = 8;    // words between slots (64 bytes)
 
 // One-dimensional tables on [0, 1] (see adg_basis_tables).  KW = K1^{-1} W is
 // the time operator of the Picard update, invw = 1 / w.
@@ -54,17 +56,16 @@ struct KArgs {
   int nblocks;  // grid size of the cell kernels (for the block -> cell map)
   const SourceDev* src;
   const double* src_w;  // [nsrc][S][nvar]
-  // per-block partial results (workspace), one slot per block of the
-  // corrector / reduction kernels
-  double* partial;
-  int* ipartial;
+  // reduction slots (workspace, zero between uses): kSlots words, each on
+  // its own 64-byte line
+  unsigned long long* slots;
 };
 
 // Kernel entry points of one (PDE, dim, order) instantiation set.
 struct KernelSet {
   int block;  // threads per block of the predictor
   int cells_per_block;    // predictor
-  int cells_per_block_b;  // corrector and reductions (one partial slot per block)
+  int cells_per_block_b;  // corrector and reductions
   hipError_t (*predict)(const KArgs&, int precision, const double* Q, const double* params,
                         const double* clock, double* Qout, double* traces, hipStream_t);
   hipError_t (*correct)(const KArgs&, double* Q, const double* params, double* clock,

@@ -21,7 +21,7 @@ struct adg_ctx {
   KArgs args{};
   double* traces = nullptr;  // [C][2 dim][2][nv][F]
   size_t trace_elems = 0;
-  void* red = nullptr;       // per-block partials of the reductions
+  void* red = nullptr;       // reduction slots
   size_t red_bytes = 0;
   SourceDev* d_src = nullptr;
   double* d_src_w = nullptr;
@@ -226,21 +226,16 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
     delete x;
     return fail(ADG_ERR_NOMEM, std::string("trace workspace: ") + hipGetErrorString(e));
   }
-  {
-    const long long nb = (C + ks->cells_per_block_b - 1) / ks->cells_per_block_b;
-    e = hipMalloc(&x->red, (size_t)nb * (sizeof(double) + sizeof(int)) + 256);
-  }
+  x->red_bytes = sizeof(unsigned long long) * kSlots * kSlotStride;
+  e = hipMalloc(&x->red, x->red_bytes);
+  if (e == hipSuccess) e = hipMemset(x->red, 0, x->red_bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(x->traces);
     delete x;
-    return fail(ADG_ERR_NOMEM, std::string("reduction workspace: ") + hipGetErrorString(e));
+    return fail(ADG_ERR_NOMEM, std::string("reduction slots: ") + hipGetErrorString(e));
   }
-  {
-    const long long nb = (C + ks->cells_per_block_b - 1) / ks->cells_per_block_b;
-    a.partial = (double*)x->red;
-    a.ipartial = (int*)((char*)x->red + ((size_t)nb * sizeof(double) + 255) / 256 * 256);
-    x->red_bytes = (size_t)nb * (sizeof(double) + sizeof(int)) + 256;
-  }
+  a.slots = (unsigned long long*)x->red;
   a.nsrc = 0;
   a.src = nullptr;
   a.src_w = nullptr;

@@ -85,7 +85,7 @@ struct Chan {
   }
 };
 
-// Predictor layout.  Time slices are processed in pairs; the two slices of
+// Layout of the FP32 predictor (one thread per node).  Time slices are processed in pairs; the two slices of
 // a pair share one 16-byte LDS element per (channel, node), so every LDS
 // access of the iteration is 128-bit wide.  Cells per block: ~256 lanes,
 // limited so the block's LDS stays within 64 KiB.
@@ -95,7 +95,7 @@ struct alignas(2 * sizeof(R)) Pair {
 };
 
 template <class PDE, int N, class R>
-struct GeoA {
+struct GeoA1 {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
   static constexpr int ITER_ELEMS = C::NCH * G::SP * 2;          // per cell, in R
@@ -107,14 +107,50 @@ struct GeoA {
   static constexpr int BLOCK = CPB * G::S;
   static constexpr int ELEMS = CPB * CELL_ELEMS;
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
-  // Occupancy target (waves per SIMD) handed to the register allocator.  At
-  // FP64 the unconstrained kernel takes more than 256 registers (one wave per
-  // SIMD); bounding it at two waves costs only a few rarely used values
-  // parked in scratch, and doubles the waves that hide LDS and barrier
-  // latency.  FP32 values take half the registers, so three waves fit.
-  static constexpr int MIN_WAVES = sizeof(R) == 8 ? 2 : 3;
+  // Occupancy target (waves per SIMD) handed to the register allocator:
+  // three 4-wave blocks per CU at FP32.
+  static constexpr int MIN_WAVES = 3;
   static_assert(ELEMS * (int)sizeof(R) <= 64 * 1024, "predictor LDS exceeds 64 KiB");
 };
+
+// Layout of the FP64 predictor (two threads per node).  A lane pair shares each spatial node; the
+// even lane owns time slices 0..H-1 and the odd lane slices H..n-1
+// (H = ceil(n/2)).  A chunk step handles one slice per lane, i.e. the slice
+// pair (c, H+c) of every node, and the two slices share one 16-byte LDS
+// element per (channel, node), so the line tasks use 128-bit LDS accesses.
+// Cells per block: up to 512 lanes, limited so the block's LDS stays within
+// 64 KiB.
+template <class PDE, int N, class R>
+struct GeoA2 {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  static constexpr int H = (G::n + 1) / 2;                       // slices per lane
+  static constexpr int TPC = 2 * G::S;                           // threads per cell
+  static constexpr int ITER_ELEMS = C::NCH * G::SP * 2;          // per cell, in R
+  static constexpr int FIN_ELEMS = (G::NV + C::NFLUX) * G::SP;   // per cell, in R
+  static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
+  static constexpr int by_threads = TPC >= 512 ? 1 : 512 / TPC;
+  static constexpr int by_lds = cmax(1, (64 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * TPC;
+  static constexpr int ELEMS = CPB * CELL_ELEMS;
+  static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
+  static_assert(ELEMS * (int)sizeof(R) <= 64 * 1024, "predictor LDS exceeds 64 KiB");
+  // Occupancy target (waves per SIMD) handed to the register allocator: half
+  // the time history per lane keeps the FP64 kernel within 256 registers at
+  // two waves per SIMD without spilling (one thread per node needs ~320).
+  static constexpr int MIN_WAVES = 2;
+};
+
+// Exchange a value with the other lane of the pair (lanes 2k and 2k+1).
+__device__ __forceinline__ double pair_swap(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
 
 // Compile-time one-dimensional tables of order n in precision R (generated at
 // build time from the same host construction as adg_basis_tables); every use
@@ -173,6 +209,14 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return m;
 }
 
+// Reductions over blocks go through kSlots slots kSlotStride words apart
+// (one 64-byte line each): block b folds its maximum into slot b % kSlots
+// with an atomic max on the bit pattern (ordered like the value for
+// non-negative doubles), so contention per address stays low.
+__device__ __forceinline__ void slot_max(unsigned long long* slots, int b, double m) {
+  atomicMax(slots + (b % kSlots) * kSlotStride, (unsigned long long)__double_as_longlong(m));
+}
+
 // true if local cell c of block b exists (ragged last block)
 __device__ __forceinline__ bool cell0_valid(const KArgs& a, int b, int cpb, int c) {
   return (long long)xcd_block(b, a.nblocks) * cpb + c < a.ncells;
@@ -186,17 +230,17 @@ __device__ __forceinline__ double ricker(double f0, double t0, double amp, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Kernel A: predictor, time averages, volume term and face projection.
+// Kernel A, one thread per node (used for the FP32 predictor).
 // ---------------------------------------------------------------------------
 template <class PDE, int N, class R>
-__global__ void __launch_bounds__((GeoA<PDE, N, R>::BLOCK), (GeoA<PDE, N, R>::MIN_WAVES))
-predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params,
+__global__ void __launch_bounds__((GeoA1<PDE, N, R>::BLOCK), (GeoA1<PDE, N, R>::MIN_WAVES))
+predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ params,
                const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
   // Q and Qout may be the same array (in-place step): each element is read
   // once at the start and written once at the end by the same thread.
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  using GA = GeoA<PDE, N, R>;
+  using GA = GeoA1<PDE, N, R>;
   using T = CT<R, G::n>;
   using P2 = Pair<R>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
@@ -540,6 +584,389 @@ predict_kernel(const KArgs a, const double* Q, const double* __restrict__ params
 }
 
 // ---------------------------------------------------------------------------
+// Kernel A, a lane pair per node (used for the FP64 predictor).
+// ---------------------------------------------------------------------------
+template <class PDE, int N, class R>
+__global__ void __launch_bounds__((GeoA2<PDE, N, R>::BLOCK), (GeoA2<PDE, N, R>::MIN_WAVES))
+predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ params,
+               const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // Q and Qout may be the same array (in-place step): each element is read
+  // at the start and written at the end by the even lane of its node.
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  using GA = GeoA2<PDE, N, R>;
+  using T = CT<R, G::n>;
+  using P2 = Pair<R>;
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK, SP = G::SP, H = GA::H, TPC = GA::TPC;
+  constexpr int NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
+  static_assert(C::uniform(), "flux sparsity must be the same in every direction");
+  __shared__ P2 lds2[GA::ELEMS / 2];
+  R* const lds = reinterpret_cast<R*>(lds2);
+
+  const int tid = threadIdx.x;
+  const int lc = tid / TPC;
+  const int rr = tid - lc * TPC;
+  const int k = rr >> 1;   // spatial node
+  const int h = rr & 1;    // time half owned by this lane
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+
+  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  {
+    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * G::LS + kd[d];
+  }
+
+  double u64[NV];
+  R u[NV], P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    u64[v] = Q[(cl * NV + v) * S + k];
+    u[v] = R(u64[v]);
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
+  const double t_n = clock[0], dt64 = clock[1];
+  const R dt = R(dt64);
+  R inv_h[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
+
+  // Per-lane coefficients of the time operator for the output slices this
+  // lane owns (i = h H + il): Kown over its own slices, Kpar over the
+  // partner's, zero where a slice index reaches n (odd n).
+  // Per-lane coefficients of the time operator for the output slices this
+  // lane owns (i = h H + il): Kown over its own slices, Kpar over the
+  // partner's, zero where a slice index reaches n (odd n).  One LDS table per
+  // half, read by broadcast.
+  auto kw = [](int i, int j) { return (i < n && j < n) ? T::KW(i, j) : R(0); };
+  __shared__ R ktab[2][2 * H * H + H];
+  if (tid < 2) {
+    const int hh = tid;
+#pragma unroll
+    for (int il = 0; il < H; ++il)
+#pragma unroll
+      for (int c = 0; c < H; ++c) {
+        ktab[hh][il * H + c] = hh ? kw(H + il, H + c) : kw(il, c);
+        ktab[hh][H * H + il * H + c] = hh ? kw(H + il, c) : kw(il, H + c);
+      }
+#pragma unroll
+    for (int c = 0; c < H; ++c) ktab[hh][2 * H * H + c] = hh ? (H + c < n ? T::w(H + c) : R(0)) : T::w(c);
+  }
+  const R* const kt = ktab[h];
+  auto Kown = [&](int il, int c) { return kt[il * H + c]; };
+  auto Kpar = [&](int il, int c) { return kt[H * H + il * H + c]; };
+  auto wown = [&](int c) { return kt[2 * H * H + c]; };
+
+  // Point sources: the Ricker amplitude at the n time nodes of this step is
+  // evaluated once per block; only blocks holding a source cell use them.
+  __shared__ double src_amp[kMaxSources * n];
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc * n) {
+    const int s = tid / n, j = tid - s * n;
+    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt64);
+  }
+  // (made visible by the first barrier below)
+
+  // point-source term of slice j at this node, added to Sv
+  auto add_point_sources = [&](int j, R* Sv) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const R amp = R(src_amp[s * n + j]);
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sv[v] += amp * R(wsk[v]);
+    }
+  };
+
+  P2* const mine = lds2 + lc * (GA::CELL_ELEMS / 2);  // this cell's pairs [NCH][SP]
+  R* const mine_h = reinterpret_cast<R*>(mine) + h;   // this lane's half of each pair
+  R q[H][NV];     // current iterate at the slices this lane owns
+  R Fbar[DIM][NV], Nbar[NV], Sbar[NV];  // final pass: time averages (own slices)
+
+  // One pass over the time slices of the current iterate; chunk step c
+  // handles slice hH + c on this lane.
+  //  KIND 0: first Picard step.  q^0 = u^n at every time node, so every slice
+  //          has the same right-hand side apart from point sources; one
+  //          chunk step suffices.
+  //  KIND 1: Picard step; R_j replaces q_j, which is no longer needed.
+  //  KIND 2: final pass at the last iterate: time averages of F, B grad q
+  //          and S over the lane's slices (READING: the averaged terms use the
+  //          final iterate).
+  R R0[NV];  // KIND 0 right-hand side
+  auto pass = [&](auto kind_tag) {
+    constexpr int KIND = decltype(kind_tag)::value;
+    constexpr bool FIN = KIND == 2;
+    constexpr bool USE_LDS = !FIN || PDE::kHasNcp;
+    constexpr int STEPS = KIND == 0 ? 1 : H;
+#pragma unroll
+    for (int c = 0; c < STEPS; ++c) {
+      const int j = h * H + c;
+      const bool valid = j < n;
+      // (1) flux and gradient inputs of slice j -> this lane's half of the pairs
+      R Fl[DIM][NV];
+      PDE::fluxes(q[c], P, a.pde, Fl);
+      if constexpr (FIN) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fbar[d][v] += wown(c) * Fl[d][v];
+      }
+      if constexpr (USE_LDS) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if constexpr (!FIN) {
+#pragma unroll
+            for (int cc = 0; cc < NFL; ++cc)
+              mine_h[2 * ((d * NCHD + cc) * SP + pk[d])] = Fl[d][C::flux_var(d, cc)];
+          }
+#pragma unroll
+          for (int cc = 0; cc < NGR; ++cc)
+            mine_h[2 * ((d * NCHD + NFL + cc) * SP + pk[d])] = q[c][C::grad_var(cc)];
+        }
+        __syncthreads();
+        // (2) line tasks (cell, direction, channel, line): differentiate both
+        //     slices of the pair in place
+        constexpr int CH0 = FIN ? NFL : 0;  // the final pass only needs gradients
+        constexpr int NCT = NCHD - CH0;
+        for (int task = tid; task < CPB * DIM * NCT * F; task += BLOCK) {
+          const int l = task % F;
+          const int ch = CH0 + (task / F) % NCT;
+          const int d = (task / (F * NCT)) % DIM;
+          const int c2 = task / (F * NCT * DIM);
+          P2* row = lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
+          const R s = inv_h[d];
+          P2 x[n];
+#pragma unroll
+          for (int m = 0; m < n; ++m) x[m] = row[m];
+#pragma unroll
+          for (int i = 0; i < n; ++i) {
+            R y0 = R(0), y1 = R(0);
+#pragma unroll
+            for (int m = 0; m < n; ++m) {
+              y0 += T::D(i, m) * x[m].x;
+              y1 += T::D(i, m) * x[m].y;
+            }
+            row[i] = P2{y0 * s, y1 * s};
+          }
+        }
+        __syncthreads();
+      }
+      // (3) right-hand side of slice j at this node
+      R divF[NV], g[DIM][NV], B[NV], Sv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        divF[v] = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) g[d][v] = R(0);
+      }
+      if constexpr (USE_LDS) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if constexpr (!FIN) {
+#pragma unroll
+            for (int cc = 0; cc < NFL; ++cc)
+              divF[C::flux_var(d, cc)] += mine_h[2 * ((d * NCHD + cc) * SP + pk[d])];
+          }
+#pragma unroll
+          for (int cc = 0; cc < NGR; ++cc)
+            g[d][C::grad_var(cc)] = mine_h[2 * ((d * NCHD + NFL + cc) * SP + pk[d])];
+        }
+      }
+      if constexpr (PDE::kHasNcp) {
+        PDE::ncp(q[c], P, a.pde, g, B);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) B[v] = R(0);
+      }
+      PDE::source(q[c], P, a.pde, Sv);
+      if constexpr (KIND == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R0[v] = Sv[v] - divF[v] - B[v];
+      } else {
+        if (valid) add_point_sources(j, Sv);
+        if constexpr (KIND == 1) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) q[c][v] = valid ? Sv[v] - divF[v] - B[v] : R(0);
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            Nbar[v] += wown(c) * B[v];
+            Sbar[v] += wown(c) * Sv[v];
+          }
+        }
+      }
+      if constexpr (USE_LDS) __syncthreads();
+    }
+  };
+
+  // q^{r+1}_i = u + dt sum_j KW_ij R_j for the lane's own i, with R_j of the
+  // own slices in q and those of the partner exchanged across the pair.
+  auto update = [&]() {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R Rp[H], t[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c) Rp[c] = pair_swap(q[c][v]);
+#pragma unroll
+      for (int il = 0; il < H; ++il) {
+        R s = R(0);
+#pragma unroll
+        for (int c = 0; c < H; ++c) s += Kown(il, c) * q[c][v] + Kpar(il, c) * Rp[c];
+        t[il] = s;
+      }
+#pragma unroll
+      for (int il = 0; il < H; ++il) q[il][v] = u[v] + dt * t[il];
+    }
+  };
+
+  const int I = a.picard_iters;
+#pragma unroll
+  for (int c = 0; c < H; ++c)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[c][v] = u[v];
+  for (int r = 0; r < I; ++r) {
+    if (r == 0) {
+      pass(std::integral_constant<int, 0>{});
+      // every slice has R0 (+ its point sources)
+#pragma unroll
+      for (int c = 0; c < H; ++c) {
+        const int j = h * H + c;
+        R Sp[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Sp[v] = R(0);
+        if (j < n) add_point_sources(j, Sp);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[c][v] = j < n ? R0[v] + Sp[v] : R(0);
+      }
+    } else {
+      pass(std::integral_constant<int, 1>{});
+    }
+    update();
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    Nbar[v] = Sbar[v] = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fbar[d][v] = R(0);
+  }
+  pass(std::integral_constant<int, 2>{});
+
+  // time averages: own half plus the partner's half
+  R qbar[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    R s = R(0);
+#pragma unroll
+    for (int c = 0; c < H; ++c) s += wown(c) * q[c][v];
+    qbar[v] = s + pair_swap(s);
+    Nbar[v] += pair_swap(Nbar[v]);
+    Sbar[v] += pair_swap(Sbar[v]);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fbar[d][v] += pair_swap(Fbar[d][v]);
+  }
+
+  // Volume term and face projection, one direction at a time.  Region A of
+  // the cell's LDS holds qbar (NV rows), region B the nonzero components of
+  // Fbar_d (NFL rows); the even lane of each node writes them.
+  R divF[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) divF[v] = R(0);
+  R* const fin_mine = lds + lc * GA::CELL_ELEMS;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (h == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fin_mine[v * SP + pk[d]] = qbar[v];
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) fin_mine[(NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
+    }
+    __syncthreads();
+    for (int task = tid; task < CPB * F * (NFL + 1); task += BLOCK) {
+      // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
+      const int l = task % F;
+      const int kind = (task / F) % (NFL + 1);
+      const int c2 = task / (F * (NFL + 1));
+      const long long tcell = cell0 + c2;
+      R* rows = lds + c2 * GA::CELL_ELEMS + l * G::LS;
+      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
+      const bool tact = tcell < a.ncells;
+      if (kind == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          R e0 = R(0), e1 = R(0);
+#pragma unroll
+          for (int m = 0; m < n; ++m) {
+            const R x = rows[v * SP + m];
+            e0 += T::l0(m) * x;
+            e1 += T::l1(m) * x;
+          }
+          if (tact) {
+            tr[(0 * NV + v) * F + l] = double(e0);  // face 2d,   state
+            tr[(2 * NV + v) * F + l] = double(e1);  // face 2d+1, state
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (!PDE::flux_nonzero(d, v) && tact) {
+            tr[(1 * NV + v) * F + l] = 0.0;
+            tr[(3 * NV + v) * F + l] = 0.0;
+          }
+        }
+      } else {
+        // normal-flux traces; derivative of Fbar_d in place
+#pragma unroll
+        for (int cc = 0; cc < NFL; ++cc) {
+          if (cc != kind - 1) continue;
+          const int v = C::flux_var(d, cc);
+          R x[n];
+#pragma unroll
+          for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
+          R e0 = R(0), e1 = R(0);
+#pragma unroll
+          for (int m = 0; m < n; ++m) {
+            e0 += T::l0(m) * x[m];
+            e1 += T::l1(m) * x[m];
+          }
+          if (tact) {
+            tr[(1 * NV + v) * F + l] = double(e0);
+            tr[(3 * NV + v) * F + l] = double(e1);
+          }
+          const R s = inv_h[d];
+#pragma unroll
+          for (int i = 0; i < n; ++i) {
+            R y = R(0);
+#pragma unroll
+            for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
+            rows[(NV + cc) * SP + i] = y * s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[(NV + cc) * SP + pk[d]];
+    __syncthreads();
+  }
+
+  if (active && h == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const R vol = dt * (Sbar[v] - divF[v] - Nbar[v]);
+      Qout[(cell * NV + v) * S + k] = u64[v] + double(vol);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel B: Rusanov flux on every face of the cell, surface integral and
 // update; optionally the per-block Eq. (7) maximum of the new state (reduced
 // over blocks by finalize_kernel, which also advances the clock).
@@ -669,7 +1096,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
   }
   if (next_dt) {
     const double m = block_max<BLOCK>(lam, red);
-    if (tid == 0) a.partial[blockIdx.x] = m;
+    if (tid == 0) slot_max(a.slots, blockIdx.x, m);
   }
 }
 
@@ -697,22 +1124,25 @@ lambda_kernel(const KArgs a, const double* __restrict__ Q, const double* __restr
     for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(q, P, a.pde, d));
   }
   const double m = block_max<GB::BLOCK>(lam, red);
-  if (tid == 0) a.partial[blockIdx.x] = m;
+  if (tid == 0) slot_max(a.slots, blockIdx.x, m);
 }
 
 namespace {  // one copy per translation unit
 
-// One block folds the per-block partials and updates the clock {t, dt}:
-// mode & 1: dt <- dt_factor / max(partial)      (Eq. (7))
+// One block folds the reduction slots, clears them for the next use, and
+// updates the clock {t, dt}:
+// mode & 1: dt <- dt_factor / max(slots)      (Eq. (7))
 // mode & 2: t <- t + dt (the dt the step used, read before it is replaced)
-__global__ void __launch_bounds__(256)
-finalize_kernel(const double* __restrict__ partial, int nparts, double dt_factor, int mode,
+__global__ void __launch_bounds__(kSlots)
+finalize_kernel(unsigned long long* __restrict__ slots, double dt_factor, int mode,
                 double* __restrict__ clock) {
-  __shared__ double red[256];
+  __shared__ double red[kSlots];
   double m = 0.0;
-  if (mode & 1)
-    for (int i = threadIdx.x; i < nparts; i += 256) m = fmax(m, partial[i]);
-  m = block_max<256>(m, red);
+  if (mode & 1) {
+    m = __longlong_as_double((long long)slots[threadIdx.x * kSlotStride]);
+    slots[threadIdx.x * kSlotStride] = 0ull;
+  }
+  m = block_max<kSlots>(m, red);
   if (threadIdx.x == 0) {
     const double dt_used = clock[1];
     if (mode & 2) clock[0] = clock[0] + dt_used;
@@ -752,20 +1182,20 @@ admissible_kernel(const KArgs a, const double* __restrict__ Q, const double* __r
   if (tid == 0) {
     int cnt = 0;
     for (int c = 0; c < CPB; ++c) cnt += (cell0_valid(a, blockIdx.x, CPB, c) ? bad[c] : 0);
-    a.ipartial[blockIdx.x] = cnt;
+    if (cnt) atomicAdd(reinterpret_cast<int*>(a.slots + (blockIdx.x % kSlots) * kSlotStride), cnt);
   }
 }
 
 namespace {
 
-__global__ void __launch_bounds__(256)
-count_kernel(const int* __restrict__ partial, int nparts, int32_t* __restrict__ count) {
-  __shared__ int red[256];
-  int s = 0;
-  for (int i = threadIdx.x; i < nparts; i += 256) s += partial[i];
-  red[threadIdx.x] = s;
+__global__ void __launch_bounds__(kSlots)
+count_kernel(unsigned long long* __restrict__ slots, int32_t* __restrict__ count) {
+  __shared__ int red[kSlots];
+  int* const sl = reinterpret_cast<int*>(slots + threadIdx.x * kSlotStride);
+  red[threadIdx.x] = *sl;
+  *sl = 0;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = kSlots / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
@@ -781,9 +1211,9 @@ template <class PDE, int N>
 struct Launch {
   using G = Geo<PDE, N>;
   using GB = GeoB<PDE, N>;
-  template <class R>
+  template <class GA>
   static int blocks_a(const KArgs& a) {
-    return (int)((a.ncells + GeoA<PDE, N, R>::CPB - 1) / GeoA<PDE, N, R>::CPB);
+    return (int)((a.ncells + GA::CPB - 1) / GA::CPB);
   }
   static int blocks_b(const KArgs& a) { return (int)((a.ncells + GB::CPB - 1) / GB::CPB); }
 
@@ -791,13 +1221,15 @@ struct Launch {
                             const double* clock, double* Qout, double* traces, hipStream_t st) {
     KArgs a = a0;
     if (precision == ADG_MIXED_FP32) {
-      a.nblocks = blocks_a<float>(a);
-      hipLaunchKernelGGL((predict_kernel<PDE, N, float>), dim3(a.nblocks),
-                         dim3(GeoA<PDE, N, float>::BLOCK), 0, st, a, Q, params, clock, Qout, traces);
+      using GA = GeoA1<PDE, N, float>;
+      a.nblocks = blocks_a<GA>(a);
+      hipLaunchKernelGGL((predict_kernel_node<PDE, N, float>), dim3(a.nblocks), dim3(GA::BLOCK), 0,
+                         st, a, Q, params, clock, Qout, traces);
     } else {
-      a.nblocks = blocks_a<double>(a);
-      hipLaunchKernelGGL((predict_kernel<PDE, N, double>), dim3(a.nblocks),
-                         dim3(GeoA<PDE, N, double>::BLOCK), 0, st, a, Q, params, clock, Qout, traces);
+      using GA = GeoA2<PDE, N, double>;
+      a.nblocks = blocks_a<GA>(a);
+      hipLaunchKernelGGL((predict_kernel_pair<PDE, N, double>), dim3(a.nblocks), dim3(GA::BLOCK), 0,
+                         st, a, Q, params, clock, Qout, traces);
     }
     return hipGetLastError();
   }
@@ -809,7 +1241,7 @@ struct Launch {
                        params, clock, traces, next_dt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, a.partial, a.nblocks, a.dt_factor,
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor,
                        next_dt ? 3 : 2, clock);
     return hipGetLastError();
   }
@@ -820,8 +1252,7 @@ struct Launch {
     hipLaunchKernelGGL((lambda_kernel<PDE, N>), dim3(a.nblocks), dim3(GB::BLOCK), 0, st, a, Q, params);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, a.partial, a.nblocks, a.dt_factor, 1,
-                       clock);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor, 1, clock);
     return hipGetLastError();
   }
   static hipError_t admissible(const KArgs& a0, const double* Q, const double* params,
@@ -832,11 +1263,11 @@ struct Launch {
                        params, troubled);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, a.ipartial, a.nblocks, count);
+    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, count);
     return hipGetLastError();
   }
   static const KernelSet* set() {
-    static const KernelSet ks = {GeoA<PDE, N, double>::BLOCK, GeoA<PDE, N, double>::CPB, GB::CPB, &predict, &correct, &stable_dt, &admissible};
+    static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB, &predict, &correct, &stable_dt, &admissible};
     return &ks;
   }
 };
