@@ -132,6 +132,8 @@ def lib():
         L.orc_cell_traces.argtypes = [pp, C.c_long, dp, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_sample_receivers.argtypes = [pp, C.c_int, dp, dp, dp]
         L.orc_check_admissible.argtypes = [pp, dp, dp, C.POINTER(C.c_ubyte), C.POINTER(C.c_int)]
+        L.orc_step_adjoint.argtypes = [pp, dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_sample_receivers_T.argtypes = [pp, C.c_int, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -285,3 +287,80 @@ def run(P: Problem, Q, params=None, steps: int = 1, t0: float = 0.0, dt_fixed=No
         Q = step(P, Q, params, dt, t)
         t += dt
     return Q, t
+
+
+def _xyz3(xyz):
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(len(xyz), -1)
+    if xyz.shape[1] < 3:
+        xyz = np.pad(xyz, ((0, 0), (0, 3 - xyz.shape[1])))
+    return np.ascontiguousarray(xyz)
+
+
+def step_adjoint(P: Problem, Q, params, dt: float, t: float, lam):
+    """Discrete adjoint of one step (linear PDEs, dt frozen): returns
+    (dJ/du^n, dJ/dm of this step) for lam = dJ/du^{n+1}."""
+    Q = _arr(Q)
+    lam_n = _arr(lam).copy()
+    g = np.zeros((P.ncells, max(P.nparam, 1)))
+    _check(lib().orc_step_adjoint(C.byref(P), _p(Q), _p(_params(P, params)), dt, t, _p(lam_n),
+                                  _p(g) if P.nparam else None), "step_adjoint")
+    return lam_n, (g if P.nparam else None)
+
+
+def sample_receivers_T(P: Problem, xyz, lamrec, lam):
+    """lam += transpose of receiver sampling applied to lamrec [nrec][nvar]."""
+    xyz = _xyz3(xyz)
+    lamrec = _arr(lamrec)
+    _check(lib().orc_sample_receivers_T(C.byref(P), len(xyz), _p(xyz), _p(lamrec), _p(lam)), "receivers_T")
+    return lam
+
+
+def seismogram_misfit(P: Problem, u0, params, dt: float, steps: int, rec_xyz, data=None):
+    """J = 1/2 sum_{n=1..steps} dt sum_r sum_c (v^n_rc - d^n_rc)^2 with v the
+    particle velocity (rho v)/rho of the receiver's cell, sampled after every
+    step with a frozen dt.  Returns (J, seismograms [steps][R][3], states)."""
+    rec_xyz = _xyz3(rec_xyz)
+    cells = _receiver_cells(P, rec_xyz)
+    Q = _arr(u0).copy()
+    states = [Q.copy()]
+    seis = []
+    t = 0.0
+    for n in range(steps):
+        Q = step(P, Q, params, dt, t)
+        t += dt
+        states.append(Q.copy())
+        samp = sample_receivers(P, rec_xyz, Q)
+        seis.append(samp[:, 6:9] / params[cells, 0:1])
+    seis = np.array(seis)
+    J = 0.0 if data is None else 0.5 * dt * float(((seis - data) ** 2).sum())
+    return J, seis, states
+
+
+def _receiver_cells(P, rec_xyz):
+    h = P.h
+    out = []
+    for x in rec_xyz:
+        cc = [int(np.floor((x[d] - P.lo[d]) / h[d])) for d in range(P.dim)]
+        c = cc[0] + P.cells[0] * (cc[1] + P.cells[1] * (cc[2] if P.dim == 3 else 0))
+        out.append(c)
+    return np.array(out)
+
+
+def misfit_gradient(P: Problem, u0, params, dt: float, steps: int, rec_xyz, data):
+    """J and its gradients with respect to u0 and the per-cell parameters by
+    the discrete adjoint (every state kept in memory: small problems only)."""
+    rec_xyz = _xyz3(rec_xyz)
+    cells = _receiver_cells(P, rec_xyz)
+    J, seis, states = seismogram_misfit(P, u0, params, dt, steps, rec_xyz, data)
+    lam = np.zeros_like(states[0])
+    g = np.zeros_like(np.asarray(params, dtype=np.float64))
+    rho = params[cells, 0]
+    for n in range(steps, 0, -1):
+        r = dt * (seis[n - 1] - data[n - 1])          # dJ/dv^n  [R][3]
+        lamrec = np.zeros((len(rec_xyz), P.nvar))
+        lamrec[:, 6:9] = r / rho[:, None]
+        sample_receivers_T(P, rec_xyz, lamrec, lam)
+        np.add.at(g[:, 0], cells, -(r * seis[n - 1]).sum(axis=1) / rho)
+        lam, gs = step_adjoint(P, states[n - 1], params, dt, (n - 1) * dt, lam)
+        g += gs
+    return J, lam, g

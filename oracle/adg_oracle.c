@@ -1031,3 +1031,479 @@ int orc_check_admissible(const orc_problem *P, const double *Q, const double *pa
   *count = cnt;
   return ORC_OK;
 }
+
+/* ========================================================================
+ * 9. Discrete adjoint of one step, for the PDEs that are linear in Q
+ *    (elasticity, advection), with dt frozen.
+ *
+ *    The step maps (u^n, m) -> u^{n+1}, m the per-cell material parameters.
+ *    Given lam = dJ/du^{n+1} it returns dJ/du^n (in place) and adds
+ *    dJ/dm to gparams, by running the forward step of Sections 4-7 and then
+ *    every operation of it in reverse order, transposed.  All inner products
+ *    are the plain Euclidean ones over nodal arrays (a discrete adjoint).
+ *    READING: the derivative of max() in the Rusanov speed is split half and
+ *    half between the two sides on a tie; the step size is held fixed.
+ * ======================================================================== */
+static int pde_is_linear(const orc_problem *P) {
+  return P->pde == ORC_ELASTIC || P->pde == ORC_ADVECTION;
+}
+
+/* lamQ += (dF_d/dQ)^T lamF */
+static void flux_T(const orc_problem *P, int d, const double *lamF, double *lamQ) {
+  if (P->pde == ORC_ELASTIC) {
+    for (int i = 0; i < 3; ++i) lamQ[sym_index(i, d)] += lamF[6 + i];
+  } else if (P->pde == ORC_ADVECTION) {
+    lamQ[0] += P->adv[d] * lamF[0];
+  }
+}
+
+/* lamQ += (dS/dQ)^T lamS for the smooth source */
+static void source_T(const orc_problem *P, const double *lamS, double *lamQ) {
+  if (P->pde == ORC_ADVECTION) lamQ[0] += -P->kappa * lamS[0];
+}
+
+/* lamG += (dB/dgradQ)^T lamB, lamG is [dim][nq] */
+static void ncp_T(const orc_problem *P, const double *Q, const double *lamB, double *lamG) {
+  if (P->pde != ORC_ELASTIC) return;
+  int nq = P->nvar + P->nparam;
+  double rho = Q[9], cp = Q[10], cs = Q[11];
+  double mu = rho * cs * cs;
+  double lam = rho * cp * cp - 2.0 * mu;
+  double lg[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double ldiv = lam * (lamB[0] + lamB[1] + lamB[2]);
+  for (int i = 0; i < 3; ++i) lg[i][i] += 2.0 * mu * lamB[i] + ldiv;
+  lg[0][1] += mu * lamB[3];
+  lg[1][0] += mu * lamB[3];
+  lg[0][2] += mu * lamB[4];
+  lg[2][0] += mu * lamB[4];
+  lg[1][2] += mu * lamB[5];
+  lg[2][1] += mu * lamB[5];
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) lamG[d * nq + 6 + i] += lg[i][d] / rho;
+}
+
+/* gp[0..2] += (dB/d(rho, cp, cs))^T lamB, with B = ncp(Q, gradQ) */
+static void ncp_dparams_T(const orc_problem *P, const double *Q, const double *gradQ,
+                          const double *lamB, double *gp) {
+  if (P->pde != ORC_ELASTIC) return;
+  int nq = P->nvar + P->nparam;
+  double rho = Q[9], cp = Q[10], cs = Q[11];
+  double mu = rho * cs * cs;
+  double lam = rho * cp * cp - 2.0 * mu;
+  double g[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) g[i][d] = gradQ[d * nq + 6 + i] / rho;
+  double divv = g[0][0] + g[1][1] + g[2][2];
+  /* derivatives of (mu, lam, g) with respect to rho, cp, cs */
+  double dmu[3] = {cs * cs, 0.0, 2.0 * rho * cs};
+  double dlam[3] = {cp * cp - 2.0 * cs * cs, 2.0 * rho * cp, -4.0 * rho * cs};
+  double dgs[3] = {-1.0 / rho, 0.0, 0.0}; /* dg/dp = dgs * g */
+  for (int p = 0; p < 3; ++p) {
+    double dB[6];
+    for (int i = 0; i < 3; ++i)
+      dB[i] = 2.0 * dmu[p] * g[i][i] + dlam[p] * divv + dgs[p] * (2.0 * mu * g[i][i] + lam * divv);
+    dB[3] = dmu[p] * (g[0][1] + g[1][0]) + dgs[p] * mu * (g[0][1] + g[1][0]);
+    dB[4] = dmu[p] * (g[0][2] + g[2][0]) + dgs[p] * mu * (g[0][2] + g[2][0]);
+    dB[5] = dmu[p] * (g[1][2] + g[2][1]) + dgs[p] * mu * (g[1][2] + g[2][1]);
+    double s = 0.0;
+    for (int v = 0; v < 6; ++v) s += lamB[v] * dB[v];
+    gp[p] += s;
+  }
+}
+
+/* Reverse of rusanov() for one face node.  lamflL / lamflR are the adjoints
+ * of the two fluctuations; the adjoints of the traces of both sides and of
+ * the parameters of both sides are accumulated. */
+static void rusanov_T(const orc_problem *P, int d, const double *qL, const double *qR,
+                      const double *lamflL, const double *lamflR, double *lqL, double *lFL,
+                      double *lqR, double *lFR, double *gpL, double *gpR) {
+  int nv = P->nvar, nq = P->nvar + P->nparam;
+  double sL = pde_max_eigen(P, qL, d), sR = pde_max_eigen(P, qR, d);
+  double s = fmax(sL, sR);
+  double lamG[ORC_MAXQ], ld[ORC_MAXQ], lamBm[ORC_MAXQ];
+  double ls = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    lamG[v] = lamflL[v] - lamflR[v];
+    lFL[v] += -lamflL[v] + 0.5 * lamG[v];
+    lFR[v] += lamflR[v] + 0.5 * lamG[v];
+    ld[v] = -0.5 * s * lamG[v];
+    ls += -0.5 * (qR[v] - qL[v]) * lamG[v];
+    lamBm[v] = 0.5 * (lamflL[v] + lamflR[v]); /* Bmid = 0.5 * ncp(...) */
+  }
+  if (P->pde == ORC_ELASTIC) {
+    /* s = max(cp_L, cp_R) */
+    if (sL > sR) gpL[1] += ls;
+    else if (sR > sL) gpR[1] += ls;
+    else { gpL[1] += 0.5 * ls; gpR[1] += 0.5 * ls; }
+    double qm[ORC_MAXQ], grad[3 * ORC_MAXQ], lgrad[3 * ORC_MAXQ], gpm[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < nq; ++v) qm[v] = 0.5 * (qL[v] + qR[v]);
+    for (int a = 0; a < 3 * ORC_MAXQ; ++a) grad[a] = lgrad[a] = 0.0;
+    for (int v = 0; v < nv; ++v) grad[d * nq + v] = qR[v] - qL[v];
+    ncp_T(P, qm, lamBm, lgrad);
+    for (int v = 0; v < nv; ++v) ld[v] += lgrad[d * nq + v];
+    ncp_dparams_T(P, qm, grad, lamBm, gpm);
+    for (int p = 0; p < 3; ++p) {
+      gpL[p] += 0.5 * gpm[p];
+      gpR[p] += 0.5 * gpm[p];
+    }
+  }
+  for (int v = 0; v < nv; ++v) {
+    lqR[v] += ld[v];
+    lqL[v] -= ld[v];
+  }
+}
+
+/* Forward predictor of one cell that also keeps every iterate q^0..q^I. */
+static void predictor_history(const orc_problem *P, const mesh *M, const tables *T, long c,
+                              const double *Q, const double *params, double dt, double t,
+                              work *W, double *hist /*[I+1][n][S][nq]*/) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv, I = P->picard_iters;
+  size_t it_sz = (size_t)n * S * nq;
+  int cc[3];
+  cell_coords(P, c, cc);
+  double xlo[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < M->dim; ++d) xlo[d] = P->lo[d] + cc[d] * M->h[d];
+  for (int k = 0; k < S; ++k) {
+    for (int v = 0; v < nv; ++v) W->u[(size_t)k * nq + v] = Q[((size_t)c * nv + v) * S + k];
+    for (int p = 0; p < P->nparam; ++p) W->u[(size_t)k * nq + nv + p] = params[(size_t)c * P->nparam + p];
+  }
+  for (int j = 0; j < n; ++j) memcpy(&W->q[(size_t)j * S * nq], W->u, sizeof(double) * S * nq);
+  memcpy(hist, W->q, sizeof(double) * it_sz);
+  for (int r = 0; r < I; ++r) {
+    eval_terms(P, M, T, c, xlo, dt, t, W);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < S; ++k) {
+        double *qi = &W->qn[((size_t)i * S + k) * nq];
+        for (int v = 0; v < nv; ++v) {
+          double acc = 0.0;
+          for (int j = 0; j < n; ++j)
+            acc += T->K1inv[i][j] *
+                   (T->l0[j] * W->u[(size_t)k * nq + v] + dt * T->w[j] * W->R[((size_t)j * S + k) * nv + v]);
+          qi[v] = acc;
+        }
+        for (int p = 0; p < P->nparam; ++p) qi[nv + p] = W->u[(size_t)k * nq + nv + p];
+      }
+    double *tmp = W->q;
+    W->q = W->qn;
+    W->qn = tmp;
+    memcpy(&hist[(size_t)(r + 1) * it_sz], W->q, sizeof(double) * it_sz);
+  }
+}
+
+/* gradient of one time slice of an iterate: grad[k][d][nq] (evolved only) */
+static void slice_gradient(const mesh *M, const tables *T, const double *qs /*[S][nq]*/, double *grad) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv, dim = M->dim;
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    double *g = &grad[(size_t)k * dim * nq];
+    for (int a = 0; a < dim * nq; ++a) g[a] = 0.0;
+    for (int d = 0; d < dim; ++d) {
+      for (int m = 0; m < n; ++m) {
+        int km = k + (m - kk[d]) * M->stride[d];
+        for (int v = 0; v < nv; ++v) g[d * nq + v] += T->D[kk[d]][m] * qs[(size_t)km * nq + v];
+      }
+      for (int v = 0; v < nv; ++v) g[d * nq + v] /= M->h[d];
+    }
+  }
+}
+
+/* Reverse of R(q_j) = -div F(q_j) - B(q_j) grad q_j + S(q_j) for one slice:
+ * lamR [S][nv] -> lamq [S][nq] (+=), gp (+=, the cell's parameters). */
+static void rhs_T(const orc_problem *P, const mesh *M, const tables *T, const double *qs,
+                  const double *lamR, double *lamq, double *gp) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv, dim = M->dim;
+  double *grad = malloc(sizeof(double) * S * dim * nq);
+  double *lamF = calloc((size_t)dim * S * nv, sizeof(double));
+  double *lamG = calloc((size_t)S * dim * nq, sizeof(double));
+  slice_gradient(M, T, qs, grad);
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    const double *lr = &lamR[(size_t)k * nv];
+    /* -div F: divF[k] = sum_d (1/h_d) sum_m D[k_d][m] F_d(q_km) */
+    for (int d = 0; d < dim; ++d)
+      for (int m = 0; m < n; ++m) {
+        int km = k + (m - kk[d]) * M->stride[d];
+        for (int v = 0; v < nv; ++v)
+          lamF[((size_t)d * S + km) * nv + v] += -T->D[kk[d]][m] * lr[v] / M->h[d];
+      }
+    /* -B grad q */
+    double lamB[ORC_MAXQ];
+    for (int v = 0; v < nv; ++v) lamB[v] = -lr[v];
+    ncp_T(P, &qs[(size_t)k * nq], lamB, &lamG[(size_t)k * dim * nq]);
+    if (gp) ncp_dparams_T(P, &qs[(size_t)k * nq], &grad[(size_t)k * dim * nq], lamB, gp);
+    /* + S(q) */
+    source_T(P, lr, &lamq[(size_t)k * nq]);
+  }
+  /* transpose of the flux evaluation */
+  for (int d = 0; d < dim; ++d)
+    for (int k = 0; k < S; ++k) flux_T(P, d, &lamF[((size_t)d * S + k) * nv], &lamq[(size_t)k * nq]);
+  /* transpose of the gradient: g[k][d] = (1/h_d) sum_m D[k_d][m] q(k:k_d<-m) */
+  for (int k = 0; k < S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    for (int d = 0; d < dim; ++d)
+      for (int m = 0; m < n; ++m) {
+        int km = k + (m - kk[d]) * M->stride[d];
+        for (int v = 0; v < nv; ++v)
+          lamq[(size_t)km * nq + v] += T->D[kk[d]][m] * lamG[((size_t)k * dim + d) * nq + v] / M->h[d];
+      }
+  }
+  free(grad);
+  free(lamF);
+  free(lamG);
+}
+
+int orc_step_adjoint(const orc_problem *P, const double *Q, const double *params, double dt,
+                     double t, double *lam, double *gparams) {
+  mesh M;
+  tables T;
+  if (!pde_is_linear(P) || make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  const int n = M.n, S = M.S, nv = M.nv, nq = M.nq, F = M.F, dim = M.dim, I = P->picard_iters;
+  const size_t face_all = (size_t)2 * dim * F * nv;
+  const long C = M.C;
+  const int np = P->nparam;
+  /* 1. forward traces of every cell */
+  double *qhat = malloc(sizeof(double) * C * face_all);
+  double *Fhat = malloc(sizeof(double) * C * face_all);
+  double *lamfl = calloc(C * face_all, sizeof(double));
+  double *lqh = calloc(C * face_all, sizeof(double));
+  double *lFh = calloc(C * face_all, sizeof(double));
+  double *lam_out = malloc(sizeof(double) * C * nv * S);
+  if (!qhat || !Fhat || !lamfl || !lqh || !lFh || !lam_out) return ORC_ENOMEM;
+#pragma omp parallel
+  {
+    work W;
+    work_alloc(&M, &W);
+    double *vol = malloc(sizeof(double) * S * nv);
+#pragma omp for schedule(dynamic, 4)
+    for (long c = 0; c < C; ++c)
+      predict_and_project(P, &M, &T, c, Q, params, dt, t, &W, vol, NULL, &qhat[c * face_all],
+                          &Fhat[c * face_all]);
+    free(vol);
+    work_free(&W);
+  }
+  /* 2. adjoints of the fluctuations each cell uses:
+   *    u^{n+1}_k = u_k + vol_k - dt sum_d (l1 fl_hi + l0 fl_lo) / (h_d w_{k_d}) */
+  for (long c = 0; c < C; ++c)
+    for (int k = 0; k < S; ++k) {
+      int kk[3];
+      node_index(&M, k, kk);
+      for (int d = 0; d < dim; ++d) {
+        int f = face_node(&M, d, kk);
+        for (int v = 0; v < nv; ++v) {
+          double l = lam[((size_t)c * nv + v) * S + k];
+          double sc = -dt / (M.h[d] * T.w[kk[d]]);
+          lamfl[c * face_all + (size_t)(2 * d + 1) * F * nv + (size_t)f * nv + v] += sc * T.l1[kk[d]] * l;
+          lamfl[c * face_all + (size_t)(2 * d + 0) * F * nv + (size_t)f * nv + v] += sc * T.l0[kk[d]] * l;
+        }
+      }
+    }
+  /* 3. Rusanov in reverse: each cell collects the adjoints of its own traces
+   *    and parameters from both fluctuations of each of its faces */
+  for (long c = 0; c < C; ++c) {
+    for (int d = 0; d < dim; ++d)
+      for (int side = 0; side < 2; ++side) {
+        long nb = neighbour(P, c, d, side ? 1 : -1);
+        long cl = side ? c : nb, cr = side ? nb : c;
+        const double *qhL = &qhat[cl * face_all + (size_t)(2 * d + 1) * F * nv];
+        const double *qhR = &qhat[cr * face_all + (size_t)(2 * d + 0) * F * nv];
+        const double *lfL = &lamfl[cl * face_all + (size_t)(2 * d + 1) * F * nv];
+        const double *lfR = &lamfl[cr * face_all + (size_t)(2 * d + 0) * F * nv];
+        for (int f = 0; f < F; ++f) {
+          double qL[ORC_MAXQ], qR[ORC_MAXQ], lqL[ORC_MAXQ] = {0}, lqR[ORC_MAXQ] = {0};
+          double lFL[ORC_MAXQ] = {0}, lFR[ORC_MAXQ] = {0}, gpL[3] = {0, 0, 0}, gpR[3] = {0, 0, 0};
+          for (int v = 0; v < nv; ++v) {
+            qL[v] = qhL[(size_t)f * nv + v];
+            qR[v] = qhR[(size_t)f * nv + v];
+          }
+          for (int p = 0; p < np; ++p) {
+            qL[nv + p] = params[(size_t)cl * np + p];
+            qR[nv + p] = params[(size_t)cr * np + p];
+          }
+          rusanov_T(P, d, qL, qR, &lfL[(size_t)f * nv], &lfR[(size_t)f * nv], lqL, lFL, lqR, lFR, gpL, gpR);
+          double *oq = &lqh[c * face_all + (size_t)(2 * d + side) * F * nv + (size_t)f * nv];
+          double *oF = &lFh[c * face_all + (size_t)(2 * d + side) * F * nv + (size_t)f * nv];
+          for (int v = 0; v < nv; ++v) {
+            oq[v] += side ? lqL[v] : lqR[v];
+            oF[v] += side ? lFL[v] : lFR[v];
+          }
+          for (int p = 0; p < np; ++p) gparams[(size_t)c * np + p] += side ? gpL[p] : gpR[p];
+        }
+      }
+  }
+  /* 4. predictor in reverse, per cell */
+  int fail = 0;
+#pragma omp parallel
+  {
+    work W;
+    int ok = work_alloc(&M, &W) == ORC_OK;
+    size_t it_sz = (size_t)n * S * nq;
+    double *hist = malloc(sizeof(double) * (I + 1) * it_sz);
+    double *lq = malloc(sizeof(double) * it_sz);   /* adjoint of an iterate [n][S][nq] */
+    double *lqn = malloc(sizeof(double) * it_sz);
+    double *lR = malloc(sizeof(double) * S * nv);
+    double *lqbar = malloc(sizeof(double) * S * nv);
+    double *lFbar = malloc(sizeof(double) * dim * S * nv);
+    double *lu = malloc(sizeof(double) * S * nv);
+    if (!ok || !hist || !lq || !lqn || !lR || !lqbar || !lFbar || !lu) {
+#pragma omp atomic write
+      fail = 1;
+    }
+    double gcell[3];
+#pragma omp for schedule(dynamic, 4)
+    for (long c = 0; c < C; ++c) {
+      if (fail) continue;
+      gcell[0] = gcell[1] = gcell[2] = 0.0;
+      predictor_history(P, &M, &T, c, Q, params, dt, t, &W, hist);
+      const double *qI = &hist[(size_t)I * it_sz];
+      for (size_t a = 0; a < (size_t)S * nv; ++a) lu[a] = 0.0;
+      /* u^{n+1} = u + vol - surf: identity part */
+      for (int k = 0; k < S; ++k)
+        for (int v = 0; v < nv; ++v) lu[(size_t)k * nv + v] = lam[((size_t)c * nv + v) * S + k];
+      /* vol = dt (-div Fbar - Nbar + Sbar) with Fbar, Nbar, Sbar time averages
+       * of F, B grad q, S at the final iterate: reverse through the time
+       * average into per-slice adjoints of R-like terms (weight w_j) */
+      for (size_t a = 0; a < (size_t)dim * S * nv; ++a) lFbar[a] = 0.0;
+      for (size_t a = 0; a < (size_t)S * nv; ++a) lqbar[a] = 0.0;
+      /* traces: qhat = sum_m l_m qbar, Fhat = sum_m l_m Fbar_d */
+      for (int k = 0; k < S; ++k) {
+        int kk[3];
+        node_index(&M, k, kk);
+        for (int d = 0; d < dim; ++d) {
+          int f = face_node(&M, d, kk);
+          for (int side = 0; side < 2; ++side) {
+            double l = side ? T.l1[kk[d]] : T.l0[kk[d]];
+            const double *a1 = &lqh[c * face_all + (size_t)(2 * d + side) * F * nv + (size_t)f * nv];
+            const double *a2 = &lFh[c * face_all + (size_t)(2 * d + side) * F * nv + (size_t)f * nv];
+            for (int v = 0; v < nv; ++v) {
+              lqbar[(size_t)k * nv + v] += l * a1[v];
+              lFbar[((size_t)d * S + k) * nv + v] += l * a2[v];
+            }
+          }
+        }
+      }
+      /* the volume term: -dt div Fbar adds to lFbar; -dt Nbar and +dt Sbar act
+       * per slice with weight w_j (handled below with the slices) */
+      for (int k = 0; k < S; ++k) {
+        int kk[3];
+        node_index(&M, k, kk);
+        for (int d = 0; d < dim; ++d)
+          for (int m = 0; m < n; ++m) {
+            int km = k + (m - kk[d]) * M.stride[d];
+            for (int v = 0; v < nv; ++v)
+              lFbar[((size_t)d * S + km) * nv + v] +=
+                  -dt * T.D[kk[d]][m] * lu[(size_t)k * nv + v] / M.h[d];
+          }
+      }
+      /* adjoint of the final iterate, slice by slice:
+       * qbar = sum_j w_j q_j;  Fbar_d = sum_j w_j F_d(q_j);
+       * Nbar = sum_j w_j B(q_j) grad q_j;  Sbar = sum_j w_j S(q_j) */
+      for (size_t a = 0; a < it_sz; ++a) lq[a] = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double *qs = &qI[(size_t)j * S * nq];
+        double *lqs = &lq[(size_t)j * S * nq];
+        for (int k = 0; k < S; ++k) {
+          for (int v = 0; v < nv; ++v) lqs[(size_t)k * nq + v] += T.w[j] * lqbar[(size_t)k * nv + v];
+          for (int d = 0; d < dim; ++d) {
+            double lf[ORC_MAXQ];
+            for (int v = 0; v < nv; ++v) lf[v] = T.w[j] * lFbar[((size_t)d * S + k) * nv + v];
+            flux_T(P, d, lf, &lqs[(size_t)k * nq]);
+          }
+        }
+        /* -dt Nbar + dt Sbar is w_j dt (-B grad q_j + S(q_j)): the same map as
+         * R without its flux part; reuse rhs_T with the flux adjoint zero by
+         * passing an R-adjoint whose divergence part is handled separately */
+        for (int k = 0; k < S; ++k)
+          for (int v = 0; v < nv; ++v) lR[(size_t)k * nv + v] = T.w[j] * dt * lu[(size_t)k * nv + v];
+        {
+          /* B grad q and S parts only */
+          double *grad = malloc(sizeof(double) * S * dim * nq);
+          double *lamG = calloc((size_t)S * dim * nq, sizeof(double));
+          slice_gradient(&M, &T, qs, grad);
+          for (int k = 0; k < S; ++k) {
+            double lamB[ORC_MAXQ];
+            for (int v = 0; v < nv; ++v) lamB[v] = -lR[(size_t)k * nv + v];
+            ncp_T(P, &qs[(size_t)k * nq], lamB, &lamG[(size_t)k * dim * nq]);
+            ncp_dparams_T(P, &qs[(size_t)k * nq], &grad[(size_t)k * dim * nq], lamB, gcell);
+            source_T(P, &lR[(size_t)k * nv], &lqs[(size_t)k * nq]);
+          }
+          for (int k = 0; k < S; ++k) {
+            int kk[3];
+            node_index(&M, k, kk);
+            for (int d = 0; d < dim; ++d)
+              for (int m = 0; m < n; ++m) {
+                int km = k + (m - kk[d]) * M.stride[d];
+                for (int v = 0; v < nv; ++v)
+                  lqs[(size_t)km * nq + v] += T.D[kk[d]][m] * lamG[((size_t)k * dim + d) * nq + v] / M.h[d];
+              }
+          }
+          free(grad);
+          free(lamG);
+        }
+      }
+      /* Picard in reverse: q^{r+1}_i = sum_j K1inv_ij (l0_j u + dt w_j R(q^r)_j) */
+      for (int r = I - 1; r >= 0; --r) {
+        const double *qr = &hist[(size_t)r * it_sz];
+        for (size_t a = 0; a < it_sz; ++a) lqn[a] = 0.0;
+        for (int j = 0; j < n; ++j) {
+          for (int k = 0; k < S; ++k)
+            for (int v = 0; v < nv; ++v) {
+              double sR = 0.0, sU = 0.0;
+              for (int i = 0; i < n; ++i) {
+                double a = lq[((size_t)i * S + k) * nq + v];
+                sR += T.K1inv[i][j] * a;
+                sU += T.K1inv[i][j] * a;
+              }
+              lR[(size_t)k * nv + v] = dt * T.w[j] * sR;
+              lu[(size_t)k * nv + v] += T.l0[j] * sU;
+            }
+          rhs_T(P, &M, &T, &qr[(size_t)j * S * nq], lR, &lqn[(size_t)j * S * nq], gcell);
+        }
+        double *tmp = lq;
+        lq = lqn;
+        lqn = tmp;
+      }
+      /* q^0_j = u for every j */
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < S; ++k)
+          for (int v = 0; v < nv; ++v) lu[(size_t)k * nv + v] += lq[((size_t)j * S + k) * nq + v];
+      for (int k = 0; k < S; ++k)
+        for (int v = 0; v < nv; ++v) lam_out[((size_t)c * nv + v) * S + k] = lu[(size_t)k * nv + v];
+      for (int p = 0; p < np; ++p) gparams[(size_t)c * np + p] += gcell[p];
+    }
+    free(hist); free(lq); free(lqn); free(lR); free(lqbar); free(lFbar); free(lu);
+    work_free(&W);
+  }
+  if (!fail) memcpy(lam, lam_out, sizeof(double) * C * nv * S);
+  free(qhat); free(Fhat); free(lamfl); free(lqh); free(lFh); free(lam_out);
+  return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Transpose of orc_sample_receivers: lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v]. */
+int orc_sample_receivers_T(const orc_problem *P, int nrec, const double *xyz, const double *lamrec,
+                           double *lam) {
+  mesh M;
+  tables T;
+  if (make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  for (int r = 0; r < nrec; ++r) {
+    int cc[3] = {0, 0, 0};
+    double xs[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < M.dim; ++d) {
+      double s = (xyz[r * 3 + d] - P->lo[d]) / M.h[d];
+      cc[d] = (int)floor(s);
+      if (cc[d] < 0 || cc[d] >= P->cells[d]) return ORC_EINVAL;
+      xs[d] = s - cc[d];
+    }
+    long c = cell_index(P, cc);
+    for (int k = 0; k < M.S; ++k) {
+      int kk[3];
+      node_index(&M, k, kk);
+      double phi = 1.0;
+      for (int d = 0; d < M.dim; ++d) phi *= lagrange(&T, kk[d], xs[d]);
+      for (int v = 0; v < M.nv; ++v) lam[((size_t)c * M.nv + v) * M.S + k] += phi * lamrec[r * M.nv + v];
+    }
+  }
+  return ORC_OK;
+}
