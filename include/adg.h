@@ -206,6 +206,40 @@ adg_status adg_set_receivers(adg_ctx* ctx, int n, const double* xyz);
  * the receiver's cell evaluated at the receiver (device output [n][nvar]). */
 adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void* stream);
 
+/* ---- Discrete adjoint (for gradients of functionals of the solution) ----
+ *
+ * The FP64 step of adg_step with the step size held fixed is, for PDEs
+ * linear in Q, an affine map u^{n+1} = A(m) u^n + b(t) of the state, m the
+ * per-cell material parameters (point sources make up b).  These two calls
+ * are the exact transposes (up to rounding) of that map and of receiver
+ * sampling, so that a caller can run a reverse sweep: with
+ * lam = dJ/du^{n+1}, adg_step_adjoint gives dJ/du^n and dJ/dm.  The inner
+ * products are the plain Euclidean ones over the nodal arrays (a discrete
+ * adjoint, not a discretised continuous adjoint).  Reading: where the two
+ * cells of a face have the same largest eigenvalue, the derivative of the
+ * Rusanov speed max() is split half and half between them. */
+
+/* One adjoint step, reverse of the step that took Q = u^n to u^{n+1} with
+ * the clock {t^n, dt} (device, read only; the same values the forward step
+ * used).
+ *   Q        [C][nvar][S] device, the forward state u^n (read only)
+ *   params   [C][nparam] device (NULL iff nparam == 0)
+ *   lam      [C][nvar][S] device, in: dJ/du^{n+1}, out: dJ/du^n (in place)
+ *   gparams  [C][nparam] device, dJ/dm of this step is ADDED (NULL iff
+ *            nparam == 0)
+ * Available for ADG_PDE_ELASTIC (orders 1..3) and ADG_PDE_ADVECTION (2-D
+ * orders 1..7, 3-D orders 1..3) with picard_iters <= order + 1; otherwise
+ * ADG_ERR_UNSUPPORTED.  Deterministic (no atomics).  Uses the context's
+ * trace workspace: a following adg_correct needs a new adg_predict. */
+adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
+                            const double* clock, double* lam, double* gparams, void* stream);
+
+/* Transpose of adg_sample_receivers: lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v]
+ * for every receiver r (device lamrec [n][nvar], lam [C][nvar][S]).
+ * Receivers in the same cell add in receiver order (deterministic). */
+adg_status adg_sample_receivers_adjoint(adg_ctx* ctx, const double* lamrec, double* lam,
+                                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,8 @@ def lib():
         L.adg_set_point_sources.argtypes = [vp, C.c_int, C.POINTER(PointSource)]
         L.adg_set_receivers.argtypes = [vp, C.c_int, dp]
         L.adg_sample_receivers.argtypes = [vp, vp, vp, vp]
+        L.adg_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.adg_sample_receivers_adjoint.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -85,7 +87,7 @@ def lib():
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_destroy",
             "adg_query", "adg_node_coords", "adg_stable_dt", "adg_step", "adg_predict", "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
-            "adg_sample_receivers")
+            "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint")
 
 
 def _check(st: int):
@@ -246,3 +248,25 @@ class Solver:
         _check(lib().adg_sample_receivers(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
                                           self._dev(out, (self.nrec, self.nvar), torch.float64, "out"),
                                           _stream(stream)))
+
+    def step_adjoint(self, Q, params, clock, lam, gparams=None, stream=None):
+        """lam <- (du^{n+1}/du^n)^T lam and gparams += (du^{n+1}/dm)^T lam for the
+        FP64 step from Q = u^n with clock {t^n, dt} (dt held fixed)."""
+        import torch
+        gp = C.c_void_p()
+        if self.nparam > 0:
+            if gparams is None:
+                raise ValueError("this PDE needs a parameter-gradient array [ncells, nparam]")
+            gp = self._dev(gparams, (self.ncells, self.nparam), torch.float64, "gparams")
+        _check(lib().adg_step_adjoint(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                      self._params(params),
+                                      self._dev(clock, (2,), torch.float64, "clock"),
+                                      self._dev(lam, self.state_shape, torch.float64, "lam"), gp,
+                                      _stream(stream)))
+
+    def sample_receivers_adjoint(self, lamrec, lam, stream=None):
+        """lam += transpose of receiver sampling applied to lamrec [nrec, nvar]."""
+        import torch
+        _check(lib().adg_sample_receivers_adjoint(
+            self._ctx, self._dev(lamrec, (self.nrec, self.nvar), torch.float64, "lamrec"),
+            self._dev(lam, self.state_shape, torch.float64, "lam"), _stream(stream)))

@@ -1,0 +1,92 @@
+"""torch.autograd.Function around a run of ADER-DG steps with receivers.
+
+``seismograms(solver, u0, params, dt, steps)`` runs ``steps`` FP64 steps of
+the solver's PDE from ``u0`` with the step size held fixed and returns the
+receiver samples after every step, ``[steps, nrec, nvar]``.  Its backward is
+the library's hand-written discrete adjoint (``adg_step_adjoint`` and
+``adg_sample_receivers_adjoint``), run in reverse over the steps with
+time-step checkpointing: the forward pass keeps the state every ``every``
+steps; the backward pass recomputes the states of one segment from its
+checkpoint, then runs the adjoint steps of that segment backwards.  Memory:
+ceil(steps / every) checkpoints plus ``every`` segment states.
+
+Gradients flow to ``u0`` and ``params``.  The step size is not
+differentiated (it is an input, as in a run with a frozen dt).  Available
+for the PDEs the adjoint is built for (elasticity, the advection test PDE).
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+
+def _time_nodes(t0: float, dt: float, steps: int):
+    """t^n as the device clock accumulates it (t <- t + dt in float64)."""
+    ts = [t0]
+    t = t0
+    for _ in range(steps):
+        t = t + dt
+        ts.append(t)
+    return ts
+
+
+class _SeismogramRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, params, solver, t0, dt, steps, every):
+        if solver.nrec == 0:
+            raise ValueError("set receivers on the solver first")
+        prm = params.detach().contiguous() if params is not None else None
+        Q = u0.detach().contiguous().clone()
+        clock = torch.tensor([t0, dt], dtype=torch.float64, device=Q.device)
+        out = torch.empty((steps, solver.nrec, solver.nvar), dtype=torch.float64, device=Q.device)
+        ckpts = [Q.clone()]
+        for n in range(steps):
+            solver.step(Q, prm, clock, next_dt=False)
+            solver.sample_receivers(Q, out[n])
+            if (n + 1) % every == 0 and n + 1 < steps:
+                ckpts.append(Q.clone())
+        ctx.solver, ctx.t0, ctx.dt, ctx.steps, ctx.every = solver, t0, dt, steps, every
+        ctx.ckpts = ckpts
+        ctx.prm = prm
+        ctx.has_params = params is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        s, dt, steps, every = ctx.solver, ctx.dt, ctx.steps, ctx.every
+        prm = ctx.prm
+        dev = ctx.ckpts[0].device
+        gout = gout.detach().to(torch.float64).contiguous()
+        lam = torch.zeros_like(ctx.ckpts[0])
+        g = torch.zeros_like(prm) if (prm is not None and s.nparam > 0) else None
+        ts = _time_nodes(ctx.t0, dt, steps)
+        clocks = torch.tensor([[ts[n], dt] for n in range(steps)], dtype=torch.float64, device=dev)
+        nseg = math.ceil(steps / every)
+        for seg in reversed(range(nseg)):
+            n0, n1 = seg * every, min(steps, (seg + 1) * every)
+            # recompute u^{n0} .. u^{n1-1} from the checkpoint
+            Q = ctx.ckpts[seg].clone()
+            clock = clocks[n0].clone()
+            states = [ctx.ckpts[seg]]
+            for n in range(n0, n1 - 1):
+                s.step(Q, prm, clock, next_dt=False)
+                states.append(Q.clone())
+            for n in reversed(range(n0, n1)):
+                # out[n] samples u^{n+1}; the step n maps u^n to u^{n+1}
+                s.sample_receivers_adjoint(gout[n], lam)
+                s.step_adjoint(states[n - n0], prm, clocks[n], lam, g)
+            del states, Q
+        gu0 = lam
+        gp = g if ctx.has_params else None
+        return gu0, gp, None, None, None, None, None
+
+
+def seismograms(solver, u0: torch.Tensor, params, dt: float, steps: int, t0: float = 0.0,
+                every: int | None = None) -> torch.Tensor:
+    """Receiver samples [steps, nrec, nvar] after each of ``steps`` fixed-dt
+    steps from ``u0``; differentiable in ``u0`` and ``params``.  ``every``:
+    checkpoint interval (default ceil(sqrt(steps)))."""
+    if every is None:
+        every = max(1, math.ceil(math.sqrt(steps)))
+    return _SeismogramRun.apply(u0, params, solver, float(t0), float(dt), int(steps), int(every))

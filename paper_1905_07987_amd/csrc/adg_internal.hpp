@@ -74,6 +74,11 @@ struct KernelSet {
                           hipStream_t);
   hipError_t (*admissible)(const KArgs&, const double* Q, const double* params,
                            uint8_t* troubled, int32_t* count, hipStream_t);
+  // Discrete adjoint of one FP64 step (nullptr where not built: PDEs that
+  // are not linear in Q, orders whose kernel does not fit).  work holds
+  // 2 C 2dim nvar F doubles (the trace workspace).
+  hipError_t (*adjoint)(const KArgs&, const double* Q, const double* params, const double* clock,
+                        double* lam, double* gparams, double* work, hipStream_t);
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

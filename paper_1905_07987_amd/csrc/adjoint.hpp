@@ -1,0 +1,619 @@
+// Discrete adjoint of one ADER-DG step for the PDEs that are linear in Q
+// (elasticity and the advection test PDE), with the step size held fixed.
+// Included by kernels.hpp after the forward kernels, whose helpers it uses.
+//
+// The step maps (u^n, m) to u^{n+1}, m the per-cell material parameters.
+// Given lam = dJ/du^{n+1}, the adjoint step overwrites lam with
+// dJ/du^n = (du^{n+1}/du^n)^T lam and adds (du^{n+1}/dm)^T lam to the
+// parameter gradient.  Inner products are the plain Euclidean ones over the
+// nodal arrays.  Linearity in Q gives three exact identities (up to rounding)
+// that shape the kernels:
+//  - the corrector's time averages depend on the predictor only through
+//    qbar = sum_j w_j q_j: Fbar_d = F_d(qbar), the averaged non-conservative
+//    product is B grad qbar and Sbar = S(qbar) plus the point sources, which
+//    depend on neither u nor m;
+//  - the face trace of Fbar_d is F_d of the face trace of qbar, so the adjoint
+//    of the flux trace folds into the adjoint of the state trace;
+//  - the Rusanov flux is linear in the traces with coefficients that depend
+//    on the parameters only (max_eigen does not read Q for these PDEs); its
+//    transpose needs no traces, its parameter derivative does.
+// Reading: the derivative of the max() in the Rusanov speed is split half
+// and half between the two cells on a tie.
+//
+// Launch sequence on the caller's stream; work holds two face arrays
+// A and B of [C][2 dim][NV][F] doubles (face = 2 d + side, side 1 = high):
+//  1. adj_face_project_kernel: A = sum_m l_side(m) / w_m lam(line f, m), the
+//     face projections of lam that the surface integral's transpose needs.
+//  2. adj_rusanov_kernel<false>: B = adjoint of each cell's own face traces
+//     (state trace plus folded flux trace) from the fluctuation adjoints of
+//     both cells of the face.
+//  3. adj_predict_kernel: per cell, the Picard iteration forward from u^n
+//     (keeping the iterates' gradient quantities), then the transposes of the
+//     face projection, the volume term and the Picard steps in reverse order;
+//     lam <- lam^n, gparams += the cell's volume terms, B <- face traces of
+//     qbar (after B's adjoints have been read).
+//  4. adj_rusanov_kernel<true> (PDEs with parameters): gparams += the
+//     Rusanov flux's parameter derivative at every face of the cell.
+#pragma once
+
+namespace adg {
+
+// Value of f(i) for a lane-dependent index i < n, built from compile-time
+// constants (a select chain; no memory access).
+template <int n, class Fn>
+__device__ __forceinline__ double ct_pick(int i, Fn f) {
+  double r = f(0);
+#pragma unroll
+  for (int ii = 1; ii < n; ++ii) r = (i == ii) ? f(ii) : r;
+  return r;
+}
+
+// Predictor-adjoint layout: one thread per (time slice j, node k) of a cell,
+// thread t = j S + k, CPB cells per block.  LDS per cell holds, in turn,
+// the derivative rows of one direction (NFL + 2 NGR channels for every slice,
+// line-major as in the forward kernels) or the time-exchange buffer [NV][n][S]
+// plus qbar [NV][S].
+template <class PDE, int N>
+struct GeoAdj {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  static constexpr int NGR = C::ngrad();
+  static constexpr int TPC = G::n * G::S;
+  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * G::n * G::SP;
+  static constexpr int TIME_ELEMS = G::NV * G::n * G::S + G::NV * G::S;
+  static constexpr int RED_ELEMS = TPC * (G::NP > 0 ? G::NP : 1);
+  static constexpr int CELL_ELEMS = cmax(cmax(DER_ELEMS, TIME_ELEMS), RED_ELEMS);
+  static constexpr int by_threads = TPC >= 256 ? 1 : 256 / TPC;
+  static constexpr int by_lds = cmax(1, (56 * 1024) / (CELL_ELEMS * 8));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * TPC;
+  static constexpr bool supported =
+      PDE::kLinear && C::uniform() && BLOCK <= 512 && CPB * CELL_ELEMS * 8 <= 56 * 1024;
+};
+
+// Face kernels: one thread per (cell, face, face node); CPB_R cells per block.
+template <class PDE, int N>
+struct GeoAdjR {
+  using G = Geo<PDE, N>;
+  static constexpr int TPF = 2 * G::DIM * G::F;  // tasks per cell
+  static constexpr int CPB = TPF >= 256 ? 1 : 256 / TPF;
+  static constexpr int BLOCK = 256;
+};
+
+// face node f of the faces normal to d, position m along d -> node index
+template <int DIM, int n>
+__device__ __forceinline__ int face_line_node(int d, int f, int m) {
+  if (DIM == 2) return d == 0 ? f * n + m : f + n * m;
+  return d == 0 ? n * f + m : (d == 1 ? (f % n) + n * m + n * n * (f / n) : f + n * n * m);
+}
+
+// ---------------------------------------------------------------------------
+// 1. Face projections of lam: A[c][face][v][f] = sum_m l_side(m) / w_m lam.
+// ---------------------------------------------------------------------------
+template <class PDE, int N>
+__global__ void __launch_bounds__(256)
+adj_face_project_kernel(const KArgs a, const double* __restrict__ lam, double* __restrict__ A) {
+  using G = Geo<PDE, N>;
+  using T = CT<double, G::n>;
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, DIM = G::DIM;
+  const long long total = a.ncells * (2 * DIM * NV * F);
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= total) return;
+  const int f = (int)(id % F);
+  long long r = id / F;
+  const int v = (int)(r % NV);
+  r /= NV;
+  const int face = (int)(r % (2 * DIM));
+  const long long c = r / (2 * DIM);
+  const int d = face >> 1, side = face & 1;
+  const double* src = lam + (c * NV + v) * S;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < n; ++m)
+    acc += (side ? T::l1(m) : T::l0(m)) * (1.0 / T::w(m)) * src[face_line_node<DIM, n>(d, f, m)];
+  A[id] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// 2./4. Rusanov flux in reverse.  GRAD = false: B <- adjoint of the cell's own
+// face traces.  GRAD = true: gparams += the flux's parameter derivative, with
+// B holding the face traces of qbar.
+//
+// Forward, at the face with normal e_d between L (low) and R (high):
+//   s = max(lambda*(pL), lambda*(pR)), G = (FL + FR)/2 - s (qR - qL)/2,
+//   Bm = B_d(pm) (qR - qL) / 2 with pm = (pL + pR)/2,
+//   flL = G - FL + Bm (into L's high face), flR = FR - G + Bm (into R's low
+//   face), each scaled by dt / h_d in the update u -= l flL / w ...
+// ---------------------------------------------------------------------------
+template <class PDE, int N, bool GRAD>
+__global__ void __launch_bounds__(256)
+adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const double* __restrict__ clock,
+                   const double* __restrict__ A, double* __restrict__ B, double* __restrict__ gparams) {
+  using G = Geo<PDE, N>;
+  using GR = GeoAdjR<PDE, N>;
+  constexpr int F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int NPX = NP > 0 ? NP : 1;
+  constexpr int TPF = GR::TPF, CPB = GR::CPB;
+  __shared__ double contrib[GRAD ? CPB * TPF * NPX : 1];
+  const int tid = threadIdx.x;
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const double dt = clock[1];
+  const int C0 = a.cells[0], C1 = a.cells[1];
+
+  for (int task = tid; task < CPB * TPF; task += GR::BLOCK) {
+    const int f = task % F;
+    const int face = (task / F) % (2 * DIM);
+    const int c2 = task / TPF;
+    const long long c = cell0 + c2;
+    double gp[NPX];
+#pragma unroll
+    for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
+    if (c < a.ncells) {
+      const int d = face >> 1, side = face & 1;
+      long long cc[3];
+      cc[0] = c % C0;
+      cc[1] = (c / C0) % C1;
+      cc[2] = DIM == 3 ? c / ((long long)C0 * C1) : 0;
+      cc[d] += side ? 1 : -1;
+      if (cc[d] < 0) cc[d] += a.cells[d];
+      if (cc[d] >= a.cells[d]) cc[d] -= a.cells[d];
+      const long long nb = cc[0] + C0 * (cc[1] + (long long)C1 * cc[2]);
+      const long long cL = side ? c : nb, cR = side ? nb : c;
+      const double scale = -dt * a.inv_h[d];
+      const double* aL = A + ((cL * (2 * DIM) + 2 * d + 1) * NV) * F + f;
+      const double* aR = A + ((cR * (2 * DIM) + 2 * d + 0) * NV) * F + f;
+      double lL[NV], lR[NV], lG[NV], lBm[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lL[v] = scale * aL[v * F];
+        lR[v] = scale * aR[v * F];
+        lG[v] = lL[v] - lR[v];
+        lBm[v] = 0.5 * (lL[v] + lR[v]);
+      }
+      double pL[NPX] = {}, pR[NPX] = {}, pm[NPX] = {}, qz[NV];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        pL[p] = params[cL * NP + p];
+        pR[p] = params[cR * NP + p];
+        pm[p] = 0.5 * (pL[p] + pR[p]);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qz[v] = 0.0;
+      const double sL = PDE::max_eigen(qz, pL, a.pde, d), sR = PDE::max_eigen(qz, pR, a.pde, d);
+      if constexpr (!GRAD) {
+        const double s = fmax(sL, sR);
+        double ld[NV], lF[NV], out[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ld[v] = -0.5 * s * lG[v];
+          lF[v] = side ? (-lL[v] + 0.5 * lG[v]) : (lR[v] + 0.5 * lG[v]);
+        }
+        if constexpr (PDE::kHasNcp) {
+          double lg[DIM][NV];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) lg[e][v] = 0.0;
+          PDE::ncp_T(pm, a.pde, lBm, lg);
+#pragma unroll
+          for (int e = 0; e < DIM; ++e)
+            if (e == d) {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) ld[v] += lg[e][v];
+            }
+        }
+        // qR enters with +ld, qL with -ld
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = side ? -ld[v] : ld[v];
+        PDE::flux_T(d, a.pde, lF, out);
+        double* o = B + ((c * (2 * DIM) + face) * NV) * F + f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o[v * F] = out[v];
+      } else {
+        const double* tL = B + ((cL * (2 * DIM) + 2 * d + 1) * NV) * F + f;
+        const double* tR = B + ((cR * (2 * DIM) + 2 * d + 0) * NV) * F + f;
+        double jump[NV], ls = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          jump[v] = tR[v * F] - tL[v * F];
+          ls += -0.5 * jump[v] * lG[v];
+        }
+        const double mine = side ? sL : sR, other = side ? sR : sL;
+        const double share = mine > other ? 1.0 : (mine == other ? 0.5 : 0.0);
+        PDE::max_eigen_dparams(side ? pL : pR, d, share * ls, gp);
+        if constexpr (PDE::kHasNcp) {
+          double g[DIM][NV], gpm[NPX];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) g[e][v] = e == d ? jump[v] : 0.0;
+#pragma unroll
+          for (int p = 0; p < NPX; ++p) gpm[p] = 0.0;
+          PDE::ncp_dparams_T(pm, a.pde, g, lBm, gpm);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) gp[p] += 0.5 * gpm[p];
+        }
+      }
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int p = 0; p < NPX; ++p) contrib[task * NPX + p] = gp[p];
+    }
+  }
+  if constexpr (GRAD) {
+    __syncthreads();
+    // fixed-order sum per (cell, parameter): deterministic
+    if (tid < CPB * NP) {
+      const int c2 = tid / NP, p = tid - c2 * NP;
+      const long long c = cell0 + c2;
+      if (c < a.ncells) {
+        double s = 0.0;
+        for (int i = 0; i < TPF; ++i) s += contrib[(c2 * TPF + i) * NPX + p];
+        gparams[c * NP + p] += s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. Predictor, volume term and face projection in reverse, per cell.
+//
+// Forward (Sec. 3.3, Eq. (5), the Picard form of the forward kernels):
+//   q^0_j = u,  q^{r+1}_j = u + dt sum_i KW_ji R(q^r_i),  r < I,
+//   R(q) = -sum_d D_d F_d(q) / h_d - B(q) grad q + S(q) + point sources,
+//   u^{n+1} = u + dt R(qbar) - surface terms,  qbar = sum_j w_j q^I_j,
+//   face traces l_side . qbar.
+// Reverse, with mu_j the adjoint of the current iterate's slice j:
+//   mu^I_j = w_j (trace^T lamhat + R^T (dt lam))   (R^T on slice j with
+//            nu_j = dt w_j lam, paired with q^I_j for the parameters)
+//   for r = I-1 .. 0:  lam_u += sum_j mu_j;  nu_j = dt sum_i KW_ij mu_i;
+//                      mu_j = R^T nu_j;  gparams += (dR/dm (q^r_j))^T nu_j
+//   lam_u += sum_j mu_j;  lam^n = lam + lam_u.
+// ---------------------------------------------------------------------------
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoAdj<PDE, N>::BLOCK))
+adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
+                   const double* __restrict__ clock, double* __restrict__ lam,
+                   double* __restrict__ gparams, double* __restrict__ hat) {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  using GA = GeoAdj<PDE, N>;
+  using T = CT<double, G::n>;
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GA::CPB, TPC = GA::TPC, SP = G::SP, LS = G::LS;
+  constexpr int NFL = C::NFLUX, NGR = GA::NGR;
+  constexpr int NPX = NP > 0 ? NP : 1, NGX = NGR > 0 ? NGR : 1;
+  constexpr int IMAX = N + 1;  // the host admits picard_iters <= N + 1
+  static_assert(GA::supported, "adjoint not available for this PDE and order");
+  __shared__ double lds[CPB * GA::CELL_ELEMS];
+  __shared__ double src_amp[kMaxSources * n];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / TPC;
+  const int t = tid - lc * TPC;
+  const int j = t / S;
+  const int k = t - j * S;
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+  double* const buf = lds + lc * GA::CELL_ELEMS;
+
+  int kk[3] = {0, 0, 0};
+  node_coords<DIM>(k, n, kk);
+  int ln[DIM], pk[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    ln[d] = G::line_of(d, kk[0], kk[1], DIM == 3 ? kk[2] : 0);
+    pk[d] = ln[d] * LS + kk[d];
+  }
+  // Lane-dependent entries of D (row kk_d or column kk_d) and KW (row or
+  // column j), rebuilt from compile-time constants where they are used.
+  auto Drow = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(i, m); }); };
+  auto Dcol = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(m, i); }); };
+  auto KWrow = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(jj, i); }); };
+  auto KWcol = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(i, jj); }); };
+  const double wj = ct_pick<n>(j, [&](int jj) { return T::w(jj); });
+
+  const double t_n = clock[0], dt = clock[1];
+  const int I = a.picard_iters;
+  double P[NPX], u[NV];
+#pragma unroll
+  for (int p = 0; p < NPX; ++p) P[p] = p < NP ? params[cl * NP + p] : 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
+
+  // Point sources enter the forward iterates (and so the parameter
+  // derivative), exactly as in the forward predictor.
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc * n) {
+    const int s = tid / n, jj = tid - s * n;
+    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[jj] * dt);
+  }
+  __syncthreads();
+
+  // R(q) of slice j at this node (forward).
+  auto rhs = [&](const double (&q)[NV], double (&R)[NV]) {
+    double Fd[DIM][NV];
+    PDE::fluxes(q, P, a.pde, Fd);
+    if constexpr (PDE::kHasSource) {
+      PDE::source(q, P, a.pde, R);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] = 0.0;
+    }
+    if (src_here) {
+      for (int s = 0; s < a.nsrc; ++s) {
+        if (a.src[s].cell != cell) continue;
+        const double amp = src_amp[s * n + j];
+        const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[v] += amp * wsk[v];
+      }
+    }
+    double g[DIM][NV];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) g[d][v] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NFL; ++c) buf[(c * n + j) * SP + pk[d]] = Fd[d][C::flux_var(d, c)];
+#pragma unroll
+      for (int c = 0; c < NGR; ++c) buf[((NFL + c) * n + j) * SP + pk[d]] = q[C::grad_var(c)];
+      __syncthreads();
+      const double* row = buf + j * SP + ln[d] * LS;
+      double Dr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) Dr[m] = Drow(d, m);
+#pragma unroll
+      for (int c = 0; c < NFL; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dr[m] * row[c * n * SP + m];
+        R[C::flux_var(d, c)] -= acc * a.inv_h[d];
+      }
+#pragma unroll
+      for (int c = 0; c < NGR; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dr[m] * row[(NFL + c) * n * SP + m];
+        g[d][C::grad_var(c)] = acc * a.inv_h[d];
+      }
+      __syncthreads();
+    }
+    if constexpr (PDE::kHasNcp) {
+      double Bv[NV];
+      PDE::ncp(q, P, a.pde, g, Bv);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] -= Bv[v];
+    }
+  };
+
+  // mu = R^T nu for slice j; gp += (dR/dm at the forward values fw)^T nu.
+  auto rhs_T = [&](const double (&nu)[NV], const double (&fw)[NGX], double (&mu)[NV], double (&gp)[NPX]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mu[v] = 0.0;
+    PDE::source_T(a.pde, nu, mu);
+    double lB[NV], lG[DIM][NV], g[DIM][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lB[v] = -nu[v];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lG[d][v] = g[d][v] = 0.0;
+    if constexpr (PDE::kHasNcp) PDE::ncp_T(P, a.pde, lB, lG);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int c = 0; c < NFL; ++c) buf[(c * n + j) * SP + pk[d]] = nu[C::flux_var(d, c)];
+#pragma unroll
+      for (int c = 0; c < NGR; ++c) {
+        buf[((NFL + c) * n + j) * SP + pk[d]] = lG[d][C::grad_var(c)];
+        buf[((NFL + NGR + c) * n + j) * SP + pk[d]] = fw[c];
+      }
+      __syncthreads();
+      const double* row = buf + j * SP + ln[d] * LS;
+      double Dr[n], Dc[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        Dr[m] = Drow(d, m);
+        Dc[m] = Dcol(d, m);
+      }
+      double lF[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lF[v] = 0.0;
+      // transposed derivative of the flux adjoints
+#pragma unroll
+      for (int c = 0; c < NFL; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dc[m] * row[c * n * SP + m];
+        lF[C::flux_var(d, c)] = -acc * a.inv_h[d];
+      }
+#pragma unroll
+      for (int c = 0; c < NGR; ++c) {
+        // transposed derivative of the gradient adjoints
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += Dc[m] * row[(NFL + c) * n * SP + m];
+        mu[C::grad_var(c)] += acc * a.inv_h[d];
+        // gradient of the forward iterate
+        double gacc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) gacc += Dr[m] * row[(NFL + NGR + c) * n * SP + m];
+        g[d][C::grad_var(c)] = gacc * a.inv_h[d];
+      }
+      PDE::flux_T(d, a.pde, lF, mu);
+      __syncthreads();
+    }
+    if constexpr (PDE::kHasNcp) PDE::ncp_dparams_T(P, a.pde, g, lB, gp);
+  };
+
+  // ---- forward Picard sweep, keeping the gradient quantities of q^r ----
+  double q[NV], fw[IMAX][NGX];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = u[v];
+#pragma unroll
+  for (int r = 0; r < IMAX; ++r) {
+    if (r < I) {
+#pragma unroll
+      for (int c = 0; c < NGX; ++c) fw[r][c] = c < NGR ? q[C::grad_var(c)] : 0.0;
+      double R[NV];
+      rhs(q, R);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = R[v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) acc += KWrow(i) * buf[(v * n + i) * S + k];
+        q[v] = u[v] + dt * acc;
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- adjoint of the face traces (read B before it is overwritten) ----
+  double tseed[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) tseed[v] = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double l = ct_pick<n>(kk[d], [&](int i) { return side ? T::l1(i) : T::l0(i); });
+      const double* h = hat + ((cl * (2 * DIM) + 2 * d + side) * NV) * F + ln[d];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tseed[v] += l * h[v * F];
+    }
+  __syncthreads();
+
+  // ---- face traces of qbar into B (for the Rusanov parameter derivative) ----
+  {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = wj * q[v];
+    __syncthreads();
+    double* const qb = buf + NV * n * S;
+    for (int it = t; it < NV * S; it += TPC) {
+      const int v = it / S, kq = it - v * S;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < n; ++i) s += buf[(v * n + i) * S + kq];
+      qb[it] = s;
+    }
+    __syncthreads();
+    for (int it = t; it < 2 * DIM * NV * F; it += TPC) {
+      const int f = it % F, v = (it / F) % NV, face = it / (F * NV);
+      const int d = face >> 1, side = face & 1;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m)
+        acc += (side ? T::l1(m) : T::l0(m)) * qb[v * S + face_line_node<DIM, n>(d, f, m)];
+      if (active) hat[cell * (2 * DIM * NV * F) + it] = acc;
+    }
+    __syncthreads();
+  }
+
+  // ---- reverse sweep ----
+  double mu[NV], nu[NV], lu[NV], gp[NPX];
+#pragma unroll
+  for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    lu[v] = 0.0;
+    nu[v] = dt * wj * lam[(cl * NV + v) * S + k];
+  }
+  {
+    double fI[NGX];
+#pragma unroll
+    for (int c = 0; c < NGX; ++c) fI[c] = c < NGR ? q[C::grad_var(c)] : 0.0;
+    rhs_T(nu, fI, mu, gp);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mu[v] += wj * tseed[v];
+#pragma unroll
+  for (int r = IMAX - 1; r >= 0; --r) {
+    if (r < I) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lu[v] += mu[v];
+        buf[(v * n + j) * S + k] = mu[v];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) acc += KWcol(i) * buf[(v * n + i) * S + k];
+        nu[v] = dt * acc;
+      }
+      __syncthreads();
+      rhs_T(nu, fw[r], mu, gp);
+    }
+  }
+
+  // ---- lam^n = lam^{n+1} + sum_j lam_u,j; the cell's parameter terms ----
+#pragma unroll
+  for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = lu[v] + mu[v];
+  __syncthreads();
+  for (int it = t; it < NV * S; it += TPC) {
+    const int v = it / S, kq = it - v * S;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) s += buf[(v * n + i) * S + kq];
+    if (active) lam[(cell * NV + v) * S + kq] += s;
+  }
+  if constexpr (NP > 0) {
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) buf[t * NP + p] = gp[p];
+    __syncthreads();
+    if (t < NP && active) {
+      double s = 0.0;
+      for (int i = 0; i < TPC; ++i) s += buf[i * NP + t];
+      gparams[cell * NP + t] += s;
+    }
+  }
+}
+
+// Launch sequence of one adjoint step.
+template <class PDE, int N>
+struct AdjLaunch {
+  using G = Geo<PDE, N>;
+  using GA = GeoAdj<PDE, N>;
+  using GR = GeoAdjR<PDE, N>;
+  static hipError_t run(const KArgs& a0, const double* Q, const double* params, const double* clock,
+                        double* lam, double* gparams, double* work, hipStream_t st) {
+    constexpr long long face_elems = 2LL * G::DIM * G::NV * G::F;
+    double* A = work;
+    double* B = work + a0.ncells * face_elems;
+    KArgs a = a0;
+    const long long nproj = a0.ncells * face_elems;
+    hipLaunchKernelGGL((adj_face_project_kernel<PDE, N>), dim3((unsigned)((nproj + 255) / 256)),
+                       dim3(256), 0, st, a, lam, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.nblocks = (int)((a0.ncells + GR::CPB - 1) / GR::CPB);
+    hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, false>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
+                       a, params, clock, A, B, gparams);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    KArgs ap = a0;
+    ap.nblocks = (int)((a0.ncells + GA::CPB - 1) / GA::CPB);
+    hipLaunchKernelGGL((adj_predict_kernel<PDE, N>), dim3(ap.nblocks), dim3(GA::BLOCK), 0, st, ap, Q,
+                       params, clock, lam, gparams, B);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (G::NP > 0) {
+      hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, true>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
+                         a, params, clock, A, B, gparams);
+      e = hipGetLastError();
+    }
+    return e;
+  }
+};
+
+}  // namespace adg

@@ -108,6 +108,22 @@ __global__ void sample_kernel(const double* __restrict__ Q, const long long* __r
   }
 }
 
+// lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v], the transpose of sample_kernel.
+// One block walks the receivers in order and thread i always owns the same
+// (v, k), so receivers that share a cell add in a fixed order.
+__global__ void sample_adjoint_kernel(const double* __restrict__ lamrec,
+                                      const long long* __restrict__ rcell,
+                                      const double* __restrict__ rw, double* __restrict__ lam,
+                                      int nrec, int nv, int S) {
+  for (int r = 0; r < nrec; ++r) {
+    const long long c = rcell[r];
+    for (int i = threadIdx.x; i < nv * S; i += blockDim.x) {
+      const int v = i / S, k = i - v * S;
+      lam[(c * nv + v) * S + k] += rw[(long long)r * S + k] * lamrec[(long long)r * nv + v];
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -474,6 +490,38 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
                      ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nv, ctx->S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return ADG_OK;
+}
+
+adg_status adg_sample_receivers_adjoint(adg_ctx* ctx, const double* lamrec, double* lam,
+                                        void* stream) {
+  adg_status st = check_state(ctx, lam, (const void*)1);
+  if (st) return st;
+  if (ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
+  if (!lamrec) return fail(ADG_ERR_INVALID_ARG, "null receiver adjoint");
+  hipLaunchKernelGGL(sample_adjoint_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, lamrec,
+                     ctx->d_rec_cell, ctx->d_rec_w, lam, ctx->nrec, ctx->nv, ctx->S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "sample adjoint launch");
+  return ADG_OK;
+}
+
+adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
+                            const double* clock, double* lam, double* gparams, void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock || !lam) return fail(ADG_ERR_INVALID_ARG, "null clock or adjoint");
+  if (ctx->np > 0 && !gparams) return fail(ADG_ERR_INVALID_ARG, "null parameter gradient");
+  if (!ctx->ks->adjoint)
+    return fail(ADG_ERR_UNSUPPORTED,
+                "the adjoint is built for the linear PDEs (elastic, advection) at orders whose "
+                "kernel fits one block (elastic and 3-D advection up to 3, 2-D advection up to 7)");
+  if (ctx->args.picard_iters > ctx->cfg.order + 1)
+    return fail(ADG_ERR_UNSUPPORTED, "the adjoint supports at most order + 1 Picard iterations");
+  hipError_t e = ctx->ks->adjoint(ctx->args, Q, params, clock, lam, gparams, ctx->traces,
+                                  (hipStream_t)stream);
+  ctx->traces_ready = false;  // the adjoint reuses the trace workspace
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return ADG_OK;
 }
 

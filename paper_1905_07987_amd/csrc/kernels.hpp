@@ -1204,6 +1204,12 @@ count_kernel(unsigned long long* __restrict__ slots, int32_t* __restrict__ count
 
 }  // namespace
 
+}  // namespace adg
+
+#include "adjoint.hpp"
+
+namespace adg {
+
 // ---------------------------------------------------------------------------
 // Launchers and the per-(PDE, N) kernel set.
 // ---------------------------------------------------------------------------
@@ -1266,8 +1272,13 @@ struct Launch {
     hipLaunchKernelGGL(count_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, count);
     return hipGetLastError();
   }
+  static constexpr decltype(KernelSet::adjoint) adjoint_entry() {
+    if constexpr (GeoAdj<PDE, N>::supported) return &AdjLaunch<PDE, N>::run;
+    else return nullptr;
+  }
   static const KernelSet* set() {
-    static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB, &predict, &correct, &stable_dt, &admissible};
+    static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB,
+                                 &predict, &correct, &stable_dt, &admissible, adjoint_entry()};
     return &ks;
   }
 };

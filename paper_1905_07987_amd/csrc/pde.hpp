@@ -15,6 +15,14 @@
 //   max_eigen(Q, P, d)  largest |eigenvalue| of the direction-d system
 //   admissible(Q, P)    physical admissibility (Sec. 3.5) incl. finiteness
 // Q points to NV evolved values, P to NP parameter values.
+//
+// PDEs that are linear in Q (kLinear) also provide the transposes the
+// discrete adjoint of the step needs (all accumulate with +=):
+//   flux_T(d, pc, lamF, lamQ)        lamQ += (dF_d/dQ)^T lamF
+//   ncp_T(P, lamB, lamG)             lamG[d][v] += (dB/d(dQ_v/dx_d))^T lamB
+//   ncp_dparams_T(P, g, lamB, gp)    gp += (dB/dP)^T lamB at gradient g
+//   source_T(lamS, lamQ)             lamQ += (dS/dQ)^T lamS
+//   max_eigen_dparams(P, d, s, gp)   gp += s * d max_eigen(d) / dP
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,7 +45,7 @@ __device__ __forceinline__ bool finite_val(R x) {
 template <int DIM_>
 struct Euler {
   static constexpr int DIM = DIM_, NV = DIM_ + 2, NP = 0;
-  static constexpr bool kHasNcp = false, kHasSource = false;
+  static constexpr bool kHasNcp = false, kHasSource = false, kLinear = false;
   static constexpr bool flux_nonzero(int, int) { return true; }
   static constexpr bool grad_needed(int) { return false; }
 
@@ -104,7 +112,7 @@ struct Euler {
 //   d/dt sigma + E(lambda, mu) grad v = 0,   d/dt (rho v) + div sigma = 0.
 struct Elastic3 {
   static constexpr int DIM = 3, NV = 9, NP = 3;
-  static constexpr bool kHasNcp = true, kHasSource = false;
+  static constexpr bool kHasNcp = true, kHasSource = false, kLinear = true;
   static constexpr bool flux_nonzero(int, int v) { return v >= 6; }
   static constexpr bool grad_needed(int v) { return v >= 6; }
   static constexpr int sym(int i, int d) {
@@ -157,6 +165,65 @@ struct Elastic3 {
     return P[1];
   }
 
+  // --- transposes for the adjoint ---------------------------------------
+  __device__ static __forceinline__ void flux_T(int d, const PdeConsts&, const double* lamF,
+                                                double* lamQ) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lamQ[sym(i, d)] += lamF[6 + i];
+  }
+
+  // B = E(lambda, mu) grad(rho v) / rho: the adjoint of the velocity
+  // gradient, lamG[d][6 + i] = (E^T lamB)_{i d} / rho.
+  __device__ static __forceinline__ void ncp_T(const double* P, const PdeConsts&,
+                                               const double* lamB, double (*lamG)[NV]) {
+    const double rho = P[0], cp = P[1], cs = P[2];
+    const double mu = rho * cs * cs;
+    const double lam = rho * cp * cp - 2.0 * mu;
+    const double ir = 1.0 / rho;
+    const double ldiv = lam * (lamB[0] + lamB[1] + lamB[2]);
+    double lg[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lg[i][i] = 2.0 * mu * lamB[i] + ldiv;
+    lg[0][1] = lg[1][0] = mu * lamB[3];
+    lg[0][2] = lg[2][0] = mu * lamB[4];
+    lg[1][2] = lg[2][1] = mu * lamB[5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lamG[d][6 + i] += lg[i][d] * ir;
+  }
+
+  // derivatives of B with respect to (rho, cp, cs) through mu, lambda and 1/rho
+  __device__ static __forceinline__ void ncp_dparams_T(const double* P, const PdeConsts&,
+                                                       const double (*g)[NV], const double* lamB,
+                                                       double* gp) {
+    const double rho = P[0], cp = P[1], cs = P[2];
+    const double mu = rho * cs * cs;
+    const double lam = rho * cp * cp - 2.0 * mu;
+    const double ir = 1.0 / rho;
+    double gv[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gv[i][d] = g[d][6 + i] * ir;
+    const double divv = gv[0][0] + gv[1][1] + gv[2][2];
+    // a = lamB . E(1, 0) gv (the lambda part), b = lamB . E(0, 1) gv (the mu part)
+    const double a = (lamB[0] + lamB[1] + lamB[2]) * divv;
+    const double b = 2.0 * (lamB[0] * gv[0][0] + lamB[1] * gv[1][1] + lamB[2] * gv[2][2]) +
+                     lamB[3] * (gv[0][1] + gv[1][0]) + lamB[4] * (gv[0][2] + gv[2][0]) +
+                     lamB[5] * (gv[1][2] + gv[2][1]);
+    // d/d rho: dmu = cs^2, dlam = cp^2 - 2 cs^2, and gv scales with -1/rho
+    gp[0] += cs * cs * b + (cp * cp - 2.0 * cs * cs) * a - ir * (mu * b + lam * a);
+    gp[1] += 2.0 * rho * cp * a;
+    gp[2] += 2.0 * rho * cs * b - 4.0 * rho * cs * a;
+  }
+
+  __device__ static __forceinline__ void source_T(const PdeConsts&, const double*, double*) {}
+
+  __device__ static __forceinline__ void max_eigen_dparams(const double*, int, double s, double* gp) {
+    gp[1] += s;
+  }
+
   template <class R>
   __device__ static __forceinline__ bool admissible(const R* Q, const R* P, const PdeConsts&) {
     bool ok = true;
@@ -172,7 +239,7 @@ struct Elastic3 {
 template <int DIM_>
 struct Advection {
   static constexpr int DIM = DIM_, NV = 1, NP = 0;
-  static constexpr bool kHasNcp = false, kHasSource = true;
+  static constexpr bool kHasNcp = false, kHasSource = true, kLinear = true;
   static constexpr bool flux_nonzero(int, int) { return true; }
   static constexpr bool grad_needed(int) { return false; }
 
@@ -195,6 +262,20 @@ struct Advection {
   __device__ static __forceinline__ R max_eigen(const R*, const R*, const PdeConsts& pc, int d) {
     return fabs(R(pc.adv[d]));
   }
+
+  __device__ static __forceinline__ void flux_T(int d, const PdeConsts& pc, const double* lamF,
+                                                double* lamQ) {
+    lamQ[0] += pc.adv[d] * lamF[0];
+  }
+  __device__ static __forceinline__ void ncp_T(const double*, const PdeConsts&, const double*,
+                                               double (*)[NV]) {}
+  __device__ static __forceinline__ void ncp_dparams_T(const double*, const PdeConsts&,
+                                                       const double (*)[NV], const double*, double*) {}
+  __device__ static __forceinline__ void source_T(const PdeConsts& pc, const double* lamS,
+                                                  double* lamQ) {
+    lamQ[0] += -pc.kappa * lamS[0];
+  }
+  __device__ static __forceinline__ void max_eigen_dparams(const double*, int, double, double*) {}
   template <class R>
   __device__ static __forceinline__ bool admissible(const R* Q, const R*, const PdeConsts&) {
     return finite_val(Q[0]);

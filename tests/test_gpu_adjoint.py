@@ -1,0 +1,217 @@
+"""Parity of the HIP discrete adjoint (through the C ABI) with the oracle's.
+
+Bar: relative L2 <= 1e-12 for dJ/du^n and dJ/dm of one adjoint step and of
+the checkpointed multi-step misfit gradient, on the same seeded inputs; the
+adjoint identity <lam, A u> = <A^T lam, u> on the GPU's own step; central
+finite differences of the GPU misfit against the GPU gradient to 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_07987_amd import adg, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def elastic_case(cells, N, seed, sources=None):
+    hi = [500.0 * c for c in cells]
+    P = O.problem(3, N, O.ELASTIC, list(cells), hi=hi, sources=sources or ())
+    s = adg.Solver(3, N, "elastic", list(cells), [0.0] * 3, hi)
+    if sources:
+        s.set_point_sources([dict(x=src["x"], weight=src["w"], f0=src["f0"], t0=src["t0"],
+                                  amp=src["amp"]) for src in sources])
+    rng = np.random.default_rng(seed)
+    params = np.column_stack([rng.uniform(2000, 3000, P.ncells), rng.uniform(5000, 7000, P.ncells),
+                              rng.uniform(2500, 3400, P.ncells)])
+    u = rng.normal(size=(P.ncells, 9, P.S)) * np.array([6000.0] * 6 + [1.0] * 3)[None, :, None]
+    lam = rng.normal(size=u.shape)
+    dt = 0.5 * O.stable_dt(P, u, params)[0]
+    return s, P, params, u, lam, dt
+
+
+def gpu_adjoint(s, u, params, lam, dt, t=0.0):
+    lam_d = dev(lam)
+    g_d = torch.zeros((s.ncells, s.nparam), dtype=torch.float64, device="cuda") if s.nparam else None
+    s.step_adjoint(dev(u), dev(params) if params is not None else None, dev([t, dt]), lam_d, g_d)
+    torch.cuda.synchronize()
+    return lam_d.cpu().numpy(), (g_d.cpu().numpy() if g_d is not None else None)
+
+
+@pytest.mark.parametrize("N,cells", [(1, (5, 4, 3)), (2, (4, 3, 5)), (3, (3, 4, 3)), (3, (7, 6, 5))])
+def test_step_adjoint_elastic_vs_oracle(N, cells):
+    say(f"elastic adjoint N={N} cells={cells}")
+    s, P, params, u, lam, dt = elastic_case(cells, N, seed=10 + N)
+    lam_g, g_g = gpu_adjoint(s, u, params, lam, dt)
+    lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.0, lam)
+    e_l, e_g = rel_l2(lam_g, lam_o), rel_l2(g_g[:, 1:], g_o[:, 1:])
+    say(f"  rel L2 lam {e_l:.2e}, grad(cp, cs) {e_g:.2e}")
+    assert e_l <= TOL and e_g <= TOL
+    # rho: analytically zero (rho cancels); both sides at rounding level
+    assert np.abs(g_g[:, 0]).max() <= 1e-10 * np.abs(g_o[:, 1:]).max()
+
+
+def test_step_adjoint_elastic_point_source_vs_oracle():
+    """A point source changes the forward iterates and so dJ/dm."""
+    src = [dict(x=(700.0, 900.0, 400.0), w=[0.0] * 6 + [0.3, -0.2, 1.0], f0=5.0, t0=0.1, amp=1e7)]
+    s, P, params, u, lam, dt = elastic_case((3, 3, 2), 3, seed=21, sources=src)
+    u *= 1e-3
+    lam_g, g_g = gpu_adjoint(s, u, params, lam, dt, t=0.05)
+    lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.05, lam)
+    e_l, e_g = rel_l2(lam_g, lam_o), rel_l2(g_g[:, 1:], g_o[:, 1:])
+    say(f"point source: rel L2 lam {e_l:.2e}, grad {e_g:.2e}")
+    assert e_l <= TOL and e_g <= TOL
+
+
+@pytest.mark.parametrize("dim,N,cells", [(2, 1, (7, 5)), (2, 3, (6, 9)), (2, 7, (3, 4)),
+                                         (3, 2, (4, 3, 5)), (3, 3, (3, 3, 4))])
+def test_step_adjoint_advection_vs_oracle(dim, N, cells):
+    say(f"advection adjoint dim={dim} N={N} cells={cells}")
+    adv = (0.7, -0.4, 0.3)[:dim]
+    P = O.problem(dim, N, O.ADVECTION, list(cells), adv=adv, kappa=1.3)
+    s = adg.Solver(dim, N, "advection", list(cells), adv=adv, kappa=1.3)
+    rng = np.random.default_rng(dim * 10 + N)
+    u = rng.normal(size=(P.ncells, 1, P.S))
+    lam = rng.normal(size=u.shape)
+    dt = O.stable_dt(P, u)[0]
+    lam_g, _ = gpu_adjoint(s, u, None, lam, dt)
+    lam_o, _ = O.step_adjoint(P, u, None, dt, 0.0, lam)
+    e = rel_l2(lam_g, lam_o)
+    say(f"  rel L2 {e:.2e}")
+    assert e <= TOL
+
+
+def test_step_adjoint_dot_product_on_gpu_step():
+    """<lam, A u> (GPU forward) = <A^T lam, u> (GPU adjoint), source-free."""
+    s, P, params, u, lam, dt = elastic_case((6, 5, 4), 3, seed=31)
+    Q = dev(u)
+    s.step(Q, dev(params), dev([0.0, dt]), next_dt=False)
+    lam_n, _ = gpu_adjoint(s, u, params, lam, dt)
+    a = float((lam * Q.cpu().numpy()).sum())
+    b = float((lam_n * u).sum())
+    say(f"dot product: {a:.16e} vs {b:.16e}")
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_sample_receivers_adjoint_vs_oracle():
+    s, P, params, u, lam, dt = elastic_case((4, 3, 3), 2, seed=41)
+    rec = np.array([[300.0, 400.0, 200.0], [1700.0, 1100.0, 900.0], [320.0, 410.0, 260.0]])
+    s.set_receivers(rec)
+    rng = np.random.default_rng(42)
+    lamrec = rng.normal(size=(3, 9))
+    lam_d = dev(lam)
+    s.sample_receivers_adjoint(dev(lamrec), lam_d)
+    torch.cuda.synchronize()
+    ref = lam.copy()
+    O.sample_receivers_T(P, rec, lamrec, ref)
+    e = rel_l2(lam_d.cpu().numpy() - lam, ref - lam)
+    say(f"receiver transpose rel L2 {e:.2e}")
+    assert e <= TOL
+
+
+def misfit_case(seed=5, steps=6):
+    cells = (4, 3, 3)
+    lo, hi = [0.0] * 3, [2000.0, 1500.0, 1500.0]
+    src = dict(x=(1250.0, 750.0, 600.0), w=[0.0] * 8 + [1.0], f0=5.0, t0=0.0, amp=1e6)
+    P = O.problem(3, 2, O.ELASTIC, list(cells), lo, hi, sources=[src])
+    s = adg.Solver(3, 2, "elastic", list(cells), lo, hi)
+    s.set_point_sources([dict(x=src["x"], weight=src["w"], f0=src["f0"], t0=src["t0"], amp=src["amp"])])
+    cen = inputs.cell_centres(cells, lo, hi)
+    params = inputs.layered_material(cen[:, 2] * 4.0, seed)
+    params_obs = params * (1.0 + 0.05 * np.random.default_rng(seed + 1).uniform(-1, 1, params.shape))
+    rec = np.array([[300.0, 400.0, 200.0], [1700.0, 1100.0, 900.0], [1000.0, 700.0, 1400.0]])
+    s.set_receivers(rec)
+    u0 = np.zeros((P.ncells, 9, P.S))
+    dt = 0.5 * min(O.stable_dt(P, u0, params)[0], O.stable_dt(P, u0, params_obs)[0])
+    _, data, _ = O.seismogram_misfit(P, u0, params_obs, dt, steps, rec)
+    cellsr = np.array([int(x[0] // 500) + 4 * (int(x[1] // 500) + 3 * int(x[2] // 500)) for x in rec])
+    return s, P, params, u0, dt, steps, rec, data, cellsr
+
+
+def gpu_misfit(s, u0, params, dt, steps, data, cellsr, every):
+    from paper_1905_07987_amd.autograd import seismograms
+    u = dev(u0).requires_grad_(True)
+    m = dev(params).requires_grad_(True)
+    samp = seismograms(s, u, m, dt, steps, every=every)
+    rho = m[torch.as_tensor(cellsr, device="cuda"), 0]
+    v = samp[:, :, 6:9] / rho[None, :, None]
+    J = 0.5 * dt * ((v - dev(data)) ** 2).sum()
+    return J, u, m
+
+
+@pytest.mark.parametrize("every", [1, 2, 4, 6])
+def test_misfit_gradient_vs_oracle(every):
+    s, P, params, u0, dt, steps, rec, data, cellsr = misfit_case()
+    J, u, m = gpu_misfit(s, u0, params, dt, steps, data, cellsr, every)
+    J.backward()
+    Jo, gu_o, gm_o = O.misfit_gradient(P, u0, params, dt, steps, rec, data)
+    e_J = abs(float(J) - Jo) / Jo
+    e_u = rel_l2(u.grad.cpu().numpy(), gu_o)
+    e_m = rel_l2(m.grad.cpu().numpy(), gm_o)
+    say(f"misfit every={every}: J {e_J:.2e}, dJ/du0 {e_u:.2e}, dJ/dm {e_m:.2e}")
+    assert e_J <= TOL and e_u <= TOL and e_m <= TOL
+
+
+def test_misfit_gradient_finite_differences_on_gpu():
+    """Central differences of the GPU misfit at the largest-gradient entries."""
+    s, P, params, u0, dt, steps, rec, data, cellsr = misfit_case(seed=7)
+    J, u, m = gpu_misfit(s, u0, params, dt, steps, data, cellsr, every=3)
+    J.backward()
+    g = m.grad.cpu().numpy()
+    flat = np.abs(g).ravel()
+    cand = np.nonzero(flat >= 1e-2 * flat.max())[0]
+    rng = np.random.default_rng(11)
+    for idx in rng.choice(cand, size=min(6, len(cand)), replace=False):
+        c, p = divmod(int(idx), 3)
+        h = 1e-4 * params[c, p]
+        vals = []
+        for sgn in (1, -1):
+            pp = params.copy()
+            pp[c, p] += sgn * h
+            with torch.no_grad():
+                Jx, _, _ = gpu_misfit(s, u0, pp, dt, steps, data, cellsr, every=3)
+            vals.append(float(Jx))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"cell {c} param {p}: fd {fd:.10e} adjoint {g[c, p]:.10e}")
+        assert abs(fd - g[c, p]) <= 1e-6 * abs(fd)
+
+
+def test_adjoint_error_paths():
+    e = adg.Solver(3, 2, "euler", [2, 2, 2])
+    Q = torch.zeros(e.state_shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(adg.AdgError) as ei:
+        e.step_adjoint(Q, None, dev([0.0, 1e-3]), Q.clone())
+    assert ei.value.status == -4
+    s = adg.Solver(3, 4, "elastic", [2, 2, 2])
+    Q = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+    prm = torch.ones((s.ncells, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(adg.AdgError) as ei:
+        s.step_adjoint(Q, prm, dev([0.0, 1e-3]), Q.clone(), prm.clone())
+    assert ei.value.status == -4
+    s = adg.Solver(3, 2, "elastic", [2, 2, 2], picard_iters=5)
+    Q = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+    prm = torch.ones((s.ncells, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(adg.AdgError) as ei:
+        s.step_adjoint(Q, prm, dev([0.0, 1e-3]), Q.clone(), prm.clone())
+    assert ei.value.status == -4
+    s = adg.Solver(3, 2, "elastic", [2, 2, 2])
+    with pytest.raises(ValueError):
+        s.step_adjoint(Q, prm, dev([0.0, 1e-3]), Q.clone(), None)
+    with pytest.raises(adg.AdgError) as ei:
+        s.sample_receivers_adjoint(torch.zeros((0, 9), dtype=torch.float64, device="cuda"), Q)
+    assert ei.value.status == -6
