@@ -57,17 +57,20 @@ def euler_flux_flops(dim: int) -> int:
 
 def kernel_source_hash() -> str:
     """Hash of the FP64 predictor's source: its layout struct, its kernel body
-    and the PDE terms it inlines."""
+    and the Euler terms it inlines."""
     csrc = os.path.join(ROOT, "paper_1905_07987_amd", "csrc")
     k = open(os.path.join(csrc, "kernels.hpp")).read()
     a = k.index("struct GeoA2 {")
     b = k.index("};", a)
     c = k.index("// Kernel A, a lane pair per node")
     d = k.index("// Kernel B:", c)
+    pde = open(os.path.join(csrc, "pde.hpp")).read()
+    e = pde.index("struct Euler {")
+    f = pde.index("\n};", e)
     h = hashlib.sha256()
     h.update(k[a:b].encode())
     h.update(k[c:d].encode())
-    h.update(open(os.path.join(csrc, "pde.hpp"), "rb").read())
+    h.update(pde[e:f].encode())
     return h.hexdigest()[:16]
 
 
@@ -108,6 +111,125 @@ def cpu_baseline(cells: int, N: int):
                       f"workload on {cells}^3 periodic cells, {el:.2f} s wall"}
 
 
+def adjoint_c4(log, steps: int | None = None, every: int = 15):
+    """C4: seconds per gradient of the seismogram misfit of the 3-D elastic
+    workload (N=3, 32^3 cells, 200 steps, 16 receivers) with respect to the
+    per-cell (rho, cp, cs) and the initial state: forward run with
+    checkpoints every `every` steps, then per segment the recomputation and
+    the adjoint steps (autograd Function over the library's adjoint)."""
+    import torch
+    from paper_1905_07987_amd import adg, inputs
+    from paper_1905_07987_amd.autograd import seismograms
+    cfg = inputs.elastic_config("c4")
+    steps = steps or cfg["steps"]
+    s = adg.Solver(3, cfg["order"], "elastic", cfg["cells"], cfg["lo"], cfg["hi"])
+    s.set_point_sources([cfg["source"]])
+    s.set_receivers(cfg["receivers"])
+    params = torch.as_tensor(cfg["params"], device="cuda")
+    pert = np.random.default_rng(cfg["seed"] + 1).uniform(-1.0, 1.0, cfg["params"].shape)
+    params_obs = torch.as_tensor(cfg["params"] * (1.0 + 0.05 * pert), device="cuda")
+    u0 = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+    clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+    s.stable_dt(u0, params, clock)
+    dt1 = float(clock[1])
+    s.stable_dt(u0, params_obs, clock)
+    dt = min(dt1, float(clock[1]))
+    h = [(cfg["hi"][d] - cfg["lo"][d]) / cfg["cells"][d] for d in range(3)]
+    rc = np.floor((cfg["receivers"] - np.array(cfg["lo"])) / np.array(h)).astype(np.int64)
+    cellsr = torch.as_tensor(rc[:, 0] + cfg["cells"][0] * (rc[:, 1] + cfg["cells"][1] * rc[:, 2]),
+                             device="cuda")
+    with torch.no_grad():
+        samp = seismograms(s, u0, params_obs, dt, steps)
+        data = samp[:, :, 6:9] / params_obs[cellsr, 0][None, :, None]
+
+    def grad_once():
+        m = params.clone().requires_grad_(True)
+        u = u0.clone().requires_grad_(True)
+        sm = seismograms(s, u, m, dt, steps, every=every)
+        v = sm[:, :, 6:9] / m[cellsr, 0][None, :, None]
+        J = 0.5 * dt * ((v - data) ** 2).sum()
+        J.backward()
+        return J, u.grad, m.grad
+
+    grad_once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, gu, gm = grad_once()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # one forward step and one adjoint step, timed with events on the stream
+    stream = torch.cuda.current_stream()
+    Q = torch.randn(s.state_shape, dtype=torch.float64, device="cuda")
+    lam = torch.randn(s.state_shape, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(params)
+    ck = torch.tensor([0.0, dt], dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 10
+    for _ in range(2):
+        s.step_adjoint(Q, params, ck, lam, g)
+    ev[0].record(stream)
+    for _ in range(reps):
+        s.step(Q, params, ck.clone(), next_dt=False)
+    ev[1].record(stream)
+    for _ in range(reps):
+        s.step_adjoint(Q, params, ck, lam, g)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / reps
+    adj_ms = ev[1].elapsed_time(ev[2]) / reps
+    nseg = -(-steps // every)
+    res = {"s_per_grad": round(el, 4), "steps": steps, "checkpoint_every": every,
+           "checkpoints": nseg, "forward_step_ms": round(fwd_ms, 4),
+           "adjoint_step_ms": round(adj_ms, 4), "J": float(J),
+           "grad_norm_params": float(torch.linalg.vector_norm(gm)),
+           "workload": "c4: 3-D elastic, N=3, 32^3 cells, 16 receivers, Ricker source, "
+                       "misfit vs a +-5% perturbed material, FP64, dt frozen"}
+    log(f"adjoint c4: {el:.3f} s/grad (fwd step {fwd_ms:.3f} ms, adjoint step {adj_ms:.3f} ms)")
+    return res
+
+
+def elastic_c3(log, steps: int | None = None, cfl: float = 0.5):
+    """C3: 3-D elastic N=4 on 48^3 cells, layered perturbed material, Ricker
+    source, 32 receivers sampled after every step; FP64 and the FP32
+    predictor, with the FP32 run's error against the FP64 run."""
+    import torch
+    from paper_1905_07987_amd import adg, inputs
+    cfg = inputs.elastic_config("c3")
+    steps = steps or cfg["steps"]
+    params = torch.as_tensor(cfg["params"], device="cuda")
+    res = {}
+    out = {}
+    for prec in ("fp64", "fp32"):
+        s = adg.Solver(3, cfg["order"], "elastic", cfg["cells"], cfg["lo"], cfg["hi"], cfl=cfl,
+                       precision=prec)
+        s.set_point_sources([cfg["source"]])
+        s.set_receivers(cfg["receivers"])
+        Q = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+        seis = torch.empty((steps, s.nrec, 9), dtype=torch.float64, device="cuda")
+        clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+        s.stable_dt(Q, params, clock)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(steps):
+            s.step(Q, params, clock, next_dt=False)
+            s.sample_receivers(Q, seis[n])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dofs = s.ncells * s.S * 9
+        res[prec] = {"value": dofs * steps / el, "ms_per_step": round(el / steps * 1e3, 4)}
+        out[prec] = (Q, seis)
+        log(f"c3 {prec}: {el / steps * 1e3:.3f} ms/step, {dofs * steps / el:.3e} DoF/s")
+        del s
+    (Q64, s64), (Q32, s32) = out["fp64"], out["fp32"]
+    res["fp32"]["rel_l2_state_vs_fp64"] = float(torch.linalg.vector_norm(Q32 - Q64) /
+                                                torch.linalg.vector_norm(Q64))
+    res["fp32"]["rel_l2_seismograms_vs_fp64"] = float(torch.linalg.vector_norm(s32 - s64) /
+                                                      torch.linalg.vector_norm(s64))
+    res["workload"] = (f"c3: 3-D elastic, N=4, 48^3 cells, layered +-10% material, Ricker source, "
+                       f"32 receivers, {steps} steps, CFL_N {cfl}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +240,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the C4 adjoint gradient")
+    ap.add_argument("--no-elastic", action="store_true", help="skip the C3 elastic variant")
     ap.add_argument("--cpu-cells", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain elementwise copy of the state (known HBM bytes) "
@@ -209,6 +333,11 @@ def main():
                                   "rel_l2_vs_fp64_after_steps": err,
                                   "steps_compared": args.warmup + args.steps}
         log(f"mixed fp32: {t32 / args.steps:.3f} ms/step, {v32:.3e} DoF/s, rel L2 vs fp64 {err:.2e}")
+
+    if not args.no_elastic:
+        variants["elastic_c3"] = elastic_c3(log)
+    if not args.no_adjoint:
+        variants["adjoint_c4"] = adjoint_c4(log)
 
     cpu = None
     if not args.no_cpu_baseline:

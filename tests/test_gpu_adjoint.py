@@ -215,3 +215,94 @@ def test_adjoint_error_paths():
     with pytest.raises(adg.AdgError) as ei:
         s.sample_receivers_adjoint(torch.zeros((0, 9), dtype=torch.float64, device="cuda"), Q)
     assert ei.value.status == -6
+
+
+def test_c4_full_size_dot_product():
+    """32^3 cells, N=3: the adjoint step in the benchmark's launch
+    configuration against the GPU's own forward step (<lam, A u> = <A^T lam, u>
+    for the source-free step)."""
+    cfg = inputs.elastic_config("c4")
+    s = adg.Solver(3, 3, "elastic", list(cfg["cells"]), cfg["lo"], cfg["hi"])
+    prm = dev(cfg["params"])
+    g = torch.Generator(device="cuda").manual_seed(71)
+    u = torch.randn(s.state_shape, dtype=torch.float64, device="cuda", generator=g)
+    lam = torch.randn(s.state_shape, dtype=torch.float64, device="cuda", generator=g)
+    clock = dev([0.0, 0.0])
+    s.stable_dt(u, prm, clock)
+    Au = u.clone()
+    s.step(Au, prm, clock.clone(), next_dt=False)
+    lam_n = lam.clone()
+    gp = torch.zeros_like(prm)
+    s.step_adjoint(u, prm, clock, lam_n, gp)
+    a = float((lam * Au).sum())
+    b = float((lam_n * u).sum())
+    say(f"c4 dot product: {a:.16e} vs {b:.16e}")
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_c4_gradient_finite_differences():
+    """The C4 gradient (200 steps, 16 receivers, checkpoints every 15 steps)
+    against central differences of the GPU misfit on 20 seeded cells among
+    those with |g| >= 1e-2 max |g| (cp and cs; rho's gradient is the small
+    receiver-cell term only).  The misfit bends on the scale of a
+    travel-time shift: a plain central difference at h = 1e-4 of the
+    parameter still carries an O(h^2) error of up to 2e-6, and below 3e-5 the
+    forward solution's rounding noise takes over (1e-6 at h = 1e-5).  The
+    check therefore extrapolates central differences at h and 2h
+    (Richardson, error O(h^4)), h = 1e-4 of the parameter."""
+    from paper_1905_07987_amd.autograd import seismograms
+    cfg = inputs.elastic_config("c4")
+    steps = cfg["steps"]
+    s = adg.Solver(3, 3, "elastic", list(cfg["cells"]), cfg["lo"], cfg["hi"])
+    s.set_point_sources([cfg["source"]])
+    s.set_receivers(cfg["receivers"])
+    params = cfg["params"]
+    pert = np.random.default_rng(cfg["seed"] + 1).uniform(-1.0, 1.0, params.shape)
+    params_obs = params * (1.0 + 0.05 * pert)
+    u0 = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+    clock = dev([0.0, 0.0])
+    s.stable_dt(u0, dev(params), clock)
+    dt1 = float(clock[1])
+    s.stable_dt(u0, dev(params_obs), clock)
+    dt = min(dt1, float(clock[1]))
+    h = np.array([(cfg["hi"][d] - cfg["lo"][d]) / cfg["cells"][d] for d in range(3)])
+    rc = np.floor((cfg["receivers"] - np.array(cfg["lo"])) / h).astype(np.int64)
+    cellsr = torch.as_tensor(rc[:, 0] + cfg["cells"][0] * (rc[:, 1] + cfg["cells"][1] * rc[:, 2]),
+                             device="cuda")
+    with torch.no_grad():
+        sm = seismograms(s, u0, dev(params_obs), dt, steps)
+        data = sm[:, :, 6:9] / dev(params_obs)[cellsr, 0][None, :, None]
+
+    def misfit(m):
+        sm = seismograms(s, u0, m, dt, steps, every=15)
+        v = sm[:, :, 6:9] / m[cellsr, 0][None, :, None]
+        return 0.5 * dt * ((v - data) ** 2).sum()
+
+    say("c4: gradient")
+    m = dev(params).requires_grad_(True)
+    J = misfit(m)
+    J.backward()
+    g = m.grad.cpu().numpy()
+    flat = np.abs(g[:, 1:]).ravel()
+    cand = np.nonzero(flat >= 1e-2 * flat.max())[0]
+    rng = np.random.default_rng(7989)
+    picks = rng.choice(cand, size=min(20, len(cand)), replace=False)
+    worst = 0.0
+    for idx in picks:
+        c, p = divmod(int(idx), 2)
+        p += 1
+        hstep = 1e-4 * params[c, p]
+        cd = []
+        for hh in (hstep, 2 * hstep):
+            vals = []
+            for sgn in (1, -1):
+                pp = params.copy()
+                pp[c, p] += sgn * hh
+                with torch.no_grad():
+                    vals.append(float(misfit(dev(pp))))
+            cd.append((vals[0] - vals[1]) / (2 * hh))
+        fd = (4.0 * cd[0] - cd[1]) / 3.0
+        err = abs(fd - g[c, p]) / abs(fd)
+        worst = max(worst, err)
+        assert err <= 1e-6, (c, p, fd, g[c, p])
+    say(f"c4: 20 cells, worst relative difference {worst:.2e}")

@@ -332,3 +332,58 @@ def test_c2_full_size_sampled():
     ref = O.step_cells(P, Q0, None, dt_o, 0.0, sample)
     got = Qd[torch.as_tensor(sample, device="cuda")].cpu().numpy()
     assert rel_l2(got, ref) <= TOL, rel_l2(got, ref)
+
+
+def test_c3_full_size_sampled():
+    """48^3 cells, N=4 elastic with the layered material, the Ricker source and
+    the 32 receivers, in the benchmark's launch configuration: one GPU step
+    checked on sampled cells (the source cell, every receiver cell, periodic
+    corners, random cells) that the oracle computes one by one, and the
+    receiver samples against the oracle's interpolation in those cells."""
+    say("c3 full size: setup")
+    cfg = inputs.elastic_config("c3")
+    cells, lo, hi = list(cfg["cells"]), list(cfg["lo"]), list(cfg["hi"])
+    src = dict(cfg["source"])
+    src["t0"] = 0.0  # the source is active at t = 0
+    s, P = pair(3, 4, "elastic", cells, lo, hi, sources=[src], cfl=0.5)
+    s.set_point_sources([src])
+    s.set_receivers(cfg["receivers"])
+    prm = cfg["params"]
+    xyz = s.node_coords()
+    Q0 = inputs.elastic_smooth_state(xyz, 61, scale_sigma=1e3, scale_rhov=1.0)
+    del xyz
+    Qd, pd = dev(Q0), dev(prm)
+    clock = dev([0.0, 0.0])
+    say("c3 full size: gpu step")
+    s.stable_dt(Qd, pd, clock)
+    s.step(Qd, pd, clock, next_dt=True)
+    out = torch.empty((len(cfg["receivers"]), 9), dtype=torch.float64, device="cuda")
+    s.sample_receivers(Qd, out)
+    torch.cuda.synchronize()
+    dt_o = O.stable_dt(P, Q0, prm)[0]
+    assert abs(float(clock[0]) - dt_o) <= 4 * np.finfo(float).eps * dt_o
+    h = np.array([(hi[d] - lo[d]) / cells[d] for d in range(3)])
+
+    def cell_of(x):
+        cc = np.floor((np.asarray(x) - np.array(lo)) / h).astype(int)
+        return int(cc[0] + cells[0] * (cc[1] + cells[1] * cc[2]))
+
+    rec_cells = [cell_of(x) for x in cfg["receivers"]]
+    C = P.ncells
+    rng = np.random.default_rng(6)
+    sample = np.unique(np.concatenate([[0, C - 1, cell_of(src["x"]), 47, 48 * 48 - 1],
+                                       rec_cells, rng.integers(0, C, 12)]))
+    say("c3 full size: oracle on", len(sample), "cells")
+    O.set_threads(8)
+    ref = O.step_cells(P, Q0, prm, dt_o, 0.0, sample)
+    got = Qd[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    assert rel_l2(got, ref) <= TOL, rel_l2(got, ref)
+    # receivers: the oracle's interpolation inside each receiver's cell
+    pos = {int(c): i for i, c in enumerate(sample)}
+    ro = np.zeros((len(rec_cells), 9))
+    for r, (x, c) in enumerate(zip(cfg["receivers"], rec_cells)):
+        cc = np.floor((np.asarray(x) - np.array(lo)) / h)
+        clo = np.array(lo) + cc * h
+        P1 = O.problem(3, 4, O.ELASTIC, [1, 1, 1], list(clo), list(clo + h))
+        ro[r] = O.sample_receivers(P1, [x], ref[pos[c]][None])[0]
+    np.testing.assert_allclose(out.cpu().numpy(), ro, rtol=0, atol=TOL * np.abs(ro).max())
