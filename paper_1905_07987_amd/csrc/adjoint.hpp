@@ -36,6 +36,10 @@
 //     Rusanov flux's parameter derivative at every face of the cell.
 #pragma once
 
+#ifndef ADJ_MIN_WAVES
+#define ADJ_MIN_WAVES 2
+#endif
+
 namespace adg {
 
 // Value of f(i) for a lane-dependent index i < n, built from compile-time
@@ -48,19 +52,29 @@ __device__ __forceinline__ double ct_pick(int i, Fn f) {
   return r;
 }
 
-// Predictor-adjoint layout: one thread per (time slice j, node k) of a cell,
-// thread t = j S + k, CPB cells per block.  LDS per cell holds, in turn,
-// the derivative rows of one direction (NFL + 2 NGR channels for every slice,
-// line-major as in the forward kernels) or the time-exchange buffer [NV][n][S]
-// plus qbar [NV][S].
+// Predictor-adjoint layout: one thread per (node k, time slice j) of a cell,
+// thread t = k n + j (the slices of a node are adjacent lanes), CPB cells per
+// block.  LDS per cell holds, in turn, the derivative rows of one direction
+// (NFL + 2 NGR channels, each [line][position][slice] with a per-direction
+// line stride), the time-exchange buffer [NV][S][n] (where slices are not
+// exchanged by DPP), qbar [NV][S], or the parameter-gradient partials.
 template <class PDE, int N>
 struct GeoAdj {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
+  static constexpr int n = G::n, S = G::S, F = G::F, DIM = G::DIM, NV = G::NV;
   static constexpr int NGR = C::ngrad();
-  static constexpr int TPC = G::n * G::S;
-  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * G::n * G::SP;
-  static constexpr int TIME_ELEMS = G::NV * G::n * G::S + G::NV * G::S;
+  static constexpr int TPC = n * S;
+  // the n slices of a node sit in one lane quad: exchange them with DPP
+  static constexpr bool kDppTime = (n == 2 || n == 4);
+  // Line stride of the derivative rows of direction d.  For n = 4 in 3-D,
+  // 4 / 5 / 5 place the 32-byte slice groups that a half-wave (8 nodes)
+  // writes, and the line elements it reads, in distinct bank groups;
+  // otherwise the forward kernels' stride.
+  static constexpr int ls(int d) { return (DIM == 3 && n == 4) ? (d == 0 ? 4 : 5) : G::LS; }
+  static constexpr int SPMAX = F * cmax(ls(0), cmax(ls(1), ls(DIM - 1)));
+  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * SPMAX * n;
+  static constexpr int TIME_ELEMS = (kDppTime ? 0 : NV * S * n) + NV * S;
   static constexpr int RED_ELEMS = TPC * (G::NP > 0 ? G::NP : 1);
   static constexpr int CELL_ELEMS = cmax(cmax(DER_ELEMS, TIME_ELEMS), RED_ELEMS);
   static constexpr int by_threads = TPC >= 256 ? 1 : 256 / TPC;
@@ -69,6 +83,7 @@ struct GeoAdj {
   static constexpr int BLOCK = CPB * TPC;
   static constexpr bool supported =
       PDE::kLinear && C::uniform() && BLOCK <= 512 && CPB * CELL_ELEMS * 8 <= 56 * 1024;
+  static constexpr int MIN_WAVES = ADJ_MIN_WAVES;
 };
 
 // Face kernels: one thread per (cell, face, face node); CPB_R cells per block.
@@ -266,12 +281,37 @@ adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const doubl
 // Reverse, with mu_j the adjoint of the current iterate's slice j:
 //   mu^I_j = w_j (trace^T lamhat + R^T (dt lam))   (R^T on slice j with
 //            nu_j = dt w_j lam, paired with q^I_j for the parameters)
-//   for r = I-1 .. 0:  lam_u += sum_j mu_j;  nu_j = dt sum_i KW_ij mu_i;
+//   for r = I-1 .. 1:  lam_u += sum_j mu_j;  nu_j = dt sum_i KW_ij mu_i;
 //                      mu_j = R^T nu_j;  gparams += (dR/dm (q^r_j))^T nu_j
-//   lam_u += sum_j mu_j;  lam^n = lam + lam_u.
+//   r = 0 (q^0_j = u for every j, so only the sum over j matters):
+//     lam_u += sum_j mu_j + R^T nu,  gparams += (dR/dm (u))^T nu,
+//     nu = dt sum_i (sum_j KW_ij) mu_i
+//   lam^n = lam + lam_u.
+// The forward iterate r = 0 likewise evaluates R(u) once (point sources,
+// which differ per time node, are added per slice).
 // ---------------------------------------------------------------------------
+
+// Broadcast lane i of each group of n adjacent lanes (n = 2 or 4) to the
+// group: one DPP quad permutation per 32-bit half.
+template <int n, int i>
+__device__ __forceinline__ double group_bcast(double x) {
+  constexpr int ctrl = n == 4 ? (i | (i << 2) | (i << 4) | (i << 6))
+                              : (i | (i << 2) | ((2 + i) << 4) | ((2 + i) << 6));
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 template <class PDE, int N>
-__global__ void __launch_bounds__((GeoAdj<PDE, N>::BLOCK))
+__global__ void __launch_bounds__((GeoAdj<PDE, N>::BLOCK), (GeoAdj<PDE, N>::MIN_WAVES))
 adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
                    const double* __restrict__ clock, double* __restrict__ lam,
                    double* __restrict__ gparams, double* __restrict__ hat) {
@@ -280,10 +320,11 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   using GA = GeoAdj<PDE, N>;
   using T = CT<double, G::n>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GA::CPB, TPC = GA::TPC, SP = G::SP, LS = G::LS;
+  constexpr int CPB = GA::CPB, TPC = GA::TPC, SPM = GA::SPMAX;
   constexpr int NFL = C::NFLUX, NGR = GA::NGR;
   constexpr int NPX = NP > 0 ? NP : 1, NGX = NGR > 0 ? NGR : 1;
   constexpr int IMAX = N + 1;  // the host admits picard_iters <= N + 1
+  constexpr bool DPP = GA::kDppTime;
   static_assert(GA::supported, "adjoint not available for this PDE and order");
   __shared__ double lds[CPB * GA::CELL_ELEMS];
   __shared__ double src_amp[kMaxSources * n];
@@ -291,13 +332,15 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   const int tid = threadIdx.x;
   const int lc = tid / TPC;
   const int t = tid - lc * TPC;
-  const int j = t / S;
-  const int k = t - j * S;
+  const int k = t / n;      // node
+  const int j = t - k * n;  // time slice (adjacent lanes share a node)
   const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
   const long long cell = cell0 + lc;
   const bool active = cell < a.ncells;
   const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
   double* const buf = lds + lc * GA::CELL_ELEMS;
+  double* const tbuf = buf;                                // [NV][S][n] (LDS time exchange)
+  double* const qb = buf + (DPP ? 0 : NV * S * n);         // [NV][S]
 
   int kk[3] = {0, 0, 0};
   node_coords<DIM>(k, n, kk);
@@ -305,14 +348,12 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     ln[d] = G::line_of(d, kk[0], kk[1], DIM == 3 ? kk[2] : 0);
-    pk[d] = ln[d] * LS + kk[d];
+    pk[d] = ln[d] * GA::ls(d) + kk[d];
   }
-  // Lane-dependent entries of D (row kk_d or column kk_d) and KW (row or
-  // column j), rebuilt from compile-time constants where they are used.
+  // Lane-dependent entries of D (row or column kk_d) and KW (row or column
+  // j), rebuilt from compile-time constants where they are used.
   auto Drow = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(i, m); }); };
   auto Dcol = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(m, i); }); };
-  auto KWrow = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(jj, i); }); };
-  auto KWcol = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(i, jj); }); };
   const double wj = ct_pick<n>(j, [&](int jj) { return T::w(jj); });
 
   const double t_n = clock[0], dt = clock[1];
@@ -323,8 +364,6 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
 
-  // Point sources enter the forward iterates (and so the parameter
-  // derivative), exactly as in the forward predictor.
   bool src_here = false;
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
@@ -334,8 +373,64 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   }
   __syncthreads();
 
-  // R(q) of slice j at this node (forward).
-  auto rhs = [&](const double (&q)[NV], double (&R)[NV]) {
+  // out[v] = sum_i coef(i) x_i[v], x_i held by slice i of this node
+  auto tsum = [&](const double (&x)[NV], auto coef, double (&out)[NV]) {
+    if constexpr (DPP) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = 0.0;
+      static_for<0, n>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        const double c = coef(i);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] += c * group_bcast<n, i>(x[v]);
+      });
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tbuf[(v * S + k) * n + j] = x[v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) acc += coef(i) * tbuf[(v * S + k) * n + i];
+        out[v] = acc;
+      }
+      __syncthreads();
+    }
+  };
+  // every slice of the node receives slice 0's x
+  auto bcast0 = [&](double (&x)[NV]) {
+    if constexpr (DPP) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = group_bcast<n, 0>(x[v]);
+    } else {
+      if (j == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tbuf[v * S + k] = x[v];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = tbuf[v * S + k];
+      __syncthreads();
+    }
+  };
+  auto add_point_sources = [&](double (&R)[NV]) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const double amp = src_amp[s * n + j];
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] += amp * wsk[v];
+    }
+  };
+  // LDS slot of channel c at line position m (or this node) for direction d
+  auto row = [&](int c, int d, int m) { return (c * SPM + ln[d] * GA::ls(d) + m) * n + j; };
+  auto mine = [&](int c, int d) { return (c * SPM + pk[d]) * n + j; };
+
+  // R(q) of slice j without point sources.  Lanes with act == false take
+  // part in the barriers only.
+  auto rhs = [&](const double (&q)[NV], double (&R)[NV], bool act) {
     double Fd[DIM][NV];
     PDE::fluxes(q, P, a.pde, Fd);
     if constexpr (PDE::kHasSource) {
@@ -344,42 +439,36 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 #pragma unroll
       for (int v = 0; v < NV; ++v) R[v] = 0.0;
     }
-    if (src_here) {
-      for (int s = 0; s < a.nsrc; ++s) {
-        if (a.src[s].cell != cell) continue;
-        const double amp = src_amp[s * n + j];
-        const double* wsk = a.src_w + ((long long)s * S + k) * NV;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v] += amp * wsk[v];
-      }
-    }
     double g[DIM][NV];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) g[d][v] = 0.0;
+      if (act) {
 #pragma unroll
-      for (int c = 0; c < NFL; ++c) buf[(c * n + j) * SP + pk[d]] = Fd[d][C::flux_var(d, c)];
+        for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = Fd[d][C::flux_var(d, c)];
 #pragma unroll
-      for (int c = 0; c < NGR; ++c) buf[((NFL + c) * n + j) * SP + pk[d]] = q[C::grad_var(c)];
-      __syncthreads();
-      const double* row = buf + j * SP + ln[d] * LS;
-      double Dr[n];
-#pragma unroll
-      for (int m = 0; m < n; ++m) Dr[m] = Drow(d, m);
-#pragma unroll
-      for (int c = 0; c < NFL; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dr[m] * row[c * n * SP + m];
-        R[C::flux_var(d, c)] -= acc * a.inv_h[d];
+        for (int c = 0; c < NGR; ++c) buf[mine(NFL + c, d)] = q[C::grad_var(c)];
       }
+      __syncthreads();
+      if (act) {
+        double Dr[n];
 #pragma unroll
-      for (int c = 0; c < NGR; ++c) {
-        double acc = 0.0;
+        for (int m = 0; m < n; ++m) Dr[m] = Drow(d, m);
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dr[m] * row[(NFL + c) * n * SP + m];
-        g[d][C::grad_var(c)] = acc * a.inv_h[d];
+        for (int c = 0; c < NFL; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) acc += Dr[m] * buf[row(c, d, m)];
+          R[C::flux_var(d, c)] -= acc * a.inv_h[d];
+        }
+#pragma unroll
+        for (int c = 0; c < NGR; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) acc += Dr[m] * buf[row(NFL + c, d, m)];
+          g[d][C::grad_var(c)] = acc * a.inv_h[d];
+        }
       }
       __syncthreads();
     }
@@ -392,7 +481,8 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   };
 
   // mu = R^T nu for slice j; gp += (dR/dm at the forward values fw)^T nu.
-  auto rhs_T = [&](const double (&nu)[NV], const double (&fw)[NGX], double (&mu)[NV], double (&gp)[NPX]) {
+  auto rhs_T = [&](const double (&nu)[NV], const double (&fw)[NGX], double (&mu)[NV],
+                   double (&gp)[NPX], bool act) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) mu[v] = 0.0;
     PDE::source_T(a.pde, nu, mu);
@@ -406,50 +496,58 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     if constexpr (PDE::kHasNcp) PDE::ncp_T(P, a.pde, lB, lG);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      if (act) {
 #pragma unroll
-      for (int c = 0; c < NFL; ++c) buf[(c * n + j) * SP + pk[d]] = nu[C::flux_var(d, c)];
+        for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = nu[C::flux_var(d, c)];
 #pragma unroll
-      for (int c = 0; c < NGR; ++c) {
-        buf[((NFL + c) * n + j) * SP + pk[d]] = lG[d][C::grad_var(c)];
-        buf[((NFL + NGR + c) * n + j) * SP + pk[d]] = fw[c];
+        for (int c = 0; c < NGR; ++c) {
+          buf[mine(NFL + c, d)] = lG[d][C::grad_var(c)];
+          buf[mine(NFL + NGR + c, d)] = fw[c];
+        }
       }
       __syncthreads();
-      const double* row = buf + j * SP + ln[d] * LS;
-      double Dr[n], Dc[n];
+      if (act) {
+        double Dr[n], Dc[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) {
-        Dr[m] = Drow(d, m);
-        Dc[m] = Dcol(d, m);
+        for (int m = 0; m < n; ++m) {
+          Dr[m] = Drow(d, m);
+          Dc[m] = Dcol(d, m);
+        }
+        double lF[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) lF[v] = 0.0;
+        // transposed derivative of the flux adjoints
+#pragma unroll
+        for (int c = 0; c < NFL; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) acc += Dc[m] * buf[row(c, d, m)];
+          lF[C::flux_var(d, c)] = -acc * a.inv_h[d];
+        }
+#pragma unroll
+        for (int c = 0; c < NGR; ++c) {
+          // transposed derivative of the gradient adjoints
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) acc += Dc[m] * buf[row(NFL + c, d, m)];
+          mu[C::grad_var(c)] += acc * a.inv_h[d];
+          // gradient of the forward iterate
+          double gacc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) gacc += Dr[m] * buf[row(NFL + NGR + c, d, m)];
+          g[d][C::grad_var(c)] = gacc * a.inv_h[d];
+        }
+        PDE::flux_T(d, a.pde, lF, mu);
       }
-      double lF[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) lF[v] = 0.0;
-      // transposed derivative of the flux adjoints
-#pragma unroll
-      for (int c = 0; c < NFL; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dc[m] * row[c * n * SP + m];
-        lF[C::flux_var(d, c)] = -acc * a.inv_h[d];
-      }
-#pragma unroll
-      for (int c = 0; c < NGR; ++c) {
-        // transposed derivative of the gradient adjoints
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < n; ++m) acc += Dc[m] * row[(NFL + c) * n * SP + m];
-        mu[C::grad_var(c)] += acc * a.inv_h[d];
-        // gradient of the forward iterate
-        double gacc = 0.0;
-#pragma unroll
-        for (int m = 0; m < n; ++m) gacc += Dr[m] * row[(NFL + NGR + c) * n * SP + m];
-        g[d][C::grad_var(c)] = gacc * a.inv_h[d];
-      }
-      PDE::flux_T(d, a.pde, lF, mu);
       __syncthreads();
     }
-    if constexpr (PDE::kHasNcp) PDE::ncp_dparams_T(P, a.pde, g, lB, gp);
+    if constexpr (PDE::kHasNcp) {
+      if (act) PDE::ncp_dparams_T(P, a.pde, g, lB, gp);
+    }
   };
+
+  auto KWrow = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(jj, i); }); };
+  auto KWcol = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(i, jj); }); };
 
   // ---- forward Picard sweep, keeping the gradient quantities of q^r ----
   double q[NV], fw[IMAX][NGX];
@@ -461,18 +559,18 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 #pragma unroll
       for (int c = 0; c < NGX; ++c) fw[r][c] = c < NGR ? q[C::grad_var(c)] : 0.0;
       double R[NV];
-      rhs(q, R);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = R[v];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < n; ++i) acc += KWrow(i) * buf[(v * n + i) * S + k];
-        q[v] = u[v] + dt * acc;
+      if (r == 0) {
+        // all slices of q^0 are u: one evaluation, then per-slice sources
+        rhs(q, R, j == 0);
+        bcast0(R);
+      } else {
+        rhs(q, R, true);
       }
-      __syncthreads();
+      add_point_sources(R);
+      double acc[NV];
+      tsum(R, KWrow, acc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] = u[v] + dt * acc[v];
     }
   }
 
@@ -493,16 +591,11 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 
   // ---- face traces of qbar into B (for the Rusanov parameter derivative) ----
   {
+    double qbar[NV];
+    tsum(q, [&](int i) { return T::w(i); }, qbar);
+    if (j == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = wj * q[v];
-    __syncthreads();
-    double* const qb = buf + NV * n * S;
-    for (int it = t; it < NV * S; it += TPC) {
-      const int v = it / S, kq = it - v * S;
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < n; ++i) s += buf[(v * n + i) * S + kq];
-      qb[it] = s;
+      for (int v = 0; v < NV; ++v) qb[v * S + k] = qbar[v];
     }
     __syncthreads();
     for (int it = t; it < 2 * DIM * NV * F; it += TPC) {
@@ -530,41 +623,49 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     double fI[NGX];
 #pragma unroll
     for (int c = 0; c < NGX; ++c) fI[c] = c < NGR ? q[C::grad_var(c)] : 0.0;
-    rhs_T(nu, fI, mu, gp);
+    rhs_T(nu, fI, mu, gp, true);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) mu[v] += wj * tseed[v];
 #pragma unroll
-  for (int r = IMAX - 1; r >= 0; --r) {
+  for (int r = IMAX - 1; r >= 1; --r) {
     if (r < I) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        lu[v] += mu[v];
-        buf[(v * n + j) * S + k] = mu[v];
-      }
-      __syncthreads();
+      for (int v = 0; v < NV; ++v) lu[v] += mu[v];
+      double acc[NV];
+      tsum(mu, KWcol, acc);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
+      for (int v = 0; v < NV; ++v) nu[v] = dt * acc[v];
+      rhs_T(nu, fw[r], mu, gp, true);
+    }
+  }
+  {
+    // r = 0 on the sum over slices, evaluated by slice 0
 #pragma unroll
-        for (int i = 0; i < n; ++i) acc += KWcol(i) * buf[(v * n + i) * S + k];
-        nu[v] = dt * acc;
-      }
-      __syncthreads();
-      rhs_T(nu, fw[r], mu, gp);
+    for (int v = 0; v < NV; ++v) lu[v] += mu[v];
+    double acc[NV];
+    tsum(mu, [&](int i) {
+      double s = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < n; ++jj) s += T::KW(i, jj);
+      return s;
+    }, acc);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) nu[v] = dt * acc[v];
+    rhs_T(nu, fw[0], mu, gp, j == 0);
+    if (j == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lu[v] += mu[v];
     }
   }
 
   // ---- lam^n = lam^{n+1} + sum_j lam_u,j; the cell's parameter terms ----
+  {
+    double s[NV];
+    tsum(lu, [](int) { return 1.0; }, s);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) buf[(v * n + j) * S + k] = lu[v] + mu[v];
-  __syncthreads();
-  for (int it = t; it < NV * S; it += TPC) {
-    const int v = it / S, kq = it - v * S;
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < n; ++i) s += buf[(v * n + i) * S + kq];
-    if (active) lam[(cell * NV + v) * S + kq] += s;
+    for (int v = 0; v < NV; ++v)
+      if (v % n == j && active) lam[(cell * NV + v) * S + k] += s[v];
   }
   if constexpr (NP > 0) {
     __syncthreads();
