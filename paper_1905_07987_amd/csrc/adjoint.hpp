@@ -36,10 +36,6 @@
 //     Rusanov flux's parameter derivative at every face of the cell.
 #pragma once
 
-#ifndef ADJ_MIN_WAVES
-#define ADJ_MIN_WAVES 2
-#endif
-
 namespace adg {
 
 // Value of f(i) for a lane-dependent index i < n, built from compile-time
@@ -83,7 +79,8 @@ struct GeoAdj {
   static constexpr int BLOCK = CPB * TPC;
   static constexpr bool supported =
       PDE::kLinear && C::uniform() && BLOCK <= 512 && CPB * CELL_ELEMS * 8 <= 56 * 1024;
-  static constexpr int MIN_WAVES = ADJ_MIN_WAVES;
+  // two waves per SIMD: 256 VGPRs without spills (three spill)
+  static constexpr int MIN_WAVES = 2;
 };
 
 // Face kernels: one thread per (cell, face, face node); CPB_R cells per block.

@@ -747,15 +747,45 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
           P2 x[n];
 #pragma unroll
           for (int m = 0; m < n; ++m) x[m] = row[m];
+          // D is centro-antisymmetric on the symmetric GL nodes
+          // (D[n-1-i][n-1-m] = -D[i][m]): with sums and differences of
+          // mirrored inputs, rows i and n-1-i share half the products.
+          constexpr int HF = n / 2;
+          R s0[HF], s1[HF], d0[HF], d1[HF];
 #pragma unroll
-          for (int i = 0; i < n; ++i) {
+          for (int m = 0; m < HF; ++m) {
+            s0[m] = x[m].x + x[n - 1 - m].x;
+            s1[m] = x[m].y + x[n - 1 - m].y;
+            d0[m] = x[m].x - x[n - 1 - m].x;
+            d1[m] = x[m].y - x[n - 1 - m].y;
+          }
+#pragma unroll
+          for (int i = 0; i < HF; ++i) {
+            R p0 = R(0), p1 = R(0), q0 = R(0), q1 = R(0);
+#pragma unroll
+            for (int m = 0; m < HF; ++m) {
+              const R A = R(0.5 * (T::D(i, m) + T::D(i, n - 1 - m)));
+              const R Bc = R(0.5 * (T::D(i, m) - T::D(i, n - 1 - m)));
+              p0 += A * s0[m];
+              p1 += A * s1[m];
+              q0 += Bc * d0[m];
+              q1 += Bc * d1[m];
+            }
+            if constexpr (n % 2 == 1) {
+              p0 += T::D(i, HF) * x[HF].x;
+              p1 += T::D(i, HF) * x[HF].y;
+            }
+            row[i] = P2{(q0 + p0) * s, (q1 + p1) * s};
+            row[n - 1 - i] = P2{(q0 - p0) * s, (q1 - p1) * s};
+          }
+          if constexpr (n % 2 == 1) {
             R y0 = R(0), y1 = R(0);
 #pragma unroll
-            for (int m = 0; m < n; ++m) {
-              y0 += T::D(i, m) * x[m].x;
-              y1 += T::D(i, m) * x[m].y;
+            for (int m = 0; m < HF; ++m) {
+              y0 += T::D(HF, m) * d0[m];
+              y1 += T::D(HF, m) * d1[m];
             }
-            row[i] = P2{y0 * s, y1 * s};
+            row[HF] = P2{y0 * s, y1 * s};
           }
         }
         __syncthreads();
