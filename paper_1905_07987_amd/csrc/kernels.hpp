@@ -583,6 +583,40 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
   }
 }
 
+// y = s D x along one line of n nodes.  D is centro-antisymmetric on the
+// symmetric GL nodes (D[n-1-i][n-1-m] = -D[i][m]): with sums and
+// differences of mirrored inputs, rows i and n-1-i share half the products
+// and half the constants.
+template <class R, int n>
+__device__ __forceinline__ void line_deriv(const R (&x)[n], R (&y)[n], R s) {
+  using T = CT<R, n>;
+  constexpr int HF = n / 2;
+  R sm[HF > 0 ? HF : 1], dm[HF > 0 ? HF : 1];
+#pragma unroll
+  for (int m = 0; m < HF; ++m) {
+    sm[m] = x[m] + x[n - 1 - m];
+    dm[m] = x[m] - x[n - 1 - m];
+  }
+#pragma unroll
+  for (int i = 0; i < HF; ++i) {
+    R p = R(0), q = R(0);
+#pragma unroll
+    for (int m = 0; m < HF; ++m) {
+      p += R(0.5 * (BasisConst<n>::D[i][m] + BasisConst<n>::D[i][n - 1 - m])) * sm[m];
+      q += R(0.5 * (BasisConst<n>::D[i][m] - BasisConst<n>::D[i][n - 1 - m])) * dm[m];
+    }
+    if constexpr (n % 2 == 1) p += T::D(i, HF) * x[HF];
+    y[i] = (q + p) * s;
+    y[n - 1 - i] = (q - p) * s;
+  }
+  if constexpr (n % 2 == 1) {
+    R c = R(0);
+#pragma unroll
+    for (int m = 0; m < HF; ++m) c += T::D(HF, m) * dm[m];
+    y[HF] = c * s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel A, a lane pair per node (used for the FP64 predictor).
 // ---------------------------------------------------------------------------
@@ -737,55 +771,46 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
         //     slices of the pair in place
         constexpr int CH0 = FIN ? NFL : 0;  // the final pass only needs gradients
         constexpr int NCT = NCHD - CH0;
-        for (int task = tid; task < CPB * DIM * NCT * F; task += BLOCK) {
+        // Tasks that fill whole rounds of the block differentiate both slices
+        // of the pair; if the remaining tasks fit half a round, they are split
+        // by slice, so the last round costs half a task instead of a whole one.
+        constexpr int NT = CPB * DIM * NCT * F;
+        constexpr int REM = NT % BLOCK;
+        constexpr bool SPLIT = REM > 0 && 2 * REM <= BLOCK;
+        constexpr int NWHOLE = SPLIT ? NT - REM : NT;
+        auto task_row = [&](int task) {
           const int l = task % F;
           const int ch = CH0 + (task / F) % NCT;
           const int d = (task / (F * NCT)) % DIM;
           const int c2 = task / (F * NCT * DIM);
-          P2* row = lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
-          const R s = inv_h[d];
-          P2 x[n];
+          return lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
+        };
+        for (int task = tid; task < NWHOLE; task += BLOCK) {
+          P2* row = task_row(task);
+          const R s = inv_h[(task / (F * NCT)) % DIM];
+          R x0[n], x1[n], y0[n], y1[n];
 #pragma unroll
-          for (int m = 0; m < n; ++m) x[m] = row[m];
-          // D is centro-antisymmetric on the symmetric GL nodes
-          // (D[n-1-i][n-1-m] = -D[i][m]): with sums and differences of
-          // mirrored inputs, rows i and n-1-i share half the products.
-          constexpr int HF = n / 2;
-          R s0[HF], s1[HF], d0[HF], d1[HF];
-#pragma unroll
-          for (int m = 0; m < HF; ++m) {
-            s0[m] = x[m].x + x[n - 1 - m].x;
-            s1[m] = x[m].y + x[n - 1 - m].y;
-            d0[m] = x[m].x - x[n - 1 - m].x;
-            d1[m] = x[m].y - x[n - 1 - m].y;
+          for (int m = 0; m < n; ++m) {
+            const P2 t = row[m];
+            x0[m] = t.x;
+            x1[m] = t.y;
           }
+          line_deriv<R, n>(x0, y0, s);
+          line_deriv<R, n>(x1, y1, s);
 #pragma unroll
-          for (int i = 0; i < HF; ++i) {
-            R p0 = R(0), p1 = R(0), q0 = R(0), q1 = R(0);
+          for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+        }
+        if constexpr (SPLIT) {
+          if (tid < 2 * REM) {
+            const int task = NWHOLE + (tid >> 1);
+            R* row = reinterpret_cast<R*>(task_row(task)) + (tid & 1);  // one half of each pair
+            const R s = inv_h[(task / (F * NCT)) % DIM];
+            R x[n], y[n];
 #pragma unroll
-            for (int m = 0; m < HF; ++m) {
-              const R A = R(0.5 * (T::D(i, m) + T::D(i, n - 1 - m)));
-              const R Bc = R(0.5 * (T::D(i, m) - T::D(i, n - 1 - m)));
-              p0 += A * s0[m];
-              p1 += A * s1[m];
-              q0 += Bc * d0[m];
-              q1 += Bc * d1[m];
-            }
-            if constexpr (n % 2 == 1) {
-              p0 += T::D(i, HF) * x[HF].x;
-              p1 += T::D(i, HF) * x[HF].y;
-            }
-            row[i] = P2{(q0 + p0) * s, (q1 + p1) * s};
-            row[n - 1 - i] = P2{(q0 - p0) * s, (q1 - p1) * s};
-          }
-          if constexpr (n % 2 == 1) {
-            R y0 = R(0), y1 = R(0);
+            for (int m = 0; m < n; ++m) x[m] = row[2 * m];
+            line_deriv<R, n>(x, y, s);
 #pragma unroll
-            for (int m = 0; m < HF; ++m) {
-              y0 += T::D(HF, m) * d0[m];
-              y1 += T::D(HF, m) * d1[m];
-            }
-            row[HF] = P2{y0 * s, y1 * s};
+            for (int i = 0; i < n; ++i) row[2 * i] = y[i];
           }
         }
         __syncthreads();
