@@ -136,6 +136,12 @@ struct GeoA2 {
   static constexpr int ELEMS = CPB * CELL_ELEMS;
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
   static_assert(ELEMS * (int)sizeof(R) <= 64 * 1024, "predictor LDS exceeds 64 KiB");
+  // A one-cell block of seven or more waves runs one block per CU at the register
+  // counts of this kernel (at most 3 waves/SIMD), so they can afford a
+  // second LDS buffer (gfx950: 160 KiB per CU): chunk steps alternate
+  // buffers, and the barrier between one chunk's read-back and the next
+  // chunk's writes goes away.
+  static constexpr int NBUF = (CPB == 1 && BLOCK > 384 && 2 * ELEMS * (int)sizeof(R) <= 156 * 1024) ? 2 : 1;
   // Occupancy target (waves per SIMD) handed to the register allocator: half
   // the time history per lane keeps the FP64 kernel within 256 registers at
   // two waves per SIMD without spilling (one thread per node needs ~320).
@@ -635,8 +641,9 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
   constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK, SP = G::SP, H = GA::H, TPC = GA::TPC;
   constexpr int NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
   static_assert(C::uniform(), "flux sparsity must be the same in every direction");
-  __shared__ P2 lds2[GA::ELEMS / 2];
-  R* const lds = reinterpret_cast<R*>(lds2);
+  __shared__ P2 lds_all[GA::NBUF * GA::ELEMS / 2];
+  P2* lds2 = lds_all;  // the buffer of the current chunk step
+  R* const lds = reinterpret_cast<R*>(lds_all);
 
   const int tid = threadIdx.x;
   const int lc = tid / TPC;
@@ -721,8 +728,6 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
     }
   };
 
-  P2* const mine = lds2 + lc * (GA::CELL_ELEMS / 2);  // this cell's pairs [NCH][SP]
-  R* const mine_h = reinterpret_cast<R*>(mine) + h;   // this lane's half of each pair
   R q[H][NV];     // current iterate at the slices this lane owns
   R Fbar[DIM][NV], Nbar[NV], Sbar[NV];  // final pass: time averages (own slices)
 
@@ -745,6 +750,9 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
     for (int c = 0; c < STEPS; ++c) {
       const int j = h * H + c;
       const bool valid = j < n;
+      if constexpr (GA::NBUF == 2 && USE_LDS) lds2 = (lds2 == lds_all) ? lds_all + GA::ELEMS / 2 : lds_all;
+      P2* const mine = lds2 + lc * (GA::CELL_ELEMS / 2);  // this cell's pairs [NCH][SP]
+      R* const mine_h = reinterpret_cast<R*>(mine) + h;   // this lane's half of each pair
       // (1) flux and gradient inputs of slice j -> this lane's half of the pairs
       R Fl[DIM][NV];
       PDE::fluxes(q[c], P, a.pde, Fl);
@@ -859,7 +867,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
           }
         }
       }
-      if constexpr (USE_LDS) __syncthreads();
+      if constexpr (USE_LDS && GA::NBUF == 1) __syncthreads();
     }
   };
 
@@ -936,6 +944,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
   R* const fin_mine = lds + lc * GA::CELL_ELEMS;
+  if constexpr (GA::NBUF == 2) __syncthreads();  // last read-backs done
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     if (h == 0) {
