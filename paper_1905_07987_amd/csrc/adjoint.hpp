@@ -69,16 +69,21 @@ struct GeoAdj {
   // otherwise the forward kernels' stride.
   static constexpr int ls(int d) { return (DIM == 3 && n == 4) ? (d == 0 ? 4 : 5) : G::LS; }
   static constexpr int SPMAX = F * cmax(ls(0), cmax(ls(1), ls(DIM - 1)));
-  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * SPMAX * n;
+  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * SPMAX * n;  // one direction
+  // One-cell blocks hold the rows of all directions at once (two barriers
+  // per right-hand side instead of two per direction) when that fits in
+  // 80 KiB (gfx950 has 160 KiB of LDS per CU: two such blocks).
+  static constexpr bool ALLDIR = TPC >= 256 && DIM * DER_ELEMS * 8 <= 80 * 1024;
+  static constexpr int DER_TOTAL = ALLDIR ? DIM * DER_ELEMS : DER_ELEMS;
   static constexpr int TIME_ELEMS = (kDppTime ? 0 : NV * S * n) + NV * S;
   static constexpr int RED_ELEMS = TPC * (G::NP > 0 ? G::NP : 1);
-  static constexpr int CELL_ELEMS = cmax(cmax(DER_ELEMS, TIME_ELEMS), RED_ELEMS);
+  static constexpr int CELL_ELEMS = cmax(cmax(DER_TOTAL, TIME_ELEMS), RED_ELEMS);
   static constexpr int by_threads = TPC >= 256 ? 1 : 256 / TPC;
   static constexpr int by_lds = cmax(1, (56 * 1024) / (CELL_ELEMS * 8));
   static constexpr int CPB = cmin(by_threads, by_lds);
   static constexpr int BLOCK = CPB * TPC;
-  static constexpr bool supported =
-      PDE::kLinear && C::uniform() && BLOCK <= 512 && CPB * CELL_ELEMS * 8 <= 56 * 1024;
+  static constexpr bool supported = PDE::kLinear && C::uniform() && BLOCK <= 512 &&
+                                    CPB * CELL_ELEMS * 8 <= (ALLDIR ? 80 : 56) * 1024;
   // two waves per SIMD: 256 VGPRs without spills (three spill)
   static constexpr int MIN_WAVES = 2;
 };
@@ -422,8 +427,28 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     }
   };
   // LDS slot of channel c at line position m (or this node) for direction d
-  auto row = [&](int c, int d, int m) { return (c * SPM + ln[d] * GA::ls(d) + m) * n + j; };
-  auto mine = [&](int c, int d) { return (c * SPM + pk[d]) * n + j; };
+  constexpr int DOFF = GA::ALLDIR ? GA::DER_ELEMS : 0;  // offset between directions
+  auto row = [&](int c, int d, int m) { return d * DOFF + (c * SPM + ln[d] * GA::ls(d) + m) * n + j; };
+  auto mine = [&](int c, int d) { return d * DOFF + (c * SPM + pk[d]) * n + j; };
+  // write_d(d) fills direction d's rows, read_d(d) consumes them
+  auto dir_phases = [&](auto write_d, auto read_d) {
+    if constexpr (GA::ALLDIR) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) write_d(d);
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) read_d(d);
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        write_d(d);
+        __syncthreads();
+        read_d(d);
+        __syncthreads();
+      }
+    }
+  };
 
   // R(q) of slice j without point sources.  Lanes with act == false take
   // part in the barriers only.
@@ -438,16 +463,18 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     }
     double g[DIM][NV];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
+    for (int d = 0; d < DIM; ++d)
 #pragma unroll
       for (int v = 0; v < NV; ++v) g[d][v] = 0.0;
+    auto write_d = [&](int d) {
       if (act) {
 #pragma unroll
         for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = Fd[d][C::flux_var(d, c)];
 #pragma unroll
         for (int c = 0; c < NGR; ++c) buf[mine(NFL + c, d)] = q[C::grad_var(c)];
       }
-      __syncthreads();
+    };
+    auto read_d = [&](int d) {
       if (act) {
         double Dr[n];
 #pragma unroll
@@ -467,8 +494,8 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
           g[d][C::grad_var(c)] = acc * a.inv_h[d];
         }
       }
-      __syncthreads();
-    }
+    };
+    dir_phases(write_d, read_d);
     if constexpr (PDE::kHasNcp) {
       double Bv[NV];
       PDE::ncp(q, P, a.pde, g, Bv);
@@ -491,8 +518,7 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 #pragma unroll
       for (int v = 0; v < NV; ++v) lG[d][v] = g[d][v] = 0.0;
     if constexpr (PDE::kHasNcp) PDE::ncp_T(P, a.pde, lB, lG);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
+    auto write_d = [&](int d) {
       if (act) {
 #pragma unroll
         for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = nu[C::flux_var(d, c)];
@@ -502,7 +528,8 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
           buf[mine(NFL + NGR + c, d)] = fw[c];
         }
       }
-      __syncthreads();
+    };
+    auto read_d = [&](int d) {
       if (act) {
         double Dr[n], Dc[n];
 #pragma unroll
@@ -536,8 +563,8 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
         }
         PDE::flux_T(d, a.pde, lF, mu);
       }
-      __syncthreads();
-    }
+    };
+    dir_phases(write_d, read_d);
     if constexpr (PDE::kHasNcp) {
       if (act) PDE::ncp_dparams_T(P, a.pde, g, lB, gp);
     }
