@@ -111,7 +111,7 @@ def cpu_baseline(cells: int, N: int):
                       f"workload on {cells}^3 periodic cells, {el:.2f} s wall"}
 
 
-def adjoint_c4(log, steps: int | None = None, every: int = 15):
+def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True):
     """C4: seconds per gradient of the seismogram misfit of the 3-D elastic
     workload (N=3, 32^3 cells, 200 steps, 16 receivers) with respect to the
     per-cell (rho, cp, cs) and the initial state: forward run with
@@ -138,9 +138,10 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15):
     rc = np.floor((cfg["receivers"] - np.array(cfg["lo"])) / np.array(h)).astype(np.int64)
     cellsr = torch.as_tensor(rc[:, 0] + cfg["cells"][0] * (rc[:, 1] + cfg["cells"][1] * rc[:, 2]),
                              device="cuda")
-    with torch.no_grad():
-        samp = seismograms(s, u0, params_obs, dt, steps)
-        data = samp[:, :, 6:9] / params_obs[cellsr, 0][None, :, None]
+    if grad:
+        with torch.no_grad():
+            samp = seismograms(s, u0, params_obs, dt, steps)
+            data = samp[:, :, 6:9] / params_obs[cellsr, 0][None, :, None]
 
     def grad_once(ev):
         m = params.clone().requires_grad_(True)
@@ -151,19 +152,21 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15):
         J.backward()
         return J, u.grad, m.grad
 
-    grad_once(every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J, gu, gm = grad_once(every)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # the same gradient keeping every state (no recomputation; 200 states of
-    # the 151 MB C4 state fit in HBM)
-    t1 = time.perf_counter()
-    J1, _, gm1 = grad_once(1)
-    torch.cuda.synchronize()
-    el_all = time.perf_counter() - t1
-    same = bool(torch.equal(gm1, gm))
+    el = el_all = J = gm = same = None
+    if grad:
+        grad_once(every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, gu, gm = grad_once(every)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # the same gradient keeping every state (no recomputation; 200 states
+        # of the 151 MB C4 state fit in HBM)
+        t1 = time.perf_counter()
+        J1, _, gm1 = grad_once(1)
+        torch.cuda.synchronize()
+        el_all = time.perf_counter() - t1
+        same = bool(torch.equal(gm1, gm))
     # one forward step and one adjoint step, timed with events on the stream
     stream = torch.cuda.current_stream()
     Q = torch.randn(s.state_shape, dtype=torch.float64, device="cuda")
@@ -185,14 +188,16 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15):
     fwd_ms = ev[0].elapsed_time(ev[1]) / reps
     adj_ms = ev[1].elapsed_time(ev[2]) / reps
     nseg = -(-steps // every)
-    res = {"s_per_grad": round(el, 4), "s_per_grad_all_states_kept": round(el_all, 4),
+    res = {"s_per_grad": round(el, 4) if grad else None,
+           "s_per_grad_all_states_kept": round(el_all, 4) if grad else None,
            "all_states_gradient_bitwise_equal": same, "steps": steps, "checkpoint_every": every,
            "checkpoints": nseg, "forward_step_ms": round(fwd_ms, 4),
-           "adjoint_step_ms": round(adj_ms, 4), "J": float(J),
-           "grad_norm_params": float(torch.linalg.vector_norm(gm)),
+           "adjoint_step_ms": round(adj_ms, 4), "J": float(J) if grad else None,
+           "grad_norm_params": float(torch.linalg.vector_norm(gm)) if grad else None,
            "workload": "c4: 3-D elastic, N=3, 32^3 cells, 16 receivers, Ricker source, "
                        "misfit vs a +-5% perturbed material, FP64, dt frozen"}
-    log(f"adjoint c4: {el:.3f} s/grad (fwd step {fwd_ms:.3f} ms, adjoint step {adj_ms:.3f} ms)")
+    log(f"adjoint c4: {el if grad else float('nan'):.3f} s/grad (fwd step {fwd_ms:.3f} ms, "
+        f"adjoint step {adj_ms:.3f} ms)")
     return res
 
 
@@ -250,6 +255,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the C4 adjoint gradient")
     ap.add_argument("--no-elastic", action="store_true", help="skip the C3 elastic variant")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="C4: time single forward/adjoint steps only, no misfit gradients")
     ap.add_argument("--cpu-cells", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain elementwise copy of the state (known HBM bytes) "
@@ -345,7 +352,7 @@ def main():
     if not args.no_elastic:
         variants["elastic_c3"] = elastic_c3(log)
     if not args.no_adjoint:
-        variants["adjoint_c4"] = adjoint_c4(log)
+        variants["adjoint_c4"] = adjoint_c4(log, grad=not args.no_grad)
 
     cpu = None
     if not args.no_cpu_baseline:
