@@ -51,9 +51,10 @@ __device__ __forceinline__ double ct_pick(int i, Fn f) {
 // Predictor-adjoint layout: one thread per (node k, time slice j) of a cell,
 // thread t = k n + j (the slices of a node are adjacent lanes), CPB cells per
 // block.  LDS per cell holds, in turn, the derivative rows of one direction
-// (NFL + 2 NGR channels, each [line][position][slice] with a per-direction
-// line stride), the time-exchange buffer [NV][S][n] (where slices are not
-// exchanged by DPP), qbar [NV][S], or the parameter-gradient partials.
+// or of all directions (NFL + 2 NGR channels per direction, each
+// [line][position][slice] with a per-direction line stride), the
+// time-exchange buffer [NV][S][n] (where slices are not exchanged by DPP),
+// qbar [NV][S], or the parameter-gradient partials.
 template <class PDE, int N>
 struct GeoAdj {
   using G = Geo<PDE, N>;

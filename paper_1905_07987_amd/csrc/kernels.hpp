@@ -937,32 +937,41 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
     for (int d = 0; d < DIM; ++d) Fbar[d][v] += pair_swap(Fbar[d][v]);
   }
 
-  // Volume term and face projection, one direction at a time.  Region A of
-  // the cell's LDS holds qbar (NV rows), region B the nonzero components of
-  // Fbar_d (NFL rows); the even lane of each node writes them.
+  // Volume term and face projection, all directions at once: direction d's
+  // region of the cell's LDS holds qbar (NV rows) and the nonzero components
+  // of Fbar_d (NFL rows) in d's line-major layout; the even lane of each node
+  // writes them.
+  constexpr int FIN_D = (NV + NFL) * SP;
+  static_assert(DIM * FIN_D <= GA::CELL_ELEMS, "final-phase rows exceed the cell's LDS");
   R divF[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
   R* const fin_mine = lds + lc * GA::CELL_ELEMS;
   if constexpr (GA::NBUF == 2) __syncthreads();  // last read-backs done
+  if (h == 0) {
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    if (h == 0) {
+    for (int d = 0; d < DIM; ++d) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) fin_mine[v * SP + pk[d]] = qbar[v];
+      for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
 #pragma unroll
-      for (int cc = 0; cc < NFL; ++cc) fin_mine[(NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
+      for (int cc = 0; cc < NFL; ++cc)
+        fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
     }
-    __syncthreads();
-    for (int task = tid; task < CPB * F * (NFL + 1); task += BLOCK) {
-      // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
-      const int l = task % F;
-      const int kind = (task / F) % (NFL + 1);
-      const int c2 = task / (F * (NFL + 1));
-      const long long tcell = cell0 + c2;
-      R* rows = lds + c2 * GA::CELL_ELEMS + l * G::LS;
+  }
+  __syncthreads();
+  for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
+    // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
+    const int l = task % F;
+    const int kind = (task / F) % (NFL + 1);
+    const int dt_ = (task / (F * (NFL + 1))) % DIM;
+    const int c2 = task / (F * (NFL + 1) * DIM);
+    const long long tcell = cell0 + c2;
+    const bool tact = tcell < a.ncells;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (d != dt_) continue;
+      R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + l * G::LS;
       double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-      const bool tact = tcell < a.ncells;
       if (kind == 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -991,7 +1000,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
         for (int cc = 0; cc < NFL; ++cc) {
           if (cc != kind - 1) continue;
           const int v = C::flux_var(d, cc);
-          R x[n];
+          R x[n], y[n];
 #pragma unroll
           for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
           R e0 = R(0), e1 = R(0);
@@ -1004,22 +1013,19 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
             tr[(1 * NV + v) * F + l] = double(e0);
             tr[(3 * NV + v) * F + l] = double(e1);
           }
-          const R s = inv_h[d];
+          line_deriv<R, n>(x, y, inv_h[d]);
 #pragma unroll
-          for (int i = 0; i < n; ++i) {
-            R y = R(0);
-#pragma unroll
-            for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
-            rows[(NV + cc) * SP + i] = y * s;
-          }
+          for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
         }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[(NV + cc) * SP + pk[d]];
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int cc = 0; cc < NFL; ++cc)
+      divF[C::flux_var(d, cc)] += fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]];
 
   if (active && h == 0) {
 #pragma unroll

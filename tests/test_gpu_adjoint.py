@@ -69,6 +69,25 @@ def test_step_adjoint_elastic_vs_oracle(N, cells):
     assert np.abs(g_g[:, 0]).max() <= 1e-10 * np.abs(g_o[:, 1:]).max()
 
 
+def test_step_adjoint_fewer_picard_iterations_vs_oracle():
+    """picard_iters = 2 < N + 1 at N = 3 (the adjoint unrolls up to N + 1)."""
+    cells = (3, 2, 2)
+    hi = [500.0 * c for c in cells]
+    P = O.problem(3, 3, O.ELASTIC, list(cells), hi=hi, picard_iters=2)
+    s = adg.Solver(3, 3, "elastic", list(cells), [0.0] * 3, hi, picard_iters=2)
+    rng = np.random.default_rng(17)
+    params = np.column_stack([rng.uniform(2000, 3000, P.ncells), rng.uniform(5000, 7000, P.ncells),
+                              rng.uniform(2500, 3400, P.ncells)])
+    u = rng.normal(size=(P.ncells, 9, P.S))
+    lam = rng.normal(size=u.shape)
+    dt = 0.5 * O.stable_dt(P, u, params)[0]
+    lam_g, g_g = gpu_adjoint(s, u, params, lam, dt)
+    lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.0, lam)
+    e_l, e_g = rel_l2(lam_g, lam_o), rel_l2(g_g[:, 1:], g_o[:, 1:])
+    say(f"picard_iters=2: rel L2 lam {e_l:.2e}, grad {e_g:.2e}")
+    assert e_l <= TOL and e_g <= TOL
+
+
 def test_step_adjoint_elastic_point_source_vs_oracle():
     """A point source changes the forward iterates and so dJ/dm."""
     src = [dict(x=(700.0, 900.0, 400.0), w=[0.0] * 6 + [0.3, -0.2, 1.0], f0=5.0, t0=0.1, amp=1e7)]
