@@ -505,9 +505,11 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
     qbar[v] = s;
   }
 
-  // Volume term and face projection, one direction at a time.  Region A of
-  // the cell's LDS holds qbar (NV rows), region B the nonzero components of
-  // Fbar_d (NFL rows).
+  // Volume term and face projection, all directions at once: direction d's
+  // region of the cell's LDS holds qbar (NV rows) and the nonzero components
+  // of Fbar_d (NFL rows) in d's line-major layout.
+  constexpr int FIN_D = (NV + NFL) * SP;
+  static_assert(DIM * FIN_D <= GA::CELL_ELEMS, "final-phase rows exceed the cell's LDS");
   R divF[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
@@ -515,70 +517,84 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fin_mine[v * SP + pk[d]] = qbar[v];
+    for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
 #pragma unroll
-    for (int c = 0; c < NFL; ++c) fin_mine[(NV + c) * SP + pk[d]] = Fbar[d][C::flux_var(d, c)];
-    __syncthreads();
-    for (int task = tid; task < CPB * F; task += BLOCK) {
-      const int l = task % F, c2 = task / F;
-      const long long tcell = cell0 + c2;
-      R* rows = lds + c2 * GA::CELL_ELEMS + l * G::LS;
+    for (int c = 0; c < NFL; ++c)
+      fin_mine[d * FIN_D + (NV + c) * SP + pk[d]] = Fbar[d][C::flux_var(d, c)];
+  }
+  __syncthreads();
+  for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
+    // task kind 0: qbar traces of line l; kind 1 + c: flux channel c
+    const int l = task % F;
+    const int kind = (task / F) % (NFL + 1);
+    const int dt_ = (task / (F * (NFL + 1))) % DIM;
+    const int c2 = task / (F * (NFL + 1) * DIM);
+    const long long tcell = cell0 + c2;
+    const bool tact = tcell < a.ncells;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (d != dt_) continue;
+      R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + l * G::LS;
       double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-      const bool tact = tcell < a.ncells;
-      // qbar traces at both ends
+      if (kind == 0) {
+        // qbar traces at both ends
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R e0 = R(0), e1 = R(0);
+        for (int v = 0; v < NV; ++v) {
+          R e0 = R(0), e1 = R(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) {
-          const R x = rows[v * SP + m];
-          e0 += T::l0(m) * x;
-          e1 += T::l1(m) * x;
+          for (int m = 0; m < n; ++m) {
+            const R x = rows[v * SP + m];
+            e0 += T::l0(m) * x;
+            e1 += T::l1(m) * x;
+          }
+          if (tact) {
+            tr[(0 * NV + v) * F + l] = double(e0);  // face 2d,   state
+            tr[(2 * NV + v) * F + l] = double(e1);  // face 2d+1, state
+          }
         }
-        if (tact) {
-          tr[(0 * NV + v) * F + l] = double(e0);  // face 2d,   state
-          tr[(2 * NV + v) * F + l] = double(e1);  // face 2d+1, state
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (!PDE::flux_nonzero(d, v) && tact) {
+            tr[(1 * NV + v) * F + l] = 0.0;
+            tr[(3 * NV + v) * F + l] = 0.0;
+          }
         }
-      }
-      // normal-flux traces; derivative of Fbar_d in place
+      } else {
+        // normal-flux traces; derivative of Fbar_d in place
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if (!PDE::flux_nonzero(d, v) && tact) {
-          tr[(1 * NV + v) * F + l] = 0.0;
-          tr[(3 * NV + v) * F + l] = 0.0;
-        }
-      }
+        for (int c = 0; c < NFL; ++c) {
+          if (c != kind - 1) continue;
+          const int v = C::flux_var(d, c);
+          R x[n];
 #pragma unroll
-      for (int c = 0; c < NFL; ++c) {
-        const int v = C::flux_var(d, c);
-        R x[n];
+          for (int m = 0; m < n; ++m) x[m] = rows[(NV + c) * SP + m];
+          R e0 = R(0), e1 = R(0);
 #pragma unroll
-        for (int m = 0; m < n; ++m) x[m] = rows[(NV + c) * SP + m];
-        R e0 = R(0), e1 = R(0);
+          for (int m = 0; m < n; ++m) {
+            e0 += T::l0(m) * x[m];
+            e1 += T::l1(m) * x[m];
+          }
+          if (tact) {
+            tr[(1 * NV + v) * F + l] = double(e0);
+            tr[(3 * NV + v) * F + l] = double(e1);
+          }
+          const R s = inv_h[d];
 #pragma unroll
-        for (int m = 0; m < n; ++m) {
-          e0 += T::l0(m) * x[m];
-          e1 += T::l1(m) * x[m];
-        }
-        if (tact) {
-          tr[(1 * NV + v) * F + l] = double(e0);
-          tr[(3 * NV + v) * F + l] = double(e1);
-        }
-        const R s = inv_h[d];
+          for (int i = 0; i < n; ++i) {
+            R y = R(0);
 #pragma unroll
-        for (int i = 0; i < n; ++i) {
-          R y = R(0);
-#pragma unroll
-          for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
-          rows[(NV + c) * SP + i] = y * s;
+            for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
+            rows[(NV + c) * SP + i] = y * s;
+          }
         }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NFL; ++c) divF[C::flux_var(d, c)] += fin_mine[(NV + c) * SP + pk[d]];
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int c = 0; c < NFL; ++c) divF[C::flux_var(d, c)] += fin_mine[d * FIN_D + (NV + c) * SP + pk[d]];
 
   if (active) {
 #pragma unroll
