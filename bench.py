@@ -62,7 +62,7 @@ def kernel_source_hash() -> str:
     k = open(os.path.join(csrc, "kernels.hpp")).read()
     a = k.index("struct GeoA2 {")
     b = k.index("};", a)
-    c = k.index("// Kernel A, a lane pair per node")
+    c = k.index("// y = s D x along one line of n nodes.")  # line_deriv, then the kernel
     d = k.index("// Kernel B:", c)
     pde = open(os.path.join(csrc, "pde.hpp")).read()
     e = pde.index("struct Euler {")
