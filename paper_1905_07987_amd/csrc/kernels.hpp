@@ -126,8 +126,30 @@ struct GeoA2 {
   using C = Chan<PDE>;
   static constexpr int H = (G::n + 1) / 2;                       // slices per lane
   static constexpr int TPC = 2 * G::S;                           // threads per cell
-  static constexpr int ITER_ELEMS = C::NCH * G::SP * 2;          // per cell, in R
-  static constexpr int FIN_ELEMS = (G::NV + C::NFLUX) * G::SP;   // per cell, in R
+  // LDS row layout of direction d: position x of line L (both in 0..n-1 and
+  // 0..F-1) sits at A_d L + L / P_d + B_d x.  In 3-D, for n = 4, 5, 6 the
+  // coefficients come from a search over this family that minimises the
+  // bank collisions of the node lanes' 8-byte writes and read-backs (a wave
+  // holds 32 consecutive nodes) while the line tasks' 16-byte reads (one
+  // line per lane, consecutive lines) stay collision-free; otherwise the odd
+  // line stride LS with contiguous lines.
+  static constexpr bool kTuned = G::DIM == 3 && G::n >= 4 && G::n <= 6;
+  static constexpr int lay_A(int d) {
+    return !kTuned ? G::LS : (G::n == 6 ? (d == 0 ? 6 : 1) : (G::n == 5 ? (d == 0 ? 5 : 1) : 1));
+  }
+  static constexpr int lay_B(int d) {
+    return !kTuned ? 1
+                   : (G::n == 6 ? (d == 0 ? 1 : (d == 1 ? 38 : 36))
+                                : (G::n == 5 ? (d == 0 ? 1 : (d == 1 ? 27 : 25)) : (d == 2 ? 16 : 20)));
+  }
+  static constexpr int lay_P(int d) { return (kTuned && G::n == 6 && d == 0) ? 8 : 0; }
+  __host__ __device__ static constexpr int addr(int d, int L, int x) {
+    return lay_A(d) * L + (lay_P(d) ? L / lay_P(d) : 0) + lay_B(d) * x;
+  }
+  static constexpr int row_len(int d) { return addr(d, G::F - 1, G::n - 1) + 1; }
+  static constexpr int SP = cmax(row_len(0), cmax(row_len(1), row_len(G::DIM - 1)));  // elements per row
+  static constexpr int ITER_ELEMS = C::NCH * SP * 2;             // per cell, in R
+  static constexpr int FIN_ELEMS = (G::NV + C::NFLUX) * SP;      // per cell, in R
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
   static constexpr int by_threads = TPC >= 512 ? 1 : 512 / TPC;
   static constexpr int by_lds = cmax(1, (64 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
@@ -654,7 +676,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
   using T = CT<R, G::n>;
   using P2 = Pair<R>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK, SP = G::SP, H = GA::H, TPC = GA::TPC;
+  constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK, SP = GA::SP, H = GA::H, TPC = GA::TPC;
   constexpr int NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
   static_assert(C::uniform(), "flux sparsity must be the same in every direction");
   __shared__ P2 lds_all[GA::NBUF * GA::ELEMS / 2];
@@ -676,7 +698,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
     const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
     const int kd[3] = {kx, ky, kz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * G::LS + kd[d];
+    for (int d = 0; d < DIM; ++d) pk[d] = GA::addr(d, G::line_of(d, kx, ky, kz), kd[d]);
   }
 
   double u64[NV];
@@ -802,39 +824,43 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
         constexpr int REM = NT % BLOCK;
         constexpr bool SPLIT = REM > 0 && 2 * REM <= BLOCK;
         constexpr int NWHOLE = SPLIT ? NT - REM : NT;
-        auto task_row = [&](int task) {
+          auto task_row = [&](int task) {
           const int l = task % F;
           const int ch = CH0 + (task / F) % NCT;
           const int d = (task / (F * NCT)) % DIM;
           const int c2 = task / (F * NCT * DIM);
-          return lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
+          return lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + GA::addr(d, l, 0);
         };
+        // element stride along a line of the task's direction
+        auto task_stride = [&](int task) { return GA::lay_B((task / (F * NCT)) % DIM); };
         for (int task = tid; task < NWHOLE; task += BLOCK) {
           P2* row = task_row(task);
+          const int st = task_stride(task);
           const R s = inv_h[(task / (F * NCT)) % DIM];
           R x0[n], x1[n], y0[n], y1[n];
 #pragma unroll
           for (int m = 0; m < n; ++m) {
-            const P2 t = row[m];
+            const P2 t = row[m * st];
             x0[m] = t.x;
             x1[m] = t.y;
           }
           line_deriv<R, n>(x0, y0, s);
           line_deriv<R, n>(x1, y1, s);
 #pragma unroll
-          for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+          for (int i = 0; i < n; ++i) row[i * st] = P2{y0[i], y1[i]};
         }
         if constexpr (SPLIT) {
           if (tid < 2 * REM) {
             const int task = NWHOLE + (tid >> 1);
             R* row = reinterpret_cast<R*>(task_row(task)) + (tid & 1);  // one half of each pair
+            const int st = 2 * task_stride(task);
             const R s = inv_h[(task / (F * NCT)) % DIM];
             R x[n], y[n];
 #pragma unroll
-            for (int m = 0; m < n; ++m) x[m] = row[2 * m];
+            for (int m = 0; m < n; ++m) x[m] = row[m * st];
             line_deriv<R, n>(x, y, s);
 #pragma unroll
-            for (int i = 0; i < n; ++i) row[2 * i] = y[i];
+            for (int i = 0; i < n; ++i) row[i * st] = y[i];
           }
         }
         __syncthreads();
@@ -986,7 +1012,8 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       if (d != dt_) continue;
-      R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + l * G::LS;
+      R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + GA::addr(d, l, 0);
+      const int st = GA::lay_B(d);
       double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
       if (kind == 0) {
 #pragma unroll
@@ -994,7 +1021,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
           R e0 = R(0), e1 = R(0);
 #pragma unroll
           for (int m = 0; m < n; ++m) {
-            const R x = rows[v * SP + m];
+            const R x = rows[v * SP + m * st];
             e0 += T::l0(m) * x;
             e1 += T::l1(m) * x;
           }
@@ -1018,7 +1045,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
           const int v = C::flux_var(d, cc);
           R x[n], y[n];
 #pragma unroll
-          for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
+          for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m * st];
           R e0 = R(0), e1 = R(0);
 #pragma unroll
           for (int m = 0; m < n; ++m) {
@@ -1031,7 +1058,7 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
           }
           line_deriv<R, n>(x, y, inv_h[d]);
 #pragma unroll
-          for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
+          for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i * st] = y[i];
         }
       }
     }
