@@ -118,6 +118,14 @@ def test_step_adjoint_advection_vs_oracle(dim, N, cells):
     assert e <= TOL
 
 
+def test_step_adjoint_is_deterministic():
+    """No atomics: two adjoint steps on the same inputs agree bitwise."""
+    s, P, params, u, lam, dt = elastic_case((5, 4, 3), 3, seed=33)
+    a = gpu_adjoint(s, u, params, lam, dt)
+    b = gpu_adjoint(s, u, params, lam, dt)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_step_adjoint_dot_product_on_gpu_step():
     """<lam, A u> (GPU forward) = <A^T lam, u> (GPU adjoint), source-free."""
     s, P, params, u, lam, dt = elastic_case((6, 5, 4), 3, seed=31)

@@ -253,6 +253,34 @@ def test_mixed_fp32_error_is_small():
     assert err3 < 1e-6
 
 
+def test_mixed_fp32_elastic_error_is_small():
+    """The FP32 predictor on the elastic system (N=4, layered material, point
+    source): error against the FP64 oracle after a few steps."""
+    say("mixed fp32 elastic")
+    cfg = inputs.elastic_config("c3")
+    cells, lo, hi = [4, 3, 3], [0.0] * 3, [2000.0, 1500.0, 1500.0]
+    src = dict(cfg["source"])
+    src["x"] = (1250.0, 750.0, 600.0)
+    src["t0"] = 0.0
+    s, P = pair(3, 4, "elastic", cells, lo, hi, sources=[src], cfl=0.5, precision="fp32")
+    s.set_point_sources([src])
+    prm = cfg["params"][: P.ncells].copy()
+    Q0 = inputs.elastic_smooth_state(O.node_coords(P), 52, scale_sigma=1e3, scale_rhov=1.0)
+    Qd, pd = dev(Q0), dev(prm)
+    clock = dev([0.0, 0.0])
+    s.stable_dt(Qd, pd, clock)
+    Qo, t = Q0.copy(), 0.0
+    for _ in range(4):
+        s.step(Qd, pd, clock, next_dt=True)
+        dt = O.stable_dt(P, Qo, prm)[0]
+        Qo = O.step(P, Qo, prm, dt, t)
+        t += dt
+    torch.cuda.synchronize()
+    err = rel_l2(Qd.cpu().numpy(), Qo)
+    say("elastic mixed fp32 rel L2 vs fp64 oracle", err)
+    assert err < 1e-6
+
+
 def test_admissibility_planted_cells():
     say("admissibility")
     s, P = pair(3, 2, "euler", [7, 5, 3])
