@@ -20,6 +20,8 @@ import math
 
 import torch
 
+from . import adg
+
 
 def _time_nodes(t0: float, dt: float, steps: int):
     """t^n as the device clock accumulates it (t <- t + dt in float64)."""
@@ -36,6 +38,9 @@ class _SeismogramRun(torch.autograd.Function):
     def forward(ctx, u0, params, solver, t0, dt, steps, every):
         if solver.nrec == 0:
             raise ValueError("set receivers on the solver first")
+        if solver.cfg.precision != adg.FP64:
+            # the library's adjoint is that of the FP64 step
+            raise ValueError("seismograms() needs an FP64 solver (the adjoint is that of the FP64 step)")
         prm = params.detach().contiguous() if params is not None else None
         Q = u0.detach().contiguous().clone()
         clock = torch.tensor([t0, dt], dtype=torch.float64, device=Q.device)
