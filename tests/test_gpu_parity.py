@@ -151,6 +151,14 @@ STEP_CASES = {
     "euler3_N2": (dict(dim=3, order=2, pde="euler", cells=[6, 4, 5]), 4),
     "euler2_N5": (dict(dim=2, order=5, pde="euler", cells=[9, 8]), 4),
     "advection3_N2_decay": (dict(dim=3, order=2, pde="advection", cells=[5, 4, 3], adv=(0.3, 0.5, -0.2), kappa=0.7), 4),
+    # largest built orders
+    "euler2_N7": (dict(dim=2, order=7, pde="euler", cells=[5, 3]), 3),
+    "advection3_N6": (dict(dim=3, order=6, pde="advection", cells=[3, 2, 2], adv=(0.3, 0.5, -0.2), kappa=0.2), 3),
+    # degenerate meshes: one cell (every face is its own periodic neighbour), one row
+    "euler3_N3_one_cell": (dict(dim=3, order=3, pde="euler", cells=[1, 1, 1]), 3),
+    "euler2_N4_one_row": (dict(dim=2, order=4, pde="euler", cells=[7, 1]), 3),
+    # a single Picard iteration
+    "euler3_N3_one_picard": (dict(dim=3, order=3, pde="euler", cells=[3, 2, 2], picard_iters=1), 3),
 }
 
 
