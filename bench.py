@@ -266,7 +266,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+        print(json.dumps({"error": "bench.py runs on one GPU only; multi-GPU sharding is a "
                                    "design note, not an implemented path"}))
         sys.exit(2)
 
