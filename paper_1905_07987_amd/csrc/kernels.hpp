@@ -1135,17 +1135,40 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     const double* tR = traces + ((long long)(cR * (2 * DIM) + 2 * d + 0) * 2) * NV * F;
     double qL[NV], qR[NV], FL[NV], FR[NV], pL[NP > 0 ? NP : 1], pR[NP > 0 ? NP : 1], pm[NP > 0 ? NP : 1];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      qL[v] = tL[v * F + f];
-      FL[v] = tL[(NV + v) * F + f];
-      qR[v] = tR[v * F + f];
-      FR[v] = tR[(NV + v) * F + f];
-    }
-#pragma unroll
     for (int p = 0; p < NP; ++p) {
       pL[p] = params[cL * NP + p];
       pR[p] = params[cR * NP + p];
       pm[p] = 0.5 * (pL[p] + pR[p]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qL[v] = tL[v * F + f];
+      qR[v] = tR[v * F + f];
+    }
+    if constexpr (PDE::kLinear) {
+      // linear flux: the trace of the averaged flux is the flux of the
+      // averaged state's trace, so only the state traces are read
+      double Fa[DIM][NV], Fb[DIM][NV];
+      PDE::fluxes(qL, pL, a.pde, Fa);
+      PDE::fluxes(qR, pR, a.pde, Fb);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) FL[v] = FR[v] = 0.0;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) {
+        if (e != d) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (!PDE::flux_nonzero(e, v)) continue;
+          FL[v] = Fa[e][v];
+          FR[v] = Fb[e][v];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        FL[v] = tL[(NV + v) * F + f];
+        FR[v] = tR[(NV + v) * F + f];
+      }
     }
     const double s = fmax(PDE::max_eigen(qL, pL, a.pde, d), PDE::max_eigen(qR, pR, a.pde, d));
     double B[NV];
