@@ -18,6 +18,7 @@ constexpr int kMaxSources = 16;
 constexpr int kMaxVar = 16;
 constexpr int kSlots = 256;       // reduction slots
 constexpr int kSlotStride = 8;    // words between slots (64 bytes)
+constexpr int kMaxLin = 16;       // Picard iterations the linear-PDE predictor takes
 
 // One-dimensional tables on [0, 1] (see adg_basis_tables).  KW = K1^{-1} W is
 // the time operator of the Picard update, invw = 1 / w.
@@ -52,6 +53,9 @@ struct KArgs {
   PdeConsts pde;
   Tables<double> t64;
   Tables<float> t32;
+  // lin_c[k] = w^T KW^k 1 (k = 0..kMaxLin): the weights of the time average
+  // of the Picard iterate as a polynomial in dt L for PDEs linear in Q
+  double lin_c[kMaxLin + 1];
   int nsrc;
   int nblocks;  // grid size of the cell kernels (for the block -> cell map)
   const SourceDev* src;

@@ -224,6 +224,23 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
         a.t64.KW[i][j] = Ki[i * n + j] * w[j];
       }
     }
+    {
+      double v[kMaxN];
+      for (int i = 0; i < n; ++i) v[i] = 1.0;
+      for (int k = 0; k <= kMaxLin; ++k) {
+        if (k > 0) {
+          double t[kMaxN];
+          for (int i = 0; i < n; ++i) {
+            t[i] = 0.0;
+            for (int j = 0; j < n; ++j) t[i] += a.t64.KW[i][j] * v[j];
+          }
+          for (int i = 0; i < n; ++i) v[i] = t[i];
+        }
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += w[i] * v[i];
+        a.lin_c[k] = c;
+      }
+    }
     for (int i = 0; i < n; ++i) {
       a.t32.xi[i] = (float)a.t64.xi[i];
       a.t32.w[i] = (float)a.t64.w[i];

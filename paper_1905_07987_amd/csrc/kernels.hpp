@@ -1080,6 +1080,270 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
+// Kernel A for PDEs linear in Q (flux, non-conservative product and source
+// linear and homogeneous in Q, with per-cell coefficients), one thread per
+// node.  With R(q) = L q + s(t) and the element operator L acting on space
+// only, the Picard update q^{r+1} = 1 u + dt (KW amp) w + dt (KW (x) L) q^r
+// (Sec. 3.3, Eq. 5; amp = point-source amplitudes at the time nodes, w =
+// their nodal weights) unrolls exactly, and the time average of the I-th
+// iterate is
+//   qbar = sum_{k=0..I} c_k (dt L)^k u + sum_{k=0..I-1} dt e_{k+1} (dt L)^k w,
+//   c_k = w_t^T KW^k 1,  e_k = w_t^T KW^k amp.
+// Horner's scheme evaluates it with I applications of L:
+//   t_I = c_I u;  t_k = c_k u + dt e_{k+1} w + dt L t_{k+1};  qbar = t_0.
+// The averaged terms of the volume term and of the traces are those of
+// qbar by linearity: vol = dt (L qbar + e_0 w), traces qhat = trace of qbar
+// and Fhat_d = F_d(qhat).  The result equals the Picard form up to the
+// order of rounding, at I + 1 applications of L instead of about n I.
+// ---------------------------------------------------------------------------
+template <class PDE, int N, class R>
+struct GeoL {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  static constexpr int ROW_ELEMS = C::NCH * G::SP;  // every derivative channel of one field
+  static constexpr int AVG_ELEMS = G::NV * G::S;    // the time average in node order
+  static constexpr int CELL_ELEMS = cmax(ROW_ELEMS, AVG_ELEMS);
+  static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
+  static constexpr int by_lds = cmax(1, (52 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * G::S;
+  static constexpr int ELEMS = CPB * CELL_ELEMS;
+  static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
+  static_assert(ELEMS * (int)sizeof(R) <= 150 * 1024, "linear predictor LDS exceeds the CU");
+  static constexpr int MIN_WAVES = 3;
+};
+
+// node index of position m on line l of direction d
+template <class G>
+__device__ __forceinline__ int line_node(int d, int l, int m) {
+  constexpr int n = G::n;
+  if constexpr (G::DIM == 2) return d == 0 ? m + n * l : l + n * m;
+  return d == 0 ? m + n * l : (d == 1 ? (l % n) + n * m + n * n * (l / n) : l + n * n * m);
+}
+
+template <class PDE, int N, class R>
+__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
+predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ params,
+                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // Q and Qout may be the same array (in-place step): each element is read
+  // at the start and written at the end by the thread of its node.
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  using GL = GeoL<PDE, N, R>;
+  using T = CT<R, G::n>;
+  static_assert(PDE::kLinear, "the linear predictor needs a PDE linear in Q");
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GL::CPB, BLOCK = GL::BLOCK, SP = G::SP, LS = G::LS;
+  constexpr int NCH = C::NCH, NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
+  static_assert(C::uniform(), "flux sparsity must be the same in every direction");
+  __shared__ R lds[GL::ELEMS];
+  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S, k = tid - lc * S;
+  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  {
+    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * LS + kd[d];
+  }
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+
+  double u64[NV];
+  R u[NV], P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    u64[v] = Q[(cl * NV + v) * S + k];
+    u[v] = R(u64[v]);
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
+  const double t_n = clock[0], dt64 = clock[1];
+  const R dt = R(dt64);
+  const int I = a.picard_iters;
+  R inv_h[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
+
+  // Point sources of this block: e_k = w_t^T KW^k amp, amp = Ricker
+  // amplitudes at the n time nodes of the step (made visible by the first
+  // barrier below).
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc) {
+    const int s = tid;
+    double v[n], t[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+      v[j] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt64);
+    for (int kk = 0; kk <= I; ++kk) {
+      if (kk > 0) {
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) acc += a.t64.KW[i][j] * v[j];
+          t[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < n; ++i) v[i] = t[i];
+      }
+      double e = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; ++j) e += a.t64.w[j] * v[j];
+      src_e[s][kk] = e;
+    }
+  }
+  // t[v] += scale * e_kk * w at this node for every source in this cell
+  auto add_sources = [&](int kk, R scale, R* t) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const R e = scale * R(src_e[s][kk]);
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v] += e * R(wsk[v]);
+    }
+  };
+
+  R* const mine = lds + lc * GL::CELL_ELEMS;
+  // out = L t at this node: S(t) - div F(t) - B(t) grad t, the derivatives
+  // by line tasks over the LDS rows of the block's cells.
+  auto apply_L = [&](const R (&t)[NV], R (&out)[NV]) {
+    R Fl[DIM][NV];
+    PDE::fluxes(t, P, a.pde, Fl);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * SP + pk[d]] = Fl[d][C::flux_var(d, cc)];
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = t[C::grad_var(cc)];
+    }
+    __syncthreads();
+    for (int task = tid; task < CPB * NCH * F; task += BLOCK) {
+      const int l = task % F;
+      const int ch = (task / F) % NCH;
+      const int c2 = task / (F * NCH);
+      R* row = lds + c2 * GL::CELL_ELEMS + ch * SP + l * LS;
+      R x[n], y[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) x[m] = row[m];
+      line_deriv<R, n>(x, y, inv_h[ch / NCHD]);
+#pragma unroll
+      for (int i = 0; i < n; ++i) row[i] = y[i];
+    }
+    __syncthreads();
+    R divF[NV], g[DIM][NV], B[NV], Sv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      divF[v] = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) g[d][v] = R(0);
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += mine[(d * NCHD + cc) * SP + pk[d]];
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) g[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+    }
+    if constexpr (PDE::kHasNcp) {
+      PDE::ncp(t, P, a.pde, g, B);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) B[v] = R(0);
+    }
+    PDE::source(t, P, a.pde, Sv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
+    __syncthreads();  // rows free for the next writes
+  };
+
+  // Horner's scheme for the time average of the I-th Picard iterate
+  R t[NV];
+  {
+    const R cI = R(a.lin_c[I]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] = cI * u[v];
+  }
+  for (int kk = I - 1; kk >= 0; --kk) {
+    R Lt[NV];
+    apply_L(t, Lt);
+    const R ck = R(a.lin_c[kk]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
+    add_sources(kk + 1, dt, t);
+  }
+
+  // volume term
+  R vol[NV];
+  {
+    R Lq[NV];
+    apply_L(t, Lq);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vol[v] = Lq[v];
+    add_sources(0, R(1), vol);
+  }
+
+  // face traces: qhat = trace of qbar, Fhat_d = F_d(qhat); one task per
+  // (cell, direction, line) extrapolates every quantity to both ends
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
+  __syncthreads();
+  for (int task = tid; task < CPB * DIM * F; task += BLOCK) {
+    const int l = task % F;
+    const int dt_ = (task / F) % DIM;
+    const int c2 = task / (F * DIM);
+    const long long tcell = cell0 + c2;
+    if (tcell >= a.ncells) continue;
+    const R* rows = lds + c2 * GL::CELL_ELEMS;
+    R e0[NV], e1[NV], Pt[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) Pt[p] = R(params[tcell * NP + p]);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (d != dt_) continue;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R s0 = R(0), s1 = R(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) {
+          const R x = rows[v * S + line_node<G>(d, l, m)];
+          s0 += T::l0(m) * x;
+          s1 += T::l1(m) * x;
+        }
+        e0[v] = s0;
+        e1[v] = s1;
+      }
+      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
+      R Fa[DIM][NV];
+      PDE::fluxes(e0, Pt, a.pde, Fa);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        tr[(0 * NV + v) * F + l] = double(e0[v]);    // face 2d,   state
+        tr[(1 * NV + v) * F + l] = double(Fa[d][v]); // face 2d,   normal flux
+      }
+      PDE::fluxes(e1, Pt, a.pde, Fa);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        tr[(2 * NV + v) * F + l] = double(e1[v]);    // face 2d+1, state
+        tr[(3 * NV + v) * F + l] = double(Fa[d][v]); // face 2d+1, normal flux
+      }
+    }
+  }
+
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Qout[(cell * NV + v) * S + k] = u64[v] + double(dt * vol[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel B: Rusanov flux on every face of the cell, surface integral and
 // update; optionally the per-block Eq. (7) maximum of the new state (reduced
 // over blocks by finalize_kernel, which also advances the clock).
@@ -1362,6 +1626,22 @@ struct Launch {
   static hipError_t predict(const KArgs& a0, int precision, const double* Q, const double* params,
                             const double* clock, double* Qout, double* traces, hipStream_t st) {
     KArgs a = a0;
+    if constexpr (PDE::kLinear) {
+      if (a.picard_iters <= kMaxLin) {
+        if (precision == ADG_MIXED_FP32) {
+          using GL = GeoL<PDE, N, float>;
+          a.nblocks = blocks_a<GL>(a);
+          hipLaunchKernelGGL((predict_kernel_lin<PDE, N, float>), dim3(a.nblocks), dim3(GL::BLOCK), 0,
+                             st, a, Q, params, clock, Qout, traces);
+        } else {
+          using GL = GeoL<PDE, N, double>;
+          a.nblocks = blocks_a<GL>(a);
+          hipLaunchKernelGGL((predict_kernel_lin<PDE, N, double>), dim3(a.nblocks), dim3(GL::BLOCK), 0,
+                             st, a, Q, params, clock, Qout, traces);
+        }
+        return hipGetLastError();
+      }
+    }
     if (precision == ADG_MIXED_FP32) {
       using GA = GeoA1<PDE, N, float>;
       a.nblocks = blocks_a<GA>(a);
