@@ -159,6 +159,16 @@ STEP_CASES = {
     "euler2_N4_one_row": (dict(dim=2, order=4, pde="euler", cells=[7, 1]), 3),
     # a single Picard iteration
     "euler3_N3_one_picard": (dict(dim=3, order=3, pde="euler", cells=[3, 2, 2], picard_iters=1), 3),
+    # PDEs linear in Q take the polynomial (Horner) form of the Picard
+    # average up to 16 iterations, the Picard kernel beyond
+    "advection3_N3_one_picard": (dict(dim=3, order=3, pde="advection", cells=[3, 2, 2], adv=(0.3, 0.5, -0.2),
+                                      kappa=0.4, picard_iters=1), 3),
+    "advection2_N3_picard16": (dict(dim=2, order=3, pde="advection", cells=[5, 4], adv=(0.7, -0.4, 0.0),
+                                    kappa=0.3, picard_iters=16), 3),
+    "advection2_N3_picard17": (dict(dim=2, order=3, pde="advection", cells=[5, 4], adv=(0.7, -0.4, 0.0),
+                                    kappa=0.3, picard_iters=17), 3),
+    "advection2_N1_ragged": (dict(dim=2, order=1, pde="advection", cells=[13, 7], adv=(0.7, -0.4, 0.0),
+                                  kappa=0.3), 4),
 }
 
 
