@@ -63,7 +63,7 @@ def kernel_source_hash() -> str:
     a = k.index("struct GeoA2 {")
     b = k.index("};", a)
     c = k.index("// y = s D x along one line of n nodes.")  # line_deriv, then the kernel
-    d = k.index("// Kernel B:", c)
+    d = k.index("// Kernel A for PDEs linear in Q", c)
     pde = open(os.path.join(csrc, "pde.hpp")).read()
     e = pde.index("struct Euler {")
     f = pde.index("\n};", e)
