@@ -705,6 +705,229 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3'. Predictor adjoint in the polynomial form of the linear predictor: the
+// forward step's time average is t_0 of Horner's scheme
+//   t_I = c_I u;  t_k = c_k u + dt e_{k+1} w + dt L(m) t_{k+1},
+// and the volume term dt (L qbar + e_0 w).  Its transpose runs the same
+// recursion backwards with L^T:
+//   mu_0 = E^T hat + dt L^T lam       (E = extrapolation to the faces)
+//   for k = 0..I-1:  lam_u += c_k mu_k;  gp += (d(L t_{k+1})/dm)^T (dt mu_k);
+//                    mu_{k+1} = dt L^T mu_k
+//   lam_u += c_I mu_I;  lam^n = lam + lam_u
+// plus gp += (d(L qbar)/dm)^T (dt lam).  A forward sweep recomputes the t_k
+// and keeps the gradients the parameter terms read (those of the
+// non-conservative product) in registers.  One thread per node; the
+// adjoint's Picard count is at most n, so the sweeps unroll.
+// ---------------------------------------------------------------------------
+template <class PDE, int N>
+struct GeoAdjL {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  static constexpr int CELL_ELEMS =
+      cmax(cmax(C::NCH * G::SP, G::NV * G::S), G::S * (G::NP > 0 ? G::NP : 1));
+  static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
+  static constexpr int by_lds = cmax(1, (52 * 1024) / (CELL_ELEMS * 8));
+  static constexpr int CPB = cmin(by_threads, by_lds);
+  static constexpr int BLOCK = CPB * G::S;
+  static constexpr bool supported = PDE::kLinear && C::uniform() && BLOCK >= 64 && BLOCK <= 1024 &&
+                                    CPB * CELL_ELEMS * 8 <= 150 * 1024;
+  static constexpr int MIN_WAVES = 2;
+};
+
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoAdjL<PDE, N>::BLOCK), (GeoAdjL<PDE, N>::MIN_WAVES))
+adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
+                       const double* __restrict__ clock, double* __restrict__ lam,
+                       double* __restrict__ gparams, double* __restrict__ hat) {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  using GA = GeoAdjL<PDE, N>;
+  using T = CT<double, G::n>;
+  using Op = LinOp<PDE, N, double, GA::CPB, GA::BLOCK, GA::CELL_ELEMS>;
+  static_assert(GA::supported, "adjoint not available for this PDE and order");
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GA::CPB, BLOCK = GA::BLOCK;
+  constexpr int NGR = C::ngrad(), NGX = NGR > 0 ? NGR : 1, NPX = NP > 0 ? NP : 1;
+  constexpr int IMAX = n;  // the adjoint step takes at most n Picard iterations
+  __shared__ double lds[GA::CPB * GA::CELL_ELEMS];
+  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S, k = tid - lc * S;
+  int kk3[3] = {0, 0, 0};
+  node_coords<DIM>(k, n, kk3);
+  int ln[DIM], pk[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    ln[d] = G::line_of(d, kk3[0], kk3[1], DIM == 3 ? kk3[2] : 0);
+    pk[d] = ln[d] * G::LS + kk3[d];
+  }
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+  double* const mine = lds + lc * GA::CELL_ELEMS;
+
+  const double t_n = clock[0], dt = clock[1];
+  const int I = a.picard_iters;
+  double P[NPX], u[NV], inv_h[3];
+#pragma unroll
+  for (int p = 0; p < NPX; ++p) P[p] = p < NP ? params[cl * NP + p] : 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inv_h[d] = a.inv_h[d];
+
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc) lin_source_weights<n>(a, tid, t_n, dt, I, src_e[tid]);
+  auto add_sources = [&](int kk, double scale, double* t) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const double e = scale * src_e[s][kk];
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v] += e * wsk[v];
+    }
+  };
+  // gp += (dB/dm at gradient gq)^T (-nu): the parameter derivative of L t
+  // for the gradients gq of t
+  auto param_terms = [&](const double (&gq)[DIM][NV], const double (&nu)[NV], double (&gp)[NPX]) {
+    if constexpr (PDE::kHasNcp) {
+      double lB[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lB[v] = -nu[v];
+      PDE::ncp_dparams_T(P, a.pde, gq, lB, gp);
+    }
+  };
+
+  // ---- forward sweep: t_k, keeping the gradients of t_{k+1} ----
+  double gfw[IMAX][DIM][NGX];
+  double t[NV];
+  {
+    const double cI = a.lin_c[I];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] = cI * u[v];
+  }
+#pragma unroll
+  for (int kk = IMAX - 1; kk >= 0; --kk) {
+    if (kk < I) {
+      double Lt[NV], g[DIM][NV];
+      Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int c = 0; c < NGX; ++c) gfw[kk][d][c] = c < NGR ? g[d][C::grad_var(c)] : 0.0;
+      const double ck = a.lin_c[kk];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
+      add_sources(kk + 1, dt, t);
+    }
+  }
+
+  // ---- volume term: parameter derivative at qbar = t, seed dt lam ----
+  double lamv[NV], nu[NV], gp[NPX];
+#pragma unroll
+  for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    lamv[v] = lam[(cl * NV + v) * S + k];
+    nu[v] = dt * lamv[v];
+  }
+  {
+    double Lq[NV], g[DIM][NV];
+    Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lq, g);
+    param_terms(g, nu, gp);
+  }
+
+  // ---- adjoint of the face traces (read hat before it is overwritten) ----
+  double tseed[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) tseed[v] = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double l = ct_pick<n>(kk3[d], [&](int i) { return side ? T::l1(i) : T::l0(i); });
+      const double* h = hat + ((cl * (2 * DIM) + 2 * d + side) * NV) * F + ln[d];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tseed[v] += l * h[v * F];
+    }
+
+  // ---- face traces of qbar into hat (for the Rusanov parameter derivative) ----
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
+  __syncthreads();  // also: every read of hat above is done
+  for (int it = tid; it < CPB * 2 * DIM * NV * F; it += BLOCK) {
+    const int f = it % F, v = (it / F) % NV, face = (it / (F * NV)) % (2 * DIM);
+    const int c2 = it / (F * NV * 2 * DIM);
+    const int d = face >> 1, side = face & 1;
+    const long long tcell = cell0 + c2;
+    if (tcell >= a.ncells) continue;
+    const double* rows = lds + c2 * GA::CELL_ELEMS;
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; ++m)
+      acc += (side ? T::l1(m) : T::l0(m)) * rows[v * S + face_line_node<DIM, n>(d, f, m)];
+    hat[tcell * (2 * DIM * NV * F) + (face * NV + v) * F + f] = acc;
+  }
+  __syncthreads();
+
+  // ---- reverse sweep ----
+  double mu[NV], lu[NV];
+  Op::apply_T(a, lds, mine, pk, tid, nu, P, inv_h, mu);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    mu[v] += tseed[v];
+    lu[v] = 0.0;
+  }
+#pragma unroll
+  for (int kk = 0; kk < IMAX; ++kk) {
+    if (kk < I) {
+      const double ck = a.lin_c[kk];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lu[v] += ck * mu[v];
+        nu[v] = dt * mu[v];
+      }
+      double gq[DIM][NV];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gq[d][v] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NGR; ++c) gq[d][C::grad_var(c)] = gfw[kk][d][c];
+      }
+      param_terms(gq, nu, gp);
+      Op::apply_T(a, lds, mine, pk, tid, nu, P, inv_h, mu);
+    }
+  }
+  {
+    const double cI = a.lin_c[I];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lu[v] += cI * mu[v];
+  }
+
+  // ---- lam^n = lam^{n+1} + lam_u; the cell's parameter terms ----
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lam[(cell * NV + v) * S + k] = lamv[v] + lu[v];
+  }
+  if constexpr (NP > 0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) mine[k * NP + p] = gp[p];
+    __syncthreads();
+    if (k < NP && active) {
+      double s = 0.0;
+      for (int i = 0; i < S; ++i) s += mine[i * NP + k];
+      gparams[cell * NP + k] += s;
+    }
+  }
+}
+
 // Launch sequence of one adjoint step.
 template <class PDE, int N>
 struct AdjLaunch {
@@ -728,8 +951,9 @@ struct AdjLaunch {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     KArgs ap = a0;
-    ap.nblocks = (int)((a0.ncells + GA::CPB - 1) / GA::CPB);
-    hipLaunchKernelGGL((adj_predict_kernel<PDE, N>), dim3(ap.nblocks), dim3(GA::BLOCK), 0, st, ap, Q,
+    using GL = GeoAdjL<PDE, N>;
+    ap.nblocks = (int)((a0.ncells + GL::CPB - 1) / GL::CPB);
+    hipLaunchKernelGGL((adj_predict_lin_kernel<PDE, N>), dim3(ap.nblocks), dim3(GL::BLOCK), 0, st, ap, Q,
                        params, clock, lam, gparams, B);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -1121,100 +1121,56 @@ __device__ __forceinline__ int line_node(int d, int l, int m) {
   return d == 0 ? m + n * l : (d == 1 ? (l % n) + n * m + n * n * (l / n) : l + n * n * m);
 }
 
-template <class PDE, int N, class R>
-__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
-predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ params,
-                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
-  // Q and Qout may be the same array (in-place step): each element is read
-  // at the start and written at the end by the thread of its node.
+// y = s D^T x along one line.  D^T is centro-antisymmetric too
+// (D^T[n-1-i][n-1-m] = -D^T[i][m]), so rows i and n-1-i share the products
+// of mirrored sums and differences as in line_deriv.
+template <class R, int n>
+__device__ __forceinline__ void line_deriv_T(const R (&x)[n], R (&y)[n], R s) {
+  using B = BasisConst<n>;
+  constexpr int HF = n / 2;
+  R sm[HF > 0 ? HF : 1], dm[HF > 0 ? HF : 1];
+#pragma unroll
+  for (int m = 0; m < HF; ++m) {
+    sm[m] = x[m] + x[n - 1 - m];
+    dm[m] = x[m] - x[n - 1 - m];
+  }
+#pragma unroll
+  for (int i = 0; i < HF; ++i) {
+    R p = R(0), q = R(0);
+#pragma unroll
+    for (int m = 0; m < HF; ++m) {
+      p += R(0.5 * (B::D[m][i] + B::D[n - 1 - m][i])) * sm[m];
+      q += R(0.5 * (B::D[m][i] - B::D[n - 1 - m][i])) * dm[m];
+    }
+    if constexpr (n % 2 == 1) p += R(B::D[HF][i]) * x[HF];
+    y[i] = (q + p) * s;
+    y[n - 1 - i] = (q - p) * s;
+  }
+  if constexpr (n % 2 == 1) {
+    R c = R(0);
+#pragma unroll
+    for (int m = 0; m < HF; ++m) c += R(B::D[m][HF]) * dm[m];
+    y[HF] = c * s;
+  }
+}
+
+// The element operator L of a PDE linear in Q on the LDS rows of a block of
+// CPB cells (CELL_ELEMS elements each, NCH channel rows of SP elements in
+// the per-direction line-major layout).  Every thread of the block calls
+// these together (they hold three barriers); a thread's own node sits at
+// pk[d] in the rows of direction d of its cell's region `mine`.
+template <class PDE, int N, class R, int CPB, int BLOCK, int CELL_ELEMS>
+struct LinOp {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  using GL = GeoL<PDE, N, R>;
-  using T = CT<R, G::n>;
-  static_assert(PDE::kLinear, "the linear predictor needs a PDE linear in Q");
-  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GL::CPB, BLOCK = GL::BLOCK, SP = G::SP, LS = G::LS;
-  constexpr int NCH = C::NCH, NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
-  static_assert(C::uniform(), "flux sparsity must be the same in every direction");
-  __shared__ R lds[GL::ELEMS];
-  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+  static constexpr int n = G::n, F = G::F, NV = G::NV, DIM = G::DIM, SP = G::SP, LS = G::LS;
+  static constexpr int NCH = C::NCH, NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
 
-  const int tid = threadIdx.x;
-  const int lc = tid / S, k = tid - lc * S;
-  int pk[DIM];  // this node's slot in the LDS rows of each direction
-  {
-    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
-    const int kd[3] = {kx, ky, kz};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * LS + kd[d];
-  }
-  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
-  const long long cell = cell0 + lc;
-  const bool active = cell < a.ncells;
-  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
-
-  double u64[NV];
-  R u[NV], P[NP > 0 ? NP : 1];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    u64[v] = Q[(cl * NV + v) * S + k];
-    u[v] = R(u64[v]);
-  }
-#pragma unroll
-  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
-  const double t_n = clock[0], dt64 = clock[1];
-  const R dt = R(dt64);
-  const int I = a.picard_iters;
-  R inv_h[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
-
-  // Point sources of this block: e_k = w_t^T KW^k amp, amp = Ricker
-  // amplitudes at the n time nodes of the step (made visible by the first
-  // barrier below).
-  bool src_here = false;
-  for (int s = 0; s < a.nsrc; ++s)
-    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
-  if (src_here && tid < a.nsrc) {
-    const int s = tid;
-    double v[n], t[n];
-#pragma unroll
-    for (int j = 0; j < n; ++j)
-      v[j] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt64);
-    for (int kk = 0; kk <= I; ++kk) {
-      if (kk > 0) {
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j = 0; j < n; ++j) acc += a.t64.KW[i][j] * v[j];
-          t[i] = acc;
-        }
-#pragma unroll
-        for (int i = 0; i < n; ++i) v[i] = t[i];
-      }
-      double e = 0.0;
-#pragma unroll
-      for (int j = 0; j < n; ++j) e += a.t64.w[j] * v[j];
-      src_e[s][kk] = e;
-    }
-  }
-  // t[v] += scale * e_kk * w at this node for every source in this cell
-  auto add_sources = [&](int kk, R scale, R* t) {
-    if (!src_here) return;
-    for (int s = 0; s < a.nsrc; ++s) {
-      if (a.src[s].cell != cell) continue;
-      const R e = scale * R(src_e[s][kk]);
-      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) t[v] += e * R(wsk[v]);
-    }
-  };
-
-  R* const mine = lds + lc * GL::CELL_ELEMS;
-  // out = L t at this node: S(t) - div F(t) - B(t) grad t, the derivatives
-  // by line tasks over the LDS rows of the block's cells.
-  auto apply_L = [&](const R (&t)[NV], R (&out)[NV]) {
+  // out = L t = S(t) - div F(t) - B(t) grad t at this node; g = the gradients
+  // the non-conservative product reads (zero elsewhere)
+  __device__ static __forceinline__ void apply(const KArgs& a, R* lds, R* mine, const int (&pk)[DIM],
+                                               int tid, const R (&t)[NV], const R* P,
+                                               const R (&inv_h)[3], R (&out)[NV], R (&g)[DIM][NV]) {
     R Fl[DIM][NV];
     PDE::fluxes(t, P, a.pde, Fl);
 #pragma unroll
@@ -1229,7 +1185,7 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
       const int l = task % F;
       const int ch = (task / F) % NCH;
       const int c2 = task / (F * NCH);
-      R* row = lds + c2 * GL::CELL_ELEMS + ch * SP + l * LS;
+      R* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
       R x[n], y[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) x[m] = row[m];
@@ -1238,7 +1194,7 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int i = 0; i < n; ++i) row[i] = y[i];
     }
     __syncthreads();
-    R divF[NV], g[DIM][NV], B[NV], Sv[NV];
+    R divF[NV], B[NV], Sv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       divF[v] = R(0);
@@ -1262,8 +1218,153 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
     __syncthreads();  // rows free for the next writes
+  }
+
+  // mu = L^T nu at this node (FP64; the PDE's transposes): the flux part
+  // through D^T of nu's flux components, the non-conservative part through
+  // D^T of the gradient adjoints, plus the source's transpose.
+  __device__ static __forceinline__ void apply_T(const KArgs& a, double* lds, double* mine,
+                                                 const int (&pk)[DIM], int tid, const double (&nu)[NV],
+                                                 const double* P, const double (&inv_h)[3],
+                                                 double (&mu)[NV]) {
+    double lB[NV], lG[DIM][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      lB[v] = -nu[v];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) lG[d][v] = 0.0;
+    }
+    if constexpr (PDE::kHasNcp) PDE::ncp_T(P, a.pde, lB, lG);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * SP + pk[d]] = nu[C::flux_var(d, cc)];
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = lG[d][C::grad_var(cc)];
+    }
+    __syncthreads();
+    for (int task = tid; task < CPB * NCH * F; task += BLOCK) {
+      const int l = task % F;
+      const int ch = (task / F) % NCH;
+      const int c2 = task / (F * NCH);
+      double* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
+      double x[n], y[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) x[m] = row[m];
+      line_deriv_T<double, n>(x, y, inv_h[ch / NCHD]);
+#pragma unroll
+      for (int i = 0; i < n; ++i) row[i] = y[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mu[v] = 0.0;
+    PDE::source_T(a.pde, nu, mu);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double lF[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) lF[v] = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) lF[C::flux_var(d, cc)] = -mine[(d * NCHD + cc) * SP + pk[d]];
+      PDE::flux_T(d, a.pde, lF, mu);
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) mu[C::grad_var(cc)] += mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+    }
+    __syncthreads();  // rows free for the next writes
+  }
+};
+
+// e_k = w_t^T KW^k amp for k = 0..I, amp = the source's Ricker amplitudes
+// at the n time nodes of the step (t_n + xi_j dt).
+template <int n>
+__device__ inline void lin_source_weights(const KArgs& a, int s, double t_n, double dt, int I, double* e) {
+  double v[n], t[n];
+#pragma unroll
+  for (int j = 0; j < n; ++j) v[j] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt);
+  for (int kk = 0; kk <= I; ++kk) {
+    if (kk > 0) {
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) acc += a.t64.KW[i][j] * v[j];
+        t[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i) v[i] = t[i];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) acc += a.t64.w[j] * v[j];
+    e[kk] = acc;
+  }
+}
+
+template <class PDE, int N, class R>
+__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
+predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ params,
+                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // Q and Qout may be the same array (in-place step): each element is read
+  // at the start and written at the end by the thread of its node.
+  using G = Geo<PDE, N>;
+  using GL = GeoL<PDE, N, R>;
+  using T = CT<R, G::n>;
+  using Op = LinOp<PDE, N, R, GL::CPB, GL::BLOCK, GL::CELL_ELEMS>;
+  static_assert(PDE::kLinear, "the linear predictor needs a PDE linear in Q");
+  static_assert(Chan<PDE>::uniform(), "flux sparsity must be the same in every direction");
+  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GL::CPB, BLOCK = GL::BLOCK;
+  __shared__ R lds[GL::ELEMS];
+  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S, k = tid - lc * S;
+  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  {
+    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pk[d] = G::line_of(d, kx, ky, kz) * G::LS + kd[d];
+  }
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+
+  double u64[NV];
+  R u[NV], P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    u64[v] = Q[(cl * NV + v) * S + k];
+    u[v] = R(u64[v]);
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
+  const double t_n = clock[0], dt64 = clock[1];
+  const R dt = R(dt64);
+  const int I = a.picard_iters;
+  R inv_h[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
+
+  // point sources of this block (made visible by the first barrier below)
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc) lin_source_weights<n>(a, tid, t_n, dt64, I, src_e[tid]);
+  // t[v] += scale * e_kk * w at this node for every source in this cell
+  auto add_sources = [&](int kk, R scale, R* t) {
+    if (!src_here) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const R e = scale * R(src_e[s][kk]);
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v] += e * R(wsk[v]);
+    }
   };
 
+  R* const mine = lds + lc * GL::CELL_ELEMS;
   // Horner's scheme for the time average of the I-th Picard iterate
   R t[NV];
   {
@@ -1272,8 +1373,8 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int v = 0; v < NV; ++v) t[v] = cI * u[v];
   }
   for (int kk = I - 1; kk >= 0; --kk) {
-    R Lt[NV];
-    apply_L(t, Lt);
+    R Lt[NV], g[DIM][NV];
+    Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
     const R ck = R(a.lin_c[kk]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
@@ -1283,10 +1384,8 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
   // volume term
   R vol[NV];
   {
-    R Lq[NV];
-    apply_L(t, Lq);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) vol[v] = Lq[v];
+    R g[DIM][NV];
+    Op::apply(a, lds, mine, pk, tid, t, P, inv_h, vol, g);
     add_sources(0, R(1), vol);
   }
 
@@ -1342,7 +1441,6 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int v = 0; v < NV; ++v) Qout[(cell * NV + v) * S + k] = u64[v] + double(dt * vol[v]);
   }
 }
-
 // ---------------------------------------------------------------------------
 // Kernel B: Rusanov flux on every face of the cell, surface integral and
 // update; optionally the per-block Eq. (7) maximum of the new state (reduced
@@ -1689,7 +1787,7 @@ struct Launch {
     return hipGetLastError();
   }
   static constexpr decltype(KernelSet::adjoint) adjoint_entry() {
-    if constexpr (GeoAdj<PDE, N>::supported) return &AdjLaunch<PDE, N>::run;
+    if constexpr (GeoAdjL<PDE, N>::supported) return &AdjLaunch<PDE, N>::run;
     else return nullptr;
   }
   static const KernelSet* set() {
