@@ -227,9 +227,9 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
  *   lam      [C][nvar][S] device, in: dJ/du^{n+1}, out: dJ/du^n (in place)
  *   gparams  [C][nparam] device, dJ/dm of this step is ADDED (NULL iff
  *            nparam == 0)
- * Available for ADG_PDE_ELASTIC (orders 1..3) and ADG_PDE_ADVECTION (2-D
- * orders 1..7, 3-D orders 1..3) with picard_iters <= order + 1; otherwise
- * ADG_ERR_UNSUPPORTED.  Deterministic (no atomics).  Uses the context's
+ * Available for ADG_PDE_ELASTIC and ADG_PDE_ADVECTION at every built order
+ * with picard_iters <= order + 1; otherwise (ADG_PDE_EULER, more Picard
+ * iterations) ADG_ERR_UNSUPPORTED.  Deterministic (no atomics).  Uses the context's
  * trace workspace: a following adg_correct needs a new adg_predict. */
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
                             const double* clock, double* lam, double* gparams, void* stream);

@@ -27,11 +27,11 @@
 //  2. adj_rusanov_kernel<false>: B = adjoint of each cell's own face traces
 //     (state trace plus folded flux trace) from the fluctuation adjoints of
 //     both cells of the face.
-//  3. adj_predict_kernel: per cell, the Picard iteration forward from u^n
-//     (keeping the iterates' gradient quantities), then the transposes of the
-//     face projection, the volume term and the Picard steps in reverse order;
-//     lam <- lam^n, gparams += the cell's volume terms, B <- face traces of
-//     qbar (after B's adjoints have been read).
+//  3. adj_predict_lin_kernel: per cell, the linear predictor's Horner sweep
+//     forward from u^n (keeping the iterates' gradient quantities), then the
+//     transposes of the face projection, the volume term and the Horner
+//     steps in reverse order; lam <- lam^n, gparams += the cell's volume
+//     terms, B <- face traces of qbar (after B's adjoints have been read).
 //  4. adj_rusanov_kernel<true> (PDEs with parameters): gparams += the
 //     Rusanov flux's parameter derivative at every face of the cell.
 #pragma once
@@ -47,47 +47,6 @@ __device__ __forceinline__ double ct_pick(int i, Fn f) {
   for (int ii = 1; ii < n; ++ii) r = (i == ii) ? f(ii) : r;
   return r;
 }
-
-// Predictor-adjoint layout: one thread per (node k, time slice j) of a cell,
-// thread t = k n + j (the slices of a node are adjacent lanes), CPB cells per
-// block.  LDS per cell holds, in turn, the derivative rows of one direction
-// or of all directions (NFL + 2 NGR channels per direction, each
-// [line][position][slice] with a per-direction line stride), the
-// time-exchange buffer [NV][S][n] (where slices are not exchanged by DPP),
-// qbar [NV][S], or the parameter-gradient partials.
-template <class PDE, int N>
-struct GeoAdj {
-  using G = Geo<PDE, N>;
-  using C = Chan<PDE>;
-  static constexpr int n = G::n, S = G::S, F = G::F, DIM = G::DIM, NV = G::NV;
-  static constexpr int NGR = C::ngrad();
-  static constexpr int TPC = n * S;
-  // the n slices of a node sit in one lane quad: exchange them with DPP
-  static constexpr bool kDppTime = (n == 2 || n == 4);
-  // Line stride of the derivative rows of direction d.  For n = 4 in 3-D,
-  // 4 / 5 / 5 place the 32-byte slice groups that a half-wave (8 nodes)
-  // writes, and the line elements it reads, in distinct bank groups;
-  // otherwise the forward kernels' stride.
-  static constexpr int ls(int d) { return (DIM == 3 && n == 4) ? (d == 0 ? 4 : 5) : G::LS; }
-  static constexpr int SPMAX = F * cmax(ls(0), cmax(ls(1), ls(DIM - 1)));
-  static constexpr int DER_ELEMS = (C::NFLUX + 2 * NGR) * SPMAX * n;  // one direction
-  // One-cell blocks hold the rows of all directions at once (two barriers
-  // per right-hand side instead of two per direction) when that fits in
-  // 80 KiB (gfx950 has 160 KiB of LDS per CU: two such blocks).
-  static constexpr bool ALLDIR = TPC >= 256 && DIM * DER_ELEMS * 8 <= 80 * 1024;
-  static constexpr int DER_TOTAL = ALLDIR ? DIM * DER_ELEMS : DER_ELEMS;
-  static constexpr int TIME_ELEMS = (kDppTime ? 0 : NV * S * n) + NV * S;
-  static constexpr int RED_ELEMS = TPC * (G::NP > 0 ? G::NP : 1);
-  static constexpr int CELL_ELEMS = cmax(cmax(DER_TOTAL, TIME_ELEMS), RED_ELEMS);
-  static constexpr int by_threads = TPC >= 256 ? 1 : 256 / TPC;
-  static constexpr int by_lds = cmax(1, (56 * 1024) / (CELL_ELEMS * 8));
-  static constexpr int CPB = cmin(by_threads, by_lds);
-  static constexpr int BLOCK = CPB * TPC;
-  static constexpr bool supported = PDE::kLinear && C::uniform() && BLOCK <= 512 &&
-                                    CPB * CELL_ELEMS * 8 <= (ALLDIR ? 80 : 56) * 1024;
-  // two waves per SIMD: 256 VGPRs without spills (three spill)
-  static constexpr int MIN_WAVES = 2;
-};
 
 // Face kernels: one thread per (cell, face, face node); CPB_R cells per block.
 template <class PDE, int N>
@@ -274,439 +233,7 @@ adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// 3. Predictor, volume term and face projection in reverse, per cell.
-//
-// Forward (Sec. 3.3, Eq. (5), the Picard form of the forward kernels):
-//   q^0_j = u,  q^{r+1}_j = u + dt sum_i KW_ji R(q^r_i),  r < I,
-//   R(q) = -sum_d D_d F_d(q) / h_d - B(q) grad q + S(q) + point sources,
-//   u^{n+1} = u + dt R(qbar) - surface terms,  qbar = sum_j w_j q^I_j,
-//   face traces l_side . qbar.
-// Reverse, with mu_j the adjoint of the current iterate's slice j:
-//   mu^I_j = w_j (trace^T lamhat + R^T (dt lam))   (R^T on slice j with
-//            nu_j = dt w_j lam, paired with q^I_j for the parameters)
-//   for r = I-1 .. 1:  lam_u += sum_j mu_j;  nu_j = dt sum_i KW_ij mu_i;
-//                      mu_j = R^T nu_j;  gparams += (dR/dm (q^r_j))^T nu_j
-//   r = 0 (q^0_j = u for every j, so only the sum over j matters):
-//     lam_u += sum_j mu_j + R^T nu,  gparams += (dR/dm (u))^T nu,
-//     nu = dt sum_i (sum_j KW_ij) mu_i
-//   lam^n = lam + lam_u.
-// The forward iterate r = 0 likewise evaluates R(u) once (point sources,
-// which differ per time node, are added per slice).
-// ---------------------------------------------------------------------------
-
-// Broadcast lane i of each group of n adjacent lanes (n = 2 or 4) to the
-// group: one DPP quad permutation per 32-bit half.
-template <int n, int i>
-__device__ __forceinline__ double group_bcast(double x) {
-  constexpr int ctrl = n == 4 ? (i | (i << 2) | (i << 4) | (i << 6))
-                              : (i | (i << 2) | ((2 + i) << 4) | ((2 + i) << 6));
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-template <int I, int N, class Fn>
-__device__ __forceinline__ void static_for(Fn&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
-template <class PDE, int N>
-__global__ void __launch_bounds__((GeoAdj<PDE, N>::BLOCK), (GeoAdj<PDE, N>::MIN_WAVES))
-adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
-                   const double* __restrict__ clock, double* __restrict__ lam,
-                   double* __restrict__ gparams, double* __restrict__ hat) {
-  using G = Geo<PDE, N>;
-  using C = Chan<PDE>;
-  using GA = GeoAdj<PDE, N>;
-  using T = CT<double, G::n>;
-  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GA::CPB, TPC = GA::TPC, SPM = GA::SPMAX;
-  constexpr int NFL = C::NFLUX, NGR = GA::NGR;
-  constexpr int NPX = NP > 0 ? NP : 1, NGX = NGR > 0 ? NGR : 1;
-  constexpr int IMAX = N + 1;  // the host admits picard_iters <= N + 1
-  constexpr bool DPP = GA::kDppTime;
-  static_assert(GA::supported, "adjoint not available for this PDE and order");
-  __shared__ double lds[CPB * GA::CELL_ELEMS];
-  __shared__ double src_amp[kMaxSources * n];
-
-  const int tid = threadIdx.x;
-  const int lc = tid / TPC;
-  const int t = tid - lc * TPC;
-  const int k = t / n;      // node
-  const int j = t - k * n;  // time slice (adjacent lanes share a node)
-  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
-  const long long cell = cell0 + lc;
-  const bool active = cell < a.ncells;
-  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
-  double* const buf = lds + lc * GA::CELL_ELEMS;
-  double* const tbuf = buf;                                // [NV][S][n] (LDS time exchange)
-  double* const qb = buf + (DPP ? 0 : NV * S * n);         // [NV][S]
-
-  int kk[3] = {0, 0, 0};
-  node_coords<DIM>(k, n, kk);
-  int ln[DIM], pk[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    ln[d] = G::line_of(d, kk[0], kk[1], DIM == 3 ? kk[2] : 0);
-    pk[d] = ln[d] * GA::ls(d) + kk[d];
-  }
-  // Lane-dependent entries of D (row or column kk_d) and KW (row or column
-  // j), rebuilt from compile-time constants where they are used.
-  auto Drow = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(i, m); }); };
-  auto Dcol = [&](int d, int m) { return ct_pick<n>(kk[d], [&](int i) { return T::D(m, i); }); };
-  const double wj = ct_pick<n>(j, [&](int jj) { return T::w(jj); });
-
-  const double t_n = clock[0], dt = clock[1];
-  const int I = a.picard_iters;
-  double P[NPX], u[NV];
-#pragma unroll
-  for (int p = 0; p < NPX; ++p) P[p] = p < NP ? params[cl * NP + p] : 0.0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
-
-  bool src_here = false;
-  for (int s = 0; s < a.nsrc; ++s)
-    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
-  if (src_here && tid < a.nsrc * n) {
-    const int s = tid / n, jj = tid - s * n;
-    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[jj] * dt);
-  }
-  __syncthreads();
-
-  // out[v] = sum_i coef(i) x_i[v], x_i held by slice i of this node
-  auto tsum = [&](const double (&x)[NV], auto coef, double (&out)[NV]) {
-    if constexpr (DPP) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] = 0.0;
-      static_for<0, n>([&](auto I_) {
-        constexpr int i = decltype(I_)::value;
-        const double c = coef(i);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) out[v] += c * group_bcast<n, i>(x[v]);
-      });
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) tbuf[(v * S + k) * n + j] = x[v];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < n; ++i) acc += coef(i) * tbuf[(v * S + k) * n + i];
-        out[v] = acc;
-      }
-      __syncthreads();
-    }
-  };
-  // every slice of the node receives slice 0's x
-  auto bcast0 = [&](double (&x)[NV]) {
-    if constexpr (DPP) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) x[v] = group_bcast<n, 0>(x[v]);
-    } else {
-      if (j == 0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) tbuf[v * S + k] = x[v];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v) x[v] = tbuf[v * S + k];
-      __syncthreads();
-    }
-  };
-  auto add_point_sources = [&](double (&R)[NV]) {
-    if (!src_here) return;
-    for (int s = 0; s < a.nsrc; ++s) {
-      if (a.src[s].cell != cell) continue;
-      const double amp = src_amp[s * n + j];
-      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] += amp * wsk[v];
-    }
-  };
-  // LDS slot of channel c at line position m (or this node) for direction d
-  constexpr int DOFF = GA::ALLDIR ? GA::DER_ELEMS : 0;  // offset between directions
-  auto row = [&](int c, int d, int m) { return d * DOFF + (c * SPM + ln[d] * GA::ls(d) + m) * n + j; };
-  auto mine = [&](int c, int d) { return d * DOFF + (c * SPM + pk[d]) * n + j; };
-  // write_d(d) fills direction d's rows, read_d(d) consumes them
-  auto dir_phases = [&](auto write_d, auto read_d) {
-    if constexpr (GA::ALLDIR) {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) write_d(d);
-      __syncthreads();
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) read_d(d);
-      __syncthreads();
-    } else {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        write_d(d);
-        __syncthreads();
-        read_d(d);
-        __syncthreads();
-      }
-    }
-  };
-
-  // R(q) of slice j without point sources.  Lanes with act == false take
-  // part in the barriers only.
-  auto rhs = [&](const double (&q)[NV], double (&R)[NV], bool act) {
-    double Fd[DIM][NV];
-    PDE::fluxes(q, P, a.pde, Fd);
-    if constexpr (PDE::kHasSource) {
-      PDE::source(q, P, a.pde, R);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] = 0.0;
-    }
-    double g[DIM][NV];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) g[d][v] = 0.0;
-    auto write_d = [&](int d) {
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = Fd[d][C::flux_var(d, c)];
-#pragma unroll
-        for (int c = 0; c < NGR; ++c) buf[mine(NFL + c, d)] = q[C::grad_var(c)];
-      }
-    };
-    auto read_d = [&](int d) {
-      if (act) {
-        double Dr[n];
-#pragma unroll
-        for (int m = 0; m < n; ++m) Dr[m] = Drow(d, m);
-#pragma unroll
-        for (int c = 0; c < NFL; ++c) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) acc += Dr[m] * buf[row(c, d, m)];
-          R[C::flux_var(d, c)] -= acc * a.inv_h[d];
-        }
-#pragma unroll
-        for (int c = 0; c < NGR; ++c) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) acc += Dr[m] * buf[row(NFL + c, d, m)];
-          g[d][C::grad_var(c)] = acc * a.inv_h[d];
-        }
-      }
-    };
-    dir_phases(write_d, read_d);
-    if constexpr (PDE::kHasNcp) {
-      double Bv[NV];
-      PDE::ncp(q, P, a.pde, g, Bv);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] -= Bv[v];
-    }
-  };
-
-  // mu = R^T nu for slice j; gp += (dR/dm at the forward values fw)^T nu.
-  auto rhs_T = [&](const double (&nu)[NV], const double (&fw)[NGX], double (&mu)[NV],
-                   double (&gp)[NPX], bool act) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) mu[v] = 0.0;
-    PDE::source_T(a.pde, nu, mu);
-    double lB[NV], lG[DIM][NV], g[DIM][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) lB[v] = -nu[v];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) lG[d][v] = g[d][v] = 0.0;
-    if constexpr (PDE::kHasNcp) PDE::ncp_T(P, a.pde, lB, lG);
-    auto write_d = [&](int d) {
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NFL; ++c) buf[mine(c, d)] = nu[C::flux_var(d, c)];
-#pragma unroll
-        for (int c = 0; c < NGR; ++c) {
-          buf[mine(NFL + c, d)] = lG[d][C::grad_var(c)];
-          buf[mine(NFL + NGR + c, d)] = fw[c];
-        }
-      }
-    };
-    auto read_d = [&](int d) {
-      if (act) {
-        double Dr[n], Dc[n];
-#pragma unroll
-        for (int m = 0; m < n; ++m) {
-          Dr[m] = Drow(d, m);
-          Dc[m] = Dcol(d, m);
-        }
-        double lF[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) lF[v] = 0.0;
-        // transposed derivative of the flux adjoints
-#pragma unroll
-        for (int c = 0; c < NFL; ++c) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) acc += Dc[m] * buf[row(c, d, m)];
-          lF[C::flux_var(d, c)] = -acc * a.inv_h[d];
-        }
-#pragma unroll
-        for (int c = 0; c < NGR; ++c) {
-          // transposed derivative of the gradient adjoints
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) acc += Dc[m] * buf[row(NFL + c, d, m)];
-          mu[C::grad_var(c)] += acc * a.inv_h[d];
-          // gradient of the forward iterate
-          double gacc = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) gacc += Dr[m] * buf[row(NFL + NGR + c, d, m)];
-          g[d][C::grad_var(c)] = gacc * a.inv_h[d];
-        }
-        PDE::flux_T(d, a.pde, lF, mu);
-      }
-    };
-    dir_phases(write_d, read_d);
-    if constexpr (PDE::kHasNcp) {
-      if (act) PDE::ncp_dparams_T(P, a.pde, g, lB, gp);
-    }
-  };
-
-  auto KWrow = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(jj, i); }); };
-  auto KWcol = [&](int i) { return ct_pick<n>(j, [&](int jj) { return T::KW(i, jj); }); };
-
-  // ---- forward Picard sweep, keeping the gradient quantities of q^r ----
-  double q[NV], fw[IMAX][NGX];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) q[v] = u[v];
-#pragma unroll
-  for (int r = 0; r < IMAX; ++r) {
-    if (r < I) {
-#pragma unroll
-      for (int c = 0; c < NGX; ++c) fw[r][c] = c < NGR ? q[C::grad_var(c)] : 0.0;
-      double R[NV];
-      if (r == 0) {
-        // all slices of q^0 are u: one evaluation, then per-slice sources
-        rhs(q, R, j == 0);
-        bcast0(R);
-      } else {
-        rhs(q, R, true);
-      }
-      add_point_sources(R);
-      double acc[NV];
-      tsum(R, KWrow, acc);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) q[v] = u[v] + dt * acc[v];
-    }
-  }
-
-  // ---- adjoint of the face traces (read B before it is overwritten) ----
-  double tseed[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) tseed[v] = 0.0;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d)
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double l = ct_pick<n>(kk[d], [&](int i) { return side ? T::l1(i) : T::l0(i); });
-      const double* h = hat + ((cl * (2 * DIM) + 2 * d + side) * NV) * F + ln[d];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) tseed[v] += l * h[v * F];
-    }
-  __syncthreads();
-
-  // ---- face traces of qbar into B (for the Rusanov parameter derivative) ----
-  {
-    double qbar[NV];
-    tsum(q, [&](int i) { return T::w(i); }, qbar);
-    if (j == 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) qb[v * S + k] = qbar[v];
-    }
-    __syncthreads();
-    for (int it = t; it < 2 * DIM * NV * F; it += TPC) {
-      const int f = it % F, v = (it / F) % NV, face = it / (F * NV);
-      const int d = face >> 1, side = face & 1;
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < n; ++m)
-        acc += (side ? T::l1(m) : T::l0(m)) * qb[v * S + face_line_node<DIM, n>(d, f, m)];
-      if (active) hat[cell * (2 * DIM * NV * F) + it] = acc;
-    }
-    __syncthreads();
-  }
-
-  // ---- reverse sweep ----
-  double mu[NV], nu[NV], lu[NV], gp[NPX];
-#pragma unroll
-  for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    lu[v] = 0.0;
-    nu[v] = dt * wj * lam[(cl * NV + v) * S + k];
-  }
-  {
-    double fI[NGX];
-#pragma unroll
-    for (int c = 0; c < NGX; ++c) fI[c] = c < NGR ? q[C::grad_var(c)] : 0.0;
-    rhs_T(nu, fI, mu, gp, true);
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) mu[v] += wj * tseed[v];
-#pragma unroll
-  for (int r = IMAX - 1; r >= 1; --r) {
-    if (r < I) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) lu[v] += mu[v];
-      double acc[NV];
-      tsum(mu, KWcol, acc);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) nu[v] = dt * acc[v];
-      rhs_T(nu, fw[r], mu, gp, true);
-    }
-  }
-  {
-    // r = 0 on the sum over slices, evaluated by slice 0
-#pragma unroll
-    for (int v = 0; v < NV; ++v) lu[v] += mu[v];
-    double acc[NV];
-    tsum(mu, [&](int i) {
-      double s = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < n; ++jj) s += T::KW(i, jj);
-      return s;
-    }, acc);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) nu[v] = dt * acc[v];
-    rhs_T(nu, fw[0], mu, gp, j == 0);
-    if (j == 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) lu[v] += mu[v];
-    }
-  }
-
-  // ---- lam^n = lam^{n+1} + sum_j lam_u,j; the cell's parameter terms ----
-  {
-    double s[NV];
-    tsum(lu, [](int) { return 1.0; }, s);
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (v % n == j && active) lam[(cell * NV + v) * S + k] += s[v];
-  }
-  if constexpr (NP > 0) {
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < NP; ++p) buf[t * NP + p] = gp[p];
-    __syncthreads();
-    if (t < NP && active) {
-      double s = 0.0;
-      for (int i = 0; i < TPC; ++i) s += buf[i * NP + t];
-      gparams[cell * NP + t] += s;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 3'. Predictor adjoint in the polynomial form of the linear predictor: the
+// 3. Predictor adjoint in the polynomial form of the linear predictor: the
 // forward step's time average is t_0 of Horner's scheme
 //   t_I = c_I u;  t_k = c_k u + dt e_{k+1} w + dt L(m) t_{k+1},
 // and the volume term dt (L qbar + e_0 w).  Its transpose runs the same
@@ -716,18 +243,20 @@ adj_predict_kernel(const KArgs a, const double* __restrict__ Q, const double* __
 //                    mu_{k+1} = dt L^T mu_k
 //   lam_u += c_I mu_I;  lam^n = lam + lam_u
 // plus gp += (d(L qbar)/dm)^T (dt lam).  A forward sweep recomputes the t_k
-// and keeps the gradients the parameter terms read (those of the
-// non-conservative product) in registers.  One thread per node; the
+// and keeps, in registers, the quantities whose gradient the parameter
+// terms read (those of the non-conservative product); each L^T application
+// differentiates them in the same LDS round.  One thread per node; the
 // adjoint's Picard count is at most n, so the sweeps unroll.
 // ---------------------------------------------------------------------------
 template <class PDE, int N>
 struct GeoAdjL {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  static constexpr int CELL_ELEMS =
-      cmax(cmax(C::NCH * G::SP, G::NV * G::S), G::S * (G::NP > 0 ? G::NP : 1));
+  // rows of L^T with the forward-gradient channels, qbar, gradient partials
+  static constexpr int CELL_ELEMS = cmax(cmax((C::NCH + G::DIM * C::ngrad()) * G::SP, G::NV * G::S),
+                                         G::S * (G::NP > 0 ? G::NP : 1));
   static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
-  static constexpr int by_lds = cmax(1, (52 * 1024) / (CELL_ELEMS * 8));
+  static constexpr int by_lds = cmax(1, (76 * 1024) / (CELL_ELEMS * 8));
   static constexpr int CPB = cmin(by_threads, by_lds);
   static constexpr int BLOCK = CPB * G::S;
   static constexpr bool supported = PDE::kLinear && C::uniform() && BLOCK >= 64 && BLOCK <= 1024 &&
@@ -804,8 +333,8 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
     }
   };
 
-  // ---- forward sweep: t_k, keeping the gradients of t_{k+1} ----
-  double gfw[IMAX][DIM][NGX];
+  // ---- forward sweep: t_k, keeping the gradient quantities of t_{k+1} ----
+  double fwv[IMAX][NGX];
   double t[NV];
   {
     const double cI = a.lin_c[I];
@@ -815,32 +344,15 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
 #pragma unroll
   for (int kk = IMAX - 1; kk >= 0; --kk) {
     if (kk < I) {
+#pragma unroll
+      for (int c = 0; c < NGX; ++c) fwv[kk][c] = c < NGR ? t[C::grad_var(c)] : 0.0;
       double Lt[NV], g[DIM][NV];
       Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d)
-#pragma unroll
-        for (int c = 0; c < NGX; ++c) gfw[kk][d][c] = c < NGR ? g[d][C::grad_var(c)] : 0.0;
       const double ck = a.lin_c[kk];
 #pragma unroll
       for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
       add_sources(kk + 1, dt, t);
     }
-  }
-
-  // ---- volume term: parameter derivative at qbar = t, seed dt lam ----
-  double lamv[NV], nu[NV], gp[NPX];
-#pragma unroll
-  for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    lamv[v] = lam[(cl * NV + v) * S + k];
-    nu[v] = dt * lamv[v];
-  }
-  {
-    double Lq[NV], g[DIM][NV];
-    Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lq, g);
-    param_terms(g, nu, gp);
   }
 
   // ---- adjoint of the face traces (read hat before it is overwritten) ----
@@ -857,7 +369,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
       for (int v = 0; v < NV; ++v) tseed[v] += l * h[v * F];
     }
 
-  // ---- face traces of qbar into hat (for the Rusanov parameter derivative) ----
+  // ---- face traces of qbar = t into hat (for the Rusanov parameter derivative) ----
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
   __syncthreads();  // also: every read of hat above is done
@@ -876,14 +388,26 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   }
   __syncthreads();
 
-  // ---- reverse sweep ----
-  double mu[NV], lu[NV];
-  Op::apply_T(a, lds, mine, pk, tid, nu, P, inv_h, mu);
+  // ---- volume term: mu_0 = dt L^T lam + E^T hat; parameter term at qbar ----
+  double nu[NV], mu[NV], gp[NPX], lu[NV];
+#pragma unroll
+  for (int p = 0; p < NPX; ++p) gp[p] = 0.0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    mu[v] += tseed[v];
+    nu[v] = dt * lam[(cl * NV + v) * S + k];
     lu[v] = 0.0;
   }
+  {
+    double fq[NGX], gq[DIM][NV];
+#pragma unroll
+    for (int c = 0; c < NGX; ++c) fq[c] = c < NGR ? t[C::grad_var(c)] : 0.0;
+    Op::template apply_T<true>(a, lds, mine, pk, tid, nu, P, inv_h, mu, fq, gq);
+    param_terms(gq, nu, gp);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mu[v] += tseed[v];
+
+  // ---- reverse sweep ----
 #pragma unroll
   for (int kk = 0; kk < IMAX; ++kk) {
     if (kk < I) {
@@ -894,15 +418,8 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
         nu[v] = dt * mu[v];
       }
       double gq[DIM][NV];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gq[d][v] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NGR; ++c) gq[d][C::grad_var(c)] = gfw[kk][d][c];
-      }
+      Op::template apply_T<true>(a, lds, mine, pk, tid, nu, P, inv_h, mu, fwv[kk], gq);
       param_terms(gq, nu, gp);
-      Op::apply_T(a, lds, mine, pk, tid, nu, P, inv_h, mu);
     }
   }
   {
@@ -914,7 +431,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   // ---- lam^n = lam^{n+1} + lam_u; the cell's parameter terms ----
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) lam[(cell * NV + v) * S + k] = lamv[v] + lu[v];
+    for (int v = 0; v < NV; ++v) lam[(cell * NV + v) * S + k] += lu[v];
   }
   if constexpr (NP > 0) {
 #pragma unroll
@@ -932,7 +449,6 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
 template <class PDE, int N>
 struct AdjLaunch {
   using G = Geo<PDE, N>;
-  using GA = GeoAdj<PDE, N>;
   using GR = GeoAdjR<PDE, N>;
   static hipError_t run(const KArgs& a0, const double* Q, const double* params, const double* clock,
                         double* lam, double* gparams, double* work, hipStream_t st) {

@@ -1222,11 +1222,18 @@ struct LinOp {
 
   // mu = L^T nu at this node (FP64; the PDE's transposes): the flux part
   // through D^T of nu's flux components, the non-conservative part through
-  // D^T of the gradient adjoints, plus the source's transpose.
+  // D^T of the gradient adjoints, plus the source's transpose.  With FW, the
+  // same round also differentiates the forward values fw (the quantities
+  // whose gradient the non-conservative product reads) into gq.  Rows: the
+  // NCHD adjoint channels of every direction, then (FW) NGR forward
+  // channels of every direction.
+  template <bool FW>
   __device__ static __forceinline__ void apply_T(const KArgs& a, double* lds, double* mine,
                                                  const int (&pk)[DIM], int tid, const double (&nu)[NV],
                                                  const double* P, const double (&inv_h)[3],
-                                                 double (&mu)[NV]) {
+                                                 double (&mu)[NV], const double* fw,
+                                                 double (&gq)[DIM][NV]) {
+    constexpr int NF = FW ? NGR : 0;
     double lB[NV], lG[DIM][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1241,19 +1248,37 @@ struct LinOp {
       for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * SP + pk[d]] = nu[C::flux_var(d, cc)];
 #pragma unroll
       for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = lG[d][C::grad_var(cc)];
+#pragma unroll
+      for (int cc = 0; cc < NF; ++cc) mine[(NCH + d * NGR + cc) * SP + pk[d]] = fw[cc];
     }
     __syncthreads();
-    for (int task = tid; task < CPB * NCH * F; task += BLOCK) {
-      const int l = task % F;
-      const int ch = (task / F) % NCH;
-      const int c2 = task / (F * NCH);
-      double* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
+    // adjoint channels (D^T) first, forward channels (D) after them, so that
+    // waves mostly take one kind
+    constexpr int NTA = CPB * NCH * F, NTF = CPB * DIM * NF * F;
+    for (int task = tid; task < NTA + NTF; task += BLOCK) {
       double x[n], y[n];
+      if (task < NTA) {
+        const int l = task % F;
+        const int ch = (task / F) % NCH;
+        const int c2 = task / (F * NCH);
+        double* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
 #pragma unroll
-      for (int m = 0; m < n; ++m) x[m] = row[m];
-      line_deriv_T<double, n>(x, y, inv_h[ch / NCHD]);
+        for (int m = 0; m < n; ++m) x[m] = row[m];
+        line_deriv_T<double, n>(x, y, inv_h[ch / NCHD]);
 #pragma unroll
-      for (int i = 0; i < n; ++i) row[i] = y[i];
+        for (int i = 0; i < n; ++i) row[i] = y[i];
+      } else if constexpr (NF > 0) {
+        const int tf = task - NTA;
+        const int l = tf % F;
+        const int ch = (tf / F) % (DIM * NF);
+        const int c2 = tf / (F * DIM * NF);
+        double* row = lds + c2 * CELL_ELEMS + (NCH + ch) * SP + l * LS;
+#pragma unroll
+        for (int m = 0; m < n; ++m) x[m] = row[m];
+        line_deriv<double, n>(x, y, inv_h[ch / NF]);
+#pragma unroll
+        for (int i = 0; i < n; ++i) row[i] = y[i];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -1263,12 +1288,17 @@ struct LinOp {
     for (int d = 0; d < DIM; ++d) {
       double lF[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) lF[v] = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        lF[v] = 0.0;
+        gq[d][v] = 0.0;
+      }
 #pragma unroll
       for (int cc = 0; cc < NFL; ++cc) lF[C::flux_var(d, cc)] = -mine[(d * NCHD + cc) * SP + pk[d]];
       PDE::flux_T(d, a.pde, lF, mu);
 #pragma unroll
       for (int cc = 0; cc < NGR; ++cc) mu[C::grad_var(cc)] += mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+#pragma unroll
+      for (int cc = 0; cc < NF; ++cc) gq[d][C::grad_var(cc)] = mine[(NCH + d * NGR + cc) * SP + pk[d]];
     }
     __syncthreads();  // rows free for the next writes
   }
