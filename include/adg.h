@@ -174,7 +174,10 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
  * ([C][nvar][S], may equal Q) and, if traces is not NULL, the face traces
  * traces[C][2 dim][2][nvar][F] with face = 2 d + side (side 0 at the low
  * end of axis d), [0] = time-averaged state, [1] = time-averaged normal
- * flux.  For tests and instrumentation; adg_step is the production path. */
+ * flux.  With traces NULL the context's workspace receives what adg_correct
+ * reads (for the PDEs with a linear flux, elasticity and advection, only the
+ * state traces).  For tests and instrumentation; adg_step is the production
+ * path. */
 adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, const double* clock,
                        double* Qvol, double* traces, void* stream);
 

@@ -56,6 +56,10 @@ struct KArgs {
   // lin_c[k] = w^T KW^k 1 (k = 0..kMaxLin): the weights of the time average
   // of the Picard iterate as a polynomial in dt L for PDEs linear in Q
   double lin_c[kMaxLin + 1];
+  // 0: the linear-PDE predictor leaves the flux traces unwritten (the
+  // corrector of a PDE with a linear flux evaluates the flux of the state
+  // trace); set per launch
+  int flux_traces;
   int nsrc;
   int nblocks;  // grid size of the cell kernels (for the block -> cell map)
   const SourceDev* src;
@@ -71,7 +75,8 @@ struct KernelSet {
   int cells_per_block;    // predictor
   int cells_per_block_b;  // corrector and reductions
   hipError_t (*predict)(const KArgs&, int precision, const double* Q, const double* params,
-                        const double* clock, double* Qout, double* traces, hipStream_t);
+                        const double* clock, double* Qout, double* traces, int flux_traces,
+                        hipStream_t);
   hipError_t (*correct)(const KArgs&, double* Q, const double* params, double* clock,
                         const double* traces, int next_dt, hipStream_t);
   hipError_t (*stable_dt)(const KArgs&, const double* Q, const double* params, double* clock,

@@ -347,8 +347,10 @@ adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, cons
   adg_status st = check_state(ctx, Q, params);
   if (st) return st;
   if (!clock || !Qvol) return fail(ADG_ERR_INVALID_ARG, "null clock or output");
+  // the caller's trace array gets both fields; the workspace only what the
+  // corrector reads
   hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Qvol,
-                                  traces ? traces : ctx->traces, (hipStream_t)stream);
+                                  traces ? traces : ctx->traces, traces ? 1 : 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
   if (!traces) ctx->traces_ready = true;
   return ADG_OK;
@@ -374,7 +376,7 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
   if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
   if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, s);
+  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
   ctx->traces_ready = true;
   e = ctx->ks->correct(ctx->args, Q, params, clock, ctx->traces, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);

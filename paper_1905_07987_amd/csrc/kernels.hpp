@@ -1093,7 +1093,8 @@ predict_kernel_pair(const KArgs a, const double* Q, const double* __restrict__ p
 //   t_I = c_I u;  t_k = c_k u + dt e_{k+1} w + dt L t_{k+1};  qbar = t_0.
 // The averaged terms of the volume term and of the traces are those of
 // qbar by linearity: vol = dt (L qbar + e_0 w), traces qhat = trace of qbar
-// and Fhat_d = F_d(qhat).  The result equals the Picard form up to the
+// and Fhat_d = F_d(qhat) (the flux traces only where KArgs::flux_traces asks
+// for them).  The result equals the Picard form up to the
 // order of rounding, at I + 1 applications of L instead of about n I.
 // ---------------------------------------------------------------------------
 template <class PDE, int N, class R>
@@ -1450,18 +1451,19 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
         e1[v] = s1;
       }
       double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-      R Fa[DIM][NV];
-      PDE::fluxes(e0, Pt, a.pde, Fa);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        tr[(0 * NV + v) * F + l] = double(e0[v]);    // face 2d,   state
-        tr[(1 * NV + v) * F + l] = double(Fa[d][v]); // face 2d,   normal flux
+        tr[(0 * NV + v) * F + l] = double(e0[v]);  // face 2d,   state
+        tr[(2 * NV + v) * F + l] = double(e1[v]);  // face 2d+1, state
       }
-      PDE::fluxes(e1, Pt, a.pde, Fa);
+      if (a.flux_traces) {
+        R Fa[DIM][NV];
+        PDE::fluxes(e0, Pt, a.pde, Fa);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        tr[(2 * NV + v) * F + l] = double(e1[v]);    // face 2d+1, state
-        tr[(3 * NV + v) * F + l] = double(Fa[d][v]); // face 2d+1, normal flux
+        for (int v = 0; v < NV; ++v) tr[(1 * NV + v) * F + l] = double(Fa[d][v]);  // face 2d
+        PDE::fluxes(e1, Pt, a.pde, Fa);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tr[(3 * NV + v) * F + l] = double(Fa[d][v]);  // face 2d+1
       }
     }
   }
@@ -1752,8 +1754,10 @@ struct Launch {
   static int blocks_b(const KArgs& a) { return (int)((a.ncells + GB::CPB - 1) / GB::CPB); }
 
   static hipError_t predict(const KArgs& a0, int precision, const double* Q, const double* params,
-                            const double* clock, double* Qout, double* traces, hipStream_t st) {
+                            const double* clock, double* Qout, double* traces, int flux_traces,
+                            hipStream_t st) {
     KArgs a = a0;
+    a.flux_traces = flux_traces;
     if constexpr (PDE::kLinear) {
       if (a.picard_iters <= kMaxLin) {
         if (precision == ADG_MIXED_FP32) {
