@@ -96,7 +96,26 @@ typedef struct {
   double gamma;     /* Euler ratio of specific heats (> 1) */
   double adv[3];    /* advection velocity */
   double kappa;     /* advection decay rate */
+  int bc[6];        /* ADG_BC_* of face 2 d + side (side 1 at the high end of
+                       axis d); all ADG_BC_PERIODIC (0) by default */
 } adg_config;
+
+/* Boundary conditions (the boundaryValues user function of the paper's
+ * Table 2 supplies the state and normal flux outside a boundary face).
+ * Both faces of an axis are periodic, or neither is.  Outside a boundary
+ * face the corrector uses, per face node, a state and normal flux built
+ * from the cell's own time-averaged traces (qin, Fin):
+ *  ADG_BC_OUTFLOW  (qin, Fin): transmissive, no jump across the face;
+ *  ADG_BC_WALL     the mirror image: Euler, the normal momentum reversed
+ *                  (qout = R qin, Fout = -R Fin, as F_d(R q) = -R F_d(q)):
+ *                  a reflecting wall, no mass or energy crosses it;
+ *                  elasticity, the traction sigma_{i d} reversed and the
+ *                  velocity kept (Fout = -Fin): a traction-free surface.
+ *                  Not defined for ADG_PDE_ADVECTION (INVALID_ARG).
+ * The adjoint entry points need a periodic mesh. */
+#define ADG_BC_PERIODIC 0
+#define ADG_BC_OUTFLOW 1
+#define ADG_BC_WALL 2
 
 /* Sizes derived from a configuration (adg_query). */
 typedef struct {
@@ -231,8 +250,8 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
  *   gparams  [C][nparam] device, dJ/dm of this step is ADDED (NULL iff
  *            nparam == 0)
  * Available for ADG_PDE_ELASTIC and ADG_PDE_ADVECTION at every built order
- * with picard_iters <= order + 1; otherwise (ADG_PDE_EULER, more Picard
- * iterations) ADG_ERR_UNSUPPORTED.  Deterministic (no atomics).  Uses the context's
+ * with picard_iters <= order + 1 on a periodic mesh; otherwise
+ * (ADG_PDE_EULER, more Picard iterations, boundaries) ADG_ERR_UNSUPPORTED.  Deterministic (no atomics).  Uses the context's
  * trace workspace: a following adg_correct needs a new adg_predict. */
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
                             const double* clock, double* lam, double* gparams, void* stream);

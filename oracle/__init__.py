@@ -46,6 +46,7 @@ class Problem(C.Structure):
         ("src_w", (C.c_double * MAXQ) * MAXSRC),
         ("src_f0", C.c_double * MAXSRC), ("src_t0", C.c_double * MAXSRC),
         ("src_amp", C.c_double * MAXSRC),
+        ("bc", C.c_int * 6),
     ]
 
     @property
@@ -71,9 +72,13 @@ class Problem(C.Structure):
 _NV = {EULER: None, ELASTIC: 9, ADVECTION: 1}
 
 
+BC_PERIODIC, BC_OUTFLOW, BC_WALL = 0, 1, 2
+
+
 def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None,
-            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=()):
-    """Build a Problem.  ``sources`` is a list of dicts with keys x, w, f0, t0, amp."""
+            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=(), bc=None):
+    """Build a Problem.  ``sources`` is a list of dicts with keys x, w, f0, t0, amp;
+    ``bc`` the boundary condition of each face 2 d + side (default periodic)."""
     P = Problem()
     P.dim, P.order, P.pde = dim, order, pde
     if pde == EULER:
@@ -103,6 +108,8 @@ def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None
         for v, wv in enumerate(src["w"]):
             P.src_w[s][v] = wv
         P.src_f0[s], P.src_t0[s], P.src_amp[s] = src["f0"], src["t0"], src["amp"]
+    for f, b in enumerate(bc or ()):
+        P.bc[f] = b
     return P
 
 

@@ -58,7 +58,12 @@ typedef struct {
   double src_x[ORC_MAXSRC][3];
   double src_w[ORC_MAXSRC][ORC_MAXQ]; /* which variables a source drives */
   double src_f0[ORC_MAXSRC], src_t0[ORC_MAXSRC], src_amp[ORC_MAXSRC];
+  /* boundary condition of face 2 d + side (side 1 at the high end of axis
+   * d): ORC_BC_PERIODIC on both faces of an axis, or OUTFLOW / WALL */
+  int bc[6];
 } orc_problem;
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_WALL = 2 };
 
 /* ------------------------------------------------------------------------
  * 1. One-dimensional tables on the reference interval [0,1].
@@ -317,8 +322,11 @@ typedef struct {
   int stride[3]; /* node stride along each axis: 1, n, n^2 */
 } mesh;
 
+static int bc_valid(const orc_problem *P);
+
 static int make_mesh(const orc_problem *P, mesh *M) {
   if (P->dim < 2 || P->dim > 3) return ORC_EINVAL;
+  if (!bc_valid(P)) return ORC_EINVAL;
   if (P->order < 1 || P->order + 1 > ORC_MAXN) return ORC_EINVAL;
   if (P->nvar < 1 || P->nvar + P->nparam > ORC_MAXQ || P->nparam < 0) return ORC_EINVAL;
   M->dim = P->dim;
@@ -353,12 +361,61 @@ static long cell_index(const orc_problem *P, const int cc[3]) {
   return c;
 }
 
-/* neighbour across the face with normal e_d on side s (-1 or +1), periodic */
+/* neighbour across the face with normal e_d on side s (-1 or +1): wrapped
+ * around on a periodic axis, -1 where the face lies on a non-periodic
+ * domain boundary */
 static long neighbour(const orc_problem *P, long c, int d, int s) {
   int cc[3];
   cell_coords(P, c, cc);
-  cc[d] = (cc[d] + s + P->cells[d]) % P->cells[d];
+  int to = cc[d] + s;
+  if ((to < 0 || to >= P->cells[d]) && P->bc[2 * d + (s > 0)] != ORC_BC_PERIODIC) return -1;
+  cc[d] = (to + P->cells[d]) % P->cells[d];
   return cell_index(P, cc);
+}
+
+/* Boundary conditions (the paper's boundaryValues user function, Table 2,
+ * gives the state and the normal flux outside a boundary face; its Euler
+ * explosion problem uses wall boundaries).  READING: both are built
+ * pointwise from the cell's own time-averaged face traces (qin, Fin):
+ *   OUTFLOW  qout = qin, Fout = Fin (a transmissive boundary: no jump);
+ *   WALL     the mirror image across the face.  Euler: R reverses the
+ *            momentum normal to the face; F_d(R q) = -R F_d(q), so
+ *            qout = R qin, Fout = -R Fin (a reflecting wall: no mass or
+ *            energy crosses it).  Elasticity: the traction sigma_{i d}
+ *            reversed, the velocity kept (a traction-free surface); the
+ *            flux is linear, Fout = F_d(qout) = -Fin.
+ * Material parameters outside are the cell's own. */
+static int bc_valid(const orc_problem *P) {
+  for (int d = 0; d < 3; ++d) {
+    int lo = P->bc[2 * d], hi = P->bc[2 * d + 1];
+    if (lo < 0 || lo > ORC_BC_WALL || hi < 0 || hi > ORC_BC_WALL) return 0;
+    if (d >= P->dim && (lo || hi)) return 0;
+    if ((lo == ORC_BC_PERIODIC) != (hi == ORC_BC_PERIODIC)) return 0;
+    if ((lo == ORC_BC_WALL || hi == ORC_BC_WALL) && P->pde == ORC_ADVECTION) return 0;
+  }
+  return 1;
+}
+
+static int bc_periodic(const orc_problem *P) {
+  for (int f = 0; f < 6; ++f)
+    if (P->bc[f] != ORC_BC_PERIODIC) return 0;
+  return 1;
+}
+
+static void bc_ghost(const orc_problem *P, int kind, int d, const double *qin, const double *Fin,
+                     double *qout, double *Fout) {
+  for (int v = 0; v < P->nvar + P->nparam; ++v) qout[v] = qin[v];
+  for (int v = 0; v < P->nvar; ++v) Fout[v] = Fin[v];
+  if (kind != ORC_BC_WALL) return;
+  if (P->pde == ORC_EULER) {
+    qout[1 + d] = -qin[1 + d];
+    for (int v = 0; v < P->nvar; ++v)
+      if (v != 1 + d) Fout[v] = -Fin[v];
+  } else if (P->pde == ORC_ELASTIC) {
+    /* traction components sigma_{x d}, sigma_{y d}, sigma_{z d} */
+    for (int i = 0; i < 3; ++i) qout[sym_index(i, d)] = -qin[sym_index(i, d)];
+    for (int v = 0; v < P->nvar; ++v) Fout[v] = -Fin[v];
+  }
 }
 
 /* node multi-index */
@@ -680,30 +737,46 @@ static void correct_cell(const orc_problem *P, const mesh *M, const tables *T, l
   double *fl = malloc(sizeof(double) * 2 * M->dim * face_sz);
   double *G = malloc(sizeof(double) * 2 * M->dim * face_sz);
   double qL[ORC_MAXQ], qR[ORC_MAXQ], flL[ORC_MAXQ], flR[ORC_MAXQ];
+  double FL[ORC_MAXQ], FR[ORC_MAXQ];
   for (int d = 0; d < M->dim; ++d) {
     for (int side = 0; side < 2; ++side) {
-      /* side 1: this cell is L, the neighbour above is R; side 0: reverse */
-      long cl = side ? c : nb[2 * d + 0];
-      long cr = side ? nb[2 * d + 1] : c;
-      const double *qhL = qhat_of[side ? 0 : 1 + 2 * d] + (size_t)(2 * d + 1) * face_sz;
-      const double *FhL = Fhat_of[side ? 0 : 1 + 2 * d] + (size_t)(2 * d + 1) * face_sz;
-      const double *qhR = qhat_of[side ? 2 + 2 * d : 0] + (size_t)(2 * d + 0) * face_sz;
-      const double *FhR = Fhat_of[side ? 2 + 2 * d : 0] + (size_t)(2 * d + 0) * face_sz;
+      /* side 1: this cell is L, the neighbour above is R; side 0: reverse.
+       * Without a neighbour (a non-periodic boundary face) the other side is
+       * the boundary condition's outside state. */
+      const long other = nb[2 * d + side];
+      const double *qown = qhat_of[0] + (size_t)(2 * d + side) * face_sz;
+      const double *Fown = Fhat_of[0] + (size_t)(2 * d + side) * face_sz;
+      const double *qoth = other < 0 ? NULL : qhat_of[1 + 2 * d + side] + (size_t)(2 * d + 1 - side) * face_sz;
+      const double *Foth = other < 0 ? NULL : Fhat_of[1 + 2 * d + side] + (size_t)(2 * d + 1 - side) * face_sz;
       for (int f = 0; f < F; ++f) {
+        double qo[ORC_MAXQ], qx[ORC_MAXQ], Fo[ORC_MAXQ], Fx[ORC_MAXQ];
         for (int v = 0; v < nv; ++v) {
-          qL[v] = qhL[(size_t)f * nv + v];
-          qR[v] = qhR[(size_t)f * nv + v];
+          qo[v] = qown[(size_t)f * nv + v];
+          Fo[v] = Fown[(size_t)f * nv + v];
         }
-        for (int p = 0; p < P->nparam; ++p) {
-          qL[nv + p] = params[(size_t)cl * P->nparam + p];
-          qR[nv + p] = params[(size_t)cr * P->nparam + p];
+        for (int p = 0; p < P->nparam; ++p) qo[nv + p] = params[(size_t)c * P->nparam + p];
+        if (other < 0) {
+          bc_ghost(P, P->bc[2 * d + side], d, qo, Fo, qx, Fx);
+        } else {
+          for (int v = 0; v < nv; ++v) {
+            qx[v] = qoth[(size_t)f * nv + v];
+            Fx[v] = Foth[(size_t)f * nv + v];
+          }
+          for (int p = 0; p < P->nparam; ++p) qx[nv + p] = params[(size_t)other * P->nparam + p];
         }
-        rusanov(P, d, qL, &FhL[(size_t)f * nv], qR, &FhR[(size_t)f * nv], flL, flR);
+        for (int v = 0; v < nv + P->nparam; ++v) {
+          qL[v] = side ? qo[v] : qx[v];
+          qR[v] = side ? qx[v] : qo[v];
+        }
+        for (int v = 0; v < nv; ++v) {
+          FL[v] = side ? Fo[v] : Fx[v];
+          FR[v] = side ? Fx[v] : Fo[v];
+        }
+        rusanov(P, d, qL, FL, qR, FR, flL, flR);
         for (int v = 0; v < nv; ++v) {
           fl[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] : flR[v];
           /* G itself, for the weak-form check */
-          G[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] + FhL[(size_t)f * nv + v]
-                                                                  : FhR[(size_t)f * nv + v] - flR[v];
+          G[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] + FL[v] : FR[v] - flR[v];
         }
       }
     }
@@ -903,8 +976,8 @@ int orc_step(const orc_problem *P, double *Q, const double *params, double dt, d
         for (int d = 0; d < M.dim; ++d)
           for (int s = 0; s < 2; ++s) {
             nb[2 * d + s] = neighbour(P, c, d, s ? 1 : -1);
-            qh[1 + 2 * d + s] = &CS.qhat[nb[2 * d + s] * face_all];
-            Fh[1 + 2 * d + s] = &CS.Fhat[nb[2 * d + s] * face_all];
+            qh[1 + 2 * d + s] = nb[2 * d + s] < 0 ? NULL : &CS.qhat[nb[2 * d + s] * face_all];
+            Fh[1 + 2 * d + s] = nb[2 * d + s] < 0 ? NULL : &CS.Fhat[nb[2 * d + s] * face_all];
           }
         correct_cell(P, &M, &T, c, Q, params, dt, &CS.vol[(size_t)c * M.S * M.nv],
                      CS.weak ? &CS.weak[(size_t)c * M.S * M.nv] : NULL, qh, Fh, nb,
@@ -939,7 +1012,11 @@ int orc_step_cells(const orc_problem *P, const double *Q, const double *params, 
     for (long i = 0; i < ncs; ++i) {
       list[i * per] = cells[i];
       for (int d = 0; d < M.dim; ++d)
-        for (int s = 0; s < 2; ++s) list[i * per + 1 + 2 * d + s] = neighbour(P, cells[i], d, s ? 1 : -1);
+        for (int s = 0; s < 2; ++s) {
+          /* a boundary face predicts the cell itself again (unused) */
+          long o = neighbour(P, cells[i], d, s ? 1 : -1);
+          list[i * per + 1 + 2 * d + s] = o < 0 ? cells[i] : o;
+        }
     }
     st = predict_all(P, &M, &T, Q, params, dt, t, list, nall, &CS);
     if (st == ORC_OK) {
@@ -950,7 +1027,7 @@ int orc_step_cells(const orc_problem *P, const double *Q, const double *params, 
         for (int a = 0; a < per; ++a) {
           qh[a] = &CS.qhat[(i * per + a) * face_all];
           Fh[a] = &CS.Fhat[(i * per + a) * face_all];
-          if (a > 0) nb[a - 1] = list[i * per + a];
+          if (a > 0) nb[a - 1] = neighbour(P, cells[i], (a - 1) / 2, (a - 1) % 2 ? 1 : -1);
         }
         correct_cell(P, &M, &T, cells[i], Q, params, dt, &CS.vol[(size_t)(i * per) * M.S * M.nv],
                      NULL, qh, Fh, nb, &out[(size_t)i * M.nv * M.S], NULL);
@@ -1259,7 +1336,8 @@ int orc_step_adjoint(const orc_problem *P, const double *Q, const double *params
                      double t, double *lam, double *gparams) {
   mesh M;
   tables T;
-  if (!pde_is_linear(P) || make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
+  /* the adjoint is that of the periodic step */
+  if (!pde_is_linear(P) || !bc_periodic(P) || make_mesh(P, &M) || make_tables(M.n, &T)) return ORC_EINVAL;
   const int n = M.n, S = M.S, nv = M.nv, nq = M.nq, F = M.F, dim = M.dim, I = P->picard_iters;
   const size_t face_all = (size_t)2 * dim * F * nv;
   const long C = M.C;

@@ -36,7 +36,12 @@ class Config(C.Structure):
         ("cells", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("cfl", C.c_double), ("picard_iters", C.c_int), ("reserved", C.c_int),
         ("gamma", C.c_double), ("adv", C.c_double * 3), ("kappa", C.c_double),
+        ("bc", C.c_int * 6),
     ]
+
+
+BC_PERIODIC, BC_OUTFLOW, BC_WALL = 0, 1, 2
+_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "wall": BC_WALL}
 
 
 class Info(C.Structure):
@@ -121,8 +126,10 @@ class Solver:
 
     def __init__(self, dim: int, order: int, pde="euler", cells=(16, 16, 1), lo=(0.0, 0.0, 0.0),
                  hi=(1.0, 1.0, 1.0), cfl: float = 0.9, picard_iters: int = 0, precision="fp64",
-                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0):
+                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None):
         cfg = Config()
+        for f, b in enumerate(bc or ()):
+            cfg.bc[f] = _BC_NAMES.get(b, b)
         cfg.dim, cfg.order = dim, order
         cfg.pde = _PDE_NAMES.get(pde, pde)
         cfg.precision = _PREC_NAMES.get(precision, precision)

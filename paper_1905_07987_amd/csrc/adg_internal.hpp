@@ -46,6 +46,7 @@ struct SourceDev {
 // Everything a kernel needs besides the data pointers; passed by value.
 struct KArgs {
   int cells[3];
+  int bc[6];  // ADG_BC_* per face 2 d + side
   int picard_iters;
   long long ncells;
   double h[3], inv_h[3];

@@ -160,6 +160,16 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
   if (c.picard_iters < 0 || c.picard_iters > 64)
     return fail(ADG_ERR_INVALID_ARG, "picard_iters must be in 0..64");
   if (c.pde == ADG_PDE_EULER && !(c.gamma > 1.0)) return fail(ADG_ERR_INVALID_ARG, "gamma must be > 1");
+  for (int d = 0; d < 3; ++d) {
+    const int blo = c.bc[2 * d], bhi = c.bc[2 * d + 1];
+    if (blo < ADG_BC_PERIODIC || blo > ADG_BC_WALL || bhi < ADG_BC_PERIODIC || bhi > ADG_BC_WALL)
+      return fail(ADG_ERR_INVALID_ARG, "unknown boundary condition");
+    if (d >= c.dim && (blo || bhi)) return fail(ADG_ERR_INVALID_ARG, "boundary condition on a missing axis");
+    if ((blo == ADG_BC_PERIODIC) != (bhi == ADG_BC_PERIODIC))
+      return fail(ADG_ERR_INVALID_ARG, "an axis is periodic on both faces or on neither");
+    if ((blo == ADG_BC_WALL || bhi == ADG_BC_WALL) && c.pde == ADG_PDE_ADVECTION)
+      return fail(ADG_ERR_INVALID_ARG, "no wall condition for the advection PDE");
+  }
   long long C = 1;
   for (int d = 0; d < c.dim; ++d) {
     if (c.cells[d] < 1) return fail(ADG_ERR_INVALID_ARG, "cells must be >= 1");
@@ -194,6 +204,7 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
   }
 
   KArgs& a = x->args;
+  for (int f = 0; f < 6; ++f) a.bc[f] = c.bc[f];
   for (int d = 0; d < 3; ++d) {
     a.cells[d] = d < c.dim ? c.cells[d] : 1;
     a.h[d] = d < c.dim ? (c.hi[d] - c.lo[d]) / c.cells[d] : 1.0;
@@ -531,10 +542,10 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
   if (st) return st;
   if (!clock || !lam) return fail(ADG_ERR_INVALID_ARG, "null clock or adjoint");
   if (ctx->np > 0 && !gparams) return fail(ADG_ERR_INVALID_ARG, "null parameter gradient");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->args.bc[f] != ADG_BC_PERIODIC) return fail(ADG_ERR_UNSUPPORTED, "the adjoint needs a periodic mesh");
   if (!ctx->ks->adjoint)
-    return fail(ADG_ERR_UNSUPPORTED,
-                "the adjoint is built for the linear PDEs (elastic, advection) at orders whose "
-                "kernel fits one block (elastic and 3-D advection up to 3, 2-D advection up to 7)");
+    return fail(ADG_ERR_UNSUPPORTED, "the adjoint is built for the PDEs linear in Q (elastic, advection)");
   if (ctx->args.picard_iters > ctx->cfg.order + 1)
     return fail(ADG_ERR_UNSUPPORTED, "the adjoint supports at most order + 1 Picard iterations");
   hipError_t e = ctx->ks->adjoint(ctx->args, Q, params, clock, lam, gparams, ctx->traces,

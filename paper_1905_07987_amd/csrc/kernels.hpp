@@ -1515,18 +1515,26 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     const int c = cell0 + c2;
     if (c >= ncells) continue;
     const int d = face >> 1, side = face & 1;
-    // periodic neighbour across this face
+    // neighbour across this face: wrapped around on a periodic axis; on a
+    // boundary face of a non-periodic axis the outside state and normal flux
+    // come from this cell's own traces (outflow: a copy, wall: the mirror
+    // image)
     int cc[3];
     cc[0] = c % C0;
     cc[1] = (c / C0) % C1;
     cc[2] = DIM == 3 ? c / (C0 * C1) : 0;
     cc[d] += side ? 1 : -1;
+    const int bc = (cc[d] < 0 || cc[d] >= a.cells[d]) ? a.bc[face] : ADG_BC_PERIODIC;
     if (cc[d] < 0) cc[d] += a.cells[d];
     if (cc[d] >= a.cells[d]) cc[d] -= a.cells[d];
-    const int nb = cc[0] + C0 * (cc[1] + C1 * cc[2]);
+    const int nb = bc == ADG_BC_PERIODIC ? cc[0] + C0 * (cc[1] + C1 * cc[2]) : c;
     const int cL = side ? c : nb, cR = side ? nb : c;
-    const double* tL = traces + ((long long)(cL * (2 * DIM) + 2 * d + 1) * 2) * NV * F;
-    const double* tR = traces + ((long long)(cR * (2 * DIM) + 2 * d + 0) * 2) * NV * F;
+    // the two traces that meet at this face; on a boundary face both are
+    // this cell's own trace of the face
+    const int fL = bc != ADG_BC_PERIODIC ? face : 2 * d + 1;
+    const int fR = bc != ADG_BC_PERIODIC ? face : 2 * d;
+    const double* tL = traces + ((long long)(cL * (2 * DIM) + fL) * 2) * NV * F;
+    const double* tR = traces + ((long long)(cR * (2 * DIM) + fR) * 2) * NV * F;
     double qL[NV], qR[NV], FL[NV], FR[NV], pL[NP > 0 ? NP : 1], pR[NP > 0 ? NP : 1], pm[NP > 0 ? NP : 1];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -1562,6 +1570,21 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
       for (int v = 0; v < NV; ++v) {
         FL[v] = tL[(NV + v) * F + f];
         FR[v] = tR[(NV + v) * F + f];
+      }
+    }
+    if (bc == ADG_BC_WALL) {
+      // both sides hold this cell's trace: replace the outside one
+      double qx[NV], Fx[NV];
+      Wall<PDE>::apply(d, side ? qL : qR, side ? FL : FR, qx, Fx);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (side) {
+          qR[v] = qx[v];
+          FR[v] = Fx[v];
+        } else {
+          qL[v] = qx[v];
+          FL[v] = Fx[v];
+        }
       }
     }
     const double s = fmax(PDE::max_eigen(qL, pL, a.pde, d), PDE::max_eigen(qR, pR, a.pde, d));

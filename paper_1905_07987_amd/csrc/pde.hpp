@@ -282,4 +282,51 @@ struct Advection {
   }
 };
 
+// Wall boundary condition per PDE: the outside state and normal flux of a
+// wall face with normal e_d from the inside traces (qin, Fin).
+template <class PDE>
+struct Wall;
+
+// Euler: the mirror image, R = normal momentum reversed; qout = R qin and,
+// as F_d(R q) = -R F_d(q), Fout = -R Fin (a reflecting wall).
+template <int DIM_>
+struct Wall<Euler<DIM_>> {
+  static constexpr int NV = Euler<DIM_>::NV;
+  __device__ static __forceinline__ void apply(int d, const double* qin, const double* Fin, double* qout,
+                                               double* Fout) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const bool normal = v == 1 + d;
+      qout[v] = normal ? -qin[v] : qin[v];
+      Fout[v] = normal ? Fin[v] : -Fin[v];
+    }
+  }
+};
+
+// Elasticity: the traction sigma_{i d} reversed, the velocity kept (a
+// traction-free surface); the flux is linear, Fout = -Fin.
+template <>
+struct Wall<Elastic3> {
+  static constexpr int NV = Elastic3::NV;
+  __device__ static __forceinline__ void apply(int d, const double* qin, const double* Fin, double* qout,
+                                               double* Fout) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const bool traction = v == Elastic3::sym(0, d) || v == Elastic3::sym(1, d) || v == Elastic3::sym(2, d);
+      qout[v] = traction ? -qin[v] : qin[v];
+      Fout[v] = -Fin[v];
+    }
+  }
+};
+
+// The advection PDE has no wall condition (refused at context creation).
+template <int DIM_>
+struct Wall<Advection<DIM_>> {
+  __device__ static __forceinline__ void apply(int, const double* qin, const double* Fin, double* qout,
+                                               double* Fout) {
+    qout[0] = qin[0];
+    Fout[0] = Fin[0];
+  }
+};
+
 }  // namespace adg
