@@ -169,6 +169,9 @@ STEP_CASES = {
                                     kappa=0.3, picard_iters=17), 3),
     "advection2_N1_ragged": (dict(dim=2, order=1, pde="advection", cells=[13, 7], adv=(0.7, -0.4, 0.0),
                                   kappa=0.3), 4),
+    # I = N: the Cauchy-Kowalevski time average for a linear PDE
+    "advection3_N4_ck": (dict(dim=3, order=4, pde="advection", cells=[3, 2, 3], adv=(0.3, 0.5, -0.2),
+                              kappa=0.4, picard_iters=4), 3),
 }
 
 
