@@ -312,6 +312,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
   if (src_here && tid < a.nsrc) lin_source_weights<n>(a, tid, t_n, dt, I, src_e[tid]);
+  if (src_here) __syncthreads();  // src_e for every wave of the block
   auto add_sources = [&](int kk, double scale, double* t) {
     if (!src_here) return;
     for (int s = 0; s < a.nsrc; ++s) {
@@ -372,21 +373,20 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   // ---- face traces of qbar = t into hat (for the Rusanov parameter derivative) ----
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
-  __syncthreads();  // also: every read of hat above is done
-  for (int it = tid; it < CPB * 2 * DIM * NV * F; it += BLOCK) {
-    const int f = it % F, v = (it / F) % NV, face = (it / (F * NV)) % (2 * DIM);
-    const int c2 = it / (F * NV * 2 * DIM);
+  Op::sync();  // also: every read of hat above is done
+  Op::template cell_tasks<2 * DIM * NV * F>(tid, [&](int c2, int it) {
+    const int f = it % F, v = (it / F) % NV, face = it / (F * NV);
     const int d = face >> 1, side = face & 1;
     const long long tcell = cell0 + c2;
-    if (tcell >= a.ncells) continue;
+    if (tcell >= a.ncells) return;
     const double* rows = lds + c2 * GA::CELL_ELEMS;
     double acc = 0.0;
 #pragma unroll
     for (int m = 0; m < n; ++m)
       acc += (side ? T::l1(m) : T::l0(m)) * rows[v * S + face_line_node<DIM, n>(d, f, m)];
     hat[tcell * (2 * DIM * NV * F) + (face * NV + v) * F + f] = acc;
-  }
-  __syncthreads();
+  });
+  Op::sync();
 
   // ---- volume term: mu_0 = dt L^T lam + E^T hat; parameter term at qbar ----
   double nu[NV], mu[NV], gp[NPX], lu[NV];
@@ -436,7 +436,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   if constexpr (NP > 0) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) mine[k * NP + p] = gp[p];
-    __syncthreads();
+    Op::sync();
     if (k < NP && active) {
       double s = 0.0;
       for (int i = 0; i < S; ++i) s += mine[i * NP + k];

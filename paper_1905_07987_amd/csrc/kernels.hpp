@@ -1166,6 +1166,32 @@ struct LinOp {
   using C = Chan<PDE>;
   static constexpr int n = G::n, F = G::F, NV = G::NV, DIM = G::DIM, SP = G::SP, LS = G::LS;
   static constexpr int NCH = C::NCH, NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
+  // A cell of 64 nodes is one wave: its rows are written, differentiated and
+  // read back by that wave alone, so the line tasks of a cell stay on its
+  // wave and a wave-level fence replaces the block barrier (LDS accesses of
+  // one wave complete in order).
+  static constexpr bool kWave = G::S == 64;
+
+  __device__ static __forceinline__ void sync() {
+    if constexpr (kWave) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+
+  // f(cell in block, task in cell) over the NT tasks of every cell of the
+  // block: on the cell's own wave (kWave) or spread over the block
+  template <int NT, class Fn>
+  __device__ static __forceinline__ void cell_tasks(int tid, Fn f) {
+    if constexpr (kWave) {
+      for (int t = tid & 63; t < NT; t += 64) f(tid >> 6, t);
+    } else {
+      for (int task = tid; task < CPB * NT; task += BLOCK) f(task / NT, task % NT);
+    }
+  }
 
   // out = L t = S(t) - div F(t) - B(t) grad t at this node; g = the gradients
   // the non-conservative product reads (zero elsewhere)
@@ -1181,11 +1207,9 @@ struct LinOp {
 #pragma unroll
       for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = t[C::grad_var(cc)];
     }
-    __syncthreads();
-    for (int task = tid; task < CPB * NCH * F; task += BLOCK) {
-      const int l = task % F;
-      const int ch = (task / F) % NCH;
-      const int c2 = task / (F * NCH);
+    sync();
+    cell_tasks<NCH * F>(tid, [&](int c2, int t) {
+      const int l = t % F, ch = t / F;
       R* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
       R x[n], y[n];
 #pragma unroll
@@ -1193,8 +1217,8 @@ struct LinOp {
       line_deriv<R, n>(x, y, inv_h[ch / NCHD]);
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i] = y[i];
-    }
-    __syncthreads();
+    });
+    sync();
     R divF[NV], B[NV], Sv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1218,7 +1242,7 @@ struct LinOp {
     PDE::source(t, P, a.pde, Sv);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
-    __syncthreads();  // rows free for the next writes
+    sync();  // rows free for the next writes
   }
 
   // mu = L^T nu at this node (FP64; the PDE's transposes): the flux part
@@ -1252,16 +1276,14 @@ struct LinOp {
 #pragma unroll
       for (int cc = 0; cc < NF; ++cc) mine[(NCH + d * NGR + cc) * SP + pk[d]] = fw[cc];
     }
-    __syncthreads();
-    // adjoint channels (D^T) first, forward channels (D) after them, so that
-    // waves mostly take one kind
-    constexpr int NTA = CPB * NCH * F, NTF = CPB * DIM * NF * F;
-    for (int task = tid; task < NTA + NTF; task += BLOCK) {
+    sync();
+    // per cell: adjoint channels (D^T) first, forward channels (D) after
+    // them, so that waves mostly take one kind
+    constexpr int NTA = NCH * F, NTF = DIM * NF * F;
+    auto task = [&](int c2, int t) {
       double x[n], y[n];
-      if (task < NTA) {
-        const int l = task % F;
-        const int ch = (task / F) % NCH;
-        const int c2 = task / (F * NCH);
+      if (t < NTA) {
+        const int l = t % F, ch = t / F;
         double* row = lds + c2 * CELL_ELEMS + ch * SP + l * LS;
 #pragma unroll
         for (int m = 0; m < n; ++m) x[m] = row[m];
@@ -1269,10 +1291,8 @@ struct LinOp {
 #pragma unroll
         for (int i = 0; i < n; ++i) row[i] = y[i];
       } else if constexpr (NF > 0) {
-        const int tf = task - NTA;
-        const int l = tf % F;
-        const int ch = (tf / F) % (DIM * NF);
-        const int c2 = tf / (F * DIM * NF);
+        const int tf = t - NTA;
+        const int l = tf % F, ch = tf / F;
         double* row = lds + c2 * CELL_ELEMS + (NCH + ch) * SP + l * LS;
 #pragma unroll
         for (int m = 0; m < n; ++m) x[m] = row[m];
@@ -1280,8 +1300,17 @@ struct LinOp {
 #pragma unroll
         for (int i = 0; i < n; ++i) row[i] = y[i];
       }
+    };
+    if constexpr (kWave) {
+      cell_tasks<NTA + NTF>(tid, task);
+    } else {
+      // all cells' adjoint tasks, then all cells' forward tasks
+      for (int i = tid; i < CPB * (NTA + NTF); i += BLOCK) {
+        if (i < CPB * NTA) task(i / NTA, i % NTA);
+        else task((i - CPB * NTA) / (NTF > 0 ? NTF : 1), NTA + (i - CPB * NTA) % (NTF > 0 ? NTF : 1));
+      }
     }
-    __syncthreads();
+    sync();
 #pragma unroll
     for (int v = 0; v < NV; ++v) mu[v] = 0.0;
     PDE::source_T(a.pde, nu, mu);
@@ -1301,7 +1330,7 @@ struct LinOp {
 #pragma unroll
       for (int cc = 0; cc < NF; ++cc) gq[d][C::grad_var(cc)] = mine[(NCH + d * NGR + cc) * SP + pk[d]];
     }
-    __syncthreads();  // rows free for the next writes
+    sync();  // rows free for the next writes
   }
 };
 
@@ -1383,6 +1412,7 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
   if (src_here && tid < a.nsrc) lin_source_weights<n>(a, tid, t_n, dt64, I, src_e[tid]);
+  if (src_here) __syncthreads();  // src_e for every wave of the block
   // t[v] += scale * e_kk * w at this node for every source in this cell
   auto add_sources = [&](int kk, R scale, R* t) {
     if (!src_here) return;
@@ -1424,13 +1454,12 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
   // (cell, direction, line) extrapolates every quantity to both ends
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
-  __syncthreads();
-  for (int task = tid; task < CPB * DIM * F; task += BLOCK) {
+  Op::sync();
+  Op::template cell_tasks<DIM * F>(tid, [&](int c2, int task) {
     const int l = task % F;
-    const int dt_ = (task / F) % DIM;
-    const int c2 = task / (F * DIM);
+    const int dt_ = task / F;
     const long long tcell = cell0 + c2;
-    if (tcell >= a.ncells) continue;
+    if (tcell >= a.ncells) return;
     const R* rows = lds + c2 * GL::CELL_ELEMS;
     R e0[NV], e1[NV], Pt[NP > 0 ? NP : 1];
 #pragma unroll
@@ -1466,7 +1495,7 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
         for (int v = 0; v < NV; ++v) tr[(3 * NV + v) * F + l] = double(Fa[d][v]);  // face 2d+1
       }
     }
-  }
+  });
 
   if (active) {
 #pragma unroll
