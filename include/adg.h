@@ -39,8 +39,10 @@
 #ifndef ADG_H
 #define ADG_H
 
+#if !defined(__HIPCC_RTC__)
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -52,6 +54,7 @@ typedef int adg_status;
 #define ADG_ERR_HIP (-2)         /* a HIP runtime call failed (message has the hipError_t) */
 #define ADG_ERR_NOMEM (-3)       /* device or host allocation failed */
 #define ADG_ERR_UNSUPPORTED (-4) /* valid but not built: order, PDE/dim pair, precision */
+#define ADG_ERR_COMPILE (-5)     /* a run-time PDE failed to compile (hiprtc log in the message) */
 #define ADG_ERR_STATE (-6)       /* call out of order, e.g. sampling with no receivers set */
 
 /* Built-in PDEs (Sec. 2 and Sec. 6).  Their pointwise terms follow the
@@ -74,6 +77,7 @@ typedef int adg_status;
 #define ADG_PDE_EULER 1
 #define ADG_PDE_ELASTIC 2
 #define ADG_PDE_ADVECTION 3
+#define ADG_PDE_USER 4 /* the PDE of adg_create_user's source text */
 
 /* Arithmetic of the predictor (space-time predictor, time averages, face
  * projection and volume integral).  The time step, the Rusanov face flux,
@@ -160,6 +164,35 @@ adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double*
  * adg_destroy.  Errors: INVALID_ARG (bad values), UNSUPPORTED (order or
  * PDE/dim not built), NOMEM, HIP. */
 adg_status adg_create(const adg_config* cfg, adg_ctx** out);
+
+/* A context for a PDE given as HIP source text (cfg->pde == ADG_PDE_USER),
+ * the run-time counterpart of the user functions of the paper's Table 2
+ * (flux, eigenvalues, nonConservativeProduct, algebraicSource,
+ * isPhysicallyAdmissible) with the (Q, direction, out) convention of its
+ * printed eigenvalues signature.  source (NUL-terminated, not retained)
+ * defines
+ *
+ *   struct AdgUserPDE {
+ *     static constexpr int DIM = 2 or 3 (== cfg->dim), NV, NP;  // NV + NP <= 16
+ *     static constexpr bool LINEAR, HAS_NCP, HAS_SOURCE;
+ *     template <class R> __device__ static void flux(const R* Q, int d, R* F);
+ *     template <class R> __device__ static void eigenvalues(const R* Q, int d, R* lam);
+ *     template <class R> __device__ static void ncp(const R* Q, const R* gradQ, R* BgradQ);
+ *     template <class R> __device__ static void source(const R* Q, R* S);
+ *     template <class R> __device__ static bool admissible(const R* Q);
+ *   };
+ *
+ * Q = NV evolved quantities then the cell's NP parameters; F, lam, BgradQ,
+ * S: NV entries; gradQ [DIM][NV]; R = double (float in the MIXED_FP32
+ * predictor).  The kernels use the largest |lam|.  LINEAR declares flux, ncp
+ * and source linear and homogeneous in the evolved quantities (the
+ * polynomial form of the predictor is then used).  The library's kernels are
+ * compiled for the struct with hiprtc for the current device, once, here
+ * (seconds).  Everything else is as for built-in PDEs (nvar, nparam come
+ * from the struct, see adg_query), except: no wall boundaries
+ * (INVALID_ARG) and no adjoint (UNSUPPORTED).  Errors as adg_create, plus
+ * COMPILE with the compiler log in adg_last_error(). */
+adg_status adg_create_user(const adg_config* cfg, const char* source, adg_ctx** out);
 
 /* Release the context and its device memory (waits for the device). */
 adg_status adg_destroy(adg_ctx* ctx);

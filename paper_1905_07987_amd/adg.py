@@ -20,7 +20,8 @@ PDE_EULER, PDE_ELASTIC, PDE_ADVECTION = 1, 2, 3
 FP64, MIXED_FP32 = 0, 1
 STEP_NEXT_DT = 1
 
-_PDE_NAMES = {"euler": PDE_EULER, "elastic": PDE_ELASTIC, "advection": PDE_ADVECTION}
+PDE_USER = 4
+_PDE_NAMES = {"euler": PDE_EULER, "elastic": PDE_ELASTIC, "advection": PDE_ADVECTION, "user": PDE_USER}
 _PREC_NAMES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32}
 
 
@@ -72,6 +73,7 @@ def lib():
         L.adg_max_order.argtypes = [C.c_int, C.c_int]
         L.adg_basis_tables.argtypes = [C.c_int] + [dp] * 6
         L.adg_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.adg_create_user.argtypes = [C.POINTER(Config), C.c_char_p, C.POINTER(vp)]
         L.adg_destroy.argtypes = [vp]
         L.adg_query.argtypes = [vp, C.POINTER(Info)]
         L.adg_node_coords.argtypes = [vp, dp]
@@ -89,7 +91,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_destroy",
+EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
             "adg_query", "adg_node_coords", "adg_stable_dt", "adg_step", "adg_predict", "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
             "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint")
@@ -126,7 +128,8 @@ class Solver:
 
     def __init__(self, dim: int, order: int, pde="euler", cells=(16, 16, 1), lo=(0.0, 0.0, 0.0),
                  hi=(1.0, 1.0, 1.0), cfl: float = 0.9, picard_iters: int = 0, precision="fp64",
-                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None):
+                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None,
+                 source: str | None = None):
         cfg = Config()
         for f, b in enumerate(bc or ()):
             cfg.bc[f] = _BC_NAMES.get(b, b)
@@ -142,7 +145,12 @@ class Solver:
         cfg.cfl, cfg.picard_iters, cfg.gamma, cfg.kappa = cfl, picard_iters, gamma, kappa
         self.cfg = cfg
         self._ctx = C.c_void_p()
-        _check(lib().adg_create(C.byref(cfg), C.byref(self._ctx)))
+        if source is not None:
+            # a PDE given as HIP source text (struct AdgUserPDE), compiled now
+            cfg.pde = PDE_USER
+            _check(lib().adg_create_user(C.byref(cfg), source.encode(), C.byref(self._ctx)))
+        else:
+            _check(lib().adg_create(C.byref(cfg), C.byref(self._ctx)))
         info = Info()
         _check(lib().adg_query(self._ctx, C.byref(info)))
         self.info = info

@@ -2,11 +2,16 @@
 // units of libadg.  Not part of the ABI.
 #pragma once
 
+// The device part (constants, tables, KArgs) is also compiled at run time by
+// hiprtc for user-supplied PDEs (__HIPCC_RTC__), which brings its own HIP
+// device runtime and no host headers.
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
-#include <cstdint>
 #include <string>
+#endif
+#include <cstdint>
 
 #include "../../include/adg.h"
 #include "basis.hpp"
@@ -70,6 +75,7 @@ struct KArgs {
   unsigned long long* slots;
 };
 
+#if !defined(__HIPCC_RTC__)
 // Kernel entry points of one (PDE, dim, order) instantiation set.
 struct KernelSet {
   int block;  // threads per block of the predictor
@@ -103,6 +109,25 @@ int max_order_euler3();
 int max_order_elastic3();
 int max_order_advection2();
 int max_order_advection3();
+
+// PDEs compiled at run time (user.hip).
+struct UserTraits {
+  int dim, nv, np, linear, has_ncp, has_source;
+};
+struct UserModule;
+adg_status user_traits(const char* source, const std::string& arch, UserTraits* t, std::string* err);
+adg_status user_module_create(const char* source, const std::string& arch, int order, int precision,
+                              bool linear_predictor, UserModule** out, std::string* err);
+void user_module_destroy(UserModule* u);
+hipError_t user_predict(const UserModule* u, const KArgs& a, const double* Q, const double* params,
+                        const double* clock, double* Qout, double* traces, int flux_traces, hipStream_t st);
+hipError_t user_correct(const UserModule* u, const KArgs& a, double* Q, const double* params, double* clock,
+                        const double* traces, int next_dt, hipStream_t st);
+hipError_t user_stable_dt(const UserModule* u, const KArgs& a, const double* Q, const double* params,
+                          double* clock, hipStream_t st);
+hipError_t user_admissible(const UserModule* u, const KArgs& a, const double* Q, const double* params,
+                           uint8_t* troubled, int32_t* count, hipStream_t st);
+#endif
 
 
 }  // namespace adg

@@ -445,6 +445,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   }
 }
 
+#if !defined(__HIPCC_RTC__)
 // Launch sequence of one adjoint step.
 template <class PDE, int N>
 struct AdjLaunch {
@@ -481,5 +482,6 @@ struct AdjLaunch {
     return e;
   }
 };
+#endif
 
 }  // namespace adg

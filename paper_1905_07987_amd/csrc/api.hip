@@ -30,6 +30,7 @@ struct adg_ctx {
   double* d_rec_w = nullptr;  // [nrec][S]
   int nrec = 0;
   bool traces_ready = false;  // workspace holds traces of a predict call
+  UserModule* user = nullptr;  // kernels of a run-time PDE (ks is null then)
 };
 
 namespace {
@@ -147,13 +148,19 @@ adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double*
   return ADG_OK;
 }
 
-adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// Shared by adg_create (built-in PDEs) and adg_create_user (source != null).
+adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) {
   if (!cfg || !out) return fail(ADG_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   const adg_config& c = *cfg;
   if (c.dim != 2 && c.dim != 3) return fail(ADG_ERR_INVALID_ARG, "dim must be 2 or 3");
   if (c.order < 1) return fail(ADG_ERR_INVALID_ARG, "order must be >= 1");
-  if (pde_nvar(c.pde, c.dim) == 0) return fail(ADG_ERR_INVALID_ARG, "unknown pde");
+  if (source ? c.pde != ADG_PDE_USER : pde_nvar(c.pde, c.dim) == 0)
+    return fail(ADG_ERR_INVALID_ARG, source ? "adg_create_user needs pde = ADG_PDE_USER" : "unknown pde");
   if (c.precision != ADG_FP64 && c.precision != ADG_MIXED_FP32)
     return fail(ADG_ERR_INVALID_ARG, "unknown precision");
   if (!(c.cfl > 0.0) || !std::isfinite(c.cfl)) return fail(ADG_ERR_INVALID_ARG, "cfl must be > 0");
@@ -167,8 +174,8 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
     if (d >= c.dim && (blo || bhi)) return fail(ADG_ERR_INVALID_ARG, "boundary condition on a missing axis");
     if ((blo == ADG_BC_PERIODIC) != (bhi == ADG_BC_PERIODIC))
       return fail(ADG_ERR_INVALID_ARG, "an axis is periodic on both faces or on neither");
-    if ((blo == ADG_BC_WALL || bhi == ADG_BC_WALL) && c.pde == ADG_PDE_ADVECTION)
-      return fail(ADG_ERR_INVALID_ARG, "no wall condition for the advection PDE");
+    if ((blo == ADG_BC_WALL || bhi == ADG_BC_WALL) && (c.pde == ADG_PDE_ADVECTION || c.pde == ADG_PDE_USER))
+      return fail(ADG_ERR_INVALID_ARG, "no wall condition for this PDE");
   }
   long long C = 1;
   for (int d = 0; d < c.dim; ++d) {
@@ -176,29 +183,62 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
     if (!(c.hi[d] > c.lo[d])) return fail(ADG_ERR_INVALID_ARG, "hi must exceed lo");
     C *= c.cells[d];
   }
-  const KernelSet* ks = find_kernels(c.pde, c.dim, c.order);
-  if (!ks) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "order %d not built for pde %d in %dD (max %d)", c.order, c.pde,
-             c.dim, adg_max_order(c.pde, c.dim));
-    return fail(ADG_ERR_UNSUPPORTED, buf);
+  const KernelSet* ks = nullptr;
+  UserModule* um = nullptr;
+  int nv = 0, np = 0;
+  if (source) {
+    // the kernels for the user's struct, compiled for the current device
+    if (c.order + 1 > kMaxN) return fail(ADG_ERR_UNSUPPORTED, "order above 7");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device properties");
+    const std::string arch = prop.gcnArchName;
+    std::string err;
+    UserTraits t{};
+    adg_status st = user_traits(source, arch, &t, &err);
+    if (st) return fail(st, err);
+    if (t.dim != c.dim) return fail(ADG_ERR_INVALID_ARG, "AdgUserPDE::DIM differs from cfg->dim");
+    if (t.nv < 1 || t.np < 0 || t.nv + t.np > kMaxVar)
+      return fail(ADG_ERR_INVALID_ARG, "AdgUserPDE: NV + NP must be in 1..16");
+    const int I = c.picard_iters ? c.picard_iters : c.order + 1;
+    st = user_module_create(source, arch, c.order, c.precision, t.linear && I <= kMaxLin, &um, &err);
+    if (st) return fail(st, err);
+    nv = t.nv;
+    np = t.np;
+  } else {
+    ks = find_kernels(c.pde, c.dim, c.order);
+    if (!ks) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "order %d not built for pde %d in %dD (max %d)", c.order, c.pde,
+               c.dim, adg_max_order(c.pde, c.dim));
+      return fail(ADG_ERR_UNSUPPORTED, buf);
+    }
+    if ((C + ks->cells_per_block - 1) / ks->cells_per_block > 0x7fffffffLL)
+      return fail(ADG_ERR_UNSUPPORTED, "too many cells for one launch");
+    nv = pde_nvar(c.pde, c.dim);
+    np = pde_nparam(c.pde);
   }
-  if ((C + ks->cells_per_block - 1) / ks->cells_per_block > 0x7fffffffLL)
-    return fail(ADG_ERR_UNSUPPORTED, "too many cells for one launch");
 
   adg_ctx* x = new (std::nothrow) adg_ctx;
-  if (!x) return fail(ADG_ERR_NOMEM, "host allocation failed");
+  if (!x) {
+    user_module_destroy(um);
+    return fail(ADG_ERR_NOMEM, "host allocation failed");
+  }
   x->cfg = c;
   x->dim = c.dim;
   x->n = c.order + 1;
   x->S = c.dim == 2 ? x->n * x->n : x->n * x->n * x->n;
   x->F = x->S / x->n;
-  x->nv = pde_nvar(c.pde, c.dim);
-  x->np = pde_nparam(c.pde);
+  x->nv = nv;
+  x->np = np;
   x->C = C;
   x->ks = ks;
+  x->user = um;
   hipError_t e = hipGetDevice(&x->device);
   if (e != hipSuccess) {
+    user_module_destroy(um);
     delete x;
     return hip_fail(e, "hipGetDevice");
   }
@@ -267,6 +307,7 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
   x->trace_elems = (size_t)C * 2 * c.dim * 2 * x->nv * x->F;
   e = hipMalloc((void**)&x->traces, x->trace_elems * sizeof(double));
   if (e != hipSuccess) {
+    user_module_destroy(um);
     delete x;
     return fail(ADG_ERR_NOMEM, std::string("trace workspace: ") + hipGetErrorString(e));
   }
@@ -276,6 +317,7 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(x->traces);
+    user_module_destroy(um);
     delete x;
     return fail(ADG_ERR_NOMEM, std::string("reduction slots: ") + hipGetErrorString(e));
   }
@@ -285,6 +327,39 @@ adg_status adg_create(const adg_config* cfg, adg_ctx** out) {
   a.src_w = nullptr;
   *out = x;
   return ADG_OK;
+}
+
+// The kernels of a context: the built-in set or the run-time module.
+hipError_t k_predict(const adg_ctx* x, const double* Q, const double* params, const double* clock,
+                     double* Qout, double* traces, int flux_traces, hipStream_t st) {
+  if (x->user) return user_predict(x->user, x->args, Q, params, clock, Qout, traces, flux_traces, st);
+  return x->ks->predict(x->args, x->cfg.precision, Q, params, clock, Qout, traces, flux_traces, st);
+}
+hipError_t k_correct(const adg_ctx* x, double* Q, const double* params, double* clock, int next_dt,
+                     hipStream_t st) {
+  if (x->user) return user_correct(x->user, x->args, Q, params, clock, x->traces, next_dt, st);
+  return x->ks->correct(x->args, Q, params, clock, x->traces, next_dt, st);
+}
+hipError_t k_stable_dt(const adg_ctx* x, const double* Q, const double* params, double* clock,
+                       hipStream_t st) {
+  if (x->user) return user_stable_dt(x->user, x->args, Q, params, clock, st);
+  return x->ks->stable_dt(x->args, Q, params, clock, st);
+}
+hipError_t k_admissible(const adg_ctx* x, const double* Q, const double* params, uint8_t* troubled,
+                        int32_t* count, hipStream_t st) {
+  if (x->user) return user_admissible(x->user, x->args, Q, params, troubled, count, st);
+  return x->ks->admissible(x->args, Q, params, troubled, count, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+adg_status adg_create(const adg_config* cfg, adg_ctx** out) { return create_ctx(cfg, nullptr, out); }
+
+adg_status adg_create_user(const adg_config* cfg, const char* source, adg_ctx** out) {
+  if (!source) return fail(ADG_ERR_INVALID_ARG, "null source");
+  return create_ctx(cfg, source, out);
 }
 
 adg_status adg_destroy(adg_ctx* ctx) {
@@ -299,6 +374,7 @@ adg_status adg_destroy(adg_ctx* ctx) {
   (void)hipFree(ctx->d_src_w);
   (void)hipFree(ctx->d_rec_cell);
   (void)hipFree(ctx->d_rec_w);
+  user_module_destroy(ctx->user);
   (void)hipSetDevice(dev);
   delete ctx;
   return ADG_OK;
@@ -348,7 +424,7 @@ adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, do
   adg_status st = check_state(ctx, Q, params);
   if (st) return st;
   if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
-  hipError_t e = ctx->ks->stable_dt(ctx->args, Q, params, clock, (hipStream_t)stream);
+  hipError_t e = k_stable_dt(ctx, Q, params, clock, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "stable_dt launch");
   return ADG_OK;
 }
@@ -360,8 +436,8 @@ adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, cons
   if (!clock || !Qvol) return fail(ADG_ERR_INVALID_ARG, "null clock or output");
   // the caller's trace array gets both fields; the workspace only what the
   // corrector reads
-  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Qvol,
-                                  traces ? traces : ctx->traces, traces ? 1 : 0, (hipStream_t)stream);
+  hipError_t e = k_predict(ctx, Q, params, clock, Qvol, traces ? traces : ctx->traces, traces ? 1 : 0,
+                           (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
   if (!traces) ctx->traces_ready = true;
   return ADG_OK;
@@ -374,8 +450,7 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
   if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
   if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
   if (!ctx->traces_ready) return fail(ADG_ERR_STATE, "adg_correct needs a preceding adg_predict");
-  hipError_t e = ctx->ks->correct(ctx->args, Q, params, clock, ctx->traces,
-                                  (flags & ADG_STEP_NEXT_DT) ? 1 : 0, (hipStream_t)stream);
+  hipError_t e = k_correct(ctx, Q, params, clock, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
   return ADG_OK;
 }
@@ -387,10 +462,10 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
   if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
   if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ctx->ks->predict(ctx->args, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
+  hipError_t e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
   ctx->traces_ready = true;
-  e = ctx->ks->correct(ctx->args, Q, params, clock, ctx->traces, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
+  e = k_correct(ctx, Q, params, clock, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
   return ADG_OK;
 }
@@ -400,7 +475,7 @@ adg_status adg_check_admissible(adg_ctx* ctx, const double* Q, const double* par
   adg_status st = check_state(ctx, Q, params);
   if (st) return st;
   if (!troubled || !count) return fail(ADG_ERR_INVALID_ARG, "null output");
-  hipError_t e = ctx->ks->admissible(ctx->args, Q, params, troubled, count, (hipStream_t)stream);
+  hipError_t e = k_admissible(ctx, Q, params, troubled, count, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "admissible launch");
   return ADG_OK;
 }
@@ -544,7 +619,7 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
   if (ctx->np > 0 && !gparams) return fail(ADG_ERR_INVALID_ARG, "null parameter gradient");
   for (int f = 0; f < 6; ++f)
     if (ctx->args.bc[f] != ADG_BC_PERIODIC) return fail(ADG_ERR_UNSUPPORTED, "the adjoint needs a periodic mesh");
-  if (!ctx->ks->adjoint)
+  if (!ctx->ks || !ctx->ks->adjoint)
     return fail(ADG_ERR_UNSUPPORTED, "the adjoint is built for the PDEs linear in Q (elastic, advection)");
   if (ctx->args.picard_iters > ctx->cfg.order + 1)
     return fail(ADG_ERR_UNSUPPORTED, "the adjoint supports at most order + 1 Picard iterations");

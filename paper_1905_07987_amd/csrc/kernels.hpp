@@ -14,7 +14,9 @@
 // tasks applied to the time averages.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
+#endif
 
 #include <type_traits>
 
@@ -1106,7 +1108,8 @@ struct GeoL {
   static constexpr int CELL_ELEMS = cmax(ROW_ELEMS, AVG_ELEMS);
   static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
   static constexpr int by_lds = cmax(1, (52 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
-  static constexpr int CPB = cmin(by_threads, by_lds);
+  // at least one full wave per block
+  static constexpr int CPB = cmax(cmin(by_threads, by_lds), (64 + G::S - 1) / G::S);
   static constexpr int BLOCK = CPB * G::S;
   static constexpr int ELEMS = CPB * CELL_ELEMS;
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
@@ -1513,7 +1516,8 @@ struct GeoB {
   static constexpr int FL_PER_CELL = 2 * G::DIM * G::NV * G::F;  // doubles
   static constexpr int by_threads = G::S >= 512 ? 1 : 512 / G::S;
   static constexpr int by_lds = cmax(1, (48 * 1024) / (FL_PER_CELL * 8));
-  static constexpr int CPB = cmin(by_threads, by_lds);
+  // at least one full wave per block
+  static constexpr int CPB = cmax(cmin(by_threads, by_lds), (64 + G::S - 1) / G::S);
   static constexpr int BLOCK = CPB * G::S;
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
 };
@@ -1790,6 +1794,7 @@ count_kernel(unsigned long long* __restrict__ slots, int32_t* __restrict__ count
 
 #include "adjoint.hpp"
 
+#if !defined(__HIPCC_RTC__)
 namespace adg {
 
 // ---------------------------------------------------------------------------
@@ -1884,3 +1889,4 @@ struct Launch {
 };
 
 }  // namespace adg
+#endif

@@ -25,7 +25,9 @@
 //   max_eigen_dparams(P, d, s, gp)   gp += s * d max_eigen(d) / dP
 #pragma once
 
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
+#endif
 
 #include "adg_internal.hpp"
 
