@@ -211,6 +211,11 @@ adg_status adg_node_coords(const adg_ctx* ctx, double* xyz);
 adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, double* clock,
                          void* stream);
 
+/* Host copy of a device clock {t, dt} (2 doubles): waits for the work
+ * queued on stream, then copies (the step path itself never synchronises;
+ * this getter does). */
+adg_status adg_read_clock_host(const double* clock, double* host, void* stream);
+
 /* One ADER-DG step (Sec. 3.3, three phases) in place: Q <- u^{n+1} with
  * dt = clock[1] and t^n = clock[0]; afterwards clock[0] <- t^n + dt.
  * flags: ADG_STEP_NEXT_DT also evaluates Eq. (7) on u^{n+1} during the

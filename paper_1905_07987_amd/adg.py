@@ -79,6 +79,7 @@ def lib():
         L.adg_node_coords.argtypes = [vp, dp]
         L.adg_stable_dt.argtypes = [vp, vp, vp, vp, vp]
         L.adg_step.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.adg_read_clock_host.argtypes = [vp, dp, vp]
         L.adg_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_correct.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_check_admissible.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -92,7 +93,8 @@ def lib():
 
 
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
-            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_step", "adg_predict", "adg_correct",
+            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_predict",
+            "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
             "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint")
 
@@ -231,6 +233,13 @@ class Solver:
         _check(lib().adg_correct(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
                                  self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
                                  STEP_NEXT_DT if next_dt else 0, _stream(stream)))
+
+    def read_clock(self, clock, stream=None):
+        """(t, dt) of a device clock, after the work queued on the stream."""
+        import torch
+        out = (C.c_double * 2)()
+        _check(lib().adg_read_clock_host(self._dev(clock, (2,), torch.float64, "clock"), out, _stream(stream)))
+        return out[0], out[1]
 
     def check_admissible(self, Q, params, troubled, count, stream=None):
         import torch

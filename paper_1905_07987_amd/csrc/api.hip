@@ -429,6 +429,14 @@ adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, do
   return ADG_OK;
 }
 
+adg_status adg_read_clock_host(const double* clock, double* host, void* stream) {
+  if (!clock || !host) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemcpy(host, clock, 2 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read clock");
+  return ADG_OK;
+}
+
 adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, const double* clock,
                        double* Qvol, double* traces, void* stream) {
   adg_status st = check_state(ctx, Q, params);
