@@ -253,7 +253,7 @@ struct GeoAdjL {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
   // rows of L^T with the forward-gradient channels, qbar, gradient partials
-  static constexpr int CELL_ELEMS = cmax(cmax((C::NCH + G::DIM * C::ngrad()) * G::SP, G::NV * G::S),
+  static constexpr int CELL_ELEMS = cmax(cmax((C::NCH + G::DIM * C::ngrad()) * LinLayout<G>::SP, G::NV * G::S),
                                          G::S * (G::NP > 0 ? G::NP : 1));
   static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
   static constexpr int by_lds = cmax(1, (76 * 1024) / (CELL_ELEMS * 8));
@@ -290,7 +290,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     ln[d] = G::line_of(d, kk3[0], kk3[1], DIM == 3 ? kk3[2] : 0);
-    pk[d] = ln[d] * G::LS + kk3[d];
+    pk[d] = LinLayout<G>::addr(d, ln[d], kk3[d]);
   }
   const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
   const long long cell = cell0 + lc;
