@@ -226,6 +226,20 @@ adg_status adg_read_clock_host(const double* clock, double* host, void* stream);
 adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                     void* stream);
 
+/* nsteps FP64 steps in place with the step size clock[1] held fixed (as in
+ * adg_step without ADG_STEP_NEXT_DT; clock[0] advances by dt each step).
+ * rec_out (device [nsteps][nrec][nvar], or NULL) receives the receiver
+ * samples after every step.  For the built-in PDEs linear in Q (elasticity,
+ * advection; FP64, picard_iters <= 16) the corrector of each step and the
+ * predictor of the next run as one kernel (the step fusion of Sec. 5.1:
+ * one pass over the state per step instead of two), with a second trace
+ * array allocated on first use; otherwise the steps run one by one.  The
+ * states are those of nsteps adg_step calls; samples agree with
+ * adg_sample_receivers to rounding.  Leaves the trace workspace unusable
+ * for adg_correct. */
+adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                   double* rec_out, void* stream);
+
 /* The predictor phase alone (Sec. 3.3 phase 1 with the projection onto the
  * faces of Sec. 5.1): Qvol <- u^n + dt (-div Fbar - Nbar + Sbar) per node
  * ([C][nvar][S], may equal Q) and, if traces is not NULL, the face traces

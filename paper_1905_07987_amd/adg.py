@@ -80,6 +80,7 @@ def lib():
         L.adg_stable_dt.argtypes = [vp, vp, vp, vp, vp]
         L.adg_step.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_read_clock_host.argtypes = [vp, dp, vp]
+        L.adg_run.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
         L.adg_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_correct.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_check_admissible.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -93,7 +94,8 @@ def lib():
 
 
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
-            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_predict",
+            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_run",
+            "adg_predict",
             "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
             "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint")
@@ -233,6 +235,17 @@ class Solver:
         _check(lib().adg_correct(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
                                  self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
                                  STEP_NEXT_DT if next_dt else 0, _stream(stream)))
+
+    def run(self, Q, params, clock, nsteps: int, rec_out=None, stream=None):
+        """nsteps steps with the step size clock[1] held fixed; rec_out
+        ([nsteps, nrec, nvar] float64 or None) receives the receiver samples
+        after every step.  Fused corrector/predictor kernels where built."""
+        import torch
+        ro = None
+        if rec_out is not None:
+            ro = self._dev(rec_out, (nsteps, self.nrec, self.nvar), torch.float64, "rec_out")
+        _check(lib().adg_run(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"), self._params(params),
+                             self._dev(clock, (2,), torch.float64, "clock"), int(nsteps), ro, _stream(stream)))
 
     def read_clock(self, clock, stream=None):
         """(t, dt) of a device clock, after the work queued on the stream."""

@@ -70,6 +70,11 @@ struct KArgs {
   int nblocks;  // grid size of the cell kernels (for the block -> cell map)
   const SourceDev* src;
   const double* src_w;  // [nsrc][S][nvar]
+  // receivers (set for the fused multi-step launches): cell and nodal
+  // weights [nrec][S]
+  int nrec;
+  const long long* rec_cell;
+  const double* rec_w;
   // reduction slots (workspace, zero between uses): kSlots words, each on
   // its own 64-byte line
   unsigned long long* slots;
@@ -95,6 +100,11 @@ struct KernelSet {
   // 2 C 2dim nvar F doubles (the trace workspace).
   hipError_t (*adjoint)(const KArgs&, const double* Q, const double* params, const double* clock,
                         double* lam, double* gparams, double* work, hipStream_t);
+  // Corrector of step n and predictor of step n + 1 in one kernel, FP64,
+  // fixed step size; then t += dt (nullptr where not built: PDEs not linear
+  // in Q).  rec_out: [nrec][nvar] samples of u^{n+1}, or null.
+  hipError_t (*step_fused)(const KArgs&, double* Q, const double* params, double* clock,
+                           const double* tr_in, double* tr_out, double* rec_out, hipStream_t);
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

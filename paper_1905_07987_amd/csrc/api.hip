@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "adg_internal.hpp"
 
@@ -20,6 +21,7 @@ struct adg_ctx {
   const KernelSet* ks = nullptr;
   KArgs args{};
   double* traces = nullptr;  // [C][2 dim][2][nv][F]
+  double* traces2 = nullptr; // the second trace array of fused runs (allocated on first use)
   size_t trace_elems = 0;
   void* red = nullptr;       // reduction slots
   size_t red_bytes = 0;
@@ -369,6 +371,7 @@ adg_status adg_destroy(adg_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(ctx->traces);
+  (void)hipFree(ctx->traces2);
   (void)hipFree(ctx->red);
   (void)hipFree(ctx->d_src);
   (void)hipFree(ctx->d_src_w);
@@ -603,6 +606,57 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
                      ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nv, ctx->S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "sample launch");
+  return ADG_OK;
+}
+
+adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                   double* rec_out, void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (nsteps < 0) return fail(ADG_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (rec_out && ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
+  if (nsteps == 0) return ADG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const long long rec_stride = (long long)ctx->nrec * ctx->nv;
+  auto sample = [&](int n) -> hipError_t {
+    if (!rec_out) return hipSuccess;
+    hipLaunchKernelGGL(sample_kernel, dim3(ctx->nrec), dim3(64), 0, s, Q, ctx->d_rec_cell, ctx->d_rec_w,
+                       rec_out + n * rec_stride, ctx->nv, ctx->S);
+    return hipGetLastError();
+  };
+  const bool fused = ctx->ks && ctx->ks->step_fused && ctx->cfg.precision == ADG_FP64 &&
+                     ctx->args.picard_iters <= kMaxLin && nsteps > 1;
+  hipError_t e = hipSuccess;
+  if (!fused) {
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+      e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);
+      if (e == hipSuccess) e = k_correct(ctx, Q, params, clock, 0, s);
+      if (e == hipSuccess) e = sample(n);
+    }
+  } else {
+    if (!ctx->traces2) {
+      e = hipMalloc((void**)&ctx->traces2, ctx->trace_elems * sizeof(double));
+      if (e != hipSuccess) {
+        ctx->traces2 = nullptr;
+        return fail(ADG_ERR_NOMEM, std::string("second trace array: ") + hipGetErrorString(e));
+      }
+    }
+    KArgs a = ctx->args;
+    a.nrec = rec_out ? ctx->nrec : 0;
+    a.rec_cell = ctx->d_rec_cell;
+    a.rec_w = ctx->d_rec_w;
+    e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);  // predictor of the first step
+    for (int n = 0; n + 1 < nsteps && e == hipSuccess; ++n) {
+      e = ctx->ks->step_fused(a, Q, params, clock, ctx->traces, ctx->traces2,
+                              rec_out ? rec_out + n * rec_stride : nullptr, s);
+      std::swap(ctx->traces, ctx->traces2);  // the newest traces are the workspace
+    }
+    if (e == hipSuccess) e = k_correct(ctx, Q, params, clock, 0, s);  // corrector of the last step
+    if (e == hipSuccess) e = sample(nsteps - 1);
+  }
+  ctx->traces_ready = false;
+  if (e != hipSuccess) return hip_fail(e, "run launch");
   return ADG_OK;
 }
 

@@ -1385,25 +1385,24 @@ __device__ inline void lin_source_weights(const KArgs& a, int s, double t_n, dou
   }
 }
 
+// The linear predictor for the CPB cells of a block from cell0 on: this
+// thread's node starts from u64 (with its cell's parameters P); the face
+// traces go to traces and u + dt vol to Qout (active nodes only).  t_n is
+// the start of the step (point sources), dt64 its size.
 template <class PDE, int N, class R>
-__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
-predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ params,
-                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
-  // Q and Qout may be the same array (in-place step): each element is read
-  // at the start and written at the end by the thread of its node.
+__device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double (*src_e)[kMaxLin + 1],
+                                                  int tid, long long cell0, const double (&u64)[PDE::NV],
+                                                  const R* P, const double* __restrict__ params, double t_n,
+                                                  double dt64, double* Qout, double* __restrict__ traces) {
   using G = Geo<PDE, N>;
   using GL = GeoL<PDE, N, R>;
   using T = CT<R, G::n>;
   using Op = LinOp<PDE, N, R, GL::CPB, GL::BLOCK, GL::CELL_ELEMS>;
-  static_assert(PDE::kLinear, "the linear predictor needs a PDE linear in Q");
-  static_assert(Chan<PDE>::uniform(), "flux sparsity must be the same in every direction");
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GL::CPB, BLOCK = GL::BLOCK;
-  __shared__ R lds[GL::ELEMS];
-  __shared__ double src_e[kMaxSources][kMaxLin + 1];
-
-  const int tid = threadIdx.x;
+  constexpr int CPB = GL::CPB;
   const int lc = tid / S, k = tid - lc * S;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
   int pk[DIM];  // this node's slot in the LDS rows of each direction
   {
     const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
@@ -1411,28 +1410,16 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
 #pragma unroll
     for (int d = 0; d < DIM; ++d) pk[d] = LinLayout<G>::addr(d, G::line_of(d, kx, ky, kz), kd[d]);
   }
-  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
-  const long long cell = cell0 + lc;
-  const bool active = cell < a.ncells;
-  const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
-
-  double u64[NV];
-  R u[NV], P[NP > 0 ? NP : 1];
+  R u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    u64[v] = Q[(cl * NV + v) * S + k];
-    u[v] = R(u64[v]);
-  }
-#pragma unroll
-  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
-  const double t_n = clock[0], dt64 = clock[1];
+  for (int v = 0; v < NV; ++v) u[v] = R(u64[v]);
   const R dt = R(dt64);
   const int I = a.picard_iters;
   R inv_h[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) inv_h[d] = R(a.inv_h[d]);
 
-  // point sources of this block (made visible by the first barrier below)
+  // point sources of this block
   bool src_here = false;
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
@@ -1527,6 +1514,35 @@ predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int v = 0; v < NV; ++v) Qout[(cell * NV + v) * S + k] = u64[v] + double(dt * vol[v]);
   }
 }
+
+template <class PDE, int N, class R>
+__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
+predict_kernel_lin(const KArgs a, const double* Q, const double* __restrict__ params,
+                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // Q and Qout may be the same array (in-place step): each element is read
+  // at the start and written at the end by the thread of its node.
+  using G = Geo<PDE, N>;
+  using GL = GeoL<PDE, N, R>;
+  static_assert(PDE::kLinear, "the linear predictor needs a PDE linear in Q");
+  static_assert(Chan<PDE>::uniform(), "flux sparsity must be the same in every direction");
+  constexpr int S = G::S, NV = G::NV, NP = G::NP;
+  __shared__ R lds[GL::ELEMS];
+  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S, k = tid - lc * S;
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * GL::CPB;
+  const long long cell = cell0 + lc;
+  const long long cl = cell < a.ncells ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+  double u64[NV];
+  R P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u64[v] = Q[(cl * NV + v) * S + k];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
+  lin_predict_block<PDE, N, R>(a, lds, src_e, tid, cell0, u64, P, params, clock[0], clock[1], Qout, traces);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel B: Rusanov flux on every face of the cell, surface integral and
 // update; optionally the per-block Eq. (7) maximum of the new state (reduced
@@ -1544,38 +1560,17 @@ struct GeoB {
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
 };
 
-template <class PDE, int N>
-__global__ void __launch_bounds__((GeoB<PDE, N>::BLOCK))
-correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__ params,
-               const double* __restrict__ clock, const double* __restrict__ traces, int next_dt) {
+// Corrector phase 1: the fluctuation of each cell's side at every face node
+// of the CPB cells from cell0 on (block-wide tasks, one per (cell, face,
+// face node)), scaled by dt / h_d, into fl[CPB][2 dim][NV][F].
+template <class PDE, int N, int CPB, int BLOCK>
+__device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* __restrict__ params,
+                                                  const double* __restrict__ traces, double dt, int cell0,
+                                                  int tid, double* fl) {
   using G = Geo<PDE, N>;
-  using GB = GeoB<PDE, N>;
-  constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
-  constexpr int CPB = GB::CPB, BLOCK = GB::BLOCK;
-  __shared__ double fl[CPB * GB::FL_PER_CELL];
-  __shared__ double red[BLOCK];
-
-  const Tables<double>& T = a.t64;
-  const int tid = threadIdx.x;
-  const int cell0 = xcd_block(blockIdx.x, a.nblocks) * CPB;
-  const double dt = clock[1];
+  constexpr int F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
   const int C0 = a.cells[0], C1 = a.cells[1];
   const int ncells = (int)a.ncells;
-
-  // this thread's node of the update; for PDEs linear in Q (few registers
-  // in the face phase) its state is loaded now, so that the loads overlap
-  // the face phase (measured: -2 to -3 % on elasticity, +5 % on Euler)
-  const int lc = tid / S, k = tid - lc * S;
-  const int cell = cell0 + lc;
-  double qold[NV];
-  if constexpr (PDE::kLinear) {
-    if (cell < ncells) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) qold[v] = Q[((long long)cell * NV + v) * S + k];
-    }
-  }
-
-  // fluctuations, one task per (cell, face, face node)
   for (int task = tid; task < CPB * 2 * DIM * F; task += BLOCK) {
     const int f = task % F;
     const int face = (task / F) % (2 * DIM);
@@ -1679,33 +1674,80 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
       fl[((c2 * 2 * DIM + face) * NV + v) * F + f] = flv * scale;
     }
   }
+}
+
+// Corrector phase 2 at node k of local cell lc: the surface term of Eq. (6),
+// from the fluctuations of its 2 dim faces in fl.
+template <class PDE, int N>
+__device__ __forceinline__ void surface_terms(const KArgs& a, const double* fl, int lc, int k,
+                                              double (&surf)[PDE::NV]) {
+  using G = Geo<PDE, N>;
+  constexpr int n = G::n, F = G::F, NV = G::NV, DIM = G::DIM;
+  const Tables<double>& T = a.t64;
+  int kk[3] = {0, 0, 0};
+  node_coords<DIM>(k, n, kk);
+  int fidx[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    // face-node index of node k on the faces normal to d
+    if (DIM == 2) fidx[d] = kk[1 - d];
+    else fidx[d] = d == 0 ? kk[1] + n * kk[2] : (d == 1 ? kk[0] + n * kk[2] : kk[0] + n * kk[1]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double sv = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double hi = fl[((lc * 2 * DIM + 2 * d + 1) * NV + v) * F + fidx[d]];
+      const double lo = fl[((lc * 2 * DIM + 2 * d) * NV + v) * F + fidx[d]];
+      sv += (T.l1[kk[d]] * hi + T.l0[kk[d]] * lo) * T.invw[kk[d]];
+    }
+    surf[v] = sv;
+  }
+}
+
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoB<PDE, N>::BLOCK))
+correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__ params,
+               const double* __restrict__ clock, const double* __restrict__ traces, int next_dt) {
+  using G = Geo<PDE, N>;
+  using GB = GeoB<PDE, N>;
+  constexpr int S = G::S, NV = G::NV, NP = G::NP, DIM = G::DIM;
+  constexpr int CPB = GB::CPB, BLOCK = GB::BLOCK;
+  __shared__ double fl[CPB * GB::FL_PER_CELL];
+  __shared__ double red[BLOCK];
+
+  const int tid = threadIdx.x;
+  const int cell0 = xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const double dt = clock[1];
+  const int ncells = (int)a.ncells;
+
+  // this thread's node of the update; for PDEs linear in Q (few registers
+  // in the face phase) its state is loaded now, so that the loads overlap
+  // the face phase (measured: -2 to -3 % on elasticity, +5 % on Euler)
+  const int lc = tid / S, k = tid - lc * S;
+  const int cell = cell0 + lc;
+  double qold[NV];
+  if constexpr (PDE::kLinear) {
+    if (cell < ncells) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qold[v] = Q[((long long)cell * NV + v) * S + k];
+    }
+  }
+
+  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, traces, dt, cell0, tid, fl);
   __syncthreads();
 
   double lam = 0.0;
   if (cell < ncells) {
-    int kk[3] = {0, 0, 0};
-    node_coords<DIM>(k, n, kk);
-    int fidx[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      // face-node index of node k on the faces normal to d
-      if (DIM == 2) fidx[d] = kk[1 - d];
-      else fidx[d] = d == 0 ? kk[1] + n * kk[2] : (d == 1 ? kk[0] + n * kk[2] : kk[0] + n * kk[1]);
-    }
-    double qn[NV], P[NP > 0 ? NP : 1];
+    double surf[NV], qn[NV], P[NP > 0 ? NP : 1];
+    surface_terms<PDE, N>(a, fl, lc, k, surf);
 #pragma unroll
     for (int p = 0; p < NP; ++p) P[p] = params[cell * NP + p];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double surf = 0.0;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double hi = fl[((lc * 2 * DIM + 2 * d + 1) * NV + v) * F + fidx[d]];
-        const double lo = fl[((lc * 2 * DIM + 2 * d) * NV + v) * F + fidx[d]];
-        surf += (T.l1[kk[d]] * hi + T.l0[kk[d]] * lo) * T.invw[kk[d]];
-      }
       const long long idx = ((long long)cell * NV + v) * S + k;
-      qn[v] = (PDE::kLinear ? qold[v] : Q[idx]) - surf;
+      qn[v] = (PDE::kLinear ? qold[v] : Q[idx]) - surf[v];
       Q[idx] = qn[v];
     }
     if (next_dt) {
@@ -1717,6 +1759,75 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     const double m = block_max<BLOCK>(lam, red);
     if (tid == 0) slot_max(a.slots, blockIdx.x, m);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Step fusion (Sec. 5.1) for PDEs linear in Q with the step size held
+// fixed: the corrector of step n (Rusanov, surface integral, update; from
+// the traces tr_in of step n's prediction and Q = u^n + dt vol^n) and the
+// predictor of step n + 1 from the resulting u^{n+1}, in one pass over the
+// cells, with the traces of step n + 1 in tr_out.  Saves the state's write
+// and re-read between the two phases.  clock = {t^n, dt}; the predictor
+// uses t^n + dt.  rec_out (when the context has receivers): u^{n+1} at the
+// receivers, [nrec][NV].
+// ---------------------------------------------------------------------------
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoL<PDE, N, double>::BLOCK), (GeoL<PDE, N, double>::MIN_WAVES))
+step_kernel_lin(const KArgs a, double* Q, const double* __restrict__ params, const double* __restrict__ clock,
+                const double* __restrict__ tr_in, double* __restrict__ tr_out, double* __restrict__ rec_out) {
+  using G = Geo<PDE, N>;
+  using GL = GeoL<PDE, N, double>;
+  using GB = GeoB<PDE, N>;
+  static_assert(PDE::kLinear, "step fusion is built for PDEs linear in Q");
+  static_assert(GB::FL_PER_CELL <= GL::CELL_ELEMS, "fluctuations exceed the cell's LDS");
+  constexpr int S = G::S, NV = G::NV, NP = G::NP, CPB = GL::CPB, BLOCK = GL::BLOCK;
+  __shared__ double lds[GL::ELEMS];
+  __shared__ double src_e[kMaxSources][kMaxLin + 1];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S, k = tid - lc * S;
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + lc;
+  const bool active = cell < a.ncells;
+  const long long cl = active ? cell : a.ncells - 1;
+  const double t_n = clock[0], dt = clock[1];
+
+  // corrector of step n
+  double u1[NV], P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u1[v] = Q[(cl * NV + v) * S + k];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = params[cl * NP + p];
+  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, tr_in, dt, (int)cell0, tid, lds);
+  __syncthreads();
+  if (active) {
+    double surf[NV];
+    surface_terms<PDE, N>(a, lds, lc, k, surf);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u1[v] -= surf[v];
+  }
+  __syncthreads();  // the fluctuations are read; the rows are free
+
+  // receivers: u^{n+1} interpolated, a fixed-order sum per (receiver, quantity)
+  if (a.nrec > 0 && rec_out) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lds[(lc * NV + v) * S + k] = u1[v];
+    __syncthreads();
+    for (int i = tid; i < a.nrec * NV; i += BLOCK) {
+      const int r = i / NV, v = i - r * NV;
+      const long long c = a.rec_cell[r];
+      if (c < cell0 || c >= cell0 + CPB || c >= a.ncells) continue;
+      const double* w = a.rec_w + (long long)r * S;
+      const double* uq = lds + ((c - cell0) * NV + v) * S;
+      double acc = 0.0;
+      for (int kk = 0; kk < S; ++kk) acc += w[kk] * uq[kk];
+      rec_out[(long long)r * NV + v] = acc;
+    }
+    __syncthreads();
+  }
+
+  // predictor of step n + 1
+  lin_predict_block<PDE, N, double>(a, lds, src_e, tid, cell0, u1, P, params, t_n + dt, dt, Q, tr_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1910,13 +2021,37 @@ struct Launch {
     hipLaunchKernelGGL(count_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, count);
     return hipGetLastError();
   }
+  // corrector of step n fused with the predictor of step n + 1, then t += dt
+  static hipError_t step_fused(const KArgs& a0, double* Q, const double* params, double* clock,
+                               const double* tr_in, double* tr_out, double* rec_out, hipStream_t st) {
+    if constexpr (PDE::kLinear && GeoB<PDE, N>::FL_PER_CELL <= GeoL<PDE, N, double>::CELL_ELEMS) {
+      using GL = GeoL<PDE, N, double>;
+      KArgs a = a0;
+      a.flux_traces = 0;
+      a.nblocks = blocks_a<GL>(a);
+      hipLaunchKernelGGL((step_kernel_lin<PDE, N>), dim3(a.nblocks), dim3(GL::BLOCK), 0, st, a, Q, params,
+                         clock, tr_in, tr_out, rec_out);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor, 2, clock);
+      return hipGetLastError();
+    } else {
+      return hipErrorNotSupported;
+    }
+  }
+  static constexpr decltype(KernelSet::step_fused) step_fused_entry() {
+    if constexpr (PDE::kLinear && GeoB<PDE, N>::FL_PER_CELL <= GeoL<PDE, N, double>::CELL_ELEMS)
+      return &step_fused;
+    else return nullptr;
+  }
   static constexpr decltype(KernelSet::adjoint) adjoint_entry() {
     if constexpr (GeoAdjL<PDE, N>::supported) return &AdjLaunch<PDE, N>::run;
     else return nullptr;
   }
   static const KernelSet* set() {
     static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB,
-                                 &predict, &correct, &stable_dt, &admissible, adjoint_entry()};
+                                 &predict, &correct, &stable_dt, &admissible, adjoint_entry(),
+                                 step_fused_entry()};
     return &ks;
   }
 };

@@ -1,0 +1,143 @@
+"""adg_run: several fixed-dt steps with the corrector of each step fused with
+the predictor of the next (PDEs linear in Q), against the same steps taken
+one by one (adg_step + adg_sample_receivers) and against the oracle.
+
+Bar: the states of the fused run equal those of the step-by-step run to
+1e-14 relative L2 (the same arithmetic in one kernel), the receiver samples
+to 1e-13 (summation order), and the oracle to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_07987_amd import adg, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def elastic_setup(order, cells, bc=None, with_source=True):
+    cfg = inputs.elastic_config("c3")
+    hi = [500.0 * c for c in cells]
+    src = dict(cfg["source"])
+    src["x"] = (0.41 * hi[0], 0.53 * hi[1], 0.37 * hi[2])
+    src["t0"] = 0.0
+    srcs = [src] if with_source else []
+    P = O.problem(3, order, O.ELASTIC, cells, [0.0] * 3, hi, bc=bc,
+                  sources=[dict(x=q["x"], w=q["w"], f0=q["f0"], t0=q["t0"], amp=q["amp"]) for q in srcs])
+    s = adg.Solver(3, order, "elastic", cells, [0.0] * 3, hi, bc=bc)
+    if srcs:
+        s.set_point_sources([dict(x=q["x"], weight=q["w"], f0=q["f0"], t0=q["t0"], amp=q["amp"]) for q in srcs])
+    rng = np.random.default_rng(90 + order)
+    params = np.column_stack([rng.uniform(2000, 3000, P.ncells), rng.uniform(5000, 7000, P.ncells),
+                              rng.uniform(2500, 3400, P.ncells)])
+    Q0 = inputs.elastic_smooth_state(O.node_coords(P), 91)
+    rec = np.array([[0.2 * hi[0], 0.5 * hi[1], 0.5 * hi[2]], [0.77 * hi[0], 0.31 * hi[1], 0.64 * hi[2]],
+                    [0.5 * hi[0] + 1.0, 0.9 * hi[1], 0.1 * hi[2]]])
+    s.set_receivers(rec)
+    dt = 0.5 * O.stable_dt(P, Q0, params)[0]
+    return s, P, params, Q0, rec, dt
+
+
+def stepwise(s, Q0, params, dt, steps):
+    Q = dev(Q0)
+    prm = dev(params) if params is not None else None
+    clock = dev([0.0, dt])
+    out = torch.zeros((steps, s.nrec, s.nvar), dtype=torch.float64, device="cuda")
+    for n in range(steps):
+        s.step(Q, prm, clock, next_dt=False)
+        s.sample_receivers(Q, out[n])
+    torch.cuda.synchronize()
+    return Q.cpu().numpy(), out.cpu().numpy(), clock.cpu().numpy()
+
+
+def fused(s, Q0, params, dt, steps, with_rec=True):
+    Q = dev(Q0)
+    prm = dev(params) if params is not None else None
+    clock = dev([0.0, dt])
+    out = torch.zeros((steps, s.nrec, s.nvar), dtype=torch.float64, device="cuda") if with_rec else None
+    s.run(Q, prm, clock, steps, out)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy(), (out.cpu().numpy() if with_rec else None), clock.cpu().numpy()
+
+
+@pytest.mark.parametrize("order,cells,bc", [(3, [4, 3, 3], None), (4, [3, 3, 2], None),
+                                            (3, [3, 4, 2], [1, 1, 2, 2, 0, 0]), (2, [5, 3, 2], None)])
+def test_fused_run_equals_step_by_step_and_oracle(order, cells, bc):
+    say("run elastic", order, cells, bc)
+    s, P, params, Q0, rec, dt = elastic_setup(order, cells, bc)
+    steps = 5
+    Qs, Rs, cs = stepwise(s, Q0, params, dt, steps)
+    Qf, Rf, cf = fused(s, Q0, params, dt, steps)
+    Qo, _ = O.run(P, Q0, params, steps=steps, dt_fixed=dt)
+    say(f"  fused vs steps {rel_l2(Qf, Qs):.2e}, receivers {rel_l2(Rf, Rs):.2e}, vs oracle {rel_l2(Qf, Qo):.2e}")
+    assert rel_l2(Qf, Qs) <= 1e-14
+    assert rel_l2(Rf, Rs) <= 1e-13
+    assert rel_l2(Qf, Qo) <= 1e-12
+    assert cf[0] == cs[0] and cf[1] == cs[1] == dt  # t advanced by the same additions
+    s.close()
+
+
+def test_fused_run_advection_outflow_vs_oracle():
+    say("run advection")
+    cells = [4, 3, 3]
+    P = O.problem(3, 3, O.ADVECTION, cells, adv=(0.6, -0.3, 0.2), kappa=0.2, bc=[1] * 6)
+    xyz = O.node_coords(P)
+    Q0 = (1.0 + np.sin(2 * np.pi * xyz[..., 0]) * np.cos(2 * np.pi * xyz[..., 1]))[:, None, :]
+    s = adg.Solver(3, 3, "advection", cells, adv=(0.6, -0.3, 0.2), kappa=0.2, bc=[1] * 6)
+    dt = O.stable_dt(P, Q0)[0]
+    Qf, _, _ = fused(s, Q0, None, dt, 6, with_rec=False)
+    Qo, _ = O.run(P, Q0, steps=6, dt_fixed=dt)
+    say(f"  vs oracle {rel_l2(Qf, Qo):.2e}")
+    assert rel_l2(Qf, Qo) <= 1e-12
+    s.close()
+
+
+def test_run_falls_back_for_nonlinear_pdes():
+    say("run euler")
+    cells = [3, 3, 2]
+    P = O.problem(3, 2, O.EULER, cells)
+    Q0 = inputs.smooth_euler_state(O.node_coords(P), 92)
+    s = adg.Solver(3, 2, "euler", cells)
+    dt = 0.5 * O.stable_dt(P, Q0)[0]
+    Qs = dev(Q0)
+    cs = dev([0.0, dt])
+    for _ in range(3):
+        s.step(Qs, None, cs, next_dt=False)
+    Qf, _, cf = fused(s, Q0, None, dt, 3, with_rec=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(Qf, Qs.cpu().numpy()) and np.array_equal(cf, cs.cpu().numpy())
+    s.close()
+
+
+def test_run_edge_cases():
+    say("run edge cases")
+    s, P, params, Q0, rec, dt = elastic_setup(3, [2, 2, 2], with_source=False)
+    for steps in (1, 2):
+        Qs, Rs, _ = stepwise(s, Q0, params, dt, steps)
+        Qf, Rf, _ = fused(s, Q0, params, dt, steps)
+        assert rel_l2(Qf, Qs) <= 1e-14 and rel_l2(Rf, Rs) <= 1e-13
+    Q = dev(Q0)
+    s.run(Q, dev(params), dev([0.0, dt]), 0)  # nothing to do
+    torch.cuda.synchronize()
+    assert np.array_equal(Q.cpu().numpy(), Q0)
+    s.close()
+    s2 = adg.Solver(3, 2, "elastic", [2, 2, 2], [0.0] * 3, [1000.0] * 3)
+    Q = torch.zeros(s2.state_shape, dtype=torch.float64, device="cuda")
+    prm = torch.ones((8, 3), dtype=torch.float64, device="cuda")
+    st = adg.lib().adg_run(s2._ctx, Q.data_ptr(), prm.data_ptr(), dev([0.0, 1e-4]).data_ptr(), 2,
+                           torch.zeros(18, dtype=torch.float64, device="cuda").data_ptr(), None)
+    assert st == -6  # samples asked for, no receivers set
+    s2.close()
