@@ -230,7 +230,7 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
  * adg_step without ADG_STEP_NEXT_DT; clock[0] advances by dt each step).
  * rec_out (device [nsteps][nrec][nvar], or NULL) receives the receiver
  * samples after every step.  For the built-in PDEs linear in Q (elasticity,
- * advection; FP64, picard_iters <= 16) the corrector of each step and the
+ * advection; picard_iters <= 16) the corrector of each step and the
  * predictor of the next run as one kernel (the step fusion of Sec. 5.1:
  * one pass over the state per step instead of two), with a second trace
  * array allocated on first use; otherwise the steps run one by one.  The

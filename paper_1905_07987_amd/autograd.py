@@ -46,10 +46,11 @@ class _SeismogramRun(torch.autograd.Function):
         clock = torch.tensor([t0, dt], dtype=torch.float64, device=Q.device)
         out = torch.empty((steps, solver.nrec, solver.nvar), dtype=torch.float64, device=Q.device)
         ckpts = [Q.clone()]
-        for n in range(steps):
-            solver.step(Q, prm, clock, next_dt=False)
-            solver.sample_receivers(Q, out[n])
-            if (n + 1) % every == 0 and n + 1 < steps:
+        for n0 in range(0, steps, every):
+            # one checkpoint segment (fused corrector/predictor kernels where built)
+            n1 = min(steps, n0 + every)
+            solver.run(Q, prm, clock, n1 - n0, out[n0:n1])
+            if n1 < steps:
                 ckpts.append(Q.clone())
         ctx.solver, ctx.t0, ctx.dt, ctx.steps, ctx.every = solver, t0, dt, steps, every
         ctx.ckpts = ckpts

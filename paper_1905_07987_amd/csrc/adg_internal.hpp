@@ -100,10 +100,11 @@ struct KernelSet {
   // 2 C 2dim nvar F doubles (the trace workspace).
   hipError_t (*adjoint)(const KArgs&, const double* Q, const double* params, const double* clock,
                         double* lam, double* gparams, double* work, hipStream_t);
-  // Corrector of step n and predictor of step n + 1 in one kernel, FP64,
-  // fixed step size; then t += dt (nullptr where not built: PDEs not linear
-  // in Q).  rec_out: [nrec][nvar] samples of u^{n+1}, or null.
-  hipError_t (*step_fused)(const KArgs&, double* Q, const double* params, double* clock,
+  // Corrector of step n and predictor of step n + 1 in one kernel (the
+  // predictor in the context's precision), fixed step size; then t += dt
+  // (nullptr where not built: PDEs not linear in Q).  rec_out: [nrec][nvar]
+  // samples of u^{n+1}, or null.
+  hipError_t (*step_fused)(const KArgs&, int precision, double* Q, const double* params, double* clock,
                            const double* tr_in, double* tr_out, double* rec_out, hipStream_t);
 };
 

@@ -625,8 +625,7 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
                        rec_out + n * rec_stride, ctx->nv, ctx->S);
     return hipGetLastError();
   };
-  const bool fused = ctx->ks && ctx->ks->step_fused && ctx->cfg.precision == ADG_FP64 &&
-                     ctx->args.picard_iters <= kMaxLin && nsteps > 1;
+  const bool fused = ctx->ks && ctx->ks->step_fused && ctx->args.picard_iters <= kMaxLin && nsteps > 1;
   hipError_t e = hipSuccess;
   if (!fused) {
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
@@ -648,7 +647,7 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
     a.rec_w = ctx->d_rec_w;
     e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);  // predictor of the first step
     for (int n = 0; n + 1 < nsteps && e == hipSuccess; ++n) {
-      e = ctx->ks->step_fused(a, Q, params, clock, ctx->traces, ctx->traces2,
+      e = ctx->ks->step_fused(a, ctx->cfg.precision, Q, params, clock, ctx->traces, ctx->traces2,
                               rec_out ? rec_out + n * rec_stride : nullptr, s);
       std::swap(ctx->traces, ctx->traces2);  // the newest traces are the workspace
     }

@@ -1771,17 +1771,24 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
 // uses t^n + dt.  rec_out (when the context has receivers): u^{n+1} at the
 // receivers, [nrec][NV].
 // ---------------------------------------------------------------------------
-template <class PDE, int N>
-__global__ void __launch_bounds__((GeoL<PDE, N, double>::BLOCK), (GeoL<PDE, N, double>::MIN_WAVES))
+template <class PDE, int N, class R>
+struct GeoStep {
+  using GL = GeoL<PDE, N, R>;
+  // doubles of LDS: the predictor's rows (R), the fluctuations, u^{n+1}
+  static constexpr int LDS_D = cmax(cmax((GL::ELEMS * (int)sizeof(R) + 7) / 8, GL::CPB * GeoB<PDE, N>::FL_PER_CELL),
+                                    GL::CPB * Geo<PDE, N>::NV * Geo<PDE, N>::S);
+  static constexpr bool built = PDE::kLinear && LDS_D * 8 <= 150 * 1024;
+};
+
+template <class PDE, int N, class R>
+__global__ void __launch_bounds__((GeoL<PDE, N, R>::BLOCK), (GeoL<PDE, N, R>::MIN_WAVES))
 step_kernel_lin(const KArgs a, double* Q, const double* __restrict__ params, const double* __restrict__ clock,
                 const double* __restrict__ tr_in, double* __restrict__ tr_out, double* __restrict__ rec_out) {
   using G = Geo<PDE, N>;
-  using GL = GeoL<PDE, N, double>;
-  using GB = GeoB<PDE, N>;
-  static_assert(PDE::kLinear, "step fusion is built for PDEs linear in Q");
-  static_assert(GB::FL_PER_CELL <= GL::CELL_ELEMS, "fluctuations exceed the cell's LDS");
+  using GL = GeoL<PDE, N, R>;
+  static_assert(GeoStep<PDE, N, R>::built, "step fusion is built for PDEs linear in Q");
   constexpr int S = G::S, NV = G::NV, NP = G::NP, CPB = GL::CPB, BLOCK = GL::BLOCK;
-  __shared__ double lds[GL::ELEMS];
+  __shared__ double lds[GeoStep<PDE, N, R>::LDS_D];
   __shared__ double src_e[kMaxSources][kMaxLin + 1];
 
   const int tid = threadIdx.x;
@@ -1793,11 +1800,12 @@ step_kernel_lin(const KArgs a, double* Q, const double* __restrict__ params, con
   const double t_n = clock[0], dt = clock[1];
 
   // corrector of step n
-  double u1[NV], P[NP > 0 ? NP : 1];
+  double u1[NV];
+  R P[NP > 0 ? NP : 1];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u1[v] = Q[(cl * NV + v) * S + k];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) P[p] = params[cl * NP + p];
+  for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
   face_fluctuations<PDE, N, CPB, BLOCK>(a, params, tr_in, dt, (int)cell0, tid, lds);
   __syncthreads();
   if (active) {
@@ -1827,7 +1835,8 @@ step_kernel_lin(const KArgs a, double* Q, const double* __restrict__ params, con
   }
 
   // predictor of step n + 1
-  lin_predict_block<PDE, N, double>(a, lds, src_e, tid, cell0, u1, P, params, t_n + dt, dt, Q, tr_out);
+  lin_predict_block<PDE, N, R>(a, reinterpret_cast<R*>(lds), src_e, tid, cell0, u1, P, params, t_n + dt, dt, Q,
+                               tr_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2022,26 +2031,31 @@ struct Launch {
     return hipGetLastError();
   }
   // corrector of step n fused with the predictor of step n + 1, then t += dt
-  static hipError_t step_fused(const KArgs& a0, double* Q, const double* params, double* clock,
+  template <class R>
+  static hipError_t step_fused_r(const KArgs& a0, double* Q, const double* params, double* clock,
+                                 const double* tr_in, double* tr_out, double* rec_out, hipStream_t st) {
+    using GL = GeoL<PDE, N, R>;
+    KArgs a = a0;
+    a.flux_traces = 0;
+    a.nblocks = blocks_a<GL>(a);
+    hipLaunchKernelGGL((step_kernel_lin<PDE, N, R>), dim3(a.nblocks), dim3(GL::BLOCK), 0, st, a, Q, params,
+                       clock, tr_in, tr_out, rec_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor, 2, clock);
+    return hipGetLastError();
+  }
+  static hipError_t step_fused(const KArgs& a, int precision, double* Q, const double* params, double* clock,
                                const double* tr_in, double* tr_out, double* rec_out, hipStream_t st) {
-    if constexpr (PDE::kLinear && GeoB<PDE, N>::FL_PER_CELL <= GeoL<PDE, N, double>::CELL_ELEMS) {
-      using GL = GeoL<PDE, N, double>;
-      KArgs a = a0;
-      a.flux_traces = 0;
-      a.nblocks = blocks_a<GL>(a);
-      hipLaunchKernelGGL((step_kernel_lin<PDE, N>), dim3(a.nblocks), dim3(GL::BLOCK), 0, st, a, Q, params,
-                         clock, tr_in, tr_out, rec_out);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor, 2, clock);
-      return hipGetLastError();
+    if constexpr (GeoStep<PDE, N, double>::built && GeoStep<PDE, N, float>::built) {
+      if (precision == ADG_MIXED_FP32) return step_fused_r<float>(a, Q, params, clock, tr_in, tr_out, rec_out, st);
+      return step_fused_r<double>(a, Q, params, clock, tr_in, tr_out, rec_out, st);
     } else {
       return hipErrorNotSupported;
     }
   }
   static constexpr decltype(KernelSet::step_fused) step_fused_entry() {
-    if constexpr (PDE::kLinear && GeoB<PDE, N>::FL_PER_CELL <= GeoL<PDE, N, double>::CELL_ELEMS)
-      return &step_fused;
+    if constexpr (GeoStep<PDE, N, double>::built && GeoStep<PDE, N, float>::built) return &step_fused;
     else return nullptr;
   }
   static constexpr decltype(KernelSet::adjoint) adjoint_entry() {

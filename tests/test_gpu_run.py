@@ -28,7 +28,7 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def elastic_setup(order, cells, bc=None, with_source=True):
+def elastic_setup(order, cells, bc=None, with_source=True, precision="fp64"):
     cfg = inputs.elastic_config("c3")
     hi = [500.0 * c for c in cells]
     src = dict(cfg["source"])
@@ -37,7 +37,7 @@ def elastic_setup(order, cells, bc=None, with_source=True):
     srcs = [src] if with_source else []
     P = O.problem(3, order, O.ELASTIC, cells, [0.0] * 3, hi, bc=bc,
                   sources=[dict(x=q["x"], w=q["w"], f0=q["f0"], t0=q["t0"], amp=q["amp"]) for q in srcs])
-    s = adg.Solver(3, order, "elastic", cells, [0.0] * 3, hi, bc=bc)
+    s = adg.Solver(3, order, "elastic", cells, [0.0] * 3, hi, bc=bc, precision=precision)
     if srcs:
         s.set_point_sources([dict(x=q["x"], weight=q["w"], f0=q["f0"], t0=q["t0"], amp=q["amp"]) for q in srcs])
     rng = np.random.default_rng(90 + order)
@@ -87,6 +87,25 @@ def test_fused_run_equals_step_by_step_and_oracle(order, cells, bc):
     assert rel_l2(Rf, Rs) <= 1e-13
     assert rel_l2(Qf, Qo) <= 1e-12
     assert cf[0] == cs[0] and cf[1] == cs[1] == dt  # t advanced by the same additions
+    s.close()
+
+
+@pytest.mark.parametrize("order,cells", [(3, [4, 3, 3]), (4, [3, 2, 3])])
+def test_fused_run_mixed_fp32(order, cells):
+    # the FP32 predictor inside the fused kernel runs the same code as the
+    # step-by-step FP32 predictor; against the FP64 oracle the bar is the one
+    # of the mixed-precision predictor (1e-5)
+    say("run elastic fp32", order, cells)
+    s, P, params, Q0, rec, dt = elastic_setup(order, cells, precision="fp32")
+    steps = 4
+    Qs, Rs, cs = stepwise(s, Q0, params, dt, steps)
+    Qf, Rf, cf = fused(s, Q0, params, dt, steps)
+    Qo, _ = O.run(P, Q0, params, steps=steps, dt_fixed=dt)
+    say(f"  fused vs steps {rel_l2(Qf, Qs):.2e}, receivers {rel_l2(Rf, Rs):.2e}, vs oracle {rel_l2(Qf, Qo):.2e}")
+    assert rel_l2(Qf, Qs) <= 1e-14
+    assert rel_l2(Rf, Rs) <= 1e-13
+    assert rel_l2(Qf, Qo) <= 1e-5
+    assert cf[0] == cs[0]
     s.close()
 
 
