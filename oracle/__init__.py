@@ -141,6 +141,10 @@ def lib():
         L.orc_check_admissible.argtypes = [pp, dp, dp, C.POINTER(C.c_ubyte), C.POINTER(C.c_int)]
         L.orc_step_adjoint.argtypes = [pp, dp, dp, C.c_double, C.c_double, dp, dp]
         L.orc_sample_receivers_T.argtypes = [pp, C.c_int, dp, dp, dp]
+        L.orc_step_limited.argtypes = [pp, dp, dp, C.c_double, C.c_double, dp, C.POINTER(C.c_ubyte),
+                                       C.POINTER(C.c_int)]
+        L.orc_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_fv_step.argtypes = [pp, dp, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -283,6 +287,46 @@ def check_admissible(P: Problem, Q, params=None):
                                       flags.ctypes.data_as(C.POINTER(C.c_ubyte)), C.byref(cnt)),
            "check_admissible")
     return flags, cnt.value
+
+
+STATUS_DG, STATUS_DG_FV_FACES, STATUS_FV, STATUS_TROUBLED = 0, 1, 2, 3
+
+
+def limiter_subcells(P: Problem) -> int:
+    return (2 * P.n - 1) ** P.dim
+
+
+def step_limited(P: Problem, Q, dt: float, t: float = 0.0, sub=None, status=None):
+    """One step with the a-posteriori subcell limiter (Euler).  ``sub``
+    [C][nv][m^dim] and ``status`` [C] carry the FV cells from step to step
+    (None: a first step, nothing on FV).  Returns (u^{n+1}, sub, status,
+    counts (troubled, FV cells, DG cells with FV faces)), all new arrays."""
+    Qn = _arr(Q).copy()
+    sub = np.zeros((P.ncells, P.nvar, limiter_subcells(P))) if sub is None else _arr(sub).copy()
+    status = np.zeros(P.ncells, dtype=np.uint8) if status is None else np.array(status, dtype=np.uint8)
+    counts = (C.c_int * 3)()
+    _check(lib().orc_step_limited(C.byref(P), _p(Qn), None, dt, t, _p(sub),
+                                  status.ctypes.data_as(C.POINTER(C.c_ubyte)), counts), "step_limited")
+    return Qn, sub, status, tuple(counts)
+
+
+def limiter_tables(n: int):
+    """(A [m][n] subcell averages of the basis, B [n][m] its least-squares
+    inverse, Qf [n][m] subface data to face nodes), m = 2n - 1."""
+    m = 2 * n - 1
+    A, B, Qf = np.zeros((m, n)), np.zeros((n, m)), np.zeros((n, m))
+    _check(lib().orc_limiter_tables(n, _p(A), _p(B), _p(Qf)), "limiter_tables")
+    return A, B, Qf
+
+
+def fv_step(P: Problem, Q, dt: float):
+    """The FV scheme alone on every cell: (u^{n+1} projected back to DG,
+    subcell averages [C][nv][m^dim] after the FV step)."""
+    Qn = _arr(Q).copy()
+    m = 2 * P.n - 1
+    sub = np.zeros((P.ncells, P.nvar, m ** P.dim))
+    _check(lib().orc_fv_step(C.byref(P), _p(Qn), dt, _p(sub)), "fv_step")
+    return Qn, sub
 
 
 def run(P: Problem, Q, params=None, steps: int = 1, t0: float = 0.0, dt_fixed=None):

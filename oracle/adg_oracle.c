@@ -725,12 +725,15 @@ static void predict_and_project(const orc_problem *P, const mesh *M, const table
   }
 }
 
-/* Assemble u^{n+1} of cell c from its own traces and its neighbours'. */
+/* Assemble u^{n+1} of cell c from its own traces and its neighbours'.
+ * Gover (NULL, or [2 dim] pointers each NULL or [F][nv]) replaces the
+ * Rusanov flux G on a face by a given normal flux (the subcell limiter's FV
+ * fluxes, section 10; conservative PDEs only). */
 static void correct_cell(const orc_problem *P, const mesh *M, const tables *T, long c,
                          const double *Q, const double *params, double dt, const double *vol,
                          const double *weak, double *const *qhat_of, double *const *Fhat_of,
                          const long *nb /*[dim][2]: low, high neighbour*/, double *out,
-                         double *weak_out) {
+                         double *weak_out, const double *const *Gover) {
   const int S = M->S, nv = M->nv, F = M->F, nq = M->nq;
   size_t face_sz = (size_t)F * nv;
   /* fluctuations on the faces of this cell, [2 dim][F][nv] */
@@ -773,6 +776,13 @@ static void correct_cell(const orc_problem *P, const mesh *M, const tables *T, l
           FR[v] = side ? Fx[v] : Fo[v];
         }
         rusanov(P, d, qL, FL, qR, FR, flL, flR);
+        if (Gover && Gover[2 * d + side]) {
+          const double *Go = Gover[2 * d + side] + (size_t)f * nv;
+          for (int v = 0; v < nv; ++v) {
+            flL[v] = Go[v] - FL[v];
+            flR[v] = FR[v] - Go[v];
+          }
+        }
         for (int v = 0; v < nv; ++v) {
           fl[(2 * d + side) * face_sz + (size_t)f * nv + v] = side ? flL[v] : flR[v];
           /* G itself, for the weak-form check */
@@ -982,7 +992,7 @@ int orc_step(const orc_problem *P, double *Q, const double *params, double dt, d
         correct_cell(P, &M, &T, c, Q, params, dt, &CS.vol[(size_t)c * M.S * M.nv],
                      CS.weak ? &CS.weak[(size_t)c * M.S * M.nv] : NULL, qh, Fh, nb,
                      &out[(size_t)c * M.nv * M.S],
-                     weak_out ? &weak_out[(size_t)c * M.nv * M.S] : NULL);
+                     weak_out ? &weak_out[(size_t)c * M.nv * M.S] : NULL, NULL);
       }
       memcpy(Q, out, sizeof(double) * M.C * M.S * M.nv);
     }
@@ -1030,7 +1040,7 @@ int orc_step_cells(const orc_problem *P, const double *Q, const double *params, 
           if (a > 0) nb[a - 1] = neighbour(P, cells[i], (a - 1) / 2, (a - 1) % 2 ? 1 : -1);
         }
         correct_cell(P, &M, &T, cells[i], Q, params, dt, &CS.vol[(size_t)(i * per) * M.S * M.nv],
-                     NULL, qh, Fh, nb, &out[(size_t)i * M.nv * M.S], NULL);
+                     NULL, qh, Fh, nb, &out[(size_t)i * M.nv * M.S], NULL, NULL);
       }
     }
   }
@@ -1583,5 +1593,545 @@ int orc_sample_receivers_T(const orc_problem *P, int nrec, const double *xyz, co
       for (int v = 0; v < M.nv; ++v) lam[((size_t)c * M.nv + v) * M.S + k] += phi * lamrec[r * M.nv + v];
     }
   }
+  return ORC_OK;
+}
+
+/* ========================================================================
+ * 10. A-posteriori subcell limiter for the Euler equations (Sec. 3.5, the
+ *     FV, limiter and projection kernels of Table 1, the status stencil of
+ *     Fig. 2).  One limited step:
+ *       1. the unlimited ADER-DG step gives a candidate u* in every cell;
+ *       2. a cell is troubled if u* fails the physical admissibility test
+ *          (at every node and every subcell average) or the relaxed discrete
+ *          maximum principle;
+ *       3. troubled cells and their face neighbours are recomputed from u^n
+ *          with a second-order FV scheme on (2N+1)^d subcells, and the FV
+ *          result is projected back to the DG space;
+ *       4. DG cells that share a face with a recomputed cell take, on that
+ *          face, the FV fluxes in place of the Rusanov flux of step 1, so
+ *          that what leaves one cell enters the other.
+ *    READINGS (the paper names these pieces but gives no formulas):
+ *    - projectOnFVLimiterSpace gives exact subcell averages,
+ *        v_s = sum_k prod_d A[s_d][k_d] u_k,
+ *        A[s][k] = m * integral of phi_k over [s/m, (s+1)/m],  m = 2N+1;
+ *    - projectOnDGSpace is the least-squares inverse, u = (B x .. x B) v,
+ *      B = (A^T A)^{-1} A^T: a projected polynomial comes back unchanged and
+ *      the cell mean is kept;
+ *    - relaxed DMP: with lo_v, hi_v the smallest and largest subcell average
+ *      of u^n over the cell and its face neighbours, every subcell average of
+ *      the candidate must lie in [lo_v - delta_v, hi_v + delta_v],
+ *      delta_v = max(1e-4, 1e-3 (hi_v - lo_v)) (the constants of the MOOD
+ *      subcell-limiter work the paper cites);
+ *    - the FV scheme is MUSCL-Hancock with the minmod limiter (Table 1's
+ *      defaults): unsplit; minmod slopes of the conserved variables along
+ *      each axis; the values extrapolated to the 2d subcell faces are moved
+ *      half a step with the flux differences of all axes; Rusanov at every
+ *      subcell face; a subcell whose extrapolated or moved values are not
+ *      admissible uses its average on all faces (first order);
+ *    - FV ghost subcells outside the domain mirror the inside ones (wall:
+ *      the normal momentum reversed; outflow: unchanged);
+ *    - hybrid ADER-DG/FV (the paper's variant of the method): a cell that
+ *      was FV in the previous step keeps its FV subcell averages as its
+ *      solution, and its DG polynomial (their projection) only serves its
+ *      neighbours; in the next step its FV data, not the projection of that
+ *      polynomial, is where its FV step starts and what the DMP and the
+ *      neighbours' ghost subcells see (projecting a shock profile to a
+ *      polynomial and back is not positive).  Every cell's DG candidate is
+ *      computed each step; a cell is DG again as soon as its candidate
+ *      passes both tests;
+ *    - the flux a DG neighbour takes at a node of the shared face is the L2
+ *      projection, with the GL face mass, of the piecewise constant subface
+ *      fluxes: G_f = sum_t prod_{a != d} Qf[f_a][t_a] Fsub_t,
+ *      Qf[j][s] = A[s][j] / (m w_j); the face's total flux is then the FV
+ *      one.
+ * ======================================================================== */
+#define ORC_MAXM (2 * ORC_MAXN - 1)
+
+typedef struct {
+  int m;
+  double A[ORC_MAXM][ORC_MAXN];  /* subcell averages of phi_k */
+  double B[ORC_MAXN][ORC_MAXM];  /* least-squares inverse of A */
+  double Qf[ORC_MAXN][ORC_MAXM]; /* piecewise constant face data -> face nodes */
+} lim_tables;
+
+static int make_lim_tables(const tables *T, lim_tables *L) {
+  const int n = T->n, m = 2 * n - 1;
+  long double A[ORC_MAXM][ORC_MAXN], xs[ORC_MAXN];
+  L->m = m;
+  for (int i = 0; i < n; ++i) xs[i] = T->xi[i];
+  for (int s = 0; s < m; ++s)
+    for (int k = 0; k < n; ++k) {
+      /* n-point Gauss quadrature on the subinterval is exact for degree N;
+       * m times (1/m) sum_q w_q phi_k(x_q) */
+      long double sum = 0.0L;
+      for (int q = 0; q < n; ++q) sum += (long double)T->w[q] * lagrange_ld(n, xs, k, ((long double)s + xs[q]) / m);
+      A[s][k] = sum;
+      L->A[s][k] = (double)sum;
+    }
+  /* B = (A^T A)^{-1} A^T by Gauss-Jordan on the normal equations */
+  long double N[ORC_MAXN][2 * ORC_MAXN];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      long double a = 0.0L;
+      for (int s = 0; s < m; ++s) a += A[s][i] * A[s][j];
+      N[i][j] = a;
+      N[i][n + j] = i == j ? 1.0L : 0.0L;
+    }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(N[r][col]) > fabsl(N[piv][col])) piv = r;
+    if (piv != col)
+      for (int c = 0; c < 2 * n; ++c) {
+        long double tmp = N[col][c];
+        N[col][c] = N[piv][c];
+        N[piv][c] = tmp;
+      }
+    long double d = N[col][col];
+    if (d == 0.0L) return ORC_EINVAL;
+    for (int c = 0; c < 2 * n; ++c) N[col][c] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      long double f = N[r][col];
+      for (int c = 0; c < 2 * n; ++c) N[r][c] -= f * N[col][c];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int s = 0; s < m; ++s) {
+      long double b = 0.0L;
+      for (int j = 0; j < n; ++j) b += N[i][n + j] * A[s][j];
+      L->B[i][s] = (double)b;
+      L->Qf[i][s] = (double)(A[s][i] / ((long double)m * (long double)T->w[i]));
+    }
+  return ORC_OK;
+}
+
+static int ipow_i(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+static void sub_multi(int m, int s, int ss[3]) {
+  ss[0] = s % m;
+  ss[1] = (s / m) % m;
+  ss[2] = s / (m * m);
+}
+
+/* v[var][s] = subcell averages of one cell's nodal values u[var][k] */
+static void lim_project(const mesh *M, const lim_tables *L, const double *u, double *v) {
+  const int m = L->m, ns = ipow_i(m, M->dim);
+  for (int s = 0; s < ns; ++s) {
+    int ss[3];
+    sub_multi(m, s, ss);
+    for (int var = 0; var < M->nv; ++var) {
+      double sum = 0.0;
+      for (int k = 0; k < M->S; ++k) {
+        int kk[3];
+        node_index(M, k, kk);
+        double a = 1.0;
+        for (int d = 0; d < M->dim; ++d) a *= L->A[ss[d]][kk[d]];
+        sum += a * u[(size_t)var * M->S + k];
+      }
+      v[(size_t)var * ns + s] = sum;
+    }
+  }
+}
+
+/* u[var][k] = least-squares DG polynomial of subcell averages v[var][s] */
+static void lim_reconstruct(const mesh *M, const lim_tables *L, const double *v, double *u) {
+  const int m = L->m, ns = ipow_i(m, M->dim);
+  for (int k = 0; k < M->S; ++k) {
+    int kk[3];
+    node_index(M, k, kk);
+    for (int var = 0; var < M->nv; ++var) {
+      double sum = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        int ss[3];
+        sub_multi(m, s, ss);
+        double b = 1.0;
+        for (int d = 0; d < M->dim; ++d) b *= L->B[kk[d]][ss[d]];
+        sum += b * v[(size_t)var * ns + s];
+      }
+      u[(size_t)var * M->S + k] = sum;
+    }
+  }
+}
+
+/* Subcell average of u^n at global subcell index g (up to two subcells
+ * outside the domain); V is [C][nv][m^dim]. */
+static void lim_value(const orc_problem *P, const mesh *M, int m, const double *V, const int gin[3],
+                      double *out) {
+  int g[3] = {gin[0], gin[1], gin[2]}, flip[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+  for (int d = 0; d < M->dim; ++d) {
+    const int G = m * P->cells[d];
+    if (g[d] < 0 || g[d] >= G) {
+      const int side = g[d] >= G, kind = P->bc[2 * d + side];
+      if (kind == ORC_BC_PERIODIC) {
+        g[d] = ((g[d] % G) + G) % G;
+      } else {
+        g[d] = side ? 2 * G - 1 - g[d] : -1 - g[d];
+        flip[d] = kind == ORC_BC_WALL;
+      }
+    }
+    cc[d] = g[d] / m;
+    ss[d] = g[d] % m;
+  }
+  const int ns = ipow_i(m, M->dim);
+  const int si = ss[0] + m * (ss[1] + m * ss[2]);
+  const long c = cell_index(P, cc);
+  for (int var = 0; var < M->nv; ++var) out[var] = V[((size_t)c * M->nv + var) * ns + si];
+  for (int d = 0; d < M->dim; ++d)
+    if (flip[d]) out[1 + d] = -out[1 + d];
+}
+
+static double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return fmin(a, b);
+  if (a < 0.0 && b < 0.0) return fmax(a, b);
+  return 0.0;
+}
+
+/* MUSCL-Hancock: the average of subcell g extrapolated to its 2 dim faces
+ * with minmod slopes and moved half a step; out[d][side][var]. */
+static void lim_evolved(const orc_problem *P, const mesh *M, int m, const double *V, const int g[3],
+                        double dt, const double *hs, double out[3][2][ORC_MAXQ]) {
+  const int nv = M->nv;
+  double w[ORC_MAXQ], ext[3][2][ORC_MAXQ], corr[ORC_MAXQ];
+  int ok = 1;
+  lim_value(P, M, m, V, g, w);
+  for (int d = 0; d < M->dim; ++d) {
+    double wl[ORC_MAXQ], wr[ORC_MAXQ];
+    int gl[3] = {g[0], g[1], g[2]}, gr[3] = {g[0], g[1], g[2]};
+    gl[d] -= 1;
+    gr[d] += 1;
+    lim_value(P, M, m, V, gl, wl);
+    lim_value(P, M, m, V, gr, wr);
+    for (int v = 0; v < nv; ++v) {
+      double slope = minmod(w[v] - wl[v], wr[v] - w[v]);
+      ext[d][0][v] = w[v] - 0.5 * slope;
+      ext[d][1][v] = w[v] + 0.5 * slope;
+    }
+    ok = ok && pde_admissible(P, ext[d][0]) && pde_admissible(P, ext[d][1]);
+  }
+  for (int v = 0; v < nv; ++v) corr[v] = 0.0;
+  for (int d = 0; d < M->dim; ++d) {
+    double Fl[ORC_MAXQ], Fr[ORC_MAXQ];
+    pde_flux(P, ext[d][0], d, Fl);
+    pde_flux(P, ext[d][1], d, Fr);
+    for (int v = 0; v < nv; ++v) corr[v] += 0.5 * dt / hs[d] * (Fl[v] - Fr[v]);
+  }
+  for (int d = 0; d < M->dim; ++d)
+    for (int side = 0; side < 2; ++side) {
+      for (int v = 0; v < nv; ++v) out[d][side][v] = ext[d][side][v] + corr[v];
+      ok = ok && pde_admissible(P, out[d][side]);
+    }
+  if (!ok)
+    for (int d = 0; d < M->dim; ++d)
+      for (int side = 0; side < 2; ++side)
+        for (int v = 0; v < nv; ++v) out[d][side][v] = w[v];
+}
+
+/* Rusanov flux between the states a (low side) and b (high side) along d */
+static void lim_rusanov(const orc_problem *P, int d, const double *a, const double *b, double *G) {
+  double Fa[ORC_MAXQ], Fb[ORC_MAXQ];
+  pde_flux(P, a, d, Fa);
+  pde_flux(P, b, d, Fb);
+  double s = fmax(pde_max_eigen(P, a, d), pde_max_eigen(P, b, d));
+  for (int v = 0; v < P->nvar; ++v) G[v] = 0.5 * (Fa[v] + Fb[v]) - 0.5 * s * (b[v] - a[v]);
+}
+
+/* index of a subface (or face node) across the axes other than d, lower
+ * axis fastest */
+static int transverse_index(int dim, int d, int m, const int ss[3]) {
+  int t = 0, mul = 1;
+  for (int a = 0; a < dim; ++a) {
+    if (a == d) continue;
+    t += ss[a] * mul;
+    mul *= m;
+  }
+  return t;
+}
+
+/* FV step of cell c from the u^n subcell averages V: vnew [nv][m^dim] and
+ * the fluxes through the cell's faces, frec [2 dim][m^(dim-1)][nv]. */
+static void lim_fv_cell(const orc_problem *P, const mesh *M, const lim_tables *L, const double *V, long c,
+                        double dt, double *vnew, double *frec) {
+  const int m = L->m, nv = M->nv, ns = ipow_i(m, M->dim), nsf = ipow_i(m, M->dim - 1);
+  double hs[3];
+  int cc[3];
+  for (int d = 0; d < M->dim; ++d) hs[d] = M->h[d] / m;
+  cell_coords(P, c, cc);
+  for (int s = 0; s < ns; ++s) {
+    int ss[3], g[3] = {0, 0, 0};
+    sub_multi(m, s, ss);
+    for (int d = 0; d < M->dim; ++d) g[d] = cc[d] * m + ss[d];
+    double w[ORC_MAXQ], acc[ORC_MAXQ], E[3][2][ORC_MAXQ];
+    lim_value(P, M, m, V, g, w);
+    lim_evolved(P, M, m, V, g, dt, hs, E);
+    for (int v = 0; v < nv; ++v) acc[v] = 0.0;
+    for (int d = 0; d < M->dim; ++d) {
+      double En[3][2][ORC_MAXQ], Glo[ORC_MAXQ], Ghi[ORC_MAXQ];
+      int gn[3] = {g[0], g[1], g[2]};
+      gn[d] = g[d] + 1;
+      lim_evolved(P, M, m, V, gn, dt, hs, En);
+      lim_rusanov(P, d, E[d][1], En[d][0], Ghi);
+      gn[d] = g[d] - 1;
+      lim_evolved(P, M, m, V, gn, dt, hs, En);
+      lim_rusanov(P, d, En[d][1], E[d][0], Glo);
+      for (int v = 0; v < nv; ++v) acc[v] += (Ghi[v] - Glo[v]) / hs[d];
+      const int t = transverse_index(M->dim, d, m, ss);
+      if (ss[d] == m - 1)
+        for (int v = 0; v < nv; ++v) frec[((size_t)(2 * d + 1) * nsf + t) * nv + v] = Ghi[v];
+      if (ss[d] == 0)
+        for (int v = 0; v < nv; ++v) frec[((size_t)(2 * d) * nsf + t) * nv + v] = Glo[v];
+    }
+    for (int v = 0; v < nv; ++v) vnew[(size_t)v * ns + s] = w[v] - dt * acc[v];
+  }
+}
+
+/* Subface fluxes of one face [m^(dim-1)][nv] -> face-node fluxes [F][nv] */
+static void lim_face_to_nodes(const mesh *M, const lim_tables *L, const double *fsub, double *G) {
+  const int m = L->m, nsf = ipow_i(m, M->dim - 1);
+  for (int f = 0; f < M->F; ++f) {
+    int ff[2] = {f % M->n, f / M->n};
+    for (int v = 0; v < M->nv; ++v) {
+      double sum = 0.0;
+      for (int t = 0; t < nsf; ++t) {
+        int tt[2] = {t % m, t / m};
+        double q = 1.0;
+        for (int a = 0; a < M->dim - 1; ++a) q *= L->Qf[ff[a]][tt[a]];
+        sum += q * fsub[(size_t)t * M->nv + v];
+      }
+      G[(size_t)f * M->nv + v] = sum;
+    }
+  }
+}
+
+/* One limited step in place (Euler only).
+ * status [C], in and out: 0 DG, 1 DG taking FV fluxes on some face, 2 FV as
+ *   a neighbour of a troubled cell, 3 troubled (FV); all zero before the
+ *   first step.
+ * sub [C][nv][m^dim], in and out: the FV subcell averages of the cells with
+ *   status >= 2 (the other cells' entries are neither read nor written).
+ * counts[3] (may be NULL): troubled cells, FV cells (status 2 or 3), DG
+ *   cells with FV faces. */
+int orc_step_limited(const orc_problem *P, double *Q, const double *params, double dt, double t,
+                     double *sub, unsigned char *status, int *counts) {
+  mesh M;
+  tables T;
+  lim_tables L;
+  if (P->pde != ORC_EULER || !sub || !status) return ORC_EINVAL;
+  if (make_mesh(P, &M) || make_tables(M.n, &T) || make_lim_tables(&T, &L)) return ORC_EINVAL;
+  const int m = L.m, nv = M.nv, S = M.S, ns = ipow_i(m, M.dim), nsf = ipow_i(m, M.dim - 1);
+  const long C = M.C;
+  for (long c = 0; c < C; ++c)
+    if (status[c] > 3) return ORC_EINVAL;
+  const size_t face_all = (size_t)2 * M.dim * M.F * nv, cell_sz = (size_t)nv * S;
+  const size_t rec_sz = (size_t)2 * M.dim * nsf * nv;
+  cellside CS;
+  CS.vol = malloc(sizeof(double) * C * S * nv);
+  CS.weak = NULL;
+  CS.qhat = malloc(sizeof(double) * C * face_all);
+  CS.Fhat = malloc(sizeof(double) * C * face_all);
+  double *Qn = malloc(sizeof(double) * C * cell_sz);
+  double *Qc = malloc(sizeof(double) * C * cell_sz);
+  double *Vn = malloc(sizeof(double) * C * nv * ns);
+  double *lo = malloc(sizeof(double) * C * nv), *hi = malloc(sizeof(double) * C * nv);
+  double *frec = malloc(sizeof(double) * C * rec_sz);
+  unsigned char *st = malloc(C);
+  int rc = ORC_ENOMEM;
+  if (!CS.vol || !CS.qhat || !CS.Fhat || !Qn || !Qc || !Vn || !lo || !hi || !frec || !st) goto done;
+  memcpy(Qn, Q, sizeof(double) * C * cell_sz);
+
+  /* 1. the unlimited candidate */
+  rc = predict_all(P, &M, &T, Qn, params, dt, t, NULL, C, &CS);
+  if (rc != ORC_OK) goto done;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long c = 0; c < C; ++c) {
+    long nb[6];
+    double *qh[7], *Fh[7];
+    qh[0] = &CS.qhat[c * face_all];
+    Fh[0] = &CS.Fhat[c * face_all];
+    for (int d = 0; d < M.dim; ++d)
+      for (int s = 0; s < 2; ++s) {
+        nb[2 * d + s] = neighbour(P, c, d, s ? 1 : -1);
+        qh[1 + 2 * d + s] = nb[2 * d + s] < 0 ? NULL : &CS.qhat[nb[2 * d + s] * face_all];
+        Fh[1 + 2 * d + s] = nb[2 * d + s] < 0 ? NULL : &CS.Fhat[nb[2 * d + s] * face_all];
+      }
+    correct_cell(P, &M, &T, c, Qn, params, dt, &CS.vol[(size_t)c * S * nv], NULL, qh, Fh, nb,
+                 &Qc[(size_t)c * cell_sz], NULL, NULL);
+  }
+
+  /* 2. subcell averages at t^n (FV cells: their own) and their ranges */
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long c = 0; c < C; ++c) {
+    double *v = &Vn[(size_t)c * nv * ns];
+    if (status[c] >= 2)
+      memcpy(v, &sub[(size_t)c * nv * ns], sizeof(double) * nv * ns);
+    else
+      lim_project(&M, &L, &Qn[(size_t)c * cell_sz], v);
+    for (int var = 0; var < nv; ++var) {
+      double a = v[(size_t)var * ns], b = a;
+      for (int s = 1; s < ns; ++s) {
+        a = fmin(a, v[(size_t)var * ns + s]);
+        b = fmax(b, v[(size_t)var * ns + s]);
+      }
+      lo[c * nv + var] = a;
+      hi[c * nv + var] = b;
+    }
+  }
+
+  /* 3. troubled cells: physical admissibility, then the relaxed DMP */
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long c = 0; c < C; ++c) {
+    const double *u = &Qc[(size_t)c * cell_sz];
+    double *v = NULL;
+    int bad = 0;
+    for (int k = 0; k < S && !bad; ++k) {
+      double q[ORC_MAXQ];
+      for (int var = 0; var < nv; ++var) q[var] = u[(size_t)var * S + k];
+      bad = !pde_admissible(P, q);
+    }
+    v = malloc(sizeof(double) * nv * ns);
+    lim_project(&M, &L, u, v);
+    for (int s = 0; s < ns && !bad; ++s) {
+      double q[ORC_MAXQ];
+      for (int var = 0; var < nv; ++var) q[var] = v[(size_t)var * ns + s];
+      bad = !pde_admissible(P, q);
+    }
+    for (int var = 0; var < nv && !bad; ++var) {
+      double a = lo[c * nv + var], b = hi[c * nv + var];
+      for (int d = 0; d < M.dim; ++d)
+        for (int sd = -1; sd <= 1; sd += 2) {
+          long o = neighbour(P, c, d, sd);
+          if (o < 0) continue;
+          a = fmin(a, lo[o * nv + var]);
+          b = fmax(b, hi[o * nv + var]);
+        }
+      double delta = fmax(1e-4, 1e-3 * (b - a));
+      for (int s = 0; s < ns && !bad; ++s) {
+        double x = v[(size_t)var * ns + s];
+        bad = !(x >= a - delta && x <= b + delta);
+      }
+    }
+    free(v);
+    st[c] = bad ? 3 : 0;
+  }
+
+  /* 4. FV set: troubled cells and their face neighbours; DG cells next to it */
+  for (long c = 0; c < C; ++c) {
+    if (st[c] == 3) continue;
+    int near = 0;
+    for (int d = 0; d < M.dim; ++d)
+      for (int sd = -1; sd <= 1; sd += 2) {
+        long o = neighbour(P, c, d, sd);
+        if (o >= 0 && st[o] == 3) near = 1;
+      }
+    if (near) st[c] = 2;
+  }
+  for (long c = 0; c < C; ++c) {
+    if (st[c] >= 2) continue;
+    for (int d = 0; d < M.dim; ++d)
+      for (int sd = -1; sd <= 1; sd += 2) {
+        long o = neighbour(P, c, d, sd);
+        if (o >= 0 && st[o] >= 2) st[c] = 1;
+      }
+  }
+
+  /* 5. FV cells, from the subcell averages at t^n */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long c = 0; c < C; ++c) {
+    if (st[c] < 2) continue;
+    double *vnew = &sub[(size_t)c * nv * ns];
+    lim_fv_cell(P, &M, &L, Vn, c, dt, vnew, &frec[(size_t)c * rec_sz]);
+    lim_reconstruct(&M, &L, vnew, &Q[(size_t)c * cell_sz]);
+  }
+
+  /* 6. DG cells: the candidate, with FV fluxes on faces shared with FV cells */
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long c = 0; c < C; ++c) {
+    if (st[c] >= 2) continue;
+    if (st[c] == 0) {
+      memcpy(&Q[(size_t)c * cell_sz], &Qc[(size_t)c * cell_sz], sizeof(double) * cell_sz);
+      continue;
+    }
+    long nb[6];
+    double *qh[7], *Fh[7], *Gbuf = malloc(sizeof(double) * 2 * M.dim * M.F * nv);
+    const double *Gover[6] = {NULL, NULL, NULL, NULL, NULL, NULL};
+    qh[0] = &CS.qhat[c * face_all];
+    Fh[0] = &CS.Fhat[c * face_all];
+    for (int d = 0; d < M.dim; ++d)
+      for (int s = 0; s < 2; ++s) {
+        long o = neighbour(P, c, d, s ? 1 : -1);
+        nb[2 * d + s] = o;
+        qh[1 + 2 * d + s] = o < 0 ? NULL : &CS.qhat[o * face_all];
+        Fh[1 + 2 * d + s] = o < 0 ? NULL : &CS.Fhat[o * face_all];
+        if (o >= 0 && st[o] >= 2) {
+          /* the neighbour's record of the same face: its opposite side */
+          double *G = &Gbuf[(size_t)(2 * d + s) * M.F * nv];
+          lim_face_to_nodes(&M, &L, &frec[(size_t)o * rec_sz + (size_t)(2 * d + 1 - s) * nsf * nv], G);
+          Gover[2 * d + s] = G;
+        }
+      }
+    correct_cell(P, &M, &T, c, Qn, params, dt, &CS.vol[(size_t)c * S * nv], NULL, qh, Fh, nb,
+                 &Q[(size_t)c * cell_sz], NULL, Gover);
+    free(Gbuf);
+  }
+
+  if (counts) {
+    counts[0] = counts[1] = counts[2] = 0;
+    for (long c = 0; c < C; ++c) {
+      counts[0] += st[c] == 3;
+      counts[1] += st[c] >= 2;
+      counts[2] += st[c] == 1;
+    }
+  }
+  memcpy(status, st, C);
+  rc = ORC_OK;
+done:
+  free(CS.vol); free(CS.qhat); free(CS.Fhat); free(Qn); free(Qc); free(Vn); free(lo); free(hi);
+  free(frec); free(st);
+  return rc;
+}
+
+/* Limiter tables for the tests: A [m][n], B [n][m], Qf [n][m]. */
+int orc_limiter_tables(int n, double *A, double *B, double *Qf) {
+  tables T;
+  lim_tables L;
+  if (make_tables(n, &T) || make_lim_tables(&T, &L)) return ORC_EINVAL;
+  const int m = L.m;
+  for (int s = 0; s < m; ++s)
+    for (int k = 0; k < n; ++k) {
+      A[s * n + k] = L.A[s][k];
+      B[k * m + s] = L.B[k][s];
+      Qf[k * m + s] = L.Qf[k][s];
+    }
+  return ORC_OK;
+}
+
+/* The FV scheme alone on every cell (status forced to FV everywhere):
+ * Q <- projectOnDG(MUSCL-Hancock(projectOnFV(Q))).  For the tests. */
+int orc_fv_step(const orc_problem *P, double *Q, double dt, double *subcells_out) {
+  mesh M;
+  tables T;
+  lim_tables L;
+  if (P->pde != ORC_EULER) return ORC_EINVAL;
+  if (make_mesh(P, &M) || make_tables(M.n, &T) || make_lim_tables(&T, &L)) return ORC_EINVAL;
+  const int m = L.m, nv = M.nv, S = M.S, ns = ipow_i(m, M.dim), nsf = ipow_i(m, M.dim - 1);
+  const size_t cell_sz = (size_t)nv * S, rec_sz = (size_t)2 * M.dim * nsf * nv;
+  double *Vn = malloc(sizeof(double) * M.C * nv * ns);
+  if (!Vn) return ORC_ENOMEM;
+#pragma omp parallel for
+  for (long c = 0; c < M.C; ++c) lim_project(&M, &L, &Q[(size_t)c * cell_sz], &Vn[(size_t)c * nv * ns]);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long c = 0; c < M.C; ++c) {
+    double *vnew = malloc(sizeof(double) * nv * ns), *frec = malloc(sizeof(double) * rec_sz);
+    lim_fv_cell(P, &M, &L, Vn, c, dt, vnew, frec);
+    if (subcells_out) memcpy(&subcells_out[(size_t)c * nv * ns], vnew, sizeof(double) * nv * ns);
+    lim_reconstruct(&M, &L, vnew, &Q[(size_t)c * cell_sz]);
+    free(vnew);
+    free(frec);
+  }
+  free(Vn);
   return ORC_OK;
 }

@@ -90,6 +90,34 @@ def blast_state(xyz, seed: int = 7991, radius: float = 0.2):
     return np.stack([rho] + [zero] * dim + [E], axis=1)
 
 
+def subcell_centres(cells, lo, hi, m: int):
+    """[C][m^dim][dim] centres of the m^dim equal subcells of every cell
+    (cells and subcells x fastest)."""
+    dim = len(cells)
+    h = [(hi[d] - lo[d]) / cells[d] for d in range(dim)]
+    cidx = np.stack(np.meshgrid(*[np.arange(c) for c in cells[::-1]], indexing="ij")[::-1], -1).reshape(-1, dim)
+    sidx = np.stack(np.meshgrid(*[np.arange(m)] * dim, indexing="ij")[::-1], -1).reshape(-1, dim)
+    out = np.empty((len(cidx), len(sidx), dim))
+    for d in range(dim):
+        out[..., d] = lo[d] + (cidx[:, None, d] + (sidx[None, :, d] + 0.5) / m) * h[d]
+    return out
+
+
+def blast_limited_start(xyz_nodes, xyz_sub, seed: int = 7991, radius: float = 0.2):
+    """The explosion data for a run with the subcell limiter, started along
+    the discontinuity (the FV and DG subdomains initialised there): cells
+    whose nodes or subcell centres lie on both sides of the sphere start on
+    FV (status 3) with their subcell values sampled at the subcell centres.
+    Returns (Q [C][nv][S] sampled at the nodes, sub [C][nv][m^dim] (zero
+    outside the FV cells), status [C] uint8)."""
+    Q = blast_state(xyz_nodes, seed, radius)
+    sub = blast_state(xyz_sub, seed, radius)
+    cut = lambda a: (a[:, 0].min(axis=1) != a[:, 0].max(axis=1))
+    fv = cut(Q) | cut(sub)
+    sub[~fv] = 0.0
+    return Q, sub, np.where(fv, 3, 0).astype(np.uint8)
+
+
 # ----------------------------------------------------------------- elasticity
 LAYERS_KM = ((0.0, 1.0, (4000.0, 2000.0, 2600.0)),    # Table 3, top layer
              (1.0, 12.0, (6000.0, 3464.0, 2700.0)),   # Table 3, half space
