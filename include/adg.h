@@ -159,6 +159,16 @@ int adg_max_order(int pde, int dim);
 adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double* l0,
                             double* l1, double* K1inv);
 
+/* Host-only: the tables of the a-posteriori subcell limiter (Sec. 3.5; the
+ * projectOnFVLimiterSpace / projectOnDGSpace kernels of Table 1) for
+ * n = order + 1 nodes and m = 2 order + 1 equal subcells of [0, 1]:
+ * A[s*n + k], the average of phi_k over subcell s; B[k*m + s], the
+ * least-squares inverse (A^T A)^{-1} A^T (so B A = I); Qf[k*m + s] =
+ * A[s*n + k] / (m w_k), which maps piecewise constant face data to face-node
+ * values with the same integral against every basis function.  Needs no
+ * GPU. */
+adg_status adg_limiter_tables(int order, double* A, double* B, double* Qf);
+
 /* Validate cfg, build the tables, and allocate the workspace on the current
  * HIP device.  *out receives a context owned by the caller, released with
  * adg_destroy.  Errors: INVALID_ARG (bad values), UNSUPPORTED (order or
@@ -261,6 +271,39 @@ adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, cons
  * STATE error if no adg_predict with workspace traces preceded it. */
 adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                        void* stream);
+
+/* One step with the a-posteriori subcell limiter (Sec. 3.5, the hybrid
+ * ADER-DG/FV method with the status stencil of Fig. 2), in place, for the
+ * Euler equations (2-D N <= 7, 3-D N <= 3; else ADG_ERR_UNSUPPORTED):
+ *   1. the unlimited step of adg_step gives a candidate in every cell;
+ *   2. a cell is troubled if the candidate fails the physical admissibility
+ *      test at a node or a subcell average, or the relaxed discrete maximum
+ *      principle: its subcell averages must lie within the range of the
+ *      subcell averages at t^n of the cell and its face neighbours, widened
+ *      by max(1e-4, 1e-3 * range) per variable;
+ *   3. troubled cells and their face neighbours take a MUSCL-Hancock step
+ *      (minmod slopes, Rusanov fluxes) on their m^dim subcells, m =
+ *      2 order + 1, from the subcell averages at t^n (for a cell that was
+ *      FV already, its FV data; else the averages of its polynomial), and
+ *      their DG polynomial becomes the least-squares fit of the result;
+ *   4. DG cells that share a face with an FV cell take the FV flux through
+ *      that face in place of the Rusanov flux of step 1, so the step
+ *      conserves what the PDE conserves.
+ * Q [C][nvar][S] device, in/out.  clock as for adg_step (t advances by dt;
+ * flags ADG_STEP_NEXT_DT evaluates Eq. (7) on the limited u^{n+1}).
+ * status [C] uint8 device, in/out: 0 DG, 1 DG with an FV face, 2 FV as a
+ * neighbour of a troubled cell, 3 troubled (FV); zero it before the first
+ * step (or mark cells that start on FV with 3 and give their data in
+ * sub_in).  sub_in, sub_out [C][nvar][m^dim] device, x fastest: the FV
+ * subcell averages at t^n and t^{n+1}; only the entries of cells with
+ * status >= 2 are read (sub_in, status before the step) or written
+ * (sub_out, status after it); they must be distinct arrays, and a run
+ * swaps them every step.  counts: device int32[3] (troubled cells, FV
+ * cells, DG cells with an FV face), or NULL.  The first call allocates the
+ * context's limiter workspace, about 1.4 state arrays plus 2 bytes and 24
+ * bytes per cell.  No host synchronisation. */
+adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
+                            uint8_t* status, int32_t* counts, int flags, void* stream);
 
 /* A-posteriori physical admissibility (Sec. 3.5): troubled[c] <- 1 if any
  * node of cell c is non-finite or fails the PDE's admissibility test, else

@@ -89,8 +89,20 @@ def lib():
         L.adg_sample_receivers.argtypes = [vp, vp, vp, vp]
         L.adg_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_sample_receivers_adjoint.argtypes = [vp, vp, vp, vp]
+        L.adg_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
+        L.adg_step_limited.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
         _lib = L
     return _lib
+
+
+def limiter_tables(order: int):
+    """Host-only: (A [m][n], B [n][m], Qf [n][m]) of the subcell limiter,
+    n = order + 1, m = 2 order + 1."""
+    n, m = order + 1, 2 * order + 1
+    A, B, Qf = np.zeros((m, n)), np.zeros((n, m)), np.zeros((n, m))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    _check(lib().adg_limiter_tables(order, dp(A), dp(B), dp(Qf)))
+    return A, B, Qf
 
 
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
@@ -98,7 +110,8 @@ EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create",
             "adg_predict",
             "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
-            "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint")
+            "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint",
+            "adg_limiter_tables", "adg_step_limited")
 
 
 def _check(st: int):
@@ -253,6 +266,27 @@ class Solver:
         out = (C.c_double * 2)()
         _check(lib().adg_read_clock_host(self._dev(clock, (2,), torch.float64, "clock"), out, _stream(stream)))
         return out[0], out[1]
+
+    @property
+    def subcell_shape(self):
+        """Shape of the FV subcell arrays of the subcell limiter."""
+        return (self.ncells, self.nvar, (2 * self.order + 1) ** self.dim)
+
+    def step_limited(self, Q, clock, sub_in, sub_out, status, counts=None, next_dt: bool = True,
+                     stream=None):
+        """One step with the a-posteriori subcell limiter (Euler): Q, status
+        (uint8 [ncells]) in place; sub_in / sub_out (subcell_shape) the FV
+        data before and after the step (distinct tensors, swapped by the
+        caller each step); counts (int32 [3]) or None."""
+        import torch
+        cnt = C.c_void_p() if counts is None else self._dev(counts, (3,), torch.int32, "counts")
+        _check(lib().adg_step_limited(
+            self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+            self._dev(clock, (2,), torch.float64, "clock"),
+            self._dev(sub_in, self.subcell_shape, torch.float64, "sub_in"),
+            self._dev(sub_out, self.subcell_shape, torch.float64, "sub_out"),
+            self._dev(status, (self.ncells,), torch.uint8, "status"), cnt,
+            STEP_NEXT_DT if next_dt else 0, _stream(stream)))
 
     def check_admissible(self, Q, params, troubled, count, stream=None):
         import torch

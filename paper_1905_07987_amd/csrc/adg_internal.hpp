@@ -80,6 +80,20 @@ struct KArgs {
   unsigned long long* slots;
 };
 
+// Workspace of a step with the a-posteriori subcell limiter (owned by the
+// context, allocated on first use).
+struct LimWork {
+  const double* tab;  // A [m][n], B [n][m], Qf [n][m] of the order (limiter_tables)
+  double* Qold;       // [C][nv][S]   u^n
+  uint8_t* st_prev;   // [C]          status at the start of the step
+  uint8_t* trb;       // [C]          troubled flags of this step
+  double* lohi;       // [C][nv][2]   range of the subcell averages at t^n
+  int* fv_list;       // [C]
+  int* y_list;        // [C]
+  int* counters;      // [4]: troubled cells, FV cells, DG cells with FV faces
+  double* gfv;        // [C][2 dim][nv][F] FV fluxes at the face nodes of FV cells
+};
+
 #if !defined(__HIPCC_RTC__)
 // Kernel entry points of one (PDE, dim, order) instantiation set.
 struct KernelSet {
@@ -106,6 +120,12 @@ struct KernelSet {
   // samples of u^{n+1}, or null.
   hipError_t (*step_fused)(const KArgs&, int precision, double* Q, const double* params, double* clock,
                            const double* tr_in, double* tr_out, double* rec_out, hipStream_t);
+  // The a-posteriori subcell limiter around an unlimited step (nullptr
+  // where not built): lim_before ahead of the step, lim_after behind it.
+  hipError_t (*lim_before)(const KArgs&, const double* Q, const double* sub_in, const uint8_t* status,
+                           const LimWork&, hipStream_t);
+  hipError_t (*lim_after)(const KArgs&, double* Q, const double* clock, const double* traces,
+                          const double* sub_in, double* sub_out, uint8_t* status, const LimWork&, hipStream_t);
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "adg_internal.hpp"
 
@@ -33,6 +34,9 @@ struct adg_ctx {
   int nrec = 0;
   bool traces_ready = false;  // workspace holds traces of a predict call
   UserModule* user = nullptr;  // kernels of a run-time PDE (ks is null then)
+  // subcell limiter workspace (allocated on the first limited step)
+  LimWork lim{};
+  void* lim_block = nullptr;
 };
 
 namespace {
@@ -147,6 +151,13 @@ adg_status adg_basis_tables(int order, double* xi, double* w, double* D, double*
   if (order < 0 || order + 1 > kMaxN) return fail(ADG_ERR_INVALID_ARG, "order out of range 0..7");
   if (basis_tables(order + 1, xi, w, D, l0, l1, K1inv) != 0)
     return fail(ADG_ERR_INVALID_ARG, "basis construction failed");
+  return ADG_OK;
+}
+
+adg_status adg_limiter_tables(int order, double* A, double* B, double* Qf) {
+  if (order < 0 || order + 1 > kBasisMaxN) return fail(ADG_ERR_INVALID_ARG, "order out of range");
+  if (!A || !B || !Qf) return fail(ADG_ERR_INVALID_ARG, "null output");
+  if (limiter_tables(order + 1, A, B, Qf)) return fail(ADG_ERR_INVALID_ARG, "limiter tables failed");
   return ADG_OK;
 }
 
@@ -377,6 +388,7 @@ adg_status adg_destroy(adg_ctx* ctx) {
   (void)hipFree(ctx->d_src_w);
   (void)hipFree(ctx->d_rec_cell);
   (void)hipFree(ctx->d_rec_w);
+  (void)hipFree(ctx->lim_block);
   user_module_destroy(ctx->user);
   (void)hipSetDevice(dev);
   delete ctx;
@@ -478,6 +490,71 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
   ctx->traces_ready = true;
   e = k_correct(ctx, Q, params, clock, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
+  return ADG_OK;
+}
+
+adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
+                            uint8_t* status, int32_t* counts, int flags, void* stream) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  if (!ctx->ks || !ctx->ks->lim_before || !ctx->ks->lim_after)
+    return fail(ADG_ERR_UNSUPPORTED,
+                "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
+  adg_status st = check_state(ctx, Q, nullptr);
+  if (st) return st;
+  if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  if (sub_in == sub_out) return fail(ADG_ERR_INVALID_ARG, "sub_in and sub_out must be different arrays");
+  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  const long long C = ctx->C;
+  const int nv = ctx->nv, S = ctx->S, n = ctx->n, m = 2 * n - 1;
+  if (!ctx->lim_block) {
+    // one allocation, each array on a 256-byte boundary
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t ntab = (size_t)3 * m * n;
+    const size_t sz[9] = {up(ntab * 8), up((size_t)C * nv * S * 8), up((size_t)C), up((size_t)C),
+                          up((size_t)C * nv * 2 * 8), up((size_t)C * 4), up((size_t)C * 4), up(4 * 4),
+                          up((size_t)C * 2 * ctx->dim * nv * ctx->F * 8)};
+    size_t total = 0;
+    for (size_t b : sz) total += b;
+    void* blk = nullptr;
+    ADG_HIP(hipMalloc(&blk, total));
+    std::vector<double> tab(ntab);
+    if (limiter_tables(n, tab.data(), tab.data() + m * n, tab.data() + 2 * m * n)) {
+      (void)hipFree(blk);
+      return fail(ADG_ERR_INVALID_ARG, "limiter tables failed");
+    }
+    hipError_t e = hipMemcpy(blk, tab.data(), ntab * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(blk);
+      return hip_fail(e, "limiter tables upload");
+    }
+    char* p = (char*)blk;
+    LimWork& w = ctx->lim;
+    w.tab = (const double*)p;   p += sz[0];
+    w.Qold = (double*)p;        p += sz[1];
+    w.st_prev = (uint8_t*)p;    p += sz[2];
+    w.trb = (uint8_t*)p;        p += sz[3];
+    w.lohi = (double*)p;        p += sz[4];
+    w.fv_list = (int*)p;        p += sz[5];
+    w.y_list = (int*)p;         p += sz[6];
+    w.counters = (int*)p;       p += sz[7];
+    w.gfv = (double*)p;
+    ctx->lim_block = blk;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ctx->ks->lim_before(ctx->args, Q, sub_in, status, ctx->lim, s);
+  if (e != hipSuccess) return hip_fail(e, "limiter prepare launch");
+  e = k_predict(ctx, Q, nullptr, clock, Q, ctx->traces, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "predict launch");
+  ctx->traces_ready = true;
+  e = k_correct(ctx, Q, nullptr, clock, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "correct launch");
+  e = ctx->ks->lim_after(ctx->args, Q, clock, ctx->traces, sub_in, sub_out, status, ctx->lim, s);
+  if (e != hipSuccess) return hip_fail(e, "limiter launch");
+  if (counts) ADG_HIP(hipMemcpyAsync(counts, ctx->lim.counters, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (flags & ADG_STEP_NEXT_DT) {
+    e = k_stable_dt(ctx, Q, nullptr, clock, s);
+    if (e != hipSuccess) return hip_fail(e, "stable_dt launch");
+  }
   return ADG_OK;
 }
 

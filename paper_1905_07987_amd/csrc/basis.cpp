@@ -138,4 +138,67 @@ int basis_tables(int n, double* xi, double* w, double* D, double* l0, double* l1
   return 0;
 }
 
+// The subcell averages come from the exact antiderivative of each Lagrange
+// polynomial, expanded in powers of y = x - 1/2; the least-squares inverse
+// from the Cholesky factorisation of A^T A.
+int limiter_tables(int n, double* A, double* B, double* Qf) {
+  if (n < 1 || n > kBasisMaxN) return -1;
+  const int m = 2 * n - 1;
+  ld x[kBasisMaxN], wt[kBasisMaxN], Al[2 * kBasisMaxN][kBasisMaxN];
+  gauss_legendre(n, x, wt);
+  for (int k = 0; k < n; ++k) {
+    ld c[kBasisMaxN + 1] = {1.0L};  // phi_k = sum_i c_i y^i
+    int deg = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == k) continue;
+      const ld yj = x[j] - 0.5L, den = x[k] - x[j];
+      for (int i = deg + 1; i >= 0; --i) c[i] = ((i > 0 ? c[i - 1] : 0.0L) - yj * (i <= deg ? c[i] : 0.0L)) / den;
+      ++deg;
+    }
+    auto prim = [&](ld y) {  // sum_i c_i y^{i+1} / (i+1)
+      ld in = 0.0L;
+      for (int i = deg; i >= 0; --i) in = in * y + c[i] / (i + 1);
+      return in * y;
+    };
+    for (int s = 0; s < m; ++s) Al[s][k] = m * (prim((ld)(s + 1) / m - 0.5L) - prim((ld)s / m - 0.5L));
+  }
+  ld G[kBasisMaxN][kBasisMaxN], L[kBasisMaxN][kBasisMaxN] = {};
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      ld g = 0.0L;
+      for (int s = 0; s < m; ++s) g += Al[s][i] * Al[s][j];
+      G[i][j] = g;
+    }
+  for (int j = 0; j < n; ++j) {
+    ld d = G[j][j];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0L)) return -1;
+    L[j][j] = sqrtl(d);
+    for (int i = j + 1; i < n; ++i) {
+      ld v = G[i][j];
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  for (int s = 0; s < m; ++s) {
+    ld y[kBasisMaxN], z[kBasisMaxN];
+    for (int i = 0; i < n; ++i) {  // L y = A[s]^T
+      ld v = Al[s][i];
+      for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+      y[i] = v / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L^T z = y
+      ld v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= L[k][i] * z[k];
+      z[i] = v / L[i][i];
+    }
+    for (int k = 0; k < n; ++k) {
+      if (A) A[s * n + k] = (double)Al[s][k];
+      if (B) B[k * m + s] = (double)z[k];
+      if (Qf) Qf[k * m + s] = (double)(Al[s][k] / (m * wt[k]));
+    }
+  }
+  return 0;
+}
+
 }  // namespace adg

@@ -1953,6 +1953,12 @@ namespace adg {
 // ---------------------------------------------------------------------------
 // Launchers and the per-(PDE, N) kernel set.
 // ---------------------------------------------------------------------------
+}  // namespace adg
+
+#include "limiter.hpp"
+
+namespace adg {
+
 template <class PDE, int N>
 struct Launch {
   using G = Geo<PDE, N>;
@@ -2062,10 +2068,18 @@ struct Launch {
     if constexpr (GeoAdjL<PDE, N>::supported) return &AdjLaunch<PDE, N>::run;
     else return nullptr;
   }
+  static constexpr decltype(KernelSet::lim_before) lim_before_entry() {
+    if constexpr (GeoLim<PDE, N>::built) return &LimLaunch<PDE, N>::before;
+    else return nullptr;
+  }
+  static constexpr decltype(KernelSet::lim_after) lim_after_entry() {
+    if constexpr (GeoLim<PDE, N>::built) return &LimLaunch<PDE, N>::after;
+    else return nullptr;
+  }
   static const KernelSet* set() {
     static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB,
                                  &predict, &correct, &stable_dt, &admissible, adjoint_entry(),
-                                 step_fused_entry()};
+                                 step_fused_entry(), lim_before_entry(), lim_after_entry()};
     return &ks;
   }
 };

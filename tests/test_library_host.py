@@ -54,3 +54,16 @@ def test_bad_order_is_an_error_not_a_crash():
     with pytest.raises(adg.AdgError) as e:
         adg.basis_tables(8)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("order", range(0, 8))
+def test_library_limiter_tables_match_oracle(order):
+    # two constructions that share nothing: exact antiderivatives of the
+    # monomial expansion and Cholesky (library) against subinterval Gauss
+    # quadrature and Gauss-Jordan on the normal equations (oracle)
+    A, B, Qf = adg.limiter_tables(order)
+    Ao, Bo, Qfo = O.limiter_tables(order + 1)
+    np.testing.assert_allclose(A, Ao, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(B, Bo, rtol=0, atol=1e-13 * max(1.0, np.abs(Bo).max()))
+    np.testing.assert_allclose(Qf, Qfo, rtol=0, atol=1e-14 * max(1.0, np.abs(Qfo).max()))
+    assert np.abs(B @ A - np.eye(order + 1)).max() < 1e-13
