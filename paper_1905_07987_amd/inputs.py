@@ -18,8 +18,11 @@ Workloads
       a Ricker point source (5 Hz) and 32 receivers, seed 7988.
   c4  3-D elasticity, N=3, 32^3 cells, same layering (seed 7989) and a
       +-5 % perturbed "observed" material (seed 7990).
-  c5  3-D Euler, N=3, 96^3 cells, spherical explosion (seed 7991): inside a
-      sphere rho = 1, E = 1, outside rho = 0.125, E = 0.1, j = 0.
+  c5  3-D Euler, N=3, 96^3 cells on [0,1]^3 with reflecting walls, spherical
+      explosion (seed 7991): inside a sphere of radius 0.2 with a random centre
+      in [0.3, 0.7]^3 rho = 1, E = 1, outside rho = 0.125, E = 0.1, j = 0;
+      run with the subcell limiter, the cells the sphere's surface crosses
+      starting on FV with their subcell values sampled at the subcell centres.
 """
 from __future__ import annotations
 
@@ -116,6 +119,33 @@ def blast_limited_start(xyz_nodes, xyz_sub, seed: int = 7991, radius: float = 0.
     fv = cut(Q) | cut(sub)
     sub[~fv] = 0.0
     return Q, sub, np.where(fv, 3, 0).astype(np.uint8)
+
+
+def blast_fv_cells(cells, lo, hi, order: int, seed: int = 7991, radius: float = 0.2):
+    """The same start for meshes whose subcell centres do not all fit in
+    host memory: the cells whose box the sphere's surface crosses start on
+    FV, and only their subcells are sampled.  Returns (fv cell indices,
+    sub [nfv][nv][m^dim] sampled at the subcell centres)."""
+    rng = np.random.default_rng(seed)
+    dim = len(cells)
+    centre = rng.uniform(0.3, 0.7, size=dim)          # the draw of blast_state
+    h = [(hi[d] - lo[d]) / cells[d] for d in range(dim)]
+    grids = np.meshgrid(*[np.arange(c) for c in cells[::-1]], indexing="ij")[::-1]
+    near = np.zeros(grids[0].shape)
+    far = np.zeros(grids[0].shape)
+    for d in range(dim):
+        a = lo[d] + grids[d] * h[d] - centre[d]
+        b = a + h[d]
+        near += np.maximum(0.0, np.maximum(a, -b)) ** 2
+        far += np.maximum(np.abs(a), np.abs(b)) ** 2
+    fv = np.flatnonzero(((near < radius * radius) & (far > radius * radius)).ravel())
+    m = 2 * order + 1
+    sidx = np.stack(np.meshgrid(*[np.arange(m)] * dim, indexing="ij")[::-1], -1).reshape(-1, dim)
+    cidx = np.stack([(fv // int(np.prod(cells[:d]))) % cells[d] for d in range(dim)], -1)
+    xs = np.empty((len(fv), len(sidx), dim))
+    for d in range(dim):
+        xs[..., d] = lo[d] + (cidx[:, None, d] + (sidx[None, :, d] + 0.5) / m) * h[d]
+    return fv, blast_state(xs, seed, radius)
 
 
 # ----------------------------------------------------------------- elasticity
