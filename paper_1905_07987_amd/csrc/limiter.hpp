@@ -46,13 +46,12 @@ struct GeoLim {
   static constexpr int EB = m + 4, NB = ipow(EB, DIM);  // subcells of the cell and two ghost layers
   static constexpr int EC = m + 2, NC = ipow(EC, DIM);  // subcells whose face values are moved
   static constexpr int NTAB = 3 * m * n;                // A [m][n], B [n][m], Qf [n][m]
-  static constexpr int BLOCK = 256;
+  static constexpr int BLOCK = 512;                     // threads of the FV kernel
   static constexpr int VPT = (NS + BLOCK - 1) / BLOCK;  // subcells per thread in the update
-  // prepare and detect: tables, nodal values, the contraction stages
-  static constexpr int PJ1 = NV * m * ipow(n, DIM - 1), PJ2 = DIM == 3 ? NV * m * m * n : 0;
-  static constexpr int PJ_D = NTAB + NV * S + PJ1 + PJ2 + NV * NS;
-  // fv: tables, the subcell box, the half-step corrections, the subface fluxes
-  static constexpr int FV_D = NTAB + NV * (NB + NC + 2 * DIM * NSF);
+  static constexpr int NOWN = DIM == 3 ? 19 : 9;        // the cell, its face and edge neighbours
+  // fv: tables, the subcell box, then either the owners' nodal values (while
+  // the box is filled) or the half-step corrections and the subface fluxes
+  static constexpr int FV_D = NTAB + NV * NB + cmax(NV * (NC + 2 * DIM * NSF), NOWN * NV * S);
   static constexpr bool built = LimiterPDE<PDE>::value && FV_D * 8 + NC <= 120 * 1024;
 };
 
@@ -77,160 +76,221 @@ __device__ __forceinline__ long long lim_neighbour(const KArgs& a, long long c, 
   return cc[0] + (long long)C0 * (cc[1] + (long long)C1 * cc[2]);
 }
 
-// One contraction stage of the projection onto the subcells: axis ax of the
-// tensor in[NV][e2][e1][e0] (x fastest) goes from extent ein to mo through
-// M[mo][ein].
-template <int BLOCK>
-__device__ __forceinline__ void lim_stage(const double* in, double* out, int nv, int e0, int e1, int e2, int ax,
-                                          int mo, const double* M, int tid) {
-  const int ein = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
-  const int o0 = ax == 0 ? mo : e0, o1 = ax == 1 ? mo : e1, o2 = ax == 2 ? mo : e2;
-  const int per = o0 * o1 * o2, stride = ax == 0 ? 1 : (ax == 1 ? e0 : e0 * e1);
-  for (int i = tid; i < nv * per; i += BLOCK) {
-    const int v = i / per, r = i - v * per;
-    const int x0 = r % o0, x1 = (r / o0) % o1, x2 = r / (o0 * o1);
-    const int xo = ax == 0 ? x0 : (ax == 1 ? x1 : x2);
-    const double* src = in + v * (e0 * e1 * e2) + (ax == 0 ? 0 : x0) + e0 * ((ax == 1 ? 0 : x1) + e1 * (ax == 2 ? 0 : x2));
+__device__ __forceinline__ void lim_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One contraction stage of the projection onto the subcells, on one wave:
+// axis AX of in[NVS][E2][E1][E0] (x fastest) goes from its extent to MO
+// through M[MO][extent].
+template <int NVS, int E0, int E1, int E2, int AX, int MO>
+__device__ __forceinline__ void lim_stage(const double* in, double* out, const double* M, int lane) {
+  constexpr int EIN = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
+  constexpr int O0 = AX == 0 ? MO : E0, O1 = AX == 1 ? MO : E1, O2 = AX == 2 ? MO : E2;
+  constexpr int PER = O0 * O1 * O2, STRIDE = AX == 0 ? 1 : (AX == 1 ? E0 : E0 * E1);
+  for (int i = lane; i < NVS * PER; i += 64) {
+    const int v = i / PER, r = i - v * PER;
+    const int x0 = r % O0, x1 = (r / O0) % O1, x2 = r / (O0 * O1);
+    const int xo = AX == 0 ? x0 : (AX == 1 ? x1 : x2);
+    const double* src =
+        in + v * (E0 * E1 * E2) + (AX == 0 ? 0 : x0) + E0 * ((AX == 1 ? 0 : x1) + E1 * (AX == 2 ? 0 : x2));
     double acc = 0.0;
-    for (int k = 0; k < ein; ++k) acc += M[xo * ein + k] * src[k * stride];
+#pragma unroll
+    for (int k = 0; k < EIN; ++k) acc += M[xo * EIN + k] * src[k * STRIDE];
     out[i] = acc;
   }
 }
 
-// Subcell averages of the nodal values u[NV][S] (LDS) into out[NV][NS].
+// Per-wave LDS of the prepare and detect kernels: the cell's nodal values
+// and the contraction stages of the projection onto the subcells (the last
+// stage is evaluated in registers, one subcell per lane at a time).  Region
+// A holds the nodal values, later the second stage (3-D); region B the
+// first stage.
 template <class PDE, int N>
-__device__ __forceinline__ void lim_project_block(const double* T, const double* u, double* t1, double* t2,
-                                                  double* out, int tid) {
+struct GeoLimW {
+  using GL = GeoLim<PDE, N>;
+  static constexpr int WPB = 4;  // cells (waves) per block
+  static constexpr int P1 = GL::NV * GL::m * ipow(GL::n, GL::DIM - 1);
+  static constexpr int P2 = GL::DIM == 3 ? GL::NV * GL::m * GL::m * GL::n : 0;
+  static constexpr int RA = cmax(GL::NV * GL::S, P2), RB = P1;
+  static constexpr int PW = RA + RB;
+};
+
+// The subcell averages of one cell: the first stages into LDS (u in A ->
+// B (-> A in 3-D)), then out(s) = the last stage at subcell s for every
+// variable.
+template <class PDE, int N>
+__device__ __forceinline__ void lim_stages_wave(const double* A, double* ra, double* rb, int lane) {
   using GL = GeoLim<PDE, N>;
   constexpr int n = GL::n, m = GL::m, NV = GL::NV;
   if constexpr (GL::DIM == 2) {
-    lim_stage<GL::BLOCK>(u, t1, NV, n, n, 1, 0, m, T, tid);
-    __syncthreads();
-    lim_stage<GL::BLOCK>(t1, out, NV, m, n, 1, 1, m, T, tid);
+    lim_stage<NV, n, n, 1, 0, m>(ra, rb, A, lane);
   } else {
-    lim_stage<GL::BLOCK>(u, t1, NV, n, n, n, 0, m, T, tid);
-    __syncthreads();
-    lim_stage<GL::BLOCK>(t1, t2, NV, m, n, n, 1, m, T, tid);
-    __syncthreads();
-    lim_stage<GL::BLOCK>(t2, out, NV, m, m, n, 2, m, T, tid);
+    lim_stage<NV, n, n, n, 0, m>(ra, rb, A, lane);
+    lim_wave_sync();
+    lim_stage<NV, m, n, n, 1, m>(rb, ra, A, lane);
   }
-  __syncthreads();
+  lim_wave_sync();
 }
 
-// Block-wide min and max of (lo, hi); the result is valid in thread 0.
-template <int BLOCK>
-__device__ __forceinline__ void lim_minmax(double& lo, double& hi, double* red) {
-  red[threadIdx.x] = lo;
-  red[BLOCK + threadIdx.x] = hi;
-  __syncthreads();
-  for (int off = BLOCK / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-      red[BLOCK + threadIdx.x] = fmax(red[BLOCK + threadIdx.x], red[BLOCK + threadIdx.x + off]);
+template <class PDE, int N>
+__device__ __forceinline__ void lim_last_stage(const double* A, const double* ra, const double* rb, int s,
+                                               double (&out)[PDE::NV]) {
+  using GL = GeoLim<PDE, N>;
+  constexpr int n = GL::n, m = GL::m, NV = GL::NV;
+  if constexpr (GL::DIM == 2) {
+    const int sx = s % m, sy = s / m;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += A[sy * n + k] * rb[(v * n + k) * m + sx];
+      out[v] = acc;
     }
-    __syncthreads();
+  } else {
+    const int sx = s % m, sy = (s / m) % m, sz = s / (m * m);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += A[sz * n + k] * ra[((v * n + k) * m + sy) * m + sx];
+      out[v] = acc;
+    }
   }
-  lo = red[0];
-  hi = red[BLOCK];
-  __syncthreads();
 }
 
-// One block per cell: u^n copied, status kept, range of the subcell
+__device__ __forceinline__ double lim_wave_min(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ double lim_wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// One wave per cell: u^n copied, status kept, range of the subcell
 // averages at t^n.  Block 0 clears the counters of the step.
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ sub_in,
                    const uint8_t* __restrict__ status, const LimWork w) {
   using GL = GeoLim<PDE, N>;
-  constexpr int NV = GL::NV, S = GL::S, NS = GL::NS, BLOCK = GL::BLOCK;
-  __shared__ double lds[GL::PJ_D];
-  __shared__ double red[2 * BLOCK];
-  double* T = lds;
-  double* u = T + GL::NTAB;
-  double* t1 = u + NV * S;
-  double* t2 = t1 + GL::PJ1;
-  double* pv = t2 + GL::PJ2;
-  const int tid = threadIdx.x;
-  const long long c = blockIdx.x;
-  if (c == 0 && tid < 4) w.counters[tid] = 0;
-  for (int i = tid; i < GL::NTAB; i += BLOCK) T[i] = w.tab[i];
-  for (int i = tid; i < NV * S; i += BLOCK) {
+  using GW = GeoLimW<PDE, N>;
+  constexpr int NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
+  __shared__ double Atab[m * n];
+  __shared__ double buf[GW::WPB][GW::PW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (blockIdx.x == 0 && tid < 4) w.counters[tid] = 0;
+  for (int i = tid; i < m * n; i += blockDim.x) Atab[i] = w.tab[i];
+  __syncthreads();
+  const long long c = (long long)blockIdx.x * GW::WPB + wv;
+  if (c >= a.ncells) return;
+  double* ra = buf[wv];
+  double* rb = ra + GW::RA;
+  for (int i = lane; i < NV * S; i += 64) {
     const double x = Q[c * NV * S + i];
-    u[i] = x;
     w.Qold[c * NV * S + i] = x;
+    ra[i] = x;
   }
   const uint8_t st = status[c];
-  if (tid == 0) w.st_prev[c] = st;
-  __syncthreads();
-  const double* W = pv;
-  if (st >= 2) W = sub_in + c * NV * NS;
-  else lim_project_block<PDE, N>(T, u, t1, t2, pv, tid);
+  if (lane == 0) w.st_prev[c] = st;
+  double lo[NV], hi[NV];
+#pragma unroll
   for (int v = 0; v < NV; ++v) {
-    double lo = INFINITY, hi = -INFINITY;
-    for (int s = tid; s < NS; s += BLOCK) {
-      lo = fmin(lo, W[v * NS + s]);
-      hi = fmax(hi, W[v * NS + s]);
+    lo[v] = INFINITY;
+    hi[v] = -INFINITY;
+  }
+  if (st >= 2) {
+    for (int s = lane; s < NS; s += 64)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double x = sub_in[(c * NV + v) * NS + s];
+        lo[v] = fmin(lo[v], x);
+        hi[v] = fmax(hi[v], x);
+      }
+  } else {
+    lim_wave_sync();
+    lim_stages_wave<PDE, N>(Atab, ra, rb, lane);
+    for (int s = lane; s < NS; s += 64) {
+      double q[NV];
+      lim_last_stage<PDE, N>(Atab, ra, rb, s, q);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lo[v] = fmin(lo[v], q[v]);
+        hi[v] = fmax(hi[v], q[v]);
+      }
     }
-    lim_minmax<BLOCK>(lo, hi, red);
-    if (tid == 0) {
-      w.lohi[(c * NV + v) * 2] = lo;
-      w.lohi[(c * NV + v) * 2 + 1] = hi;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double l = lim_wave_min(lo[v]), h = lim_wave_max(hi[v]);
+    if (lane == 0) {
+      w.lohi[(c * NV + v) * 2] = l;
+      w.lohi[(c * NV + v) * 2 + 1] = h;
     }
   }
 }
 
-// One block per cell: is the candidate troubled?
+// One wave per cell: is the candidate troubled?
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) {
   using GL = GeoLim<PDE, N>;
-  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS, BLOCK = GL::BLOCK;
-  __shared__ double lds[GL::PJ_D];
-  __shared__ double bounds[NV][2];
-  double* T = lds;
-  double* u = T + GL::NTAB;
-  double* t1 = u + NV * S;
-  double* t2 = t1 + GL::PJ1;
-  double* pv = t2 + GL::PJ2;
-  const int tid = threadIdx.x;
-  const long long c = blockIdx.x;
-  for (int i = tid; i < GL::NTAB; i += BLOCK) T[i] = w.tab[i];
-  for (int i = tid; i < NV * S; i += BLOCK) u[i] = Q[c * NV * S + i];
-  if (tid < NV) {
-    double lo = w.lohi[(c * NV + tid) * 2], hi = w.lohi[(c * NV + tid) * 2 + 1];
-    for (int d = 0; d < DIM; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        const long long o = lim_neighbour<DIM>(a, c, d, s);
-        if (o < 0) continue;
-        lo = fmin(lo, w.lohi[(o * NV + tid) * 2]);
-        hi = fmax(hi, w.lohi[(o * NV + tid) * 2 + 1]);
-      }
-    bounds[tid][0] = lo;
-    bounds[tid][1] = hi;
-  }
+  using GW = GeoLimW<PDE, N>;
+  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
+  __shared__ double Atab[m * n];
+  __shared__ double buf[GW::WPB][GW::PW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < m * n; i += blockDim.x) Atab[i] = w.tab[i];
   __syncthreads();
+  const long long c = (long long)blockIdx.x * GW::WPB + wv;
+  if (c >= a.ncells) return;
+  double* ra = buf[wv];
+  double* rb = ra + GW::RA;
+  for (int i = lane; i < NV * S; i += 64) ra[i] = Q[c * NV * S + i];
+  // DMP range: the cell's and its face neighbours' subcell averages at t^n
+  double lo[NV], hi[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    lo[v] = w.lohi[(c * NV + v) * 2];
+    hi[v] = w.lohi[(c * NV + v) * 2 + 1];
+  }
+  for (int d = 0; d < DIM; ++d)
+    for (int sd = -1; sd <= 1; sd += 2) {
+      const long long o = lim_neighbour<DIM>(a, c, d, sd);
+      if (o < 0) continue;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lo[v] = fmin(lo[v], w.lohi[(o * NV + v) * 2]);
+        hi[v] = fmax(hi[v], w.lohi[(o * NV + v) * 2 + 1]);
+      }
+    }
+  lim_wave_sync();
   bool bad = false;
-  for (int k = tid; k < S; k += BLOCK) {
+  for (int k = lane; k < S; k += 64) {
     double q[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = u[v * S + k];
+    for (int v = 0; v < NV; ++v) q[v] = ra[v * S + k];
     bad = bad || !PDE::admissible(q, q, a.pde);
   }
-  lim_project_block<PDE, N>(T, u, t1, t2, pv, tid);
-  for (int s = tid; s < NS; s += BLOCK) {
+  lim_wave_sync();
+  lim_stages_wave<PDE, N>(Atab, ra, rb, lane);
+  for (int s = lane; s < NS; s += 64) {
     double q[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = pv[v * NS + s];
+    lim_last_stage<PDE, N>(Atab, ra, rb, s, q);
     bad = bad || !PDE::admissible(q, q, a.pde);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double lo = bounds[v][0], hi = bounds[v][1];
-      const double delta = fmax(1e-4, 1e-3 * (hi - lo));
-      bad = bad || !(q[v] >= lo - delta && q[v] <= hi + delta);
+      const double delta = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
+      bad = bad || !(q[v] >= lo[v] - delta && q[v] <= hi[v] + delta);
     }
   }
-  bad = __syncthreads_or(bad);
-  if (tid == 0) {
+  bad = __ballot(bad) != 0;
+  if (lane == 0) {
     w.trb[c] = bad ? 1 : 0;
     if (bad) atomicAdd(&w.counters[0], 1);
   }
@@ -273,54 +333,6 @@ __device__ __forceinline__ double lim_minmod(double x, double y) {
   return 0.0;
 }
 
-// The subcell average at t^n of a subcell box position whose global subcell
-// index is g: the owner's FV data, or the projection of its DG polynomial.
-template <class PDE, int N>
-__device__ __forceinline__ void lim_ghost_value(const KArgs& a, const double* T, const double* __restrict__ Qold,
-                                                const double* __restrict__ sub_in,
-                                                const uint8_t* __restrict__ st_prev, const int (&gin)[3],
-                                                double (&out)[PDE::NV]) {
-  using GL = GeoLim<PDE, N>;
-  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
-  int g[3] = {gin[0], gin[1], gin[2]}, cc[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
-  bool flip[3] = {false, false, false};
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int G = m * a.cells[d];
-    if (g[d] < 0 || g[d] >= G) {
-      const int side = g[d] >= G, kind = a.bc[2 * d + side];
-      if (kind == ADG_BC_PERIODIC) {
-        g[d] = ((g[d] % G) + G) % G;
-      } else {
-        g[d] = side ? 2 * G - 1 - g[d] : -1 - g[d];
-        flip[d] = kind == ADG_BC_WALL;
-      }
-    }
-    cc[d] = g[d] / m;
-    ss[d] = g[d] - cc[d] * m;
-  }
-  const long long o = cc[0] + (long long)a.cells[0] * (cc[1] + (long long)a.cells[1] * cc[2]);
-  if (st_prev[o] >= 2) {
-    const int si = ss[0] + m * (ss[1] + m * ss[2]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = sub_in[(o * NV + v) * NS + si];
-  } else {
-    const double* u = Qold + o * NV * S;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    for (int k = 0; k < S; ++k) {
-      const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
-      double c = T[ss[0] * n + kx] * T[ss[1] * n + ky];
-      if (DIM == 3) c *= T[ss[2] * n + kz];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v] += c * u[v * S + k];
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < DIM; ++d)
-    if (flip[d]) out[1 + d] = -out[1 + d];
-}
-
 // Rusanov flux along d between the states qa (low side) and qb (high side).
 template <class PDE>
 __device__ __forceinline__ void lim_rusanov(const PdeConsts& pc, int d, const double* qa, const double* qb,
@@ -357,7 +369,7 @@ __device__ __forceinline__ void lim_moved(const double* box, const double* corr,
 
 // FV cells, a persistent grid over the FV list.
 template <class PDE, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __restrict__ sub_in, double* __restrict__ Q,
               double* __restrict__ sub_out, const LimWork w) {
   using GL = GeoLim<PDE, N>;
@@ -365,10 +377,13 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
   constexpr int m = GL::m, n = GL::n, EB = GL::EB, NB = GL::NB, EC = GL::EC, NC = GL::NC, BLOCK = GL::BLOCK;
   __shared__ double lds[GL::FV_D];
   __shared__ uint8_t okf[NC];
+  __shared__ long long owner[GL::NOWN];  // owner cell of each slot, -1 beyond a non-periodic face
+  __shared__ uint8_t fvdata[GL::NOWN];   // the owner was FV at t^n: its subcell data is read
   double* T = lds;
   double* box = T + GL::NTAB;
   double* corr = box + NV * NB;
   double* fsub = corr + NV * NC;
+  double* ou = corr;  // the owners' nodal values, only while the box is filled
   const double* A = T;
   const double* B = T + m * n;
   const double* Qf = T + 2 * m * n;
@@ -385,21 +400,90 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
     const int cc[3] = {(int)(c % C0), (int)((c / C0) % C1), DIM == 3 ? (int)(c / ((long long)C0 * C1)) : 0};
     __syncthreads();  // the previous cell's LDS reads are done
     // 1. the subcell box: the cell, two ghost layers across each face, one
-    //    across each edge (corners are never read)
+    //    across each edge (corners are never read).  Every position belongs
+    //    to the cell or to a face or edge neighbour (beyond a non-periodic
+    //    face it mirrors a subcell of the cell on this side, the wall
+    //    reversing the normal momentum).  The owners' nodal values are
+    //    staged in LDS first (owner slot: the offset's rank among the
+    //    offsets in {-1,0,1}^dim with at most two nonzero entries).
+    if (tid == 0) {
+      int slot = 0;
+      for (int k = 0; k < ipow(3, DIM); ++k) {
+        const int off[3] = {k % 3 - 1, (k / 3) % 3 - 1, DIM == 3 ? k / 9 - 1 : 0};
+        if ((off[0] != 0) + (off[1] != 0) + (off[2] != 0) > 2) continue;
+        int oc[3] = {cc[0], cc[1], cc[2]};
+        bool exists = true;
+        for (int d = 0; d < DIM; ++d) {
+          oc[d] += off[d];
+          if (oc[d] < 0 || oc[d] >= a.cells[d]) {
+            if (a.bc[2 * d + (off[d] > 0)] != ADG_BC_PERIODIC) exists = false;
+            oc[d] = (oc[d] + a.cells[d]) % a.cells[d];
+          }
+        }
+        const long long o = exists ? oc[0] + (long long)C0 * (oc[1] + (long long)C1 * oc[2]) : -1;
+        owner[slot] = o;
+        fvdata[slot] = (exists && w.st_prev[o] >= 2) ? 1 : 0;
+        ++slot;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < GL::NOWN * NV * S; i += BLOCK) {
+      const int slot = i / (NV * S), j = i - slot * NV * S;
+      if (owner[slot] >= 0 && !fvdata[slot]) ou[i] = w.Qold[owner[slot] * NV * S + j];
+    }
+    __syncthreads();
     for (int p = tid; p < NB; p += BLOCK) {
       int x[3];
       lim_multi<DIM>(p, EB, x);
-      int outside = 0, far = 0, g[3] = {0, 0, 0};
+      int outside = 0, far = 0, po[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+      bool flip[3] = {false, false, false};
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const int r = x[d] - 2;
-        if (r < 0 || r >= m) ++outside;
+        if (r < 0 || r >= m) {
+          ++outside;
+          const int side = r >= m, to = cc[d] + (side ? 1 : -1);
+          if ((to < 0 || to >= a.cells[d]) && a.bc[2 * d + side] != ADG_BC_PERIODIC) {
+            ss[d] = side ? 2 * m - 1 - r : -1 - r;
+            flip[d] = a.bc[2 * d + side] == ADG_BC_WALL;
+          } else {
+            po[d] = side ? 1 : -1;
+            ss[d] = r - po[d] * m;
+          }
+        } else {
+          ss[d] = r;
+        }
         if (r < -1 || r > m) ++far;
-        g[d] = cc[d] * m + r;
       }
       if (outside > 2 || (outside == 2 && far > 0)) continue;
+      // slot of the offset po
+      const int kpo = (po[0] + 1) + 3 * (po[1] + 1) + (DIM == 3 ? 9 * (po[2] + 1) : 0);
+      int slot = 0;
+      for (int k = 0; k < kpo; ++k) {
+        const int a0 = k % 3 - 1, a1 = (k / 3) % 3 - 1, a2 = DIM == 3 ? k / 9 - 1 : 0;
+        slot += ((a0 != 0) + (a1 != 0) + (a2 != 0) > 2) ? 0 : 1;
+      }
+      const long long o = owner[slot];
       double val[NV];
-      lim_ghost_value<PDE, N>(a, T, w.Qold, sub_in, w.st_prev, g, val);
+      if (fvdata[slot]) {
+        const int si = ss[0] + m * (ss[1] + m * ss[2]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) val[v] = sub_in[(o * NV + v) * NS + si];
+      } else {
+        const double* uo = ou + slot * NV * S;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) val[v] = 0.0;
+        for (int kk = 0; kk < S; ++kk) {
+          const int kx = kk % n, ky = (kk / n) % n, kz = DIM == 3 ? kk / (n * n) : 0;
+          double cf = A[ss[0] * n + kx] * A[ss[1] * n + ky];
+          if (DIM == 3) cf *= A[ss[2] * n + kz];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) val[v] += cf * uo[v * S + kk];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        if (flip[d]) val[1 + d] = -val[1 + d];
 #pragma unroll
       for (int v = 0; v < NV; ++v) box[v * NB + p] = val[v];
     }
@@ -548,7 +632,7 @@ __global__ void __launch_bounds__(256)
 lim_faces_kernel(const KArgs a, const double* __restrict__ clock, const double* __restrict__ traces,
                  const uint8_t* __restrict__ status, double* __restrict__ Q, const LimWork w) {
   using GL = GeoLim<PDE, N>;
-  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, F = GL::F, n = GL::n, BLOCK = GL::BLOCK;
+  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, F = GL::F, n = GL::n, BLOCK = 256;
   const Tables<double>& T = a.t64;
   const double dt = clock[1];
   const int count = w.counters[2];
@@ -592,7 +676,8 @@ struct LimLaunch {
   // prepare; the caller's DG step follows
   static hipError_t before(const KArgs& a, const double* Q, const double* sub_in, const uint8_t* status,
                            const LimWork& w, hipStream_t st) {
-    hipLaunchKernelGGL((lim_prepare_kernel<PDE, N>), dim3((unsigned)a.ncells), dim3(GL::BLOCK), 0, st, a, Q,
+    const unsigned grid = (unsigned)((a.ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
+    hipLaunchKernelGGL((lim_prepare_kernel<PDE, N>), dim3(grid), dim3(64 * GeoLimW<PDE, N>::WPB), 0, st, a, Q,
                        sub_in, status, w);
     return hipGetLastError();
   }
@@ -600,7 +685,8 @@ struct LimLaunch {
   static hipError_t after(const KArgs& a, double* Q, const double* clock, const double* traces,
                           const double* sub_in, double* sub_out, uint8_t* status, const LimWork& w,
                           hipStream_t st) {
-    hipLaunchKernelGGL((lim_detect_kernel<PDE, N>), dim3((unsigned)a.ncells), dim3(GL::BLOCK), 0, st, a, Q, w);
+    const unsigned grid = (unsigned)((a.ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
+    hipLaunchKernelGGL((lim_detect_kernel<PDE, N>), dim3(grid), dim3(64 * GeoLimW<PDE, N>::WPB), 0, st, a, Q, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((lim_classify_kernel<GL::DIM>), dim3((unsigned)((a.ncells + 255) / 256)), dim3(256), 0, st,
@@ -609,7 +695,7 @@ struct LimLaunch {
     hipLaunchKernelGGL((lim_fv_kernel<PDE, N>), dim3(kFvGrid), dim3(GL::BLOCK), 0, st, a, clock, sub_in, Q,
                        sub_out, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((lim_faces_kernel<PDE, N>), dim3(kFaceGrid), dim3(GL::BLOCK), 0, st, a, clock, traces,
+    hipLaunchKernelGGL((lim_faces_kernel<PDE, N>), dim3(kFaceGrid), dim3(256), 0, st, a, clock, traces,
                        status, Q, w);
     return hipGetLastError();
   }
