@@ -82,32 +82,12 @@ __device__ __forceinline__ void lim_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One contraction stage of the projection onto the subcells, on one wave:
-// axis AX of in[NVS][E2][E1][E0] (x fastest) goes from its extent to MO
-// through M[MO][extent].
-template <int NVS, int E0, int E1, int E2, int AX, int MO>
-__device__ __forceinline__ void lim_stage(const double* in, double* out, const double* M, int lane) {
-  constexpr int EIN = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
-  constexpr int O0 = AX == 0 ? MO : E0, O1 = AX == 1 ? MO : E1, O2 = AX == 2 ? MO : E2;
-  constexpr int PER = O0 * O1 * O2, STRIDE = AX == 0 ? 1 : (AX == 1 ? E0 : E0 * E1);
-  for (int i = lane; i < NVS * PER; i += 64) {
-    const int v = i / PER, r = i - v * PER;
-    const int x0 = r % O0, x1 = (r / O0) % O1, x2 = r / (O0 * O1);
-    const int xo = AX == 0 ? x0 : (AX == 1 ? x1 : x2);
-    const double* src =
-        in + v * (E0 * E1 * E2) + (AX == 0 ? 0 : x0) + E0 * ((AX == 1 ? 0 : x1) + E1 * (AX == 2 ? 0 : x2));
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < EIN; ++k) acc += M[xo * EIN + k] * src[k * STRIDE];
-    out[i] = acc;
-  }
-}
-
 // Per-wave LDS of the prepare and detect kernels: the cell's nodal values
 // and the contraction stages of the projection onto the subcells (the last
-// stage is evaluated in registers, one subcell per lane at a time).  Region
+// stage is evaluated in registers, one line of subcells per lane).  Region
 // A holds the nodal values, later the second stage (3-D); region B the
-// first stage.
+// first stage.  The subcell averages of the basis, LimConst<n>::A, are
+// compile-time constants.
 template <class PDE, int N>
 struct GeoLimW {
   using GL = GeoLim<PDE, N>;
@@ -116,47 +96,72 @@ struct GeoLimW {
   static constexpr int P2 = GL::DIM == 3 ? GL::NV * GL::m * GL::m * GL::n : 0;
   static constexpr int RA = cmax(GL::NV * GL::S, P2), RB = P1;
   static constexpr int PW = RA + RB;
+  // lines of the last stage (one per lane): subcell columns along the last axis
+  static constexpr int LAST = ipow(GL::m, GL::DIM - 1);
 };
 
-// The subcell averages of one cell: the first stages into LDS (u in A ->
-// B (-> A in 3-D)), then out(s) = the last stage at subcell s for every
-// variable.
+// The leading stages, one line per lane and step: along x (nodal values in
+// A, [v][kz][ky][kx], to B, [v][kz][ky][sx]); in 3-D then along y (B to A,
+// [v][kz][sy][sx]).
 template <class PDE, int N>
-__device__ __forceinline__ void lim_stages_wave(const double* A, double* ra, double* rb, int lane) {
+__device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane) {
   using GL = GeoLim<PDE, N>;
+  using LC = LimConst<GL::n>;
   constexpr int n = GL::n, m = GL::m, NV = GL::NV;
-  if constexpr (GL::DIM == 2) {
-    lim_stage<NV, n, n, 1, 0, m>(ra, rb, A, lane);
-  } else {
-    lim_stage<NV, n, n, n, 0, m>(ra, rb, A, lane);
-    lim_wave_sync();
-    lim_stage<NV, m, n, n, 1, m>(rb, ra, A, lane);
+  constexpr int L1 = NV * ipow(n, GL::DIM - 1);
+  for (int line = lane; line < L1; line += 64) {
+    double in[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) in[k] = ra[line * n + k];
+#pragma unroll
+    for (int s = 0; s < m; ++s) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc += LC::A[s][k] * in[k];
+      rb[line * m + s] = acc;
+    }
   }
   lim_wave_sync();
+  if constexpr (GL::DIM == 3) {
+    constexpr int L2 = NV * n * m;
+    for (int line = lane; line < L2; line += 64) {
+      const int sx = line % m, vk = line / m;  // vk = v n + kz
+      double in[n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) in[k] = rb[(vk * n + k) * m + sx];
+#pragma unroll
+      for (int s = 0; s < m; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc += LC::A[s][k] * in[k];
+        ra[(vk * m + s) * m + sx] = acc;
+      }
+    }
+    lim_wave_sync();
+  }
 }
 
+// The last stage for the column of subcells `col` along the last axis:
+// out[v][j] = the average of variable v over the j-th subcell of the column
+// (subcell index col + j m^(dim-1)).
 template <class PDE, int N>
-__device__ __forceinline__ void lim_last_stage(const double* A, const double* ra, const double* rb, int s,
-                                               double (&out)[PDE::NV]) {
+__device__ __forceinline__ void lim_last_stage(const double* ra, const double* rb, int col,
+                                               double (&out)[PDE::NV][2 * N + 1]) {
   using GL = GeoLim<PDE, N>;
+  using LC = LimConst<GL::n>;
   constexpr int n = GL::n, m = GL::m, NV = GL::NV;
-  if constexpr (GL::DIM == 2) {
-    const int sx = s % m, sy = s / m;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+  for (int v = 0; v < NV; ++v) {
+    double in[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+      in[k] = GL::DIM == 2 ? rb[(v * n + k) * m + col] : ra[(v * n + k) * m * m + col];
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) acc += A[sy * n + k] * rb[(v * n + k) * m + sx];
-      out[v] = acc;
-    }
-  } else {
-    const int sx = s % m, sy = (s / m) % m, sz = s / (m * m);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < n; ++k) acc += A[sz * n + k] * ra[((v * n + k) * m + sy) * m + sx];
-      out[v] = acc;
+      for (int k = 0; k < n; ++k) acc += LC::A[j][k] * in[k];
+      out[v][j] = acc;
     }
   }
 }
@@ -181,12 +186,9 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   using GL = GeoLim<PDE, N>;
   using GW = GeoLimW<PDE, N>;
   constexpr int NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
-  __shared__ double Atab[m * n];
   __shared__ double buf[GW::WPB][GW::PW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (blockIdx.x == 0 && tid < 4) w.counters[tid] = 0;
-  for (int i = tid; i < m * n; i += blockDim.x) Atab[i] = w.tab[i];
-  __syncthreads();
   const long long c = (long long)blockIdx.x * GW::WPB + wv;
   if (c >= a.ncells) return;
   double* ra = buf[wv];
@@ -214,15 +216,17 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
       }
   } else {
     lim_wave_sync();
-    lim_stages_wave<PDE, N>(Atab, ra, rb, lane);
-    for (int s = lane; s < NS; s += 64) {
-      double q[NV];
-      lim_last_stage<PDE, N>(Atab, ra, rb, s, q);
+    lim_stages_wave<PDE, N>(ra, rb, lane);
+    for (int col = lane; col < GW::LAST; col += 64) {
+      double q[NV][m];
+      lim_last_stage<PDE, N>(ra, rb, col, q);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        lo[v] = fmin(lo[v], q[v]);
-        hi[v] = fmax(hi[v], q[v]);
-      }
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+          lo[v] = fmin(lo[v], q[v][j]);
+          hi[v] = fmax(hi[v], q[v][j]);
+        }
     }
   }
 #pragma unroll
@@ -242,11 +246,8 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
   using GL = GeoLim<PDE, N>;
   using GW = GeoLimW<PDE, N>;
   constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
-  __shared__ double Atab[m * n];
   __shared__ double buf[GW::WPB][GW::PW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < m * n; i += blockDim.x) Atab[i] = w.tab[i];
-  __syncthreads();
   const long long c = (long long)blockIdx.x * GW::WPB + wv;
   if (c >= a.ncells) return;
   double* ra = buf[wv];
@@ -278,15 +279,21 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
     bad = bad || !PDE::admissible(q, q, a.pde);
   }
   lim_wave_sync();
-  lim_stages_wave<PDE, N>(Atab, ra, rb, lane);
-  for (int s = lane; s < NS; s += 64) {
-    double q[NV];
-    lim_last_stage<PDE, N>(Atab, ra, rb, s, q);
-    bad = bad || !PDE::admissible(q, q, a.pde);
+  lim_stages_wave<PDE, N>(ra, rb, lane);
+  double delta[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double delta = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
-      bad = bad || !(q[v] >= lo[v] - delta && q[v] <= hi[v] + delta);
+  for (int v = 0; v < NV; ++v) delta[v] = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
+  for (int col = lane; col < GW::LAST; col += 64) {
+    double qv[NV][m];
+    lim_last_stage<PDE, N>(ra, rb, col, qv);
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      double q[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] = qv[v][j];
+      bad = bad || !PDE::admissible(q, q, a.pde);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bad = bad || !(q[v] >= lo[v] - delta[v] && q[v] <= hi[v] + delta[v]);
     }
   }
   bad = __ballot(bad) != 0;
@@ -597,17 +604,58 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
         for (int v = 0; v < NV; ++v) vn[v * NS + s] = vnew[j][v];
     }
     __syncthreads();
-    for (int i = tid; i < NV * S; i += BLOCK) {
-      const int v = i / S, k = i - v * S;
-      const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
-      double acc = 0.0;
-      for (int s = 0; s < NS; ++s) {
-        const int sx = s % m, sy = (s / m) % m, sz = DIM == 3 ? s / (m * m) : 0;
-        double b = B[kx * m + sx] * B[ky * m + sy];
-        if (DIM == 3) b *= B[kz * m + sz];
-        acc += b * vn[v * NS + s];
+    // least-squares fit, one axis at a time: x (vn -> r1), y (r1 -> r2,
+    // 3-D), the last axis into Q
+    {
+      using LC = LimConst<n>;
+      double* r1 = box + NV * NS;  // [v][(sz)][sy][kx]
+      double* r2 = corr;           // 3-D: [v][sz][ky][kx]
+      constexpr int L1 = NV * ipow(m, DIM - 1);
+      for (int line = tid; line < L1; line += BLOCK) {
+        double in[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) in[j] = vn[line * m + j];
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < m; ++j) acc += LC::B[k][j] * in[j];
+          r1[line * n + k] = acc;
+        }
       }
-      Q[c * NV * S + i] = acc;
+      __syncthreads();
+      const double* rl = r1;
+      if constexpr (DIM == 3) {
+        for (int line = tid; line < NV * m * n; line += BLOCK) {
+          const int kx = line % n, vz = line / n;  // vz = v m + sz
+          double in[m];
+#pragma unroll
+          for (int j = 0; j < m; ++j) in[j] = r1[(vz * m + j) * n + kx];
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < m; ++j) acc += LC::B[k][j] * in[j];
+            r2[(vz * n + k) * n + kx] = acc;
+          }
+        }
+        __syncthreads();
+        rl = r2;
+      }
+      constexpr int RL = ipow(n, DIM - 1);  // lines per variable of the last stage
+      for (int line = tid; line < NV * RL; line += BLOCK) {
+        const int v = line / RL, r = line - v * RL;
+        double in[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) in[j] = rl[(v * m + j) * RL + r];
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < m; ++j) acc += LC::B[k][j] * in[j];
+          Q[c * NV * S + v * S + k * RL + r] = acc;
+        }
+      }
     }
     for (int i = tid; i < 2 * DIM * NV * F; i += BLOCK) {
       const int f = i % F, v = (i / F) % NV, face = i / (F * NV);
