@@ -207,3 +207,51 @@ def test_limiter_errors():
                        torch.zeros(s.ncells, dtype=torch.uint8, device="cuda"))
     assert e.value.status == -1  # sub_in and sub_out alias
     s.close()
+
+
+def test_full_c5_size_properties():
+    # the benchmark's explosion at its full size, as bench.py runs it (one
+    # warm-up and two timed steps): conservation, admissibility, counts
+    say("limiter c5 96^3 N=3")
+    cells, order = 96, 3
+    C = cells ** 3
+    s = adg.Solver(3, order, "euler", [cells] * 3, bc=["wall"] * 6, cfl=0.5)
+    Q = torch.as_tensor(inputs.blast_state(s.node_coords()), device="cuda")
+    fv, subfv = inputs.blast_fv_cells([cells] * 3, [0.0] * 3, [1.0] * 3, order)
+    sin = torch.zeros(s.subcell_shape, dtype=torch.float64, device="cuda")
+    fv_d = torch.as_tensor(fv, device="cuda")
+    sin[fv_d] = torch.as_tensor(subfv, device="cuda")
+    sout = torch.zeros_like(sin)
+    st = torch.zeros(C, dtype=torch.uint8, device="cuda")
+    st[fv_d] = 3
+    counts = torch.zeros(3, dtype=torch.int32, device="cuda")
+    clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+    w = torch.as_tensor(adg.basis_tables(order)["w"], device="cuda")
+    wk = (w[None, None, :] * w[None, :, None] * w[:, None, None]).reshape(-1)
+
+    def totals(Q, sub, st):
+        per = (Q * wk).sum(dim=2)
+        f = st >= 2
+        per[f] = sub[f].mean(dim=2)
+        return per.sum(dim=0)
+
+    m0 = totals(Q, sin, st)
+    s.stable_dt(Q, None, clock)
+    for _ in range(3):
+        s.step_limited(Q, clock, sin, sout, st, counts, next_dt=True)
+        sin, sout = sout, sin
+    torch.cuda.synchronize()
+    m1 = totals(Q, sin, st)
+    c = counts.cpu().tolist()
+    g = st.cpu().numpy()
+    say(f"  counts {c}, mass {(m1[0] / m0[0] - 1).item():.1e}, energy {(m1[4] / m0[4] - 1).item():.1e}")
+    assert c == [int((g == 3).sum()), int((g >= 2).sum()), int((g == 1).sum())] and c[0] > 0
+    assert abs((m1[0] - m0[0]) / m0[0]).item() <= 1e-12 and abs((m1[4] - m0[4]) / m0[4]).item() <= 1e-12
+    flags = torch.zeros(C, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s.check_admissible(Q, None, flags, cnt)
+    f = torch.as_tensor(g >= 2, device="cuda")
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+    assert bool(torch.isfinite(sin[f]).all()) and float(sin[f][:, 0].min()) > 0.0
+    s.close()
