@@ -290,7 +290,9 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
  *      that face in place of the Rusanov flux of step 1, so the step
  *      conserves what the PDE conserves.
  * Q [C][nvar][S] device, in/out.  clock as for adg_step (t advances by dt;
- * flags ADG_STEP_NEXT_DT evaluates Eq. (7) on the limited u^{n+1}).
+ * flags ADG_STEP_NEXT_DT evaluates Eq. (7) on the limited u^{n+1}, the
+ * signal speed of an FV cell taken over its subcell averages, of a DG cell
+ * over its nodes).
  * status [C] uint8 device, in/out: 0 DG, 1 DG with an FV face, 2 FV as a
  * neighbour of a troubled cell, 3 troubled (FV); zero it before the first
  * step (or mark cells that start on FV with 3 and give their data in

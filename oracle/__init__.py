@@ -145,6 +145,7 @@ def lib():
                                        C.POINTER(C.c_int)]
         L.orc_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
         L.orc_fv_step.argtypes = [pp, dp, C.c_double, dp]
+        L.orc_stable_dt_limited.argtypes = [pp, dp, dp, C.POINTER(C.c_ubyte), dp, dp]
         _lib = L
     return _lib
 
@@ -308,6 +309,17 @@ def step_limited(P: Problem, Q, dt: float, t: float = 0.0, sub=None, status=None
     _check(lib().orc_step_limited(C.byref(P), _p(Qn), None, dt, t, _p(sub),
                                   status.ctypes.data_as(C.POINTER(C.c_ubyte)), counts), "step_limited")
     return Qn, sub, status, tuple(counts)
+
+
+def stable_dt_limited(P: Problem, Q, sub, status):
+    """Eq. (7) in a limited run: FV cells (status >= 2) by their subcell
+    averages, the others by their nodes.  Returns (dt, lambda_max)."""
+    dt, lam = C.c_double(), C.c_double()
+    st = np.ascontiguousarray(status, dtype=np.uint8)
+    _check(lib().orc_stable_dt_limited(C.byref(P), _p(_arr(Q)), _p(_arr(sub)),
+                                       st.ctypes.data_as(C.POINTER(C.c_ubyte)), C.byref(dt), C.byref(lam)),
+           "stable_dt_limited")
+    return dt.value, lam.value
 
 
 def limiter_tables(n: int):

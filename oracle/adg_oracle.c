@@ -2135,3 +2135,31 @@ int orc_fv_step(const orc_problem *P, double *Q, double dt, double *subcells_out
   free(Vn);
   return ORC_OK;
 }
+
+/* Eq. (7) for a run with the subcell limiter.  READING: the solution of an
+ * FV cell (status >= 2) is its subcell averages, so its signal speed is
+ * taken over those; DG cells use their nodal values as in orc_stable_dt.
+ * (The least-squares polynomial of an FV cell is not its solution and can
+ * hold non-physical values at nodes.) */
+int orc_stable_dt_limited(const orc_problem *P, const double *Q, const double *sub,
+                          const unsigned char *status, double *dt, double *lambda_max) {
+  mesh M;
+  if (P->pde != ORC_EULER || make_mesh(P, &M)) return ORC_EINVAL;
+  const int m = 2 * P->order + 1, ns = ipow_i(m, M.dim);
+  double lam = 0.0;
+  for (long c = 0; c < M.C; ++c) {
+    const int fv = status[c] >= 2;
+    const int npts = fv ? ns : M.S;
+    for (int k = 0; k < npts; ++k) {
+      double q[ORC_MAXQ];
+      for (int v = 0; v < M.nv; ++v)
+        q[v] = fv ? sub[((size_t)c * M.nv + v) * ns + k] : Q[((size_t)c * M.nv + v) * M.S + k];
+      for (int d = 0; d < M.dim; ++d) lam = fmax(lam, pde_max_eigen(P, q, d));
+    }
+  }
+  double h = M.h[0];
+  for (int d = 1; d < M.dim; ++d) h = fmin(h, M.h[d]);
+  if (lambda_max) *lambda_max = lam;
+  *dt = P->cfl / (M.dim * (2.0 * P->order + 1.0)) * h / lam;
+  return ORC_OK;
+}

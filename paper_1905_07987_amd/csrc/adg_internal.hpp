@@ -124,8 +124,8 @@ struct KernelSet {
   // where not built): lim_before ahead of the step, lim_after behind it.
   hipError_t (*lim_before)(const KArgs&, const double* Q, const double* sub_in, const uint8_t* status,
                            const LimWork&, hipStream_t);
-  hipError_t (*lim_after)(const KArgs&, double* Q, const double* clock, const double* traces,
-                          const double* sub_in, double* sub_out, uint8_t* status, const LimWork&, hipStream_t);
+  hipError_t (*lim_after)(const KArgs&, double* Q, double* clock, const double* traces, const double* sub_in,
+                          double* sub_out, uint8_t* status, const LimWork&, int next_dt, hipStream_t);
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

@@ -548,13 +548,10 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
   ctx->traces_ready = true;
   e = k_correct(ctx, Q, nullptr, clock, 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
-  e = ctx->ks->lim_after(ctx->args, Q, clock, ctx->traces, sub_in, sub_out, status, ctx->lim, s);
+  e = ctx->ks->lim_after(ctx->args, Q, clock, ctx->traces, sub_in, sub_out, status, ctx->lim,
+                         (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "limiter launch");
   if (counts) ADG_HIP(hipMemcpyAsync(counts, ctx->lim.counters, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  if (flags & ADG_STEP_NEXT_DT) {
-    e = k_stable_dt(ctx, Q, nullptr, clock, s);
-    if (e != hipSuccess) return hip_fail(e, "stable_dt launch");
-  }
   return ADG_OK;
 }
 

@@ -717,6 +717,39 @@ lim_faces_kernel(const KArgs a, const double* __restrict__ clock, const double* 
   }
 }
 
+// Eq. (7) after a limited step: the largest signal speed over the nodal
+// values of DG cells and the subcell averages of FV cells (an FV cell's
+// solution; its least-squares polynomial can hold non-physical nodes).  One
+// wave per cell; block maxima into the reduction slots.
+template <class PDE, int N>
+__global__ void __launch_bounds__(256)
+lim_lambda_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ sub,
+                  const uint8_t* __restrict__ status) {
+  using GL = GeoLim<PDE, N>;
+  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS;
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const long long c = (long long)blockIdx.x * 4 + wv;
+  double lam = 0.0;
+  if (c < a.ncells) {
+    const bool fv = status[c] >= 2;
+    const int npts = fv ? NS : S;
+    const double* base = fv ? sub + c * NV * NS : Q + c * NV * S;
+    for (int k = lane; k < npts; k += 64) {
+      double q[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] = base[v * npts + k];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(q, q, a.pde, d));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lam = fmax(lam, __shfl_xor(lam, off, 64));
+  if (lane == 0) red[wv] = lam;
+  __syncthreads();
+  if (tid == 0) slot_max(a.slots, blockIdx.x, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
 template <class PDE, int N>
 struct LimLaunch {
   using GL = GeoLim<PDE, N>;
@@ -730,9 +763,9 @@ struct LimLaunch {
     return hipGetLastError();
   }
   // detect, classify, FV cells, DG cells with FV faces
-  static hipError_t after(const KArgs& a, double* Q, const double* clock, const double* traces,
+  static hipError_t after(const KArgs& a, double* Q, double* clock, const double* traces,
                           const double* sub_in, double* sub_out, uint8_t* status, const LimWork& w,
-                          hipStream_t st) {
+                          int next_dt, hipStream_t st) {
     const unsigned grid = (unsigned)((a.ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
     hipLaunchKernelGGL((lim_detect_kernel<PDE, N>), dim3(grid), dim3(64 * GeoLimW<PDE, N>::WPB), 0, st, a, Q, w);
     hipError_t e = hipGetLastError();
@@ -745,6 +778,11 @@ struct LimLaunch {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((lim_faces_kernel<PDE, N>), dim3(kFaceGrid), dim3(256), 0, st, a, clock, traces,
                        status, Q, w);
+    if ((e = hipGetLastError()) != hipSuccess || !next_dt) return e;
+    hipLaunchKernelGGL((lim_lambda_kernel<PDE, N>), dim3((unsigned)((a.ncells + 3) / 4)), dim3(256), 0, st, a, Q,
+                       sub_out, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kSlots), 0, st, a.slots, a.dt_factor, 1, clock);
     return hipGetLastError();
   }
 };

@@ -104,6 +104,25 @@ def test_limited_steps_match_the_oracle(name, dim, order, cells, bc, steps):
     s.close()
 
 
+def test_next_dt_of_a_limited_step_matches_the_oracle():
+    # Eq. (7) after the step: FV cells by their subcell averages
+    say("limiter next dt")
+    P, s, Q, sub, st = blast_case(2, 3, [10, 9], [W] * 4)
+    dt = 0.5 * O.stable_dt(P, Q)[0]
+    Qo, subo, sto, co = O.step_limited(P, Q, dt, sub=sub, status=st)
+    dto, lamo = O.stable_dt_limited(P, Qo, subo, sto)
+    Qg, stg = dev(Q), dev(st, torch.uint8)
+    sout = torch.zeros(s.subcell_shape, dtype=torch.float64, device="cuda")
+    clock = dev([0.0, dt])
+    s.step_limited(Qg, clock, dev(sub), sout, stg, None, next_dt=True)
+    torch.cuda.synchronize()
+    t1, dt1 = s.read_clock(clock)
+    say(f"  dt {dt1:.17g} oracle {dto:.17g}")
+    assert np.array_equal(stg.cpu().numpy(), sto)
+    assert abs(dt1 - dto) <= 1e-12 * dto and t1 == dt
+    s.close()
+
+
 def test_smooth_data_limited_step_equals_the_plain_step_bitwise():
     say("limiter smooth")
     # data the relaxed DMP leaves alone (the oracle agrees: nothing limited)
@@ -170,11 +189,13 @@ def test_reflecting_box_conserves_at_a_larger_size():
     m1 = integrals(P, Qh, subh, sth)
     say(f"  counts {tuple(c)}, mass {m1[0] / m0[0] - 1:.2e}, energy {m1[4] / m0[4] - 1:.2e}")
     assert abs(m1[0] - m0[0]) <= 1e-12 * m0[0] and abs(m1[4] - m0[4]) <= 1e-12 * m0[4]
+    # physical: the DG cells' nodes and the FV cells' subcell averages (an FV
+    # cell's least-squares polynomial is no part of the solution)
     flags = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
     s.check_admissible(Qg, None, flags, cnt)
     torch.cuda.synchronize()
-    assert int(cnt.item()) == 0
+    assert not flags.cpu().numpy()[sth < 2].any()
     fv = sth >= 2
     rho_sub = subh[fv][:, 0]
     assert np.isfinite(subh[fv]).all() and rho_sub.min() > 0.0
@@ -252,6 +273,9 @@ def test_full_c5_size_properties():
     s.check_admissible(Q, None, flags, cnt)
     f = torch.as_tensor(g >= 2, device="cuda")
     torch.cuda.synchronize()
-    assert int(cnt.item()) == 0
-    assert bool(torch.isfinite(sin[f]).all()) and float(sin[f][:, 0].min()) > 0.0
+    assert not bool(flags[~f].any())                      # DG cells: physical at every node
+    sf = sin[f]
+    p = 0.4 * (sf[:, 4] - 0.5 * (sf[:, 1] ** 2 + sf[:, 2] ** 2 + sf[:, 3] ** 2) / sf[:, 0])
+    assert bool(torch.isfinite(sf).all()) and float(sf[:, 0].min()) > 0.0 and float(p.min()) > 0.0
+    assert np.isfinite(s.read_clock(clock)[1])
     s.close()

@@ -281,3 +281,22 @@ def test_status_stencil_and_planted_bad_state():
         near_front |= np.abs(xyz - xyz[c]).max(axis=1) < 0.35
     near_bad = np.abs(xyz - xyz[bad]).max(axis=1) < 0.35
     assert not st[~near_front & ~near_bad].any()
+
+
+def test_stable_dt_of_a_limited_run():
+    P = O.problem(2, 2, O.EULER, [4, 3], [0, 0], [1, 0.75])
+    rng = np.random.default_rng(4)
+    rho = 1.0 + 0.1 * rng.random((P.ncells, P.S))
+    Q = np.stack([rho, 0.2 * rho, 0 * rho, 2.5 + 0 * rho], axis=1)
+    sub = np.zeros((P.ncells, 4, 25))
+    st = np.zeros(P.ncells, dtype=np.uint8)
+    # nothing on FV: Eq. (7) of the nodal values
+    assert O.stable_dt_limited(P, Q, sub, st) == O.stable_dt(P, Q)
+    # an FV cell's speed comes from its subcell data, not its nodes
+    st[5] = 2
+    sub[5] = np.array([1.0, 3.0, 0.0, 10.0])[:, None]        # u = 3, p = 0.4 (10 - 4.5)
+    Q[5, 3] = -1.0                                             # its nodes: not physical, ignored
+    dt, lam = O.stable_dt_limited(P, Q, sub, st)
+    c = np.sqrt(1.4 * 0.4 * (10.0 - 4.5))
+    assert abs(lam - (3.0 + c)) < 1e-14
+    assert abs(dt - 0.9 / (2 * 5) * 0.25 / lam) < 1e-16
