@@ -102,6 +102,8 @@ typedef struct {
   double kappa;     /* advection decay rate */
   int bc[6];        /* ADG_BC_* of face 2 d + side (side 1 at the high end of
                        axis d); all ADG_BC_PERIODIC (0) by default */
+  double bc_state[6][16]; /* ADG_BC_INFLOW: the outside state of face
+                             2 d + side (its first nvar entries) */
 } adg_config;
 
 /* Boundary conditions (the boundaryValues user function of the paper's
@@ -116,10 +118,16 @@ typedef struct {
  *                  elasticity, the traction sigma_{i d} reversed and the
  *                  velocity kept (Fout = -Fin): a traction-free surface.
  *                  Not defined for ADG_PDE_ADVECTION (INVALID_ARG).
- * The adjoint entry points need a periodic mesh. */
+ *  ADG_BC_INFLOW   a prescribed outside state, cfg.bc_state of the face
+ *                  (constant in time, material parameters the cell's own),
+ *                  and its normal flux F_d(qout).
+ * Walls and inflow faces are not offered for run-time PDEs (INVALID_ARG).
+ * The adjoint entry points need a periodic mesh; the subcell limiter has no
+ * inflow faces (UNSUPPORTED). */
 #define ADG_BC_PERIODIC 0
 #define ADG_BC_OUTFLOW 1
 #define ADG_BC_WALL 2
+#define ADG_BC_INFLOW 3
 
 /* Sizes derived from a configuration (adg_query). */
 typedef struct {

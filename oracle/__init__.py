@@ -47,6 +47,7 @@ class Problem(C.Structure):
         ("src_f0", C.c_double * MAXSRC), ("src_t0", C.c_double * MAXSRC),
         ("src_amp", C.c_double * MAXSRC),
         ("bc", C.c_int * 6),
+        ("bc_state", (C.c_double * MAXQ) * 6),
     ]
 
     @property
@@ -72,13 +73,14 @@ class Problem(C.Structure):
 _NV = {EULER: None, ELASTIC: 9, ADVECTION: 1}
 
 
-BC_PERIODIC, BC_OUTFLOW, BC_WALL = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_INFLOW = 0, 1, 2, 3
 
 
 def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None,
-            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=(), bc=None):
+            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=(), bc=None, bc_state=None):
     """Build a Problem.  ``sources`` is a list of dicts with keys x, w, f0, t0, amp;
-    ``bc`` the boundary condition of each face 2 d + side (default periodic)."""
+    ``bc`` the boundary condition of each face 2 d + side (default periodic);
+    ``bc_state`` {face: outside state} for BC_INFLOW faces."""
     P = Problem()
     P.dim, P.order, P.pde = dim, order, pde
     if pde == EULER:
@@ -110,6 +112,9 @@ def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None
         P.src_f0[s], P.src_t0[s], P.src_amp[s] = src["f0"], src["t0"], src["amp"]
     for f, b in enumerate(bc or ()):
         P.bc[f] = b
+    for f, q in (bc_state or {}).items():
+        for v, x in enumerate(q):
+            P.bc_state[f][v] = x
     return P
 
 

@@ -61,9 +61,11 @@ typedef struct {
   /* boundary condition of face 2 d + side (side 1 at the high end of axis
    * d): ORC_BC_PERIODIC on both faces of an axis, or OUTFLOW / WALL */
   int bc[6];
+  /* the outside state of an ORC_BC_INFLOW face (its first nvar entries) */
+  double bc_state[6][ORC_MAXQ];
 } orc_problem;
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_WALL = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_WALL = 2, ORC_BC_INFLOW = 3 };
 
 /* ------------------------------------------------------------------------
  * 1. One-dimensional tables on the reference interval [0,1].
@@ -384,11 +386,13 @@ static long neighbour(const orc_problem *P, long c, int d, int s) {
  *            energy crosses it).  Elasticity: the traction sigma_{i d}
  *            reversed, the velocity kept (a traction-free surface); the
  *            flux is linear, Fout = F_d(qout) = -Fin.
+ *   INFLOW   a prescribed outside state (bc_state of the face, constant in
+ *            time) and its flux, Fout = F_d(qout).
  * Material parameters outside are the cell's own. */
 static int bc_valid(const orc_problem *P) {
   for (int d = 0; d < 3; ++d) {
     int lo = P->bc[2 * d], hi = P->bc[2 * d + 1];
-    if (lo < 0 || lo > ORC_BC_WALL || hi < 0 || hi > ORC_BC_WALL) return 0;
+    if (lo < 0 || lo > ORC_BC_INFLOW || hi < 0 || hi > ORC_BC_INFLOW) return 0;
     if (d >= P->dim && (lo || hi)) return 0;
     if ((lo == ORC_BC_PERIODIC) != (hi == ORC_BC_PERIODIC)) return 0;
     if ((lo == ORC_BC_WALL || hi == ORC_BC_WALL) && P->pde == ORC_ADVECTION) return 0;
@@ -402,10 +406,16 @@ static int bc_periodic(const orc_problem *P) {
   return 1;
 }
 
-static void bc_ghost(const orc_problem *P, int kind, int d, const double *qin, const double *Fin,
+static void bc_ghost(const orc_problem *P, int face, const double *qin, const double *Fin,
                      double *qout, double *Fout) {
+  const int kind = P->bc[face], d = face / 2;
   for (int v = 0; v < P->nvar + P->nparam; ++v) qout[v] = qin[v];
   for (int v = 0; v < P->nvar; ++v) Fout[v] = Fin[v];
+  if (kind == ORC_BC_INFLOW) {
+    for (int v = 0; v < P->nvar; ++v) qout[v] = P->bc_state[face][v];
+    pde_flux(P, qout, d, Fout);
+    return;
+  }
   if (kind != ORC_BC_WALL) return;
   if (P->pde == ORC_EULER) {
     qout[1 + d] = -qin[1 + d];
@@ -759,7 +769,7 @@ static void correct_cell(const orc_problem *P, const mesh *M, const tables *T, l
         }
         for (int p = 0; p < P->nparam; ++p) qo[nv + p] = params[(size_t)c * P->nparam + p];
         if (other < 0) {
-          bc_ghost(P, P->bc[2 * d + side], d, qo, Fo, qx, Fx);
+          bc_ghost(P, 2 * d + side, qo, Fo, qx, Fx);
         } else {
           for (int v = 0; v < nv; ++v) {
             qx[v] = qoth[(size_t)f * nv + v];
@@ -1921,6 +1931,8 @@ int orc_step_limited(const orc_problem *P, double *Q, const double *params, doub
   tables T;
   lim_tables L;
   if (P->pde != ORC_EULER || !sub || !status) return ORC_EINVAL;
+  for (int f = 0; f < 6; ++f)
+    if (P->bc[f] == ORC_BC_INFLOW) return ORC_EINVAL; /* FV ghosts: mirror faces only */
   if (make_mesh(P, &M) || make_tables(M.n, &T) || make_lim_tables(&T, &L)) return ORC_EINVAL;
   const int m = L.m, nv = M.nv, S = M.S, ns = ipow_i(m, M.dim), nsf = ipow_i(m, M.dim - 1);
   const long C = M.C;

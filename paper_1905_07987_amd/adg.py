@@ -38,11 +38,12 @@ class Config(C.Structure):
         ("cfl", C.c_double), ("picard_iters", C.c_int), ("reserved", C.c_int),
         ("gamma", C.c_double), ("adv", C.c_double * 3), ("kappa", C.c_double),
         ("bc", C.c_int * 6),
+        ("bc_state", (C.c_double * 16) * 6),
     ]
 
 
-BC_PERIODIC, BC_OUTFLOW, BC_WALL = 0, 1, 2
-_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "wall": BC_WALL}
+BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_INFLOW = 0, 1, 2, 3
+_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "wall": BC_WALL, "inflow": BC_INFLOW}
 
 
 class Info(C.Structure):
@@ -145,11 +146,14 @@ class Solver:
 
     def __init__(self, dim: int, order: int, pde="euler", cells=(16, 16, 1), lo=(0.0, 0.0, 0.0),
                  hi=(1.0, 1.0, 1.0), cfl: float = 0.9, picard_iters: int = 0, precision="fp64",
-                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None,
+                 gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None, bc_state=None,
                  source: str | None = None):
         cfg = Config()
         for f, b in enumerate(bc or ()):
             cfg.bc[f] = _BC_NAMES.get(b, b)
+        for f, q in (bc_state or {}).items():
+            for v, x in enumerate(q):
+                cfg.bc_state[f][v] = x
         cfg.dim, cfg.order = dim, order
         cfg.pde = _PDE_NAMES.get(pde, pde)
         cfg.precision = _PREC_NAMES.get(precision, precision)

@@ -52,6 +52,7 @@ struct SourceDev {
 struct KArgs {
   int cells[3];
   int bc[6];  // ADG_BC_* per face 2 d + side
+  const double* bc_state;  // [6][kMaxVar] outside states of ADG_BC_INFLOW faces (device)
   int picard_iters;
   long long ncells;
   double h[3], inv_h[3];

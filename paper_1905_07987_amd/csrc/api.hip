@@ -37,6 +37,7 @@ struct adg_ctx {
   // subcell limiter workspace (allocated on the first limited step)
   LimWork lim{};
   void* lim_block = nullptr;
+  double* d_bc_state = nullptr;  // [6][kMaxVar] inflow states
 };
 
 namespace {
@@ -182,13 +183,20 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
   if (c.pde == ADG_PDE_EULER && !(c.gamma > 1.0)) return fail(ADG_ERR_INVALID_ARG, "gamma must be > 1");
   for (int d = 0; d < 3; ++d) {
     const int blo = c.bc[2 * d], bhi = c.bc[2 * d + 1];
-    if (blo < ADG_BC_PERIODIC || blo > ADG_BC_WALL || bhi < ADG_BC_PERIODIC || bhi > ADG_BC_WALL)
+    if (blo < ADG_BC_PERIODIC || blo > ADG_BC_INFLOW || bhi < ADG_BC_PERIODIC || bhi > ADG_BC_INFLOW)
       return fail(ADG_ERR_INVALID_ARG, "unknown boundary condition");
     if (d >= c.dim && (blo || bhi)) return fail(ADG_ERR_INVALID_ARG, "boundary condition on a missing axis");
     if ((blo == ADG_BC_PERIODIC) != (bhi == ADG_BC_PERIODIC))
       return fail(ADG_ERR_INVALID_ARG, "an axis is periodic on both faces or on neither");
     if ((blo == ADG_BC_WALL || bhi == ADG_BC_WALL) && (c.pde == ADG_PDE_ADVECTION || c.pde == ADG_PDE_USER))
       return fail(ADG_ERR_INVALID_ARG, "no wall condition for this PDE");
+    if ((blo == ADG_BC_INFLOW || bhi == ADG_BC_INFLOW) && c.pde == ADG_PDE_USER)
+      return fail(ADG_ERR_INVALID_ARG, "no inflow condition for a run-time PDE");
+    for (int side = 0; side < 2; ++side)
+      if (c.bc[2 * d + side] == ADG_BC_INFLOW)
+        for (int v = 0; v < 16; ++v)
+          if (!std::isfinite(c.bc_state[2 * d + side][v]))
+            return fail(ADG_ERR_INVALID_ARG, "inflow state must be finite");
   }
   long long C = 1;
   for (int d = 0; d < c.dim; ++d) {
@@ -335,6 +343,18 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     return fail(ADG_ERR_NOMEM, std::string("reduction slots: ") + hipGetErrorString(e));
   }
   a.slots = (unsigned long long*)x->red;
+  static_assert(kMaxVar == 16, "adg_config::bc_state holds 16 values per face");
+  e = hipMalloc((void**)&x->d_bc_state, sizeof(double) * 6 * kMaxVar);
+  if (e == hipSuccess) e = hipMemcpy(x->d_bc_state, &c.bc_state[0][0], sizeof(double) * 6 * kMaxVar, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(x->d_bc_state);
+    (void)hipFree(x->red);
+    (void)hipFree(x->traces);
+    user_module_destroy(um);
+    delete x;
+    return fail(ADG_ERR_NOMEM, std::string("boundary states: ") + hipGetErrorString(e));
+  }
+  a.bc_state = x->d_bc_state;
   a.nsrc = 0;
   a.src = nullptr;
   a.src_w = nullptr;
@@ -389,6 +409,7 @@ adg_status adg_destroy(adg_ctx* ctx) {
   (void)hipFree(ctx->d_rec_cell);
   (void)hipFree(ctx->d_rec_w);
   (void)hipFree(ctx->lim_block);
+  (void)hipFree(ctx->d_bc_state);
   user_module_destroy(ctx->user);
   (void)hipSetDevice(dev);
   delete ctx;
@@ -499,6 +520,8 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
   if (!ctx->ks || !ctx->ks->lim_before || !ctx->ks->lim_after)
     return fail(ADG_ERR_UNSUPPORTED,
                 "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->args.bc[f] == ADG_BC_INFLOW) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter has no inflow faces");
   adg_status st = check_state(ctx, Q, nullptr);
   if (st) return st;
   if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");

@@ -1649,6 +1649,23 @@ __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* 
           FL[v] = Fx[v];
         }
       }
+    } else if (bc == ADG_BC_INFLOW) {
+      // a prescribed outside state and its flux (material: the cell's own)
+      double qx[NV], Fx[DIM][NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qx[v] = a.bc_state[face * kMaxVar + v];
+      PDE::fluxes(qx, pL, a.pde, Fx);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double fx = PDE::flux_nonzero(d, v) ? Fx[d][v] : 0.0;
+        if (side) {
+          qR[v] = qx[v];
+          FR[v] = fx;
+        } else {
+          qL[v] = qx[v];
+          FL[v] = fx;
+        }
+      }
     }
     const double s = fmax(PDE::max_eigen(qL, pL, a.pde, d), PDE::max_eigen(qR, pR, a.pde, d));
     double B[NV];

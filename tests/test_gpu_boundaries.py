@@ -1,5 +1,5 @@
 """Parity of the HIP step with the oracle on meshes with non-periodic
-boundaries (outflow and wall faces), through the C ABI.
+boundaries (outflow, wall and inflow faces), through the C ABI.
 
 Bar: relative L2 <= 1e-12 over all evolved DoFs after several steps with
 Eq. (7) recomputed every step, the same seeded inputs on both sides; invalid
@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-W, OUT, PER = 2, 1, 0
+W, OUT, PER, IN = 2, 1, 0, 3
 
 
 def say(*a):
@@ -105,6 +105,56 @@ def test_advection_outflow_vs_oracle(dim, order, cells):
     assert e <= TOL
 
 
+def euler_state(rho, u, p, gamma=1.4):
+    u = list(u)
+    return [rho] + [rho * x for x in u] + [p / (gamma - 1) + 0.5 * rho * sum(x * x for x in u)]
+
+
+INFLOW_CASES = {
+    "2d_inflow_outflow_walls": (2, 3, [6, 4], [IN, OUT, W, W], {0: euler_state(1.1, (0.5, 0.1), 1.2)}),
+    "2d_inflow_both_y": (2, 2, [5, 5], [PER, PER, IN, IN], {2: euler_state(0.9, (0.0, 0.4), 1.0),
+                                                            3: euler_state(1.2, (0.1, -0.3), 0.8)}),
+    "3d_inflow_mixed": (3, 3, [3, 3, 2], [IN, OUT, W, W, PER, PER], {0: euler_state(1.05, (0.6, 0.0, 0.1), 1.1)}),
+}
+
+
+@pytest.mark.parametrize("case", list(INFLOW_CASES))
+def test_euler_inflow_vs_oracle(case):
+    dim, order, cells, bc, states = INFLOW_CASES[case]
+    say("euler inflow", case)
+    P = O.problem(dim, order, O.EULER, cells, bc=bc)
+    Q0 = inputs.smooth_euler_state(O.node_coords(P), 74)
+    Qg, Qo, tg, to = run_both(dim, order, "euler", cells, bc, Q0, steps=4, bc_state=states)
+    e = rel_l2(Qg, Qo)
+    say(f"  rel L2 {e:.2e}")
+    assert e <= TOL
+
+
+def test_elastic_and_advection_inflow_vs_oracle():
+    say("elastic / advection inflow")
+    cells, hi = [3, 2, 2], [1500.0, 1000.0, 1000.0]
+    P = O.problem(3, 3, O.ELASTIC, cells, [0.0] * 3, hi, bc=[IN, OUT, W, W, PER, PER])
+    rng = np.random.default_rng(75)
+    params = np.column_stack([rng.uniform(2000, 3000, P.ncells), rng.uniform(5000, 7000, P.ncells),
+                              rng.uniform(2500, 3400, P.ncells)])
+    Q0 = inputs.elastic_smooth_state(O.node_coords(P), 76)
+    state = {0: [1e3, -2e3, 5e2, 0.0, 3e2, 0.0, 0.5, -0.2, 0.1]}
+    Qg, Qo, _, _ = run_both(3, 3, "elastic", cells, [IN, OUT, W, W, PER, PER], Q0, params, steps=3,
+                            lo=[0.0] * 3, hi=hi, bc_state=state)
+    e = rel_l2(Qg, Qo)
+    say(f"  elastic rel L2 {e:.2e}")
+    assert e <= TOL
+    P = O.problem(2, 3, O.ADVECTION, [6, 5], bc=[IN, OUT, PER, PER], adv=(0.7, 0.2, 0.0), kappa=0.1,
+                  bc_state={0: [3.0]})
+    xyz = O.node_coords(P)
+    Q0 = (1.0 + 0.3 * np.sin(2 * np.pi * xyz[..., 0]))[:, None, :]
+    Qg, Qo, _, _ = run_both(2, 3, "advection", [6, 5], [IN, OUT, PER, PER], Q0, steps=4, adv=(0.7, 0.2),
+                            kappa=0.1, bc_state={0: [3.0]})
+    e = rel_l2(Qg, Qo)
+    say(f"  advection rel L2 {e:.2e}")
+    assert e <= TOL
+
+
 def test_invalid_boundaries_and_adjoint_are_refused():
     for pde, dim, bc in (("euler", 2, [W, PER, PER, PER]), ("advection", 2, [W, W, PER, PER]),
                          ("euler", 2, [PER, PER, PER, PER, W, W]), ("euler", 3, [7, 7, 0, 0, 0, 0])):
@@ -118,3 +168,14 @@ def test_invalid_boundaries_and_adjoint_are_refused():
         s.step_adjoint(Q, prm, dev([0.0, 1e-3]), Q.clone(), prm.clone())
     assert ei.value.status == -4
     s.close()
+    # the subcell limiter has no inflow faces
+    s = adg.Solver(2, 2, "euler", [3, 3], bc=[IN, OUT, PER, PER], bc_state={0: euler_state(1.0, (0.5, 0.0), 1.0)})
+    z = torch.zeros(s.subcell_shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(adg.AdgError) as ei:
+        s.step_limited(torch.ones(s.state_shape, dtype=torch.float64, device="cuda"), dev([0.0, 1e-3]), z,
+                       torch.zeros_like(z), torch.zeros(s.ncells, dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == -4
+    s.close()
+    with pytest.raises(adg.AdgError) as ei:  # a non-finite inflow state
+        adg.Solver(2, 2, "euler", [3, 3], bc=[IN, OUT, PER, PER], bc_state={0: [float("nan")] * 4})
+    assert ei.value.status == -1

@@ -108,3 +108,40 @@ def test_invalid_boundary_combinations_are_refused(pde, dim, bc):
     Q = np.ones((P.ncells, P.nvar, P.S))
     with pytest.raises(Exception):
         O.step(P, Q, None, 1e-3)
+
+
+IN = O.BC_INFLOW
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_inflow_face_is_upwind_for_advection(side):
+    # a = +-e_x, uniform q = 2, inflow 3 on the upstream face: the Rusanov
+    # flux there is the upwind a q_in, so one step changes only the cells on
+    # that face, by dt l(xi_k) / (h w_k) at their nodes (l = l0 at x = 0,
+    # l1 at x = 1), and leaves every other cell at exactly 2
+    N, cells = 3, [5, 3]
+    a = 1.0 if side == 0 else -1.0
+    bc = [IN, OUT, PER, PER] if side == 0 else [OUT, IN, PER, PER]
+    P = O.problem(2, N, O.ADVECTION, cells, adv=(a, 0.0), kappa=0.0, bc=bc, bc_state={side: [3.0]})
+    Q = np.full((P.ncells, 1, P.S), 2.0)
+    dt = 0.01
+    Q1 = O.step(P, Q, None, dt)
+    T = O.tables(P.n)
+    h = 1.0 / cells[0]
+    kx = np.arange(P.S) % P.n
+    lb = T["l0"] if side == 0 else T["l1"]
+    bump = dt * lb[kx] / (h * T["w"][kx])
+    for c in range(P.ncells):
+        cx = c % cells[0]
+        if cx == (0 if side == 0 else cells[0] - 1):
+            np.testing.assert_allclose(Q1[c, 0], 2.0 + bump, rtol=0, atol=1e-14)
+        else:
+            assert np.array_equal(Q1[c, 0], Q[c, 0])
+
+
+def test_inflow_of_the_interior_state_keeps_a_uniform_euler_flow():
+    q = [1.2, 0.6, -0.3, 3.1]
+    P = O.problem(2, 3, O.EULER, [4, 3], bc=[IN, OUT, IN, IN], bc_state={0: q, 2: q, 3: q})
+    Q = np.tile(np.array(q)[None, :, None], (P.ncells, 1, P.S))
+    Q1 = O.step(P, Q, None, 0.5 * O.stable_dt(P, Q)[0])
+    assert np.abs(Q1 - Q).max() < 1e-14
