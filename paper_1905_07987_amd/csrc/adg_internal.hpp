@@ -52,7 +52,10 @@ struct SourceDev {
 struct KArgs {
   int cells[3];
   int bc[6];  // ADG_BC_* per face 2 d + side
-  const double* bc_state;  // [6][kMaxVar] outside states of ADG_BC_INFLOW faces (device)
+  // ADG_BC_INFLOW faces (device): an outside trace per face in the layout of
+  // a cell's face trace, [6][2][nvar][F]: the prescribed state and its
+  // normal flux at every face node (filled once per context)
+  const double* bc_trace;
   int picard_iters;
   long long ncells;
   double h[3], inv_h[3];
@@ -127,6 +130,8 @@ struct KernelSet {
                            const LimWork&, hipStream_t);
   hipError_t (*lim_after)(const KArgs&, double* Q, double* clock, const double* traces, const double* sub_in,
                           double* sub_out, uint8_t* status, const LimWork&, int next_dt, hipStream_t);
+  // the flux half of KArgs::bc_trace from its state half (inflow faces)
+  hipError_t (*bc_flux)(const KArgs&, double* bc_trace, hipStream_t);
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

@@ -37,7 +37,7 @@ struct adg_ctx {
   // subcell limiter workspace (allocated on the first limited step)
   LimWork lim{};
   void* lim_block = nullptr;
-  double* d_bc_state = nullptr;  // [6][kMaxVar] inflow states
+  double* d_bc_state = nullptr;  // [6][2][nvar][F] outside traces of inflow faces
 };
 
 namespace {
@@ -343,9 +343,26 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     return fail(ADG_ERR_NOMEM, std::string("reduction slots: ") + hipGetErrorString(e));
   }
   a.slots = (unsigned long long*)x->red;
-  static_assert(kMaxVar == 16, "adg_config::bc_state holds 16 values per face");
-  e = hipMalloc((void**)&x->d_bc_state, sizeof(double) * 6 * kMaxVar);
-  if (e == hipSuccess) e = hipMemcpy(x->d_bc_state, &c.bc_state[0][0], sizeof(double) * 6 * kMaxVar, hipMemcpyHostToDevice);
+  {
+    // inflow faces: the prescribed state at every face node; the flux half
+    // is filled on the device
+    const size_t nbt = (size_t)6 * 2 * nv * x->F;
+    std::vector<double> bt(nbt, 0.0);
+    bool inflow = false;
+    for (int f = 0; f < 6; ++f) {
+      if (c.bc[f] != ADG_BC_INFLOW) continue;
+      inflow = true;
+      for (int v = 0; v < nv; ++v)
+        for (int k = 0; k < x->F; ++k) bt[((size_t)f * 2 * nv + v) * x->F + k] = c.bc_state[f][v];
+    }
+    e = hipMalloc((void**)&x->d_bc_state, sizeof(double) * nbt);
+    if (e == hipSuccess) e = hipMemcpy(x->d_bc_state, bt.data(), sizeof(double) * nbt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      a.bc_trace = x->d_bc_state;
+      if (inflow && ks) e = ks->bc_flux(a, x->d_bc_state, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+  }
   if (e != hipSuccess) {
     (void)hipFree(x->d_bc_state);
     (void)hipFree(x->red);
@@ -354,7 +371,6 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     delete x;
     return fail(ADG_ERR_NOMEM, std::string("boundary states: ") + hipGetErrorString(e));
   }
-  a.bc_state = x->d_bc_state;
   a.nsrc = 0;
   a.src = nullptr;
   a.src_w = nullptr;

@@ -1598,6 +1598,8 @@ __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* 
     const int fR = bc != ADG_BC_PERIODIC ? face : 2 * d;
     const double* tL = traces + ((long long)(cL * (2 * DIM) + fL) * 2) * NV * F;
     const double* tR = traces + ((long long)(cR * (2 * DIM) + fR) * 2) * NV * F;
+    // an inflow face: the outside trace is the prescribed state and its flux
+    if (bc == ADG_BC_INFLOW) (side ? tR : tL) = a.bc_trace + face * 2 * NV * F;
     double qL[NV], qR[NV], FL[NV], FR[NV], pL[NP > 0 ? NP : 1], pR[NP > 0 ? NP : 1], pm[NP > 0 ? NP : 1];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -1647,23 +1649,6 @@ __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* 
         } else {
           qL[v] = qx[v];
           FL[v] = Fx[v];
-        }
-      }
-    } else if (bc == ADG_BC_INFLOW) {
-      // a prescribed outside state and its flux (material: the cell's own)
-      double qx[NV], Fx[DIM][NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) qx[v] = a.bc_state[face * kMaxVar + v];
-      PDE::fluxes(qx, pL, a.pde, Fx);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double fx = PDE::flux_nonzero(d, v) ? Fx[d][v] : 0.0;
-        if (side) {
-          qR[v] = qx[v];
-          FR[v] = fx;
-        } else {
-          qL[v] = qx[v];
-          FL[v] = fx;
         }
       }
     }
@@ -1976,6 +1961,24 @@ namespace adg {
 
 namespace adg {
 
+// The flux half of each inflow face's outside trace: F_d(q_out) at every
+// face node (the built-in fluxes do not depend on the material parameters).
+template <class PDE, int N>
+__global__ void __launch_bounds__(64) bc_flux_kernel(const KArgs a, double* __restrict__ tr) {
+  constexpr int NV = PDE::NV, NP = PDE::NP, DIM = PDE::DIM, F = Geo<PDE, N>::F;
+  const int f = threadIdx.x;
+  if (f >= 2 * DIM || a.bc[f] != ADG_BC_INFLOW) return;
+  const int d = f / 2;
+  double q[NV], P[NP > 0 ? NP : 1], Fx[DIM][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = tr[(f * 2 * NV + v) * F];
+#pragma unroll
+  for (int p = 0; p < (NP > 0 ? NP : 1); ++p) P[p] = 1.0;
+  PDE::fluxes(q, P, a.pde, Fx);
+  for (int v = 0; v < NV; ++v)
+    for (int k = 0; k < F; ++k) tr[((f * 2 + 1) * NV + v) * F + k] = PDE::flux_nonzero(d, v) ? Fx[d][v] : 0.0;
+}
+
 template <class PDE, int N>
 struct Launch {
   using G = Geo<PDE, N>;
@@ -2093,10 +2096,14 @@ struct Launch {
     if constexpr (GeoLim<PDE, N>::built) return &LimLaunch<PDE, N>::after;
     else return nullptr;
   }
+  static hipError_t bc_flux(const KArgs& a, double* tr, hipStream_t st) {
+    hipLaunchKernelGGL((bc_flux_kernel<PDE, N>), dim3(1), dim3(64), 0, st, a, tr);
+    return hipGetLastError();
+  }
   static const KernelSet* set() {
     static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB,
                                  &predict, &correct, &stable_dt, &admissible, adjoint_entry(),
-                                 step_fused_entry(), lim_before_entry(), lim_after_entry()};
+                                 step_fused_entry(), lim_before_entry(), lim_after_entry(), &bc_flux};
     return &ks;
   }
 };
