@@ -279,3 +279,30 @@ def test_full_c5_size_properties():
     assert bool(torch.isfinite(sf).all()) and float(sf[:, 0].min()) > 0.0 and float(p.min()) > 0.0
     assert np.isfinite(s.read_clock(clock)[1])
     s.close()
+
+
+def test_limited_step_with_the_fp32_predictor():
+    # the candidate from the mixed-precision predictor, the limiter in FP64:
+    # close to the FP64 run (the troubled sets may differ where a test is
+    # decided within the FP32 error)
+    say("limiter fp32 predictor")
+    P, s, Q, sub, st = blast_case(2, 3, [10, 9], [W] * 4)
+    s32 = adg.Solver(2, 3, "euler", [10, 9], [0.0, 0.0], [1.0, 1.0], bc=[W] * 4, precision="fp32")
+    dt = 0.5 * O.stable_dt(P, Q)[0]
+    out = []
+    for solver in (s, s32):
+        Qg, stg, sin = dev(Q), dev(st, torch.uint8), dev(sub)
+        sout = torch.zeros_like(sin)
+        clock = dev([0.0, dt])
+        for _ in range(3):
+            solver.step_limited(Qg, clock, sin, sout, stg, None, next_dt=False)
+            sin, sout = sout, sin
+        torch.cuda.synchronize()
+        out.append((Qg.cpu().numpy(), stg.cpu().numpy()))
+    (Q64, st64), (Q32, st32) = out
+    agree = float((st64 == st32).mean())
+    e = rel_l2(Q32, Q64)
+    say(f"  status agreement {agree:.3f}, rel L2 vs fp64 {e:.2e}")
+    assert agree >= 0.95 and e <= 1e-3 and np.isfinite(Q32).all()
+    s.close()
+    s32.close()
