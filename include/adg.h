@@ -310,8 +310,9 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
  * (sub_out, status after it); they must be distinct arrays, and a run
  * swaps them every step.  counts: device int32[3] (troubled cells, FV
  * cells, DG cells with an FV face), or NULL.  The first call allocates the
- * context's limiter workspace, about 1.4 state arrays plus 2 bytes and 24
- * bytes per cell.  No host synchronisation. */
+ * context's limiter workspace: a copy of u^n and the FV face fluxes,
+ * 1 + 2 dim / (order + 1) state arrays, plus 16 nvar + 10 bytes per cell.
+ * Calls on one context must not overlap.  No host synchronisation. */
 adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
                             uint8_t* status, int32_t* counts, int flags, void* stream);
 

