@@ -413,13 +413,17 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
     //    reversing the normal momentum).  The owners' nodal values are
     //    staged in LDS first (owner slot: the offset's rank among the
     //    offsets in {-1,0,1}^dim with at most two nonzero entries).
-    if (tid == 0) {
-      int slot = 0;
-      for (int k = 0; k < ipow(3, DIM); ++k) {
-        const int off[3] = {k % 3 - 1, (k / 3) % 3 - 1, DIM == 3 ? k / 9 - 1 : 0};
-        if ((off[0] != 0) + (off[1] != 0) + (off[2] != 0) > 2) continue;
+    // one thread per offset k in {-1,0,1}^dim: its owner cell and whether
+    // that owner was FV at t^n
+    if (tid < ipow(3, DIM)) {
+      const int k = tid;
+      const int off[3] = {k % 3 - 1, (k / 3) % 3 - 1, DIM == 3 ? k / 9 - 1 : 0};
+      if ((off[0] != 0) + (off[1] != 0) + (off[2] != 0) <= 2) {
+        const int slot = DIM == 2 ? k
+                                  : k - ((k > 0) + (k > 2) + (k > 6) + (k > 8) + (k > 18) + (k > 20) + (k > 24));
         int oc[3] = {cc[0], cc[1], cc[2]};
         bool exists = true;
+#pragma unroll
         for (int d = 0; d < DIM; ++d) {
           oc[d] += off[d];
           if (oc[d] < 0 || oc[d] >= a.cells[d]) {
@@ -430,7 +434,6 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
         const long long o = exists ? oc[0] + (long long)C0 * (oc[1] + (long long)C1 * oc[2]) : -1;
         owner[slot] = o;
         fvdata[slot] = (exists && w.st_prev[o] >= 2) ? 1 : 0;
-        ++slot;
       }
     }
     __syncthreads();
@@ -465,11 +468,11 @@ lim_fv_kernel(const KArgs a, const double* __restrict__ clock, const double* __r
       if (outside > 2 || (outside == 2 && far > 0)) continue;
       // slot of the offset po
       const int kpo = (po[0] + 1) + 3 * (po[1] + 1) + (DIM == 3 ? 9 * (po[2] + 1) : 0);
-      int slot = 0;
-      for (int k = 0; k < kpo; ++k) {
-        const int a0 = k % 3 - 1, a1 = (k / 3) % 3 - 1, a2 = DIM == 3 ? k / 9 - 1 : 0;
-        slot += ((a0 != 0) + (a1 != 0) + (a2 != 0) > 2) ? 0 : 1;
-      }
+      // rank of kpo among the offsets with at most two nonzero entries: in
+      // 3-D the eight corners k = 0, 2, 6, 8, 18, 20, 24, 26 are left out
+      const int slot = DIM == 2 ? kpo
+                                : kpo - ((kpo > 0) + (kpo > 2) + (kpo > 6) + (kpo > 8) + (kpo > 18) + (kpo > 20) +
+                                         (kpo > 24));
       const long long o = owner[slot];
       double val[NV];
       if (fvdata[slot]) {
