@@ -82,33 +82,36 @@ __device__ __forceinline__ void lim_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS of the prepare and detect kernels: the cell's nodal values
-// and the contraction stages of the projection onto the subcells (the last
-// stage is evaluated in registers, one line of subcells per lane).  Region
-// A holds the nodal values, later the second stage (3-D); region B the
-// first stage.  The subcell averages of the basis, LimConst<n>::A, are
-// compile-time constants.
+// Per-wave LDS of the prepare and detect kernels: one group of variables'
+// nodal values and the contraction stages of the projection onto the
+// subcells (the last stage is evaluated in registers, one column of subcells
+// per lane).  Region A holds the nodal values, later the second stage
+// (3-D); region B the first stage.  The variables go in two groups, so a
+// wave needs half the LDS and more waves share a CU.  The subcell averages
+// of the basis, LimConst<n>::A, are compile-time constants.
 template <class PDE, int N>
 struct GeoLimW {
   using GL = GeoLim<PDE, N>;
-  static constexpr int WPB = 4;  // cells (waves) per block
-  static constexpr int P1 = GL::NV * GL::m * ipow(GL::n, GL::DIM - 1);
-  static constexpr int P2 = GL::DIM == 3 ? GL::NV * GL::m * GL::m * GL::n : 0;
-  static constexpr int RA = cmax(GL::NV * GL::S, P2), RB = P1;
+  static constexpr int WPB = 4;                   // cells (waves) per block
+  static constexpr int VG = (GL::NV + 1) / 2;     // variables of the first group
+  static constexpr int P1 = VG * GL::m * ipow(GL::n, GL::DIM - 1);
+  static constexpr int P2 = GL::DIM == 3 ? VG * GL::m * GL::m * GL::n : 0;
+  static constexpr int RA = cmax(VG * GL::S, P2), RB = P1;
   static constexpr int PW = RA + RB;
-  // lines of the last stage (one per lane): subcell columns along the last axis
+  // columns of subcells along the last axis: one per lane
   static constexpr int LAST = ipow(GL::m, GL::DIM - 1);
+  static_assert(LAST <= 64, "one column of subcells per lane");
 };
 
-// The leading stages, one line per lane and step: along x (nodal values in
-// A, [v][kz][ky][kx], to B, [v][kz][ky][sx]); in 3-D then along y (B to A,
-// [v][kz][sy][sx]).
-template <class PDE, int N>
+// The leading stages for NVS variables, one line per lane and step: along x
+// (nodal values in A, [v][kz][ky][kx], to B, [v][kz][ky][sx]); in 3-D then
+// along y (B to A, [v][kz][sy][sx]).
+template <class PDE, int N, int NVS>
 __device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane) {
   using GL = GeoLim<PDE, N>;
   using LC = LimConst<GL::n>;
-  constexpr int n = GL::n, m = GL::m, NV = GL::NV;
-  constexpr int L1 = NV * ipow(n, GL::DIM - 1);
+  constexpr int n = GL::n, m = GL::m;
+  constexpr int L1 = NVS * ipow(n, GL::DIM - 1);
   for (int line = lane; line < L1; line += 64) {
     double in[n];
 #pragma unroll
@@ -123,7 +126,7 @@ __device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane
   }
   lim_wave_sync();
   if constexpr (GL::DIM == 3) {
-    constexpr int L2 = NV * n * m;
+    constexpr int L2 = NVS * n * m;
     for (int line = lane; line < L2; line += 64) {
       const int sx = line % m, vk = line / m;  // vk = v n + kz
       double in[n];
@@ -141,29 +144,40 @@ __device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane
   }
 }
 
-// The last stage for the column of subcells `col` along the last axis:
-// out[v][j] = the average of variable v over the j-th subcell of the column
-// (subcell index col + j m^(dim-1)).
-template <class PDE, int N>
-__device__ __forceinline__ void lim_last_stage(const double* ra, const double* rb, int col,
-                                               double (&out)[PDE::NV][2 * N + 1]) {
+// Variables V0 .. V0 + NVS - 1 of the cell at Qc ([nv][S], global) through
+// the projection: out[V0 + v][j] = the average of variable V0 + v over the
+// j-th subcell of this lane's column (subcell index lane + j m^(dim-1)), for
+// lanes below the column count.  Qold (if not null) receives a copy.
+template <class PDE, int N, int V0, int NVS>
+__device__ __forceinline__ void lim_group_wave(const double* __restrict__ Qc, double* __restrict__ Qold, double* ra,
+                                               double* rb, int lane, double (&out)[PDE::NV][2 * N + 1]) {
   using GL = GeoLim<PDE, N>;
   using LC = LimConst<GL::n>;
-  constexpr int n = GL::n, m = GL::m, NV = GL::NV;
+  constexpr int n = GL::n, m = GL::m, S = GL::S;
+  for (int i = lane; i < NVS * S; i += 64) {
+    const double x = Qc[V0 * S + i];
+    ra[i] = x;
+    if (Qold) Qold[V0 * S + i] = x;
+  }
+  lim_wave_sync();
+  lim_stages_wave<PDE, N, NVS>(ra, rb, lane);
+  if (lane < GeoLimW<PDE, N>::LAST) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double in[n];
+    for (int v = 0; v < NVS; ++v) {
+      double in[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k)
-      in[k] = GL::DIM == 2 ? rb[(v * n + k) * m + col] : ra[(v * n + k) * m * m + col];
+      for (int k = 0; k < n; ++k)
+        in[k] = GL::DIM == 2 ? rb[(v * n + k) * m + lane] : ra[(v * n + k) * m * m + lane];
 #pragma unroll
-    for (int j = 0; j < m; ++j) {
-      double acc = 0.0;
+      for (int j = 0; j < m; ++j) {
+        double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < n; ++k) acc += LC::A[j][k] * in[k];
-      out[v][j] = acc;
+        for (int k = 0; k < n; ++k) acc += LC::A[j][k] * in[k];
+        out[V0 + v][j] = acc;
+      }
     }
   }
+  lim_wave_sync();  // the next group overwrites the stages
 }
 
 __device__ __forceinline__ double lim_wave_min(double x) {
@@ -193,11 +207,6 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   if (c >= a.ncells) return;
   double* ra = buf[wv];
   double* rb = ra + GW::RA;
-  for (int i = lane; i < NV * S; i += 64) {
-    const double x = Q[c * NV * S + i];
-    w.Qold[c * NV * S + i] = x;
-    ra[i] = x;
-  }
   const uint8_t st = status[c];
   if (lane == 0) w.st_prev[c] = st;
   double lo[NV], hi[NV];
@@ -207,6 +216,7 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     hi[v] = -INFINITY;
   }
   if (st >= 2) {
+    for (int i = lane; i < NV * S; i += 64) w.Qold[c * NV * S + i] = Q[c * NV * S + i];
     for (int s = lane; s < NS; s += 64)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -215,11 +225,10 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
         hi[v] = fmax(hi[v], x);
       }
   } else {
-    lim_wave_sync();
-    lim_stages_wave<PDE, N>(ra, rb, lane);
-    for (int col = lane; col < GW::LAST; col += 64) {
-      double q[NV][m];
-      lim_last_stage<PDE, N>(ra, rb, col, q);
+    double q[NV][m];
+    lim_group_wave<PDE, N, 0, GW::VG>(Q + c * NV * S, w.Qold + c * NV * S, ra, rb, lane, q);
+    lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(Q + c * NV * S, w.Qold + c * NV * S, ra, rb, lane, q);
+    if (lane < GW::LAST)
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -227,7 +236,6 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
           lo[v] = fmin(lo[v], q[v][j]);
           hi[v] = fmax(hi[v], q[v][j]);
         }
-    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -252,7 +260,6 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
   if (c >= a.ncells) return;
   double* ra = buf[wv];
   double* rb = ra + GW::RA;
-  for (int i = lane; i < NV * S; i += 64) ra[i] = Q[c * NV * S + i];
   // DMP range: the cell's and its face neighbours' subcell averages at t^n
   double lo[NV], hi[NV];
 #pragma unroll
@@ -270,22 +277,17 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
         hi[v] = fmax(hi[v], w.lohi[(o * NV + v) * 2 + 1]);
       }
     }
-  lim_wave_sync();
   bool bad = false;
   for (int k = lane; k < S; k += 64) {
     double q[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = ra[v * S + k];
+    for (int v = 0; v < NV; ++v) q[v] = Q[(c * NV + v) * S + k];
     bad = bad || !PDE::admissible(q, q, a.pde);
   }
-  lim_wave_sync();
-  lim_stages_wave<PDE, N>(ra, rb, lane);
-  double delta[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) delta[v] = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
-  for (int col = lane; col < GW::LAST; col += 64) {
-    double qv[NV][m];
-    lim_last_stage<PDE, N>(ra, rb, col, qv);
+  double qv[NV][m];
+  lim_group_wave<PDE, N, 0, GW::VG>(Q + c * NV * S, nullptr, ra, rb, lane, qv);
+  lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(Q + c * NV * S, nullptr, ra, rb, lane, qv);
+  if (lane < GW::LAST) {
 #pragma unroll
     for (int j = 0; j < m; ++j) {
       double q[NV];
@@ -293,7 +295,10 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
       for (int v = 0; v < NV; ++v) q[v] = qv[v][j];
       bad = bad || !PDE::admissible(q, q, a.pde);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) bad = bad || !(q[v] >= lo[v] - delta[v] && q[v] <= hi[v] + delta[v]);
+      for (int v = 0; v < NV; ++v) {
+        const double delta = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
+        bad = bad || !(q[v] >= lo[v] - delta && q[v] <= hi[v] + delta);
+      }
     }
   }
   bad = __ballot(bad) != 0;
