@@ -16,6 +16,11 @@
  *     Eq. (6) with a diagonal mass matrix): Sec. 3.3;
  *   - the time step restriction Eq. (7): Sec. 3.4;
  *   - the admissibility check of the a-posteriori limiter: Sec. 3.5;
+ *   - the a-posteriori subcell limiter in its hybrid ADER-DG/FV form (FV
+ *     subcells, discrete maximum principle, MUSCL-Hancock, projections):
+ *     Sec. 3.5, Table 1, Fig. 2 (section 10 below);
+ *   - boundary faces (outflow, wall, inflow; the paper's boundaryValues,
+ *     Table 2);
  *   - the PDEs: compressible Euler, Eqs. (8) and (10) (Sec. 6.1) and linear
  *     elasticity in velocity-stress form (Sec. 2.1).
  * Readings of silent or ambiguous passages are marked READING below.
