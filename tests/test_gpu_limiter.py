@@ -18,7 +18,7 @@ from paper_1905_07987_amd import adg, inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-W, PER = O.BC_WALL, O.BC_PERIODIC
+W, PER, OUT = O.BC_WALL, O.BC_PERIODIC, O.BC_OUTFLOW
 
 
 def say(*a):
@@ -68,6 +68,8 @@ CASES = [
     ("3d_N2_walls", 3, 2, [5, 5, 4], [W] * 6, 3),
     ("3d_N3_mixed", 3, 3, [4, 5, 4], [W, W, PER, PER, W, W], 2),
     ("3d_N1_periodic", 3, 1, [6, 5, 6], None, 3),
+    ("2d_N2_outflow", 2, 2, [9, 8], [OUT] * 4, 3),
+    ("3d_N2_one_cell_y", 3, 2, [4, 1, 3], [W, W, PER, PER, W, W], 2),
 ]
 
 
