@@ -121,6 +121,13 @@ typedef struct {
  *  ADG_BC_INFLOW   a prescribed outside state, cfg.bc_state of the face
  *                  (constant in time, material parameters the cell's own),
  *                  and its normal flux F_d(qout).
+ *  ADG_BC_USER     run-time PDEs only (adg_create_user): the struct's
+ *                  boundary_values(x, t, dt, face, Qin, Fin, Qout, Fout),
+ *                  the paper's boundaryValues user function, called at every
+ *                  node x of the face with the step's start time t and size
+ *                  dt and the cell's own trace (Qin with the parameters
+ *                  appended, Fin); it returns the outside state and normal
+ *                  flux.  The struct declares HAS_BOUNDARY = true.
  * Walls and inflow faces are not offered for run-time PDEs (INVALID_ARG).
  * The adjoint entry points need a periodic mesh; the subcell limiter has no
  * inflow faces (UNSUPPORTED). */
@@ -128,6 +135,7 @@ typedef struct {
 #define ADG_BC_OUTFLOW 1
 #define ADG_BC_WALL 2
 #define ADG_BC_INFLOW 3
+#define ADG_BC_USER 4
 
 /* Sizes derived from a configuration (adg_query). */
 typedef struct {

@@ -42,8 +42,9 @@ class Config(C.Structure):
     ]
 
 
-BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_INFLOW = 0, 1, 2, 3
-_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "wall": BC_WALL, "inflow": BC_INFLOW}
+BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_INFLOW, BC_USER = 0, 1, 2, 3, 4
+_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "wall": BC_WALL, "inflow": BC_INFLOW,
+             "user": BC_USER}
 
 
 class Info(C.Structure):

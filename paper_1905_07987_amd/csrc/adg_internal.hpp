@@ -58,7 +58,7 @@ struct KArgs {
   const double* bc_trace;
   int picard_iters;
   long long ncells;
-  double h[3], inv_h[3];
+  double lo[3], h[3], inv_h[3];  // lower corner of the domain, cell sizes
   double dt_factor;  // cfl / (dim (2N+1)) * min_d h_d
   PdeConsts pde;
   Tables<double> t64;
@@ -149,7 +149,7 @@ int max_order_advection3();
 
 // PDEs compiled at run time (user.hip).
 struct UserTraits {
-  int dim, nv, np, linear, has_ncp, has_source;
+  int dim, nv, np, linear, has_ncp, has_source, has_boundary;
 };
 struct UserModule;
 adg_status user_traits(const char* source, const std::string& arch, UserTraits* t, std::string* err);

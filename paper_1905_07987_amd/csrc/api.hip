@@ -183,8 +183,10 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
   if (c.pde == ADG_PDE_EULER && !(c.gamma > 1.0)) return fail(ADG_ERR_INVALID_ARG, "gamma must be > 1");
   for (int d = 0; d < 3; ++d) {
     const int blo = c.bc[2 * d], bhi = c.bc[2 * d + 1];
-    if (blo < ADG_BC_PERIODIC || blo > ADG_BC_INFLOW || bhi < ADG_BC_PERIODIC || bhi > ADG_BC_INFLOW)
+    if (blo < ADG_BC_PERIODIC || blo > ADG_BC_USER || bhi < ADG_BC_PERIODIC || bhi > ADG_BC_USER)
       return fail(ADG_ERR_INVALID_ARG, "unknown boundary condition");
+    if ((blo == ADG_BC_USER || bhi == ADG_BC_USER) && !source)
+      return fail(ADG_ERR_INVALID_ARG, "ADG_BC_USER needs a run-time PDE with boundary_values");
     if (d >= c.dim && (blo || bhi)) return fail(ADG_ERR_INVALID_ARG, "boundary condition on a missing axis");
     if ((blo == ADG_BC_PERIODIC) != (bhi == ADG_BC_PERIODIC))
       return fail(ADG_ERR_INVALID_ARG, "an axis is periodic on both faces or on neither");
@@ -221,6 +223,9 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     adg_status st = user_traits(source, arch, &t, &err);
     if (st) return fail(st, err);
     if (t.dim != c.dim) return fail(ADG_ERR_INVALID_ARG, "AdgUserPDE::DIM differs from cfg->dim");
+    for (int f = 0; f < 6; ++f)
+      if (c.bc[f] == ADG_BC_USER && !t.has_boundary)
+        return fail(ADG_ERR_INVALID_ARG, "ADG_BC_USER needs AdgUserPDE::HAS_BOUNDARY and boundary_values");
     if (t.nv < 1 || t.np < 0 || t.nv + t.np > kMaxVar)
       return fail(ADG_ERR_INVALID_ARG, "AdgUserPDE: NV + NP must be in 1..16");
     const int I = c.picard_iters ? c.picard_iters : c.order + 1;
@@ -267,6 +272,7 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
   KArgs& a = x->args;
   for (int f = 0; f < 6; ++f) a.bc[f] = c.bc[f];
   for (int d = 0; d < 3; ++d) {
+    a.lo[d] = d < c.dim ? c.lo[d] : 0.0;
     a.cells[d] = d < c.dim ? c.cells[d] : 1;
     a.h[d] = d < c.dim ? (c.hi[d] - c.lo[d]) / c.cells[d] : 1.0;
     a.inv_h[d] = 1.0 / a.h[d];

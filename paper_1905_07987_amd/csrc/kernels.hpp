@@ -1563,10 +1563,23 @@ struct GeoB {
 // Corrector phase 1: the fluctuation of each cell's side at every face node
 // of the CPB cells from cell0 on (block-wide tasks, one per (cell, face,
 // face node)), scaled by dt / h_d, into fl[CPB][2 dim][NV][F].
+// PDEs with a boundary_values function for ADG_BC_USER faces (run-time PDEs
+// that define one)
+template <class... T>
+using kern_void_t = void;
+template <class P, class = void>
+struct HasUserBoundary {
+  static constexpr bool value = false;
+};
+template <class P>
+struct HasUserBoundary<P, kern_void_t<decltype(P::kUserBoundary)>> {
+  static constexpr bool value = P::kUserBoundary;
+};
+
 template <class PDE, int N, int CPB, int BLOCK>
 __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* __restrict__ params,
-                                                  const double* __restrict__ traces, double dt, int cell0,
-                                                  int tid, double* fl) {
+                                                  const double* __restrict__ traces, double t, double dt,
+                                                  int cell0, int tid, double* fl) {
   using G = Geo<PDE, N>;
   constexpr int F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
   const int C0 = a.cells[0], C1 = a.cells[1];
@@ -1578,6 +1591,7 @@ __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* 
     const int c = cell0 + c2;
     if (c >= ncells) continue;
     const int d = face >> 1, side = face & 1;
+    const int c_own[3] = {c % C0, (c / C0) % C1, DIM == 3 ? c / (C0 * C1) : 0};
     // neighbour across this face: wrapped around on a periodic axis; on a
     // boundary face of a non-periodic axis the outside state and normal flux
     // come from this cell's own traces (outflow: a copy, wall: the mirror
@@ -1649,6 +1663,35 @@ __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* 
         } else {
           qL[v] = qx[v];
           FL[v] = Fx[v];
+        }
+      }
+    }
+    if constexpr (HasUserBoundary<PDE>::value) {
+      if (bc == ADG_BC_USER) {
+        // the user's boundaryValues at this face node
+        const int fa = DIM == 2 ? f : f % Geo<PDE, N>::n, fb = DIM == 2 ? 0 : f / Geo<PDE, N>::n;
+        double x[3] = {0.0, 0.0, 0.0};
+        int in_face = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+          if (e == d) {
+            x[e] = a.lo[e] + (c_own[e] + side) * a.h[e];
+          } else {
+            const int ke = in_face++ == 0 ? fa : fb;
+            x[e] = a.lo[e] + (c_own[e] + a.t64.xi[ke]) * a.h[e];
+          }
+        }
+        double qx[NV], Fx[NV];
+        PDE::boundary(x, t, dt, face, side ? qL : qR, side ? pL : pR, side ? FL : FR, qx, Fx);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (side) {
+            qR[v] = qx[v];
+            FR[v] = Fx[v];
+          } else {
+            qL[v] = qx[v];
+            FL[v] = Fx[v];
+          }
         }
       }
     }
@@ -1737,7 +1780,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     }
   }
 
-  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, traces, dt, cell0, tid, fl);
+  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, traces, clock[0], dt, cell0, tid, fl);
   __syncthreads();
 
   double lam = 0.0;
@@ -1808,7 +1851,7 @@ step_kernel_lin(const KArgs a, double* Q, const double* __restrict__ params, con
   for (int v = 0; v < NV; ++v) u1[v] = Q[(cl * NV + v) * S + k];
 #pragma unroll
   for (int p = 0; p < NP; ++p) P[p] = R(params[cl * NP + p]);
-  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, tr_in, dt, (int)cell0, tid, lds);
+  face_fluctuations<PDE, N, CPB, BLOCK>(a, params, tr_in, t_n, dt, (int)cell0, tid, lds);
   __syncthreads();
   if (active) {
     double surf[NV];

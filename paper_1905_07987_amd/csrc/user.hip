@@ -104,17 +104,18 @@ std::string prelude(const char* source) {
 
 adg_status user_traits(const char* source, const std::string& arch, UserTraits* t, std::string* err) {
   const std::string src = prelude(source) +
-                          "extern \"C\" __constant__ int adg_user_traits[6] = {AdgUserPDE::DIM, "
+                          "extern \"C\" __constant__ int adg_user_traits[7] = {AdgUserPDE::DIM, "
                           "AdgUserPDE::NV, AdgUserPDE::NP, (int)AdgUserPDE::LINEAR, "
-                          "(int)AdgUserPDE::HAS_NCP, (int)AdgUserPDE::HAS_SOURCE};\n";
+                          "(int)AdgUserPDE::HAS_NCP, (int)AdgUserPDE::HAS_SOURCE, "
+                          "(int)adg::UserHasBoundary<AdgUserPDE>::value};\n";
   Compiled c;
   adg_status st = rtc_compile(src, {}, arch, &c, err);
   if (st) return st;
   hipModule_t m = nullptr;
   hipError_t e = hipModuleLoadData(&m, c.code.data());
   if (e != hipSuccess) return hip_err(e, "hipModuleLoadData", err);
-  int v[6];
-  st = read_ints(m, "adg_user_traits", v, 6, err);
+  int v[7];
+  st = read_ints(m, "adg_user_traits", v, 7, err);
   (void)hipModuleUnload(m);
   if (st) return st;
   t->dim = v[0];
@@ -123,6 +124,7 @@ adg_status user_traits(const char* source, const std::string& arch, UserTraits* 
   t->linear = v[3];
   t->has_ncp = v[4];
   t->has_source = v[5];
+  t->has_boundary = v[6];
   return ADG_OK;
 }
 

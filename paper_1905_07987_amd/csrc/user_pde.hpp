@@ -15,6 +15,11 @@
 //     template <class R> __device__ static void ncp(const R* Q, const R* gradQ, R* BgradQ);
 //     template <class R> __device__ static void source(const R* Q, R* S);
 //     template <class R> __device__ static bool admissible(const R* Q);
+//     // optional, for ADG_BC_USER faces (the paper's boundaryValues):
+//     static constexpr bool HAS_BOUNDARY = true;
+//     __device__ static void boundary_values(const double* x, double t, double dt, int face,
+//                                            const double* Qin, const double* Fin,
+//                                            double* Qout, double* Fout);
 //   };
 //
 // Q holds the NV evolved quantities followed by the cell's NP parameters;
@@ -22,11 +27,28 @@
 // have NV entries; gradQ is [DIM][NV] (gradQ[d * NV + v] = dQ_v / dx_d).
 // R is double, or float in the mixed-precision predictor.  The kernels use
 // the largest absolute eigenvalue; admissible() is checked after finiteness.
+// boundary_values gets, at a node of a boundary face 2 d + side, the node's
+// position x[DIM], the step's start time t and size dt, the cell's own
+// time-averaged state (Qin, NV values and the NP parameters) and normal
+// flux (Fin, NV values) there, and returns the outside state and normal
+// flux (NV values each).
 #pragma once
 
 #include "kernels.hpp"
 
 namespace adg {
+
+template <class... T>
+using adg_void_t = void;
+
+template <class U, class = void>
+struct UserHasBoundary {
+  static constexpr bool value = false;
+};
+template <class U>
+struct UserHasBoundary<U, adg_void_t<decltype(U::HAS_BOUNDARY)>> {
+  static constexpr bool value = U::HAS_BOUNDARY;
+};
 
 template <class U>
 struct UserTerms {
@@ -35,6 +57,7 @@ struct UserTerms {
                 "AdgUserPDE: NV + NP must be in 1..16");
   static constexpr int DIM = U::DIM, NV = U::NV, NP = U::NP;
   static constexpr bool kHasNcp = U::HAS_NCP, kHasSource = U::HAS_SOURCE, kLinear = U::LINEAR;
+  static constexpr bool kUserBoundary = UserHasBoundary<U>::value;
   static constexpr bool flux_nonzero(int, int) { return true; }
   static constexpr bool grad_needed(int) { return U::HAS_NCP; }
 
@@ -88,6 +111,16 @@ struct UserTerms {
 #pragma unroll
     for (int v = 0; v < NV; ++v) m = fmax(m, fabs(lam[v]));
     return m;
+  }
+
+  __device__ static __forceinline__ void boundary(const double* x, double t, double dt, int face,
+                                                  const double* qin, const double* P, const double* Fin,
+                                                  double* qout, double* Fout) {
+    if constexpr (kUserBoundary) {
+      double q[NV + NP];
+      gather(qin, P, q);
+      U::boundary_values(x, t, dt, face, q, Fin, qout, Fout);
+    }
   }
 
   template <class R>

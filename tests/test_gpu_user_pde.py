@@ -222,3 +222,60 @@ def test_user_pde_errors():
     with pytest.raises(adg.AdgError) as ei:
         adg.Solver(3, 2, "euler", [2, 2, 2], source=EULER3, bc=[2, 2, 0, 0, 0, 0])
     assert ei.value.status == -1
+
+
+# Euler with the paper's boundaryValues user function: an inflow state that
+# depends on the face position and the time on the low x face, the mirror
+# image (a reflecting wall) elsewhere
+EULER3_BV = EULER3.replace("struct AdgUserPDE {", r"""struct AdgUserPDE {
+  static constexpr bool HAS_BOUNDARY = true;
+  __device__ static void boundary_values(const double* x, double t, double dt, int face, const double* Qin,
+                                         const double* Fin, double* Qout, double* Fout) {
+    if (face == 0) {
+      const double rho = 1.1 + 2.0 * (x[0] - 0.25) + 0.5 * (t - 0.3), u = 0.5, v = 0.1, p = 1.2;
+      Qout[0] = rho;
+      Qout[1] = rho * u;
+      Qout[2] = rho * v;
+      Qout[3] = 0.0;
+      Qout[4] = p / 0.4 + 0.5 * rho * (u * u + v * v);
+      flux<double>(Qout, 0, Fout);
+    } else {
+      const int d = face / 2;
+      for (int k = 0; k < 5; ++k) {
+        Qout[k] = Qin[k];
+        Fout[k] = -Fin[k];
+      }
+      Qout[1 + d] = -Qin[1 + d];
+      Fout[1 + d] = Fin[1 + d];
+    }
+  }""", 1)
+
+
+def test_user_boundary_values_vs_oracle():
+    # at x = 0.25 (the low face) and t = 0.3 the user's state is the oracle's
+    # prescribed inflow state; the other non-periodic faces are walls
+    print("[gpu-test] user boundary_values", flush=True)
+    cells, lo, hi = [3, 3, 2], [0.25, 0.0, 0.0], [1.25, 1.0, 1.0]
+    rho, u, v, p = 1.1, 0.5, 0.1, 1.2
+    q_in = [rho, rho * u, rho * v, 0.0, p / 0.4 + 0.5 * rho * (u * u + v * v)]
+    P = O.problem(3, 3, O.EULER, cells, lo, hi, bc=[O.BC_INFLOW, O.BC_WALL, 0, 0, O.BC_WALL, O.BC_WALL],
+                  bc_state={0: q_in})
+    Q0 = inputs.smooth_euler_state(O.node_coords(P), 77)
+    dt = 0.5 * O.stable_dt(P, Q0)[0]
+    Qo = O.step(P, Q0, None, dt, 0.3)
+    s = adg.Solver(3, 3, "euler", cells, lo, hi, source=EULER3_BV,
+                   bc=["user", "user", "periodic", "periodic", "user", "user"])
+    Q = torch.as_tensor(Q0, device="cuda")
+    s.step(Q, None, torch.tensor([0.3, dt], dtype=torch.float64, device="cuda"), next_dt=False)
+    torch.cuda.synchronize()
+    e = float(np.linalg.norm(Q.cpu().numpy() - Qo) / np.linalg.norm(Qo))
+    print(f"[gpu-test]   rel L2 vs oracle {e:.2e}", flush=True)
+    assert e <= TOL
+    s.close()
+    # without boundary_values the user face kind is refused
+    with pytest.raises(adg.AdgError) as ei:
+        adg.Solver(3, 2, "euler", cells, source=EULER3, bc=["user", "user", 0, 0, 0, 0])
+    assert ei.value.status == -1
+    with pytest.raises(adg.AdgError) as ei:
+        adg.Solver(3, 2, "euler", cells, bc=["user", "user", 0, 0, 0, 0])
+    assert ei.value.status == -1
