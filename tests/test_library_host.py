@@ -67,3 +67,11 @@ def test_library_limiter_tables_match_oracle(order):
     np.testing.assert_allclose(B, Bo, rtol=0, atol=1e-13 * max(1.0, np.abs(Bo).max()))
     np.testing.assert_allclose(Qf, Qfo, rtol=0, atol=1e-14 * max(1.0, np.abs(Qfo).max()))
     assert np.abs(B @ A - np.eye(order + 1)).max() < 1e-13
+
+
+def test_bad_limiter_order_is_an_error():
+    with pytest.raises(adg.AdgError) as e:
+        adg.limiter_tables(8)
+    assert e.value.status == -1
+    with pytest.raises(adg.AdgError):
+        adg.limiter_tables(-1)
