@@ -100,7 +100,7 @@ def lib():
 def limiter_tables(order: int):
     """Host-only: (A [m][n], B [n][m], Qf [n][m]) of the subcell limiter,
     n = order + 1, m = 2 order + 1."""
-    n, m = order + 1, 2 * order + 1
+    n, m = max(order + 1, 1), max(2 * order + 1, 1)  # the library refuses a bad order
     A, B, Qf = np.zeros((m, n)), np.zeros((n, m)), np.zeros((n, m))
     dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
     _check(lib().adg_limiter_tables(order, dp(A), dp(B), dp(Qf)))
