@@ -308,3 +308,48 @@ def test_limited_step_with_the_fp32_predictor():
     assert agree >= 0.9 and e <= 1e-2 and np.isfinite(Q32).all()
     s.close()
     s32.close()
+
+
+def test_long_limited_run_stays_conservative_and_physical():
+    # 400 limited steps of the explosion on 48^3 cells (t = 0.15): mass and
+    # energy conserved to rounding, FV data physical and above the ambient
+    # state's density and pressure (no new minima), the state finite
+    say("limiter 400 steps, 48^3 N=3")
+    cells, order = 48, 3
+    C = cells ** 3
+    s = adg.Solver(3, order, "euler", [cells] * 3, bc=["wall"] * 6, cfl=0.5)
+    Q = torch.as_tensor(inputs.blast_state(s.node_coords()), device="cuda")
+    fv, subfv = inputs.blast_fv_cells([cells] * 3, [0.0] * 3, [1.0] * 3, order)
+    sin = torch.zeros(s.subcell_shape, dtype=torch.float64, device="cuda")
+    fvd = torch.as_tensor(fv, device="cuda")
+    sin[fvd] = torch.as_tensor(subfv, device="cuda")
+    sout = torch.zeros_like(sin)
+    st = torch.zeros(C, dtype=torch.uint8, device="cuda")
+    st[fvd] = 3
+    clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+    w = torch.as_tensor(adg.basis_tables(order)["w"], device="cuda")
+    wk = (w[None, None, :] * w[None, :, None] * w[:, None, None]).reshape(-1)
+
+    def totals():
+        per = (Q * wk).sum(dim=2)
+        f = st >= 2
+        per[f] = sin[f].mean(dim=2)
+        return per.sum(dim=0)
+
+    m0 = totals()
+    s.stable_dt(Q, None, clock)
+    for _ in range(400):
+        s.step_limited(Q, clock, sin, sout, st, None, next_dt=True)
+        sin, sout = sout, sin
+    torch.cuda.synchronize()
+    m1 = totals()
+    t, dt = s.read_clock(clock)
+    f = st >= 2
+    sf = sin[f]
+    p = 0.4 * (sf[:, 4] - 0.5 * (sf[:, 1] ** 2 + sf[:, 2] ** 2 + sf[:, 3] ** 2) / sf[:, 0])
+    say(f"  t {t:.4f}, FV cells {int(f.sum())}, mass {(m1[0] / m0[0] - 1).item():.1e}, "
+        f"energy {(m1[4] / m0[4] - 1).item():.1e}, min rho {sf[:, 0].min().item():.4f}, min p {p.min().item():.4f}")
+    assert t > 0.1 and np.isfinite(dt) and bool(torch.isfinite(Q).all())
+    assert abs((m1[0] / m0[0] - 1).item()) <= 1e-12 and abs((m1[4] / m0[4] - 1).item()) <= 1e-12
+    assert sf[:, 0].min().item() >= 0.125 * (1 - 1e-9) and p.min().item() >= 0.04 * (1 - 1e-9)
+    s.close()
