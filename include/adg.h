@@ -320,7 +320,11 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
  * cells, DG cells with an FV face), or NULL.  The first call allocates the
  * context's limiter workspace: a copy of u^n and the FV face fluxes,
  * 1 + 2 dim / (order + 1) state arrays, plus 16 nvar + 10 bytes per cell.
- * Calls on one context must not overlap.  No host synchronisation. */
+ * Calls on one context must not overlap.  No host synchronisation, so the
+ * status values are not checked: the caller keeps them in 0..3.  Errors:
+ * INVALID_ARG (null arrays, sub_in == sub_out, unknown flags), UNSUPPORTED
+ * (not Euler, an order above the limit, inflow faces, run-time PDEs), NOMEM
+ * or HIP (workspace, launches). */
 adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
                             uint8_t* status, int32_t* counts, int flags, void* stream);
 
