@@ -153,7 +153,10 @@ struct GeoA2 {
   static constexpr int ITER_ELEMS = C::NCH * SP * 2;             // per cell, in R
   static constexpr int FIN_ELEMS = (G::NV + C::NFLUX) * SP;      // per cell, in R
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
-  static constexpr int by_threads = TPC >= 512 ? 1 : 512 / TPC;
+  // Blocks of about 512 threads; cells of at most 128 threads (N <= 3 in
+  // 3-D) go two to a block of 256, so that three blocks, not one, fill a CU
+  // at this kernel's register count and their barriers overlap.
+  static constexpr int by_threads = TPC >= 512 ? 1 : (TPC <= 128 ? 256 : 512) / TPC;
   static constexpr int by_lds = cmax(1, (64 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
   static constexpr int CPB = cmin(by_threads, by_lds);
   static constexpr int BLOCK = CPB * TPC;
