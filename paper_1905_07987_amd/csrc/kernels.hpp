@@ -1563,9 +1563,6 @@ struct GeoB {
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
 };
 
-// Corrector phase 1: the fluctuation of each cell's side at every face node
-// of the CPB cells from cell0 on (block-wide tasks, one per (cell, face,
-// face node)), scaled by dt / h_d, into fl[CPB][2 dim][NV][F].
 // PDEs with a boundary_values function for ADG_BC_USER faces (run-time PDEs
 // that define one)
 template <class... T>
@@ -1579,6 +1576,9 @@ struct HasUserBoundary<P, kern_void_t<decltype(P::kUserBoundary)>> {
   static constexpr bool value = P::kUserBoundary;
 };
 
+// Corrector phase 1: the fluctuation of each cell's side at every face node
+// of the CPB cells from cell0 on (block-wide tasks, one per (cell, face,
+// face node)), scaled by dt / h_d, into fl[CPB][2 dim][NV][F].
 template <class PDE, int N, int CPB, int BLOCK>
 __device__ __forceinline__ void face_fluctuations(const KArgs& a, const double* __restrict__ params,
                                                   const double* __restrict__ traces, double t, double dt,
