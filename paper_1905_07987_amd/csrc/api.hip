@@ -544,6 +544,7 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
                 "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
   for (int f = 0; f < 6; ++f)
     if (ctx->args.bc[f] == ADG_BC_INFLOW) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter has no inflow faces");
+  if (ctx->C > 0x7fffffffLL) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter indexes cells with 32-bit lists");
   adg_status st = check_state(ctx, Q, nullptr);
   if (st) return st;
   if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");
