@@ -288,6 +288,14 @@ adg_status adg_predict(adg_ctx* ctx, const double* Q, const double* params, cons
 adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                        void* stream);
 
+/* Allocates the workspace of adg_step_limited on the context's device (a
+ * copy of u^n and the FV face fluxes, 1 + 2 dim / (order + 1) state arrays,
+ * plus 16 nvar + 10 bytes per cell, and the limiter tables), once; later
+ * calls do nothing.  Synchronous; the step itself then allocates nothing.
+ * Errors: UNSUPPORTED where adg_step_limited is not built, NOMEM, HIP,
+ * STATE (another current device). */
+adg_status adg_limiter_reserve(adg_ctx* ctx);
+
 /* One step with the a-posteriori subcell limiter (Sec. 3.5, the hybrid
  * ADER-DG/FV method with the status stencil of Fig. 2), in place, for the
  * Euler equations (2-D N <= 7, 3-D N <= 3; else ADG_ERR_UNSUPPORTED):
@@ -317,14 +325,13 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
  * status >= 2 are read (sub_in, status before the step) or written
  * (sub_out, status after it); they must be distinct arrays, and a run
  * swaps them every step.  counts: device int32[3] (troubled cells, FV
- * cells, DG cells with an FV face), or NULL.  The first call allocates the
- * context's limiter workspace: a copy of u^n and the FV face fluxes,
- * 1 + 2 dim / (order + 1) state arrays, plus 16 nvar + 10 bytes per cell.
- * Calls on one context must not overlap.  No host synchronisation, so the
- * status values are not checked: the caller keeps them in 0..3.  Errors:
- * INVALID_ARG (null arrays, sub_in == sub_out, unknown flags), UNSUPPORTED
- * (not Euler, an order above the limit, inflow faces, run-time PDEs), NOMEM
- * or HIP (workspace, launches). */
+ * cells, DG cells with an FV face), or NULL.  The context's limiter
+ * workspace comes from adg_limiter_reserve (STATE without it).  Calls on
+ * one context must not overlap.  No allocation and no host synchronisation,
+ * so the status values are not checked: the caller keeps them in 0..3.
+ * Errors: INVALID_ARG (null arrays, sub_in == sub_out, unknown flags),
+ * UNSUPPORTED (not Euler, an order above the limit, inflow faces, run-time
+ * PDEs), STATE (no workspace reserved), HIP (launches). */
 adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
                             uint8_t* status, int32_t* counts, int flags, void* stream);
 

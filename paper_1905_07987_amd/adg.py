@@ -93,6 +93,7 @@ def lib():
         L.adg_sample_receivers_adjoint.argtypes = [vp, vp, vp, vp]
         L.adg_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
         L.adg_step_limited.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.adg_limiter_reserve.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -113,7 +114,7 @@ EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create",
             "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
             "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint",
-            "adg_limiter_tables", "adg_step_limited")
+            "adg_limiter_tables", "adg_limiter_reserve", "adg_step_limited")
 
 
 def _check(st: int):
@@ -180,6 +181,7 @@ class Solver:
         self.nvar, self.nparam = info.nvar, info.nparam
         self.S, self.F, self.ncells = info.nodes_per_cell, info.face_nodes, info.ncells
         self.nrec = 0
+        self._limiter_ready = False
 
     def close(self):
         if self._ctx:
@@ -277,6 +279,12 @@ class Solver:
         """Shape of the FV subcell arrays of the subcell limiter."""
         return (self.ncells, self.nvar, (2 * self.order + 1) ** self.dim)
 
+    def reserve_limiter(self):
+        """Allocate the subcell limiter's workspace (done on the first
+        step_limited call otherwise)."""
+        _check(lib().adg_limiter_reserve(self._ctx))
+        self._limiter_ready = True
+
     def step_limited(self, Q, clock, sub_in, sub_out, status, counts=None, next_dt: bool = True,
                      stream=None):
         """One step with the a-posteriori subcell limiter (Euler): Q, status
@@ -284,6 +292,8 @@ class Solver:
         data before and after the step (distinct tensors, swapped by the
         caller each step); counts (int32 [3]) or None."""
         import torch
+        if not self._limiter_ready:
+            self.reserve_limiter()
         cnt = C.c_void_p() if counts is None else self._dev(counts, (3,), torch.int32, "counts")
         _check(lib().adg_step_limited(
             self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),

@@ -536,20 +536,15 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
   return ADG_OK;
 }
 
-adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
-                            uint8_t* status, int32_t* counts, int flags, void* stream) {
+adg_status adg_limiter_reserve(adg_ctx* ctx) {
   if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
   if (!ctx->ks || !ctx->ks->lim_before || !ctx->ks->lim_after)
     return fail(ADG_ERR_UNSUPPORTED,
                 "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
-  for (int f = 0; f < 6; ++f)
-    if (ctx->args.bc[f] == ADG_BC_INFLOW) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter has no inflow faces");
   if (ctx->C > 0x7fffffffLL) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter indexes cells with 32-bit lists");
-  adg_status st = check_state(ctx, Q, nullptr);
-  if (st) return st;
-  if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");
-  if (sub_in == sub_out) return fail(ADG_ERR_INVALID_ARG, "sub_in and sub_out must be different arrays");
-  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+    return fail(ADG_ERR_STATE, "current HIP device differs from the context's device");
   const long long C = ctx->C;
   const int nv = ctx->nv, S = ctx->S, n = ctx->n, m = 2 * n - 1;
   if (!ctx->lim_block) {
@@ -562,7 +557,7 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
     size_t total = 0;
     for (size_t b : sz) total += b;
     void* blk = nullptr;
-    ADG_HIP(hipMalloc(&blk, total));
+    if (hipMalloc(&blk, total) != hipSuccess) return fail(ADG_ERR_NOMEM, "limiter workspace");
     std::vector<double> tab(ntab);
     if (limiter_tables(n, tab.data(), tab.data() + m * n, tab.data() + 2 * m * n)) {
       (void)hipFree(blk);
@@ -586,6 +581,24 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
     w.gfv = (double*)p;
     ctx->lim_block = blk;
   }
+  return ADG_OK;
+}
+
+adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double* sub_in, double* sub_out,
+                            uint8_t* status, int32_t* counts, int flags, void* stream) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  if (!ctx->ks || !ctx->ks->lim_before || !ctx->ks->lim_after)
+    return fail(ADG_ERR_UNSUPPORTED,
+                "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->args.bc[f] == ADG_BC_INFLOW) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter has no inflow faces");
+  if (ctx->C > 0x7fffffffLL) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter indexes cells with 32-bit lists");
+  adg_status st = check_state(ctx, Q, nullptr);
+  if (st) return st;
+  if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");
+  if (sub_in == sub_out) return fail(ADG_ERR_INVALID_ARG, "sub_in and sub_out must be different arrays");
+  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  if (!ctx->lim_block) return fail(ADG_ERR_STATE, "adg_step_limited needs adg_limiter_reserve first");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = ctx->ks->lim_before(ctx->args, Q, sub_in, status, ctx->lim, s);
   if (e != hipSuccess) return hip_fail(e, "limiter prepare launch");

@@ -214,6 +214,22 @@ def test_limiter_errors():
     r = adg.lib().adg_step_limited(s._ctx, Q.data_ptr(), dev([0.0, 1e-3]).data_ptr(), sub.data_ptr(),
                                    sub2.data_ptr(), st.data_ptr(), None, 0, None)
     assert r == -4  # not built for elasticity
+    assert adg.lib().adg_limiter_reserve(s._ctx) == -4
+    s.close()
+    # the step allocates nothing: without the reserved workspace it is a
+    # state error, after adg_limiter_reserve (idempotent) it runs
+    s = adg.Solver(2, 2, "euler", [3, 3])
+    Q = torch.ones(s.state_shape, dtype=torch.float64, device="cuda")
+    Q[:, 3] = 2.5
+    z1 = torch.zeros(s.subcell_shape, dtype=torch.float64, device="cuda")
+    z2 = torch.zeros_like(z1)
+    st = torch.zeros(s.ncells, dtype=torch.uint8, device="cuda")
+    clk = dev([0.0, 1e-3])
+    args = (s._ctx, Q.data_ptr(), clk.data_ptr(), z1.data_ptr(), z2.data_ptr(), st.data_ptr(), None, 0, None)
+    assert adg.lib().adg_step_limited(*args) == -6
+    assert adg.lib().adg_limiter_reserve(s._ctx) == 0 and adg.lib().adg_limiter_reserve(s._ctx) == 0
+    assert adg.lib().adg_step_limited(*args) == 0
+    torch.cuda.synchronize()
     s.close()
     if adg.max_order("euler", 3) >= 4:
         s = adg.Solver(3, 4, "euler", [2, 2, 2])
