@@ -144,7 +144,9 @@ typedef struct {
   int face_nodes;        /* n^(dim-1) */
   long long ncells;      /* C */
   long long state_elems; /* C * nvar * S */
-  size_t workspace_bytes;
+  size_t workspace_bytes; /* device bytes the context holds: face traces,
+                            reduction slots, and the limiter workspace once
+                            adg_limiter_reserve has run */
   size_t trace_elems;    /* C * 2 dim * 2 * nvar * face_nodes */
 } adg_info;
 

@@ -37,6 +37,7 @@ struct adg_ctx {
   // subcell limiter workspace (allocated on the first limited step)
   LimWork lim{};
   void* lim_block = nullptr;
+  size_t lim_bytes = 0;  // size of lim_block
   double* d_bc_state = nullptr;  // [6][2][nvar][F] outside traces of inflow faces
 };
 
@@ -447,7 +448,7 @@ adg_status adg_query(const adg_ctx* ctx, adg_info* info) {
   info->ncells = ctx->C;
   info->state_elems = ctx->C * ctx->nv * ctx->S;
   info->trace_elems = ctx->trace_elems;
-  info->workspace_bytes = ctx->trace_elems * sizeof(double) + ctx->red_bytes;
+  info->workspace_bytes = ctx->trace_elems * sizeof(double) + ctx->red_bytes + ctx->lim_bytes;
   return ADG_OK;
 }
 
@@ -580,6 +581,7 @@ adg_status adg_limiter_reserve(adg_ctx* ctx) {
     w.counters = (int*)p;       p += sz[7];
     w.gfv = (double*)p;
     ctx->lim_block = blk;
+    ctx->lim_bytes = total;
   }
   return ADG_OK;
 }
