@@ -235,7 +235,12 @@ adg_status adg_node_coords(const adg_ctx* ctx, double* xyz);
 
 /* Eq. (7): clock[1] <- cfl / (dim (2N + 1)) * min_d h_d / lambda_max, with
  * lambda_max the largest absolute eigenvalue over all cells, nodes and
- * directions of Q.  clock[0] is not touched.  A NaN anywhere makes dt NaN. */
+ * directions of Q.  clock[0] is not touched.  A NaN eigenvalue bound at any
+ * node is not skipped: lambda_max and dt become NaN.  For Euler that is any
+ * NaN in Q and any state whose sound speed is the square root of a negative
+ * number (e.g. a negative pressure at positive density); the speeds of
+ * elasticity (cp of the cell) and advection (|a_d|) do not depend on Q, so a
+ * non-finite Q leaves their dt finite: adg_check_admissible detects it. */
 adg_status adg_stable_dt(adg_ctx* ctx, const double* Q, const double* params, double* clock,
                          void* stream);
 
@@ -248,23 +253,36 @@ adg_status adg_read_clock_host(const double* clock, double* host, void* stream);
  * dt = clock[1] and t^n = clock[0]; afterwards clock[0] <- t^n + dt.
  * flags: ADG_STEP_NEXT_DT also evaluates Eq. (7) on u^{n+1} during the
  * update and stores it in clock[1] (bitwise the value adg_stable_dt would
- * give); without it clock[1] is left unchanged (a frozen step size).
+ * give, NaN included); without it clock[1] is left unchanged (a frozen step
+ * size).
  * Does not test for non-finite values: that is adg_check_admissible. */
 #define ADG_STEP_NEXT_DT 1
 adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                     void* stream);
 
-/* nsteps FP64 steps in place with the step size clock[1] held fixed (as in
- * adg_step without ADG_STEP_NEXT_DT; clock[0] advances by dt each step).
- * rec_out (device [nsteps][nrec][nvar], or NULL) receives the receiver
- * samples after every step.  For the built-in PDEs linear in Q (elasticity,
- * advection; picard_iters <= 16) the corrector of each step and the
- * predictor of the next run as one kernel (the step fusion of Sec. 5.1:
- * one pass over the state per step instead of two), with a second trace
- * array allocated on first use; otherwise the steps run one by one.  The
- * states are those of nsteps adg_step calls; samples agree with
- * adg_sample_receivers to rounding.  Leaves the trace workspace unusable
- * for adg_correct. */
+/* Allocates the second face-trace array that fused runs of adg_run swap
+ * with the workspace (trace_elems doubles, see adg_query), once, on the
+ * context's device; later calls, and contexts whose runs do not fuse
+ * (PDEs not linear in Q, picard_iters > 16, run-time PDEs), do nothing.
+ * Synchronous.  Errors: INVALID_ARG (null), STATE (another current device),
+ * NOMEM. */
+adg_status adg_run_reserve(adg_ctx* ctx);
+
+/* nsteps steps in place with the step size clock[1] held fixed (as in
+ * adg_step without ADG_STEP_NEXT_DT; clock[0] advances by dt each step), in
+ * the context's precision.  rec_out (device [nsteps][nrec][nvar], or NULL)
+ * receives the receiver samples after every step.  For the built-in PDEs
+ * linear in Q (elasticity, advection; picard_iters <= 16) the corrector of
+ * each step and the predictor of the next run as one kernel (the step
+ * fusion of Sec. 5.1: one pass over the state per step instead of two),
+ * alternating between the trace workspace and the array of adg_run_reserve
+ * (STATE if that was not called); otherwise the steps run one by one.  No
+ * allocation and no host synchronisation.  The states are those of nsteps
+ * adg_step calls; samples agree with adg_sample_receivers to rounding.
+ * Leaves the trace workspace unusable for adg_correct.  Errors:
+ * INVALID_ARG (null Q or clock, nsteps < 0, missing params), STATE (no
+ * receivers set with rec_out, fused run without adg_run_reserve, another
+ * current device), HIP. */
 adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
                    double* rec_out, void* stream);
 
@@ -294,8 +312,10 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
  * copy of u^n and the FV face fluxes, 1 + 2 dim / (order + 1) state arrays,
  * plus 16 nvar + 10 bytes per cell, and the limiter tables), once; later
  * calls do nothing.  Synchronous; the step itself then allocates nothing.
- * Errors: UNSUPPORTED where adg_step_limited is not built, NOMEM, HIP,
- * STATE (another current device). */
+ * Errors: INVALID_ARG (null context; limiter tables not constructible),
+ * UNSUPPORTED where adg_step_limited is not built (not Euler, an order
+ * above the limit, inflow faces, run-time PDEs, more than 2^31 - 1 cells),
+ * NOMEM, HIP, STATE (another current device). */
 adg_status adg_limiter_reserve(adg_ctx* ctx);
 
 /* One step with the a-posteriori subcell limiter (Sec. 3.5, the hybrid

@@ -909,9 +909,19 @@ int orc_rusanov(const orc_problem *P, int d, const double *qL, const double *FL,
   return ORC_OK;
 }
 
+/* Maximum of two signal speeds for Eq. (7).  READING: a NaN speed (for
+ * Euler: a NaN in the state, or a state where the sound speed is the square
+ * root of a negative number, such as a negative pressure at positive density)
+ * is not skipped: the maximum, and with it dt, becomes NaN.  Speeds of the
+ * linear PDEs do not depend on the state. */
+static double speed_max(double a, double b) {
+  if (isnan(a) || isnan(b)) return NAN;
+  return a > b ? a : b;
+}
+
 /* Eq. (7): dt = CFL / (d (2N+1)) * h / |lambda_max|.
  * READING: h = min_d h_d, lambda_max = max over cells, nodes and directions
- * of the largest absolute eigenvalue, evaluated on u^n. */
+ * of the largest absolute eigenvalue, evaluated on u^n; NaN as above. */
 int orc_stable_dt(const orc_problem *P, const double *Q, const double *params, double *dt,
                   double *lambda_max) {
   mesh M;
@@ -922,7 +932,7 @@ int orc_stable_dt(const orc_problem *P, const double *Q, const double *params, d
       double q[ORC_MAXQ];
       for (int v = 0; v < M.nv; ++v) q[v] = Q[((size_t)c * M.nv + v) * M.S + k];
       for (int p = 0; p < P->nparam; ++p) q[M.nv + p] = params[(size_t)c * P->nparam + p];
-      for (int d = 0; d < M.dim; ++d) lam = fmax(lam, pde_max_eigen(P, q, d));
+      for (int d = 0; d < M.dim; ++d) lam = speed_max(lam, pde_max_eigen(P, q, d));
     }
   double h = M.h[0];
   for (int d = 1; d < M.dim; ++d) h = fmin(h, M.h[d]);
@@ -2171,7 +2181,7 @@ int orc_stable_dt_limited(const orc_problem *P, const double *Q, const double *s
       double q[ORC_MAXQ];
       for (int v = 0; v < M.nv; ++v)
         q[v] = fv ? sub[((size_t)c * M.nv + v) * ns + k] : Q[((size_t)c * M.nv + v) * M.S + k];
-      for (int d = 0; d < M.dim; ++d) lam = fmax(lam, pde_max_eigen(P, q, d));
+      for (int d = 0; d < M.dim; ++d) lam = speed_max(lam, pde_max_eigen(P, q, d));
     }
   }
   double h = M.h[0];

@@ -83,6 +83,7 @@ def lib():
         L.adg_step.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_read_clock_host.argtypes = [vp, dp, vp]
         L.adg_run.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.adg_run_reserve.argtypes = [vp]
         L.adg_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_correct.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_check_admissible.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -110,6 +111,7 @@ def limiter_tables(order: int):
 
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
             "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_run",
+            "adg_run_reserve",
             "adg_predict",
             "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
@@ -182,6 +184,7 @@ class Solver:
         self.S, self.F, self.ncells = info.nodes_per_cell, info.face_nodes, info.ncells
         self.nrec = 0
         self._limiter_ready = False
+        self._run_ready = False
 
     def close(self):
         if self._ctx:
@@ -261,11 +264,19 @@ class Solver:
         ([nsteps, nrec, nvar] float64 or None) receives the receiver samples
         after every step.  Fused corrector/predictor kernels where built."""
         import torch
+        if not self._run_ready:
+            self.reserve_run()
         ro = None
         if rec_out is not None:
             ro = self._dev(rec_out, (nsteps, self.nrec, self.nvar), torch.float64, "rec_out")
         _check(lib().adg_run(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"), self._params(params),
                              self._dev(clock, (2,), torch.float64, "clock"), int(nsteps), ro, _stream(stream)))
+
+    def reserve_run(self):
+        """Allocate the second trace array of fused runs (done on the first
+        run call otherwise)."""
+        _check(lib().adg_run_reserve(self._ctx))
+        self._run_ready = True
 
     def read_clock(self, clock, stream=None):
         """(t, dt) of a device clock, after the work queued on the stream."""

@@ -22,7 +22,7 @@ struct adg_ctx {
   const KernelSet* ks = nullptr;
   KArgs args{};
   double* traces = nullptr;  // [C][2 dim][2][nv][F]
-  double* traces2 = nullptr; // the second trace array of fused runs (allocated on first use)
+  double* traces2 = nullptr; // the second trace array of fused runs (adg_run_reserve)
   size_t trace_elems = 0;
   void* red = nullptr;       // reduction slots
   size_t red_bytes = 0;
@@ -448,7 +448,8 @@ adg_status adg_query(const adg_ctx* ctx, adg_info* info) {
   info->ncells = ctx->C;
   info->state_elems = ctx->C * ctx->nv * ctx->S;
   info->trace_elems = ctx->trace_elems;
-  info->workspace_bytes = ctx->trace_elems * sizeof(double) + ctx->red_bytes + ctx->lim_bytes;
+  info->workspace_bytes = ctx->trace_elems * sizeof(double) * (ctx->traces2 ? 2 : 1) + ctx->red_bytes +
+                          ctx->lim_bytes;
   return ADG_OK;
 }
 
@@ -542,6 +543,8 @@ adg_status adg_limiter_reserve(adg_ctx* ctx) {
   if (!ctx->ks || !ctx->ks->lim_before || !ctx->ks->lim_after)
     return fail(ADG_ERR_UNSUPPORTED,
                 "the subcell limiter is built for the Euler equations (2-D: N <= 7, 3-D: N <= 3)");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->args.bc[f] == ADG_BC_INFLOW) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter has no inflow faces");
   if (ctx->C > 0x7fffffffLL) return fail(ADG_ERR_UNSUPPORTED, "the subcell limiter indexes cells with 32-bit lists");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
@@ -744,6 +747,23 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
   return ADG_OK;
 }
 
+static bool run_fuses(const adg_ctx* ctx) {
+  return ctx->ks && ctx->ks->step_fused && ctx->args.picard_iters <= kMaxLin;
+}
+
+adg_status adg_run_reserve(adg_ctx* ctx) {
+  if (!ctx) return fail(ADG_ERR_INVALID_ARG, "null context");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+    return fail(ADG_ERR_STATE, "current HIP device differs from the context's device");
+  if (!run_fuses(ctx) || ctx->traces2) return ADG_OK;
+  double* p = nullptr;
+  hipError_t e = hipMalloc((void**)&p, ctx->trace_elems * sizeof(double));
+  if (e != hipSuccess) return fail(ADG_ERR_NOMEM, std::string("second trace array: ") + hipGetErrorString(e));
+  ctx->traces2 = p;
+  return ADG_OK;
+}
+
 adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
                    double* rec_out, void* stream) {
   adg_status st = check_state(ctx, Q, params);
@@ -760,7 +780,8 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
                        rec_out + n * rec_stride, ctx->nv, ctx->S);
     return hipGetLastError();
   };
-  const bool fused = ctx->ks && ctx->ks->step_fused && ctx->args.picard_iters <= kMaxLin && nsteps > 1;
+  const bool fused = run_fuses(ctx) && nsteps > 1;
+  if (fused && !ctx->traces2) return fail(ADG_ERR_STATE, "adg_run needs adg_run_reserve first (fused steps)");
   hipError_t e = hipSuccess;
   if (!fused) {
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
@@ -769,13 +790,6 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
       if (e == hipSuccess) e = sample(n);
     }
   } else {
-    if (!ctx->traces2) {
-      e = hipMalloc((void**)&ctx->traces2, ctx->trace_elems * sizeof(double));
-      if (e != hipSuccess) {
-        ctx->traces2 = nullptr;
-        return fail(ADG_ERR_NOMEM, std::string("second trace array: ") + hipGetErrorString(e));
-      }
-    }
     KArgs a = ctx->args;
     a.nrec = rec_out ? ctx->nrec : 0;
     a.rec_cell = ctx->d_rec_cell;

@@ -225,19 +225,28 @@ __device__ __forceinline__ void node_coords(int k, int n, int* kk) {
   if (DIM == 3) kk[2] = k / (n * n);
 }
 
-// Block-level max of non-negative doubles; returns the block max in thread 0.
-// Every thread stores its value in LDS; the first wave (always complete:
-// BLOCK >= 64) folds the block and reduces across its lanes, so no shuffle
-// ever reads a lane that does not exist in a partial last wave.
+// Maximum of two signal speeds (non-negative doubles) for Eq. (7) that keeps
+// a NaN: a NaN operand gives the positive quiet NaN, whose bit pattern ranks
+// above +inf in the ordered-bits atomic max of the reduction slots, so one
+// NaN speed anywhere makes the step size NaN (fmax would drop it).
+__device__ __forceinline__ double lam_max(double a, double b) {
+  const double m = fmax(a, b);
+  return (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000LL) : m;
+}
+
+// Block-level maximum of signal speeds (lam_max); returns the block maximum
+// in thread 0.  Every thread stores its value in LDS; the first wave (always
+// complete: BLOCK >= 64) folds the block and reduces across its lanes, so no
+// shuffle ever reads a lane that does not exist in a partial last wave.
 template <int BLOCK>
 __device__ __forceinline__ double block_max(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
   double m = 0.0;
   if (threadIdx.x < 64) {
-    for (int i = threadIdx.x; i < BLOCK; i += 64) m = fmax(m, red[i]);
+    for (int i = threadIdx.x; i < BLOCK; i += 64) m = lam_max(m, red[i]);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    for (int off = 32; off > 0; off >>= 1) m = lam_max(m, __shfl_xor(m, off, 64));
   }
   return m;
 }
@@ -1800,7 +1809,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
     }
     if (next_dt) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(qn, P, a.pde, d));
+      for (int d = 0; d < DIM; ++d) lam = lam_max(lam, PDE::max_eigen(qn, P, a.pde, d));
     }
   }
   if (next_dt) {
@@ -1908,7 +1917,7 @@ lambda_kernel(const KArgs a, const double* __restrict__ Q, const double* __restr
 #pragma unroll
     for (int p = 0; p < NP; ++p) P[p] = params[cell * NP + p];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(q, P, a.pde, d));
+    for (int d = 0; d < DIM; ++d) lam = lam_max(lam, PDE::max_eigen(q, P, a.pde, d));
   }
   const double m = block_max<GB::BLOCK>(lam, red);
   if (tid == 0) slot_max(a.slots, blockIdx.x, m);
@@ -1993,6 +2002,7 @@ count_kernel(unsigned long long* __restrict__ slots, int32_t* __restrict__ count
 
 }  // namespace adg
 
+#include "predict64.hpp"
 #include "adjoint.hpp"
 
 #if !defined(__HIPCC_RTC__)
@@ -2025,10 +2035,23 @@ __global__ void __launch_bounds__(64) bc_flux_kernel(const KArgs a, double* __re
     for (int k = 0; k < F; ++k) tr[((f * 2 + 1) * NV + v) * F + k] = PDE::flux_nonzero(d, v) ? Fx[d][v] : 0.0;
 }
 
+// The FP64 predictor of PDEs that are not linear in Q: one thread per node
+// (predict_kernel_n64) where a cell fits one block of at most four waves,
+// else the lane-pair kernel.
+template <class PDE, int N>
+struct UseN64 {
+#if defined(ADG_PAIR_PREDICTOR)
+  static constexpr bool value = false;
+#else
+  static constexpr bool value = GeoN64<PDE, N>::fits;
+#endif
+};
+
 template <class PDE, int N>
 struct Launch {
   using G = Geo<PDE, N>;
   using GB = GeoB<PDE, N>;
+  using GP = std::conditional_t<UseN64<PDE, N>::value, GeoN64<PDE, N>, GeoA2<PDE, N, double>>;
   template <class GA>
   static int blocks_a(const KArgs& a) {
     return (int)((a.ncells + GA::CPB - 1) / GA::CPB);
@@ -2061,6 +2084,11 @@ struct Launch {
       a.nblocks = blocks_a<GA>(a);
       hipLaunchKernelGGL((predict_kernel_node<PDE, N, float>), dim3(a.nblocks), dim3(GA::BLOCK), 0,
                          st, a, Q, params, clock, Qout, traces);
+    } else if constexpr (UseN64<PDE, N>::value) {
+      using GA = GeoN64<PDE, N>;
+      a.nblocks = blocks_a<GA>(a);
+      hipLaunchKernelGGL((predict_kernel_n64<PDE, N>), dim3(a.nblocks), dim3(GA::BLOCK), 0, st, a, Q,
+                         params, clock, Qout, traces);
     } else {
       using GA = GeoA2<PDE, N, double>;
       a.nblocks = blocks_a<GA>(a);
@@ -2147,7 +2175,7 @@ struct Launch {
     return hipGetLastError();
   }
   static const KernelSet* set() {
-    static const KernelSet ks = {GeoA2<PDE, N, double>::BLOCK, GeoA2<PDE, N, double>::CPB, GB::CPB,
+    static const KernelSet ks = {GP::BLOCK, GP::CPB, GB::CPB,
                                  &predict, &correct, &stable_dt, &admissible, adjoint_entry(),
                                  step_fused_entry(), lim_before_entry(), lim_after_entry(), &bc_flux};
     return &ks;

@@ -748,14 +748,14 @@ lim_lambda_kernel(const KArgs a, const double* __restrict__ Q, const double* __r
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] = base[v * npts + k];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) lam = fmax(lam, PDE::max_eigen(q, q, a.pde, d));
+      for (int d = 0; d < DIM; ++d) lam = lam_max(lam, PDE::max_eigen(q, q, a.pde, d));
     }
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) lam = fmax(lam, __shfl_xor(lam, off, 64));
+  for (int off = 32; off > 0; off >>= 1) lam = lam_max(lam, __shfl_xor(lam, off, 64));
   if (lane == 0) red[wv] = lam;
   __syncthreads();
-  if (tid == 0) slot_max(a.slots, blockIdx.x, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+  if (tid == 0) slot_max(a.slots, blockIdx.x, lam_max(lam_max(red[0], red[1]), lam_max(red[2], red[3])));
 }
 
 template <class PDE, int N>

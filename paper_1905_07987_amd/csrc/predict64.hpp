@@ -1,0 +1,382 @@
+// FP64 space-time predictor with one thread per spatial node and the whole
+// time history of the node in that thread's registers (ExaHyPE paper,
+// Sec. 3.3, Eq. (5): q^{r+1}_i = u^n + dt sum_j (K1^{-1})_ij w_j R(q^r)_j).
+//
+// Because every lane of a wave owns all n time slices, the coefficients of
+// the time operator are the same for every lane: they are compile-time
+// constants and live in scalar registers, and the Picard update needs no
+// exchange between lanes.  A cell of n^3 <= 256 nodes is one block of at most
+// four waves, so with <= 256 registers per lane two blocks share a compute
+// unit and one block's barriers are covered by the other's work.
+//
+// Spatial derivatives go through LDS one time slice at a time: the node
+// threads write the fluxes (and the quantities the non-conservative product
+// differentiates) of slice j into line-major rows, one thread per
+// (direction, channel, line) differentiates its line in place, and the node
+// threads read their derivatives back, two slices per round.
+#pragma once
+
+namespace adg {
+
+template <class PDE, int N>
+struct GeoN64 {
+  using G = Geo<PDE, N>;
+  using C = Chan<PDE>;
+  static constexpr int n = G::n, S = G::S, F = G::F, DIM = G::DIM, NV = G::NV;
+  // Cells of fewer than 64 nodes share a wave.
+  static constexpr int CPB = S >= 64 ? 1 : 64 / S;
+  static constexpr int LANES = CPB * S;
+  static constexpr int BLOCK = (LANES + 63) / 64 * 64;
+  static constexpr int LS = G::LS, SP = G::SP;
+  static constexpr int ITER_ELEMS = 2 * C::NCH * SP;           // two slices of one cell, paired
+  static constexpr int FIN_ELEMS = DIM * (NV + C::NFLUX) * SP;  // final phase, all directions
+  static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
+  static constexpr int ELEMS = CPB * CELL_ELEMS;
+  static constexpr bool fits = ELEMS * 8 <= 80 * 1024 && BLOCK <= 256;
+  // two 4-wave blocks per compute unit: at most 256 registers per lane
+  static constexpr int MIN_WAVES = 2;
+};
+
+template <class PDE, int N>
+__global__ void __launch_bounds__((GeoN64<PDE, N>::BLOCK), (GeoN64<PDE, N>::MIN_WAVES))
+predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ params,
+                   const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // Q and Qout may be the same array (in-place step): each element is read
+  // at the start and written at the end by the thread of its node.
+  using GN = GeoN64<PDE, N>;
+  using C = Chan<PDE>;
+  using T = CT<double, GN::n>;
+  constexpr int n = GN::n, S = GN::S, F = GN::F, NV = GN::NV, NP = PDE::NP, DIM = GN::DIM;
+  constexpr int CPB = GN::CPB, BLOCK = GN::BLOCK, SP = GN::SP, LS = GN::LS;
+  constexpr int NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
+  static_assert(C::uniform(), "flux sparsity must be the same in every direction");
+  static_assert(GN::fits, "predictor block exceeds its LDS or thread budget");
+  __shared__ double lds[GN::ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lc = tid / S;  // local cell (CPB means idle lanes in the last wave)
+  const int k = tid - lc * S;
+  const bool node = lc < CPB;
+  const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const long long cell = cell0 + (node ? lc : 0);
+  const bool active = node && cell < a.ncells;
+  const long long cl = cell < a.ncells ? cell : a.ncells - 1;  // clamp loads of the ragged tail
+
+  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  {
+    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kd[3] = {kx, ky, kz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pk[d] = GN::G::line_of(d, kx, ky, kz) * LS + kd[d];
+  }
+
+  double u[NV], P[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) P[p] = params[cl * NP + p];
+  const double t_n = clock[0], dt = clock[1];
+
+  // Point sources: the Ricker amplitude at the n time nodes of this step,
+  // once per block; only blocks holding a source cell use them.
+  __shared__ double src_amp[kMaxSources * n];
+  bool src_here = false;
+  for (int s = 0; s < a.nsrc; ++s)
+    src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
+  if (src_here && tid < a.nsrc * n) {
+    const int s = tid / n, j = tid - s * n;
+    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt);
+  }
+  // (made visible by the first barrier below)
+  auto add_point_sources = [&](int j, double* Sv) {
+    if (!src_here || !node) return;
+    for (int s = 0; s < a.nsrc; ++s) {
+      if (a.src[s].cell != cell) continue;
+      const double amp = src_amp[s * n + j];
+      const double* wsk = a.src_w + ((long long)s * S + k) * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sv[v] += amp * wsk[v];
+    }
+  };
+
+  double q[n][NV];  // iterate at the n time nodes of node k; R_j replaces q_j
+  double Fbar[DIM][NV], Nbar[NV], Sbar[NV], qbar[NV];  // final pass: time averages
+
+  // One LDS round for slices j0 and j1 of the current iterate (j1 == j0:
+  // one slice): the two slices of a (channel, node) share one 16-byte
+  // element, so the node threads' writes and read-backs and the line tasks
+  // all move 16 bytes per access.  FIN: only the gradients the
+  // non-conservative product reads (the final pass averages the fluxes and
+  // differentiates their average once).
+  using P2 = Pair<double>;
+  P2* const lds2 = reinterpret_cast<P2*>(lds);
+  auto round = [&](auto fin_tag, int j0, int j1, double (&div0)[NV], double (&g0)[DIM][NV], double (&div1)[NV],
+                   double (&g1)[DIM][NV]) {
+    constexpr bool FIN = decltype(fin_tag)::value;
+    P2* const mine = lds2 + lc * (GN::CELL_ELEMS / 2);
+    if (node) {
+      if constexpr (!FIN) {
+        double Fa[DIM][NV], Fb[DIM][NV];
+        PDE::fluxes(q[j0], P, a.pde, Fa);
+        PDE::fluxes(q[j1], P, a.pde, Fb);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int cc = 0; cc < NFL; ++cc)
+            mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[d][C::flux_var(d, cc)], Fb[d][C::flux_var(d, cc)]};
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int cc = 0; cc < NGR; ++cc)
+          mine[(d * NCHD + NFL + cc) * SP + pk[d]] = P2{q[j0][C::grad_var(cc)], q[j1][C::grad_var(cc)]};
+    }
+    __syncthreads();
+    constexpr int CH0 = FIN ? NFL : 0;
+    constexpr int NCT = NCHD - CH0;
+    constexpr int NT = CPB * DIM * NCT * F;
+    for (int task = tid; task < NT; task += BLOCK) {
+      const int l = task % F;
+      const int ch = CH0 + (task / F) % NCT;
+      const int d = (task / (F * NCT)) % DIM;
+      const int c2 = task / (F * NCT * DIM);
+      P2* row = lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * LS;
+      double x0[n], x1[n], y0[n], y1[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        const P2 t = row[m];
+        x0[m] = t.x;
+        x1[m] = t.y;
+      }
+      line_deriv<double, n>(x0, y0, a.inv_h[d]);
+      line_deriv<double, n>(x1, y1, a.inv_h[d]);
+#pragma unroll
+      for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      div0[v] = div1[v] = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) g0[d][v] = g1[d][v] = 0.0;
+    }
+    if (node) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if constexpr (!FIN) {
+#pragma unroll
+          for (int cc = 0; cc < NFL; ++cc) {
+            const P2 t = mine[(d * NCHD + cc) * SP + pk[d]];
+            div0[C::flux_var(d, cc)] += t.x;
+            div1[C::flux_var(d, cc)] += t.y;
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < NGR; ++cc) {
+          const P2 t = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+          g0[d][C::grad_var(cc)] = t.x;
+          g1[d][C::grad_var(cc)] = t.y;
+        }
+      }
+    }
+    __syncthreads();  // read-backs done before the next round's writes
+  };
+
+  // right-hand side R = S - div F - B grad q (+ point sources of slice j)
+  auto rhs = [&](int j, const double (&div)[NV], const double (&g)[DIM][NV], double (&Rv)[NV], double (&B)[NV],
+                 double (&Sv)[NV], bool sources) {
+    if constexpr (PDE::kHasNcp) {
+      PDE::ncp(q[j], P, a.pde, g, B);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) B[v] = 0.0;
+    }
+    PDE::source(q[j], P, a.pde, Sv);
+    if (sources) add_point_sources(j, Sv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Rv[v] = Sv[v] - div[v] - B[v];
+  };
+
+  // q^{r+1}_i = u + dt sum_j KW_ij R_j, R_j held in q[j]
+  auto update = [&]() {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double t[n];
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < n; ++jj) s += T::KW(i, jj) * q[jj][v];
+        t[i] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i) q[i][v] = u[v] + dt * t[i];
+    }
+  };
+
+  const int I = a.picard_iters;
+  // First Picard step: q^0 = u^n at every time node, so every slice has the
+  // same right-hand side apart from point sources; one round suffices.
+  {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[0][v] = u[v];
+    double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], R0[NV], B[NV], Sv[NV];
+    round(std::false_type{}, 0, 0, div, g, div1, g1);
+    rhs(0, div, g, R0, B, Sv, false);
+#pragma unroll
+    for (int jj = 0; jj < n; ++jj) {
+      double Sp[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sp[v] = 0.0;
+      add_point_sources(jj, Sp);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[jj][v] = R0[v] + Sp[v];
+    }
+    update();
+  }
+  for (int r = 1; r < I; ++r) {
+#pragma unroll
+    for (int j = 0; j < n; j += 2) {
+      const int j1 = j + 1 < n ? j + 1 : j;
+      double div0[NV], g0[DIM][NV], div1[NV], g1[DIM][NV], Rv[NV], B[NV], Sv[NV];
+      round(std::false_type{}, j, j1, div0, g0, div1, g1);
+      rhs(j, div0, g0, Rv, B, Sv, true);
+      if (j1 != j) {
+        double Rw[NV];
+        rhs(j1, div1, g1, Rw, B, Sv, true);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[j1][v] = Rw[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[j][v] = Rv[v];
+    }
+    update();
+  }
+
+  // Final pass at the last iterate (READING: the averaged terms use the
+  // final iterate): time averages of q, F, B grad q and S.
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    Nbar[v] = Sbar[v] = qbar[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fbar[d][v] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    double div[NV], g[DIM][NV], Rv[NV], B[NV], Sv[NV];
+    if constexpr (PDE::kHasNcp) {
+      double div1[NV], g1[DIM][NV];
+      round(std::true_type{}, j, j, div, g, div1, g1);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        div[v] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) g[d][v] = 0.0;
+      }
+    }
+    double Fl[DIM][NV];
+    PDE::fluxes(q[j], P, a.pde, Fl);
+    rhs(j, div, g, Rv, B, Sv, true);
+    const double wj = T::w(j);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qbar[v] += wj * q[j][v];
+      Nbar[v] += wj * B[v];
+      Sbar[v] += wj * Sv[v];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) Fbar[d][v] += wj * Fl[d][v];
+    }
+  }
+
+  // Volume term and face projection, all directions at once: direction d's
+  // region of the cell's LDS holds qbar (NV rows) and the nonzero components
+  // of Fbar_d (NFL rows) in d's line-major layout.
+  constexpr int FIN_D = (NV + NFL) * SP;
+  double* const fin_mine = lds + lc * GN::CELL_ELEMS;
+  if (node) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
+    }
+  }
+  __syncthreads();
+  for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
+    // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
+    const int l = task % F;
+    const int kind = (task / F) % (NFL + 1);
+    const int dt_ = (task / (F * (NFL + 1))) % DIM;
+    const int c2 = task / (F * (NFL + 1) * DIM);
+    const long long tcell = cell0 + c2;
+    const bool tact = tcell < a.ncells;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (d != dt_) continue;
+      double* rows = lds + c2 * GN::CELL_ELEMS + d * FIN_D + l * LS;
+      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
+      if (kind == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double e0 = 0.0, e1 = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) {
+            const double x = rows[v * SP + m];
+            e0 += T::l0(m) * x;
+            e1 += T::l1(m) * x;
+          }
+          if (tact) {
+            tr[(0 * NV + v) * F + l] = e0;  // face 2d,   state
+            tr[(2 * NV + v) * F + l] = e1;  // face 2d+1, state
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (!PDE::flux_nonzero(d, v) && tact) {
+            tr[(1 * NV + v) * F + l] = 0.0;
+            tr[(3 * NV + v) * F + l] = 0.0;
+          }
+        }
+      } else {
+        // normal-flux traces; derivative of Fbar_d in place
+#pragma unroll
+        for (int cc = 0; cc < NFL; ++cc) {
+          if (cc != kind - 1) continue;
+          const int v = C::flux_var(d, cc);
+          double x[n], y[n];
+#pragma unroll
+          for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
+          double e0 = 0.0, e1 = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) {
+            e0 += T::l0(m) * x[m];
+            e1 += T::l1(m) * x[m];
+          }
+          if (tact) {
+            tr[(1 * NV + v) * F + l] = e0;
+            tr[(3 * NV + v) * F + l] = e1;
+          }
+          line_deriv<double, n>(x, y, a.inv_h[d]);
+#pragma unroll
+          for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    double divF[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) divF[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Qout[(cell * NV + v) * S + k] = u[v] + dt * (Sbar[v] - divF[v] - Nbar[v]);
+  }
+}
+
+}  // namespace adg

@@ -107,10 +107,16 @@ struct UserTerms {
     R q[NV + NP], lam[NV];
     gather(Q, P, q);
     U::eigenvalues(q, d, lam);
+    // the largest |eigenvalue|; a NaN eigenvalue is kept (fmax would drop it)
     R m = R(0);
+    bool nan = false;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) m = fmax(m, fabs(lam[v]));
-    return m;
+    for (int v = 0; v < NV; ++v) {
+      const R x = fabs(lam[v]);
+      nan = nan || x != x;
+      m = fmax(m, x);
+    }
+    return nan ? R(__builtin_nan("")) : m;
   }
 
   __device__ static __forceinline__ void boundary(const double* x, double t, double dt, int face,

@@ -542,3 +542,88 @@ def test_admissibility_flags_planted_cells():
     flags, count = O.check_admissible(P, Q)
     assert count == 4
     assert set(np.nonzero(flags)[0]) == {3, 7, 11, 17}
+
+
+# ------------------------------------------------- Eq. (7) with NaN speeds
+def test_cfl_keeps_nan_speeds():
+    """READING of Eq. (7): the maximum over nodes does not skip a NaN signal
+    speed, so dt is NaN.  Pinned by IEEE arithmetic: a NaN state gives a NaN
+    speed, and a negative pressure at positive density makes the sound speed
+    the square root of a negative number.  A clean state keeps the closed
+    form of test_cfl_closed_form."""
+    P = O.problem(3, 2, O.EULER, [3, 2, 2], cfl=0.9)
+    rho, u, p = 1.0, np.array([0.3, -0.2, 0.1]), 1.0
+    Q = np.broadcast_to(_euler_state(rho, u, p)[None, :, None], (P.ncells, 5, P.S)).copy()
+    dt0, lam0 = O.stable_dt(P, Q)
+    assert abs(lam0 - (0.3 + np.sqrt(1.4 * p / rho))) < 1e-14 * lam0
+    for c, v, k in ((5, 2, 7), (0, 0, 0), (11, 4, 26)):
+        Qb = Q.copy()
+        Qb[c, v, k] = np.nan
+        dt, lam = O.stable_dt(P, Qb)
+        assert np.isnan(dt) and np.isnan(lam), (c, v, k)
+    Qb = Q.copy()
+    Qb[7, 4, 3] = 0.5 * rho * u @ u - 0.1  # E below the kinetic energy: p < 0 at rho > 0
+    assert np.isnan(O.stable_dt(P, Qb)[0])
+    Qb = Q.copy()
+    Qb[4, 4, 9] = np.inf  # infinite energy: an infinite sound speed, dt = 0
+    assert O.stable_dt(P, Qb)[0] == 0.0
+    Qb[4, 1, 9] = np.inf  # infinite momentum: p = -inf, a NaN sound speed
+    assert np.isnan(O.stable_dt(P, Qb)[0])
+    # the speeds of elasticity are the cells' cp: a NaN in Q leaves dt as it
+    # is, a NaN cp makes it NaN
+    Pe = O.problem(3, 2, O.ELASTIC, [2, 2, 2], hi=[1000.0] * 3)
+    Qe = np.zeros((8, 9, Pe.S))
+    prm = np.tile([2700.0, 6000.0, 3464.0], (8, 1))
+    dte = O.stable_dt(Pe, Qe, prm)[0]
+    assert abs(dte - 0.9 / 15 * 500.0 / 6000.0) < 1e-15 * dte
+    Qe[3, 6, 4] = np.nan
+    assert O.stable_dt(Pe, Qe, prm)[0] == dte
+    prm[5, 1] = np.nan
+    assert np.isnan(O.stable_dt(Pe, Qe, prm)[0])
+
+
+def test_cfl_limited_keeps_nan_speeds():
+    """Eq. (7) in a limited run reads FV cells' subcell averages and DG
+    cells' nodes: a NaN in an FV cell's subcell data gives NaN; a NaN at a
+    node of an FV cell (whose solution is its subcell data) does not."""
+    P = O.problem(2, 2, O.EULER, [4, 3], cfl=0.9)
+    q = _euler_state(1.0, [0.3, -0.2], 1.0)
+    Q = np.broadcast_to(q[None, :, None], (P.ncells, 4, P.S)).copy()
+    sub = np.broadcast_to(q[None, :, None], (P.ncells, 4, O.limiter_subcells(P))).copy()
+    status = np.zeros(P.ncells, dtype=np.uint8)
+    status[5] = O.STATUS_FV
+    dt0 = O.stable_dt_limited(P, Q, sub, status)[0]
+    assert dt0 == O.stable_dt(P, Q)[0]
+    Qb = Q.copy()
+    Qb[5, 2, 3] = np.nan
+    assert O.stable_dt_limited(P, Qb, sub, status)[0] == dt0
+    assert np.isnan(O.stable_dt(P, Qb)[0])
+    sb = sub.copy()
+    sb[5, 0, 11] = np.nan
+    assert np.isnan(O.stable_dt_limited(P, Q, sb, status)[0])
+    sb = sub.copy()
+    sb[6, 0, 11] = np.nan  # a DG cell's subcell entries are not read
+    assert O.stable_dt_limited(P, Q, sb, status)[0] == dt0
+
+
+def test_oversized_dt_is_detected_and_rolled_back():
+    """Failure injection: a step size far above Eq. (7) makes the FP64 state
+    blow up (non-finite or non-physical values); the admissibility check
+    flags it; restarting from the caller's saved u^n with the Eq. (7) step
+    gives the clean run exactly."""
+    from paper_1905_07987_amd import inputs
+    P = O.problem(2, 3, O.EULER, [8, 8], cfl=0.9)
+    Q0 = inputs.c1_state(O.node_coords(P))
+    dt, _ = O.stable_dt(P, Q0)
+    saved = Q0.copy()
+    Qb, t, detected = Q0.copy(), 0.0, 0
+    for _ in range(12):
+        Qb = O.step(P, Qb, None, 60.0 * dt, t)
+        t += 60.0 * dt
+        flags, detected = O.check_admissible(P, Qb)
+        if detected:
+            break
+    assert detected > 0
+    Qr = O.step(P, saved, None, dt, 0.0)
+    Qc = O.step(P, Q0, None, dt, 0.0)
+    assert np.array_equal(Qr, Qc) and O.check_admissible(P, Qr)[1] == 0
