@@ -27,14 +27,21 @@ struct GeoN64 {
   static constexpr int CPB = S >= 64 ? 1 : 64 / S;
   static constexpr int LANES = CPB * S;
   static constexpr int BLOCK = (LANES + 63) / 64 * 64;
-  static constexpr int LS = G::LS, SP = G::SP;
+  // Line stride of the LDS rows: the odd stride of Geo, except n = 6, where
+  // rows of 6 two-slice elements (96 bytes apart) already fall into distinct
+  // banks for the 16-byte accesses, and the smaller rows let three blocks
+  // share a compute unit.
+  static constexpr int LS = n == 6 ? 6 : G::LS, SP = F * LS;
   static constexpr int ITER_ELEMS = 2 * C::NCH * SP;           // two slices of one cell, paired
   static constexpr int FIN_ELEMS = DIM * (NV + C::NFLUX) * SP;  // final phase, all directions
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
   static constexpr int ELEMS = CPB * CELL_ELEMS;
   static constexpr bool fits = ELEMS * 8 <= 80 * 1024 && BLOCK <= 256;
-  // two 4-wave blocks per compute unit: at most 256 registers per lane
-  static constexpr int MIN_WAVES = 2;
+  // Waves per SIMD the register allocator aims at: as many as the blocks
+  // whose LDS fits a compute unit (160 KiB) provide, at most 3 (<= 168
+  // registers per lane; fewer spill).
+  static constexpr int LDS_BLOCKS = (156 * 1024) / (ELEMS * 8);
+  static constexpr int MIN_WAVES = cmax(1, cmin(3, LDS_BLOCKS * (BLOCK / 64) / 4));
 };
 
 template <class PDE, int N>
@@ -254,12 +261,28 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   }
 
   // Final pass at the last iterate (READING: the averaged terms use the
-  // final iterate): time averages of q, F, B grad q and S.
+  // final iterate): time averages of q, F, B grad q and S.  Without a
+  // non-conservative product the final pass needs no LDS round, so qbar goes
+  // to its rows of the final phase at once (fewer registers live).
+  constexpr int FIN_D = (NV + NFL) * SP;
+  double* const fin_mine = lds + lc * GN::CELL_ELEMS;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     Nbar[v] = Sbar[v] = qbar[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Fbar[d][v] = 0.0;
+  }
+  if constexpr (!PDE::kHasNcp) {
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qbar[v] += T::w(j) * q[j][v];
+    if (node) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
+    }
   }
 #pragma unroll
   for (int j = 0; j < n; ++j) {
@@ -281,7 +304,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     const double wj = T::w(j);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      qbar[v] += wj * q[j][v];
+      if constexpr (PDE::kHasNcp) qbar[v] += wj * q[j][v];
       Nbar[v] += wj * B[v];
       Sbar[v] += wj * Sv[v];
 #pragma unroll
@@ -292,13 +315,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // Volume term and face projection, all directions at once: direction d's
   // region of the cell's LDS holds qbar (NV rows) and the nonzero components
   // of Fbar_d (NFL rows) in d's line-major layout.
-  constexpr int FIN_D = (NV + NFL) * SP;
-  double* const fin_mine = lds + lc * GN::CELL_ELEMS;
+  if constexpr (PDE::kHasNcp) __syncthreads();  // the final pass's rounds are done
   if (node) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      if constexpr (PDE::kHasNcp) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
+        for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
+      }
 #pragma unroll
       for (int cc = 0; cc < NFL; ++cc) fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
     }
@@ -374,8 +398,13 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int d = 0; d < DIM; ++d)
 #pragma unroll
       for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]];
+    // u^n again from memory (not kept in registers through the final pass;
+    // Q is only written here, by this thread)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Qout[(cell * NV + v) * S + k] = u[v] + dt * (Sbar[v] - divF[v] - Nbar[v]);
+    for (int v = 0; v < NV; ++v) {
+      const double un = Q[(cell * NV + v) * S + k];
+      Qout[(cell * NV + v) * S + k] = un + dt * (Sbar[v] - divF[v] - Nbar[v]);
+    }
   }
 }
 
