@@ -260,6 +260,22 @@ adg_status adg_read_clock_host(const double* clock, double* host, void* stream);
 adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                     void* stream);
 
+/* For callers that cannot allocate device memory or use a context's
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the step of adg_step, same kernels, same result
+ * bit for bit, with its face traces and reduction slots in the library's
+ * static device scratch array (32 MiB of traces plus 16 KiB of slots, held
+ * by every GPU the library runs on until the process ends) instead of the
+ * context's workspace.  Allocates nothing and does not synchronise; the
+ * context's own workspace is not touched.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several streams, several
+ * contexts) race and must be ordered by the caller.  The slots are cleared
+ * by a kernel at the start of every call.  Errors: as adg_step, plus
+ * UNSUPPORTED when the mesh's face traces (adg_query trace_elems * 8 bytes)
+ * exceed 32 MiB. */
+adg_status adg_step_noalloc(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                            void* stream);
+
 /* Allocates the second face-trace array that fused runs of adg_run swap
  * with the workspace (trace_elems doubles, see adg_query), once, on the
  * context's device; later calls, and contexts whose runs do not fuse

@@ -81,6 +81,7 @@ def lib():
         L.adg_node_coords.argtypes = [vp, dp]
         L.adg_stable_dt.argtypes = [vp, vp, vp, vp, vp]
         L.adg_step.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.adg_step_noalloc.argtypes = [vp, vp, vp, vp, C.c_int, vp]
         L.adg_read_clock_host.argtypes = [vp, dp, vp]
         L.adg_run.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
         L.adg_run_reserve.argtypes = [vp]
@@ -110,7 +111,7 @@ def limiter_tables(order: int):
 
 
 EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create", "adg_create_user", "adg_destroy",
-            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_run",
+            "adg_query", "adg_node_coords", "adg_stable_dt", "adg_read_clock_host", "adg_step", "adg_step_noalloc", "adg_run",
             "adg_run_reserve",
             "adg_predict",
             "adg_correct",

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -39,7 +40,17 @@ struct adg_ctx {
   void* lim_block = nullptr;
   size_t lim_bytes = 0;  // size of lim_block
   double* d_bc_state = nullptr;  // [6][2][nvar][F] outside traces of inflow faces
+  void* scratch = nullptr;       // this device's copy of the static scratch array
 };
+
+// Device scratch of adg_step_noalloc (callers that cannot allocate: graph
+// capture, serving loops): the reduction slots and the face traces of one
+// step.  Every GPU the library runs on holds its own copy for the life of
+// the process; host code uses the per-device address from
+// hipGetSymbolAddress, never the array's name.
+constexpr size_t kScratchSlotBytes = sizeof(unsigned long long) * adg::kSlots * adg::kSlotStride;  // 16 KiB
+constexpr size_t kScratchTraceBytes = size_t(32) << 20;                                          // 32 MiB
+static __device__ __align__(256) unsigned char scratch[kScratchSlotBytes + kScratchTraceBytes];
 
 namespace {
 
@@ -60,6 +71,32 @@ adg_status hip_fail(hipError_t e, const char* what) {
     hipError_t e_ = (call);                             \
     if (e_ != hipSuccess) return hip_fail(e_, #call);   \
   } while (0)
+
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices];  // scratch address per device, set once
+std::mutex g_scratch_mu;
+
+// The address of this device's scratch array (the current device's), looked
+// up once per device.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
+// zero the reduction slots (a kernel, not a memset node, so the call can be
+// captured in a graph)
+__global__ void clear_slots_kernel(unsigned long long* __restrict__ slots, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) slots[i] = 0ull;
+}
 
 const KernelSet* find_kernels(int pde, int dim, int order) {
   if (pde == ADG_PDE_EULER && dim == 2) return kernels_euler2(order);
@@ -268,6 +305,13 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     user_module_destroy(um);
     delete x;
     return hip_fail(e, "hipGetDevice");
+  }
+
+  e = scratch_address(x->device, &x->scratch);
+  if (e != hipSuccess) {
+    user_module_destroy(um);
+    delete x;
+    return hip_fail(e, "hipGetSymbolAddress(scratch)");
   }
 
   KArgs& a = x->args;
@@ -535,6 +579,41 @@ adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock
   ctx->traces_ready = true;
   e = k_correct(ctx, Q, params, clock, (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
+  return ADG_OK;
+}
+
+adg_status adg_step_noalloc(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
+                            void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  const size_t tbytes = ctx->trace_elems * sizeof(double);
+  if (tbytes > kScratchTraceBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "adg_step_noalloc: the face traces of this mesh take %zu bytes, the static scratch holds %zu",
+             tbytes, kScratchTraceBytes);
+    return fail(ADG_ERR_UNSUPPORTED, buf);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* slots = static_cast<unsigned long long*>(ctx->scratch);
+  double* traces = reinterpret_cast<double*>(static_cast<unsigned char*>(ctx->scratch) + kScratchSlotBytes);
+  KArgs a = ctx->args;
+  a.slots = slots;
+  const int nslot = kSlots * kSlotStride;
+  hipLaunchKernelGGL(clear_slots_kernel, dim3((nslot + 255) / 256), dim3(256), 0, s, slots, nslot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "clear launch");
+  const int next = (flags & ADG_STEP_NEXT_DT) ? 1 : 0;
+  if (ctx->user) {
+    e = user_predict(ctx->user, a, Q, params, clock, Q, traces, 0, s);
+    if (e == hipSuccess) e = user_correct(ctx->user, a, Q, params, clock, traces, next, s);
+  } else {
+    e = ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, traces, 0, s);
+    if (e == hipSuccess) e = ctx->ks->correct(a, Q, params, clock, traces, next, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "step launch");
   return ADG_OK;
 }
 
