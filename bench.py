@@ -95,20 +95,93 @@ def read_traffic(workload: str):
 
 def cpu_baseline(cells: int, N: int):
     """The oracle, as it stands, timed on the host cores for one step of the
-    same per-cell work on a smaller periodic mesh."""
+    same per-cell work on a smaller periodic mesh; also on one thread (a
+    quarter of the cells)."""
     import oracle as O
     from paper_1905_07987_amd import inputs
-    threads = O.set_threads(min(os.cpu_count() or 1, 16))
-    P = O.problem(3, N, O.EULER, [cells] * 3, cfl=0.5)
-    Q = inputs.c2_state(O.node_coords(P))
-    t0 = time.perf_counter()
-    dt, _ = O.stable_dt(P, Q)
-    O.step(P, Q, None, dt, 0.0)
-    el = time.perf_counter() - t0
-    dofs = P.ncells * 5 * (N + 1) ** 3
-    return {"value": dofs / el, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
+
+    def one_step(m, threads):
+        used = O.set_threads(threads)
+        P = O.problem(3, N, O.EULER, [m] * 3, cfl=0.5)
+        Q = inputs.c2_state(O.node_coords(P))
+        t0 = time.perf_counter()
+        dt, _ = O.stable_dt(P, Q)
+        O.step(P, Q, None, dt, 0.0)
+        el = time.perf_counter() - t0
+        return P.ncells * 5 * (N + 1) ** 3 / el, el, used
+
+    value, el, threads = one_step(cells, min(os.cpu_count() or 1, 16))
+    m1 = max(2, cells // 4)
+    v1, el1, _ = one_step(m1, 1)
+    return {"value": value, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one step (dt reduction + predictor + corrector) of the same 3-D Euler N={N} "
-                      f"workload on {cells}^3 periodic cells, {el:.2f} s wall"}
+                      f"workload on {cells}^3 periodic cells, {el:.2f} s wall",
+            "single_thread": {"value": v1, "unit": "DoF-updates/s", "cores": 1,
+                              "sample": f"the same step on {m1}^3 cells, {el1:.2f} s wall"}}
+
+
+def euler_c1(log, steps: int = 10):
+    """C1: 2-D Euler N=3, 16^2 periodic cells, CFL 0.9, 10 steps of the
+    paper's density wave (Eqs. (8), (10)), Eq. (7) every step; microseconds
+    per step, launched step by step and replayed from a HIP graph of the 10
+    steps (the workload is launch-bound); error against the closed form."""
+    import torch
+    from paper_1905_07987_amd import adg, inputs
+    s = adg.Solver(2, 3, "euler", [16, 16], cfl=0.9)
+    xyz = s.node_coords()
+    Q0 = torch.as_tensor(inputs.c1_state(xyz), device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def eager():
+        Q = Q0.clone()
+        clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+        s.stable_dt(Q, None, clock)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            s.step(Q, None, clock, next_dt=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return Q, clock, a.elapsed_time(b) * 1e3 / steps
+
+    for _ in range(3):
+        eager()
+    Q, clock, us = eager()
+    t = float(clock[0])
+    exact = torch.as_tensor(inputs.c1_state(xyz, t), device="cuda")
+    err = float(torch.linalg.vector_norm(Q - exact) / torch.linalg.vector_norm(exact))
+    res = {"workload": "c1: 2-D Euler, N=3, 16^2 periodic cells, CFL 0.9, 10 steps",
+           "us_per_step": round(us, 2), "t_end": t, "rel_l2_vs_closed_form": err}
+    # the same 10 steps captured once in a graph and replayed
+    gs = torch.cuda.Stream()
+    Qg = Q0.clone()
+    cg = torch.zeros(2, dtype=torch.float64, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=gs):  # gs is the current stream inside
+        s.stable_dt(Qg, None, cg)
+        for _ in range(steps):
+            s.step(Qg, None, cg, next_dt=True)
+    equal = True
+    for _ in range(3):
+        Qg.copy_(Q0)
+        cg.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        equal = equal and bool(torch.equal(Qg, Q)) and bool(torch.equal(cg, clock))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    a.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    res["graph_us_per_step"] = round(a.elapsed_time(b) * 1e3 / (reps * steps), 2)
+    res["graph_replays_bitwise_equal_eager"] = equal
+    log(f"c1: {us:.1f} us/step eager, {res['graph_us_per_step']:.1f} us/step graph replay "
+        f"(bitwise {equal}), rel L2 vs closed form {err:.2e}")
+    del graph
+    return res
 
 
 def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True):
@@ -253,6 +326,47 @@ def elastic_c3(log, steps: int | None = None, cfl: float = 0.5):
                                                       torch.linalg.vector_norm(s64))
     res["workload"] = (f"c3: 3-D elastic, N=4, 48^3 cells, layered +-10% material, Ricker source, "
                        f"32 receivers, {steps} steps, CFL_N {cfl}")
+    return res
+
+
+def ck_compare(log, which: str, cfl: float = 0.5):
+    """The linear kernels' Cauchy-Kowalevski predictor (Table 1) against the
+    Picard predictor on an elastic workload: FP64 fused runs with I = N (the
+    CK time average), I = N + 1 (the default) and I = 3N + 1 (the exact
+    element fixed point: for a linear PDE the Picard iteration is nilpotent
+    after dN + 1 steps); ms/step, and the relative L2 of the final state and
+    of the seismograms against I = 3N + 1."""
+    import torch
+    from paper_1905_07987_amd import adg, inputs
+    cfg = inputs.elastic_config(which)
+    N, steps = cfg["order"], cfg["steps"]
+    params = torch.as_tensor(cfg["params"], device="cuda")
+    runs = {}
+    for I in (N, N + 1, 3 * N + 1):
+        s = adg.Solver(3, N, "elastic", cfg["cells"], cfg["lo"], cfg["hi"], cfl=cfl, picard_iters=I)
+        s.set_point_sources([cfg["source"]])
+        s.set_receivers(cfg["receivers"])
+        Q = torch.zeros(s.state_shape, dtype=torch.float64, device="cuda")
+        seis = torch.empty((steps, s.nrec, 9), dtype=torch.float64, device="cuda")
+        clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+        s.stable_dt(Q, params, clock)
+        s.reserve_run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(Q, params, clock, steps, seis)
+        torch.cuda.synchronize()
+        runs[I] = ((time.perf_counter() - t0) / steps * 1e3, Q, seis)
+        del s
+    ref = runs[3 * N + 1]
+    res = {"workload": f"{which}: 3-D elastic, N={N}, {steps} steps, fused FP64 runs, CFL_N {cfl}"}
+    for I, (ms, Q, seis) in runs.items():
+        key = "ck_I_eq_N" if I == N else ("picard_I_eq_N+1" if I == N + 1 else "reference_I_eq_3N+1")
+        res[key] = {"picard_iters": I, "ms_per_step": round(ms, 4),
+                    "rel_l2_state_vs_reference": float(torch.linalg.vector_norm(Q - ref[1]) /
+                                                       torch.linalg.vector_norm(ref[1])),
+                    "rel_l2_seismograms_vs_reference": float(torch.linalg.vector_norm(seis - ref[2]) /
+                                                             torch.linalg.vector_norm(ref[2]))}
+        log(f"{which} I={I}: {ms:.3f} ms/step, state vs reference {res[key]['rel_l2_state_vs_reference']:.2e}")
     return res
 
 
@@ -413,6 +527,7 @@ def main():
                 "flops_per_launch": flops_launch, "ms_per_launch": round(pred_ms, 4)}
 
     variants = {"correct_kernel_ms": round(corr_ms, 4)}
+    variants["c1"] = euler_c1(log)
     if not args.no_mixed and args.precision == "fp64":
         s32 = adg.Solver(3, N, "euler", [m, m, m], precision="fp32", cfl=args.cfl)
         Q32, clock32, t32, _, p32, c32 = run(s32, args.steps, args.warmup)
@@ -426,6 +541,8 @@ def main():
 
     if not args.no_elastic:
         variants["elastic_c3"] = elastic_c3(log)
+        variants["ck_vs_picard_c3"] = ck_compare(log, "c3")
+        variants["ck_vs_picard_c4"] = ck_compare(log, "c4")
     if not args.no_adjoint:
         variants["adjoint_c4"] = adjoint_c4(log, grad=not args.no_grad)
     if not args.no_limiter:

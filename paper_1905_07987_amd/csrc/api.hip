@@ -140,18 +140,21 @@ bool locate(const adg_ctx* c, const double* x, long long* cell, double* ref) {
   return true;
 }
 
+// out[r][v] = sum_k Phi_k(xi_r) Q[c_r][v][k], one thread per (receiver,
+// quantity), the nodes summed in order: the same sum, bit for bit, as the
+// receivers sampled inside the fused step kernel.
 __global__ void sample_kernel(const double* __restrict__ Q, const long long* __restrict__ rcell,
-                              const double* __restrict__ rw, double* __restrict__ out, int nv,
+                              const double* __restrict__ rw, double* __restrict__ out, int nrec, int nv,
                               int S) {
-  const int r = blockIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrec * nv) return;
+  const int r = i / nv, v = i - r * nv;
   const long long c = rcell[r];
-  for (int v = 0; v < nv; ++v) {
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < S; k += 64) acc += rw[(long long)r * S + k] * Q[(c * nv + v) * S + k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (threadIdx.x == 0) out[(long long)r * nv + v] = acc;
-  }
+  const double* w = rw + (long long)r * S;
+  const double* uq = Q + (c * nv + v) * S;
+  double acc = 0.0;
+  for (int k = 0; k < S; ++k) acc += w[k] * uq[k];
+  out[(long long)r * nv + v] = acc;
 }
 
 // lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v], the transpose of sample_kernel.
@@ -819,8 +822,8 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
   if (st) return st;
   if (ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
   if (!out) return fail(ADG_ERR_INVALID_ARG, "null output");
-  hipLaunchKernelGGL(sample_kernel, dim3(ctx->nrec), dim3(64), 0, (hipStream_t)stream, Q,
-                     ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nv, ctx->S);
+  hipLaunchKernelGGL(sample_kernel, dim3((ctx->nrec * ctx->nv + 63) / 64), dim3(64), 0, (hipStream_t)stream, Q,
+                     ctx->d_rec_cell, ctx->d_rec_w, out, ctx->nrec, ctx->nv, ctx->S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "sample launch");
   return ADG_OK;
@@ -855,8 +858,8 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
   const long long rec_stride = (long long)ctx->nrec * ctx->nv;
   auto sample = [&](int n) -> hipError_t {
     if (!rec_out) return hipSuccess;
-    hipLaunchKernelGGL(sample_kernel, dim3(ctx->nrec), dim3(64), 0, s, Q, ctx->d_rec_cell, ctx->d_rec_w,
-                       rec_out + n * rec_stride, ctx->nv, ctx->S);
+    hipLaunchKernelGGL(sample_kernel, dim3((ctx->nrec * ctx->nv + 63) / 64), dim3(64), 0, s, Q, ctx->d_rec_cell,
+                       ctx->d_rec_w, rec_out + n * rec_stride, ctx->nrec, ctx->nv, ctx->S);
     return hipGetLastError();
   };
   const bool fused = run_fuses(ctx) && nsteps > 1;

@@ -321,7 +321,11 @@ def test_limited_step_with_the_fp32_predictor():
     agree = float((st64 == st32).mean())
     e = rel_l2(Q32, Q64)
     say(f"  status agreement {agree:.3f}, rel L2 vs fp64 {e:.2e}")
-    assert agree >= 0.9 and e <= 1e-2 and np.isfinite(Q32).all()
+    # measured: every status equal, 3.2e-9 after three steps (the FP32
+    # predictor's increments are dt-small against the FP64 state); bounds
+    # with margin for a status decided within the FP32 error: 99 % of the
+    # cells, 1e-7
+    assert agree >= 0.99 and e <= 1e-7 and np.isfinite(Q32).all()
     s.close()
     s32.close()
 
