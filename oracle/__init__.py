@@ -20,17 +20,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "adg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with the address and undefined-behaviour sanitizers
+# (host code only; tests/test_oracle_sanitizers.py runs the oracle's pins on
+# it in a subprocess that preloads the sanitizer runtime)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
 
 EULER, ELASTIC, ADVECTION = 1, 2, 3
 MAXQ, MAXSRC = 16, 8
 
 
-def build() -> str:
-    """Compile the oracle with gcc (no FMA contraction, IEEE binary64)."""
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared",
-           "-fPIC", "-o", _LIB, _SRC, "-lm"]
+def build(sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, IEEE binary64); with
+    sanitize=True a second library instrumented with AddressSanitizer and
+    UndefinedBehaviorSanitizer (aborting on the first report)."""
+    out = _LIB_SAN if sanitize else _LIB
+    san = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+    cmd = (["gcc", "-O1" if sanitize else "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared",
+            "-fPIC"] + (san if sanitize else []) + ["-o", out, _SRC, "-lm"])
     subprocess.run(cmd, check=True)
-    return _LIB
+    return out
 
 
 class Problem(C.Structure):
@@ -124,9 +132,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            raise RuntimeError(f"oracle library missing: {_LIB} (run __graft_entry__.build())")
-        L = C.CDLL(_LIB)
+        path = _LIB_SAN if os.environ.get("ADG_ORACLE_SANITIZED") == "1" else _LIB
+        if not os.path.exists(path):
+            raise RuntimeError(f"oracle library missing: {path} (run __graft_entry__.build())")
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         pp = C.POINTER(Problem)
         L.orc_tables.argtypes = [C.c_int] + [dp] * 7
