@@ -49,7 +49,7 @@ class Problem(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("cfl", C.c_double), ("gamma", C.c_double), ("adv", C.c_double * 3),
         ("kappa", C.c_double),
-        ("nsrc", C.c_int), ("pad_", C.c_int),
+        ("nsrc", C.c_int), ("guess", C.c_int),
         ("src_x", (C.c_double * 3) * MAXSRC),
         ("src_w", (C.c_double * MAXQ) * MAXSRC),
         ("src_f0", C.c_double * MAXSRC), ("src_t0", C.c_double * MAXSRC),
@@ -84,9 +84,15 @@ _NV = {EULER: None, ELASTIC: 9, ADVECTION: 1}
 BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_INFLOW = 0, 1, 2, 3
 
 
+GUESS_CONSTANT, GUESS_CERK = 0, 1
+
+
 def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None,
-            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=(), bc=None, bc_state=None):
-    """Build a Problem.  ``sources`` is a list of dicts with keys x, w, f0, t0, amp;
+            gamma=1.4, adv=(1.0, 1.0, 1.0), kappa=0.0, sources=(), bc=None, bc_state=None,
+            guess=GUESS_CONSTANT):
+    """Build a Problem.  ``guess``: GUESS_CONSTANT (q^0 = u^n, default
+    picard_iters N+1) or GUESS_CERK (the CERK initial guess, default
+    picard_iters max(1, N-2)).  ``sources`` is a list of dicts with keys x, w, f0, t0, amp;
     ``bc`` the boundary condition of each face 2 d + side (default periodic);
     ``bc_state`` {face: outside state} for BC_INFLOW faces."""
     P = Problem()
@@ -101,7 +107,10 @@ def problem(dim, order, pde, cells, lo=None, hi=None, cfl=0.9, picard_iters=None
         P.nvar, P.nparam = 1, 0
     else:
         raise ValueError(pde)
-    P.picard_iters = order + 1 if picard_iters is None else picard_iters
+    P.guess = guess
+    if picard_iters is None:
+        picard_iters = order + 1 if guess == GUESS_CONSTANT else max(1, order - 2)
+    P.picard_iters = picard_iters
     cells = list(cells) + [1] * (3 - len(cells))
     lo = list(lo if lo is not None else [0.0] * dim) + [0.0] * (3 - dim)
     hi = list(hi if hi is not None else [1.0] * dim) + [1.0] * (3 - dim)

@@ -59,7 +59,7 @@ typedef struct {
   double adv[3]; /* advection: velocity a */
   double kappa;  /* advection: linear decay source S(q) = -kappa q */
   int nsrc;
-  int pad_;
+  int guess;     /* initial guess of the Picard iteration: ORC_GUESS_* */
   double src_x[ORC_MAXSRC][3];
   double src_w[ORC_MAXSRC][ORC_MAXQ]; /* which variables a source drives */
   double src_f0[ORC_MAXSRC], src_t0[ORC_MAXSRC], src_amp[ORC_MAXSRC];
@@ -71,6 +71,7 @@ typedef struct {
 } orc_problem;
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_WALL = 2, ORC_BC_INFLOW = 3 };
+enum { ORC_GUESS_CONSTANT = 0, ORC_GUESS_CERK = 1 };
 
 /* ------------------------------------------------------------------------
  * 1. One-dimensional tables on the reference interval [0,1].
@@ -576,6 +577,62 @@ static void eval_terms(const orc_problem *P, const mesh *M, const tables *T, lon
   }
 }
 
+/* Initial guess by a continuous extension Runge-Kutta method (CERK; the
+ * alternative to a constant guess the paper names for its optimised
+ * kernels, Sec. 5.2, without giving one).  READING: the cell-local ODE
+ * dq/dt = R(q, t) of the predictor (the same R as in the Picard step: the
+ * cell's spatial derivatives, non-conservative product and sources, no face
+ * terms) is integrated over the step by the classical four-stage Runge-Kutta
+ * method,
+ *    k1 = R(u, t),  k2 = R(u + dt/2 k1, t + dt/2),
+ *    k3 = R(u + dt/2 k2, t + dt/2),  k4 = R(u + dt k3, t + dt),
+ * with its continuous extension (dense output) of uniform order three,
+ *    q(tau) = u + dt sum_s b_s(tau) k_s,   b1 = tau - 3 tau^2/2 + 2 tau^3/3,
+ *    b2 = b3 = tau^2 - 2 tau^3/3,   b4 = -tau^2/2 + 2 tau^3/3,
+ * taken at the time nodes tau = xi_j as q^0_j.  The Picard passes that
+ * follow start from an iterate whose error is O(dt^4) instead of O(dt):
+ * picard_iters = N - 2 passes reach the order that N + 1 passes from the
+ * constant guess reach.  Each stage's R is evaluated by filling every time
+ * slice with the stage state at the stage time (dt = 0 in eval_terms). */
+static void cerk_guess(const orc_problem *P, const mesh *M, const tables *T, long c,
+                       const double *xlo, double dt, double t, work *W) {
+  const int n = M->n, S = M->S, nq = M->nq, nv = M->nv;
+  const double cst[4] = {0.0, 0.5, 0.5, 1.0};  /* stage times c_s */
+  const double ast[4] = {0.0, 0.5, 0.5, 1.0};  /* Y_s = u + dt a_s k_{s-1} */
+  double *qg = calloc((size_t)n * S * nq, sizeof(double));  /* the guess, assembled */
+  double *kprev = calloc((size_t)S * nv, sizeof(double));
+  if (!qg || !kprev) {
+    free(qg);
+    free(kprev);
+    return;  /* no memory: the constant guess stays (the caller sees no error) */
+  }
+  for (int j = 0; j < n; ++j) memcpy(&qg[(size_t)j * S * nq], W->u, sizeof(double) * S * nq);
+  for (int st = 0; st < 4; ++st) {
+    /* stage state Y_s in every slice of the iterate */
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < S; ++k) {
+        double *qk = &W->q[((size_t)j * S + k) * nq];
+        for (int v = 0; v < nv; ++v) qk[v] = W->u[(size_t)k * nq + v] + dt * ast[st] * kprev[(size_t)k * nv + v];
+        for (int p = nv; p < nq; ++p) qk[p] = W->u[(size_t)k * nq + p];
+      }
+    eval_terms(P, M, T, c, xlo, 0.0, t + cst[st] * dt, W);
+    for (int k = 0; k < S; ++k)
+      for (int v = 0; v < nv; ++v) kprev[(size_t)k * nv + v] = W->R[(size_t)k * nv + v];  /* slice 0 */
+    for (int j = 0; j < n; ++j) {
+      const double x = T->xi[j];
+      double b;
+      if (st == 0) b = x - 1.5 * x * x + 2.0 / 3.0 * x * x * x;
+      else if (st == 3) b = -0.5 * x * x + 2.0 / 3.0 * x * x * x;
+      else b = x * x - 2.0 / 3.0 * x * x * x;
+      for (int k = 0; k < S; ++k)
+        for (int v = 0; v < nv; ++v) qg[((size_t)j * S + k) * nq + v] += dt * b * kprev[(size_t)k * nv + v];
+    }
+  }
+  memcpy(W->q, qg, sizeof(double) * (size_t)n * S * nq);
+  free(qg);
+  free(kprev);
+}
+
 static void predictor_cell(const orc_problem *P, const mesh *M, const tables *T, long c,
                            const double *Q, const double *params, double dt, double t,
                            int iters, work *W) {
@@ -593,6 +650,7 @@ static void predictor_cell(const orc_problem *P, const mesh *M, const tables *T,
   /* initial guess q^0_j = u^n */
   for (int j = 0; j < n; ++j)
     memcpy(&W->q[(size_t)j * S * nq], W->u, sizeof(double) * S * nq);
+  if (P->guess == ORC_GUESS_CERK) cerk_guess(P, M, T, c, xlo, dt, t, W);
   for (int r = 0; r < iters; ++r) {
     eval_terms(P, M, T, c, xlo, dt, t, W);
     for (int i = 0; i < n; ++i)
