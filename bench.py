@@ -539,6 +539,20 @@ def main():
                                   "steps_compared": args.warmup + args.steps}
         log(f"mixed fp32: {t32 / args.steps:.3f} ms/step, {v32:.3e} DoF/s, rel L2 vs fp64 {err:.2e}")
 
+    if args.precision == "fp64":
+        # the CERK initial guess with N - 2 Picard passes (same order as
+        # N + 1 passes from the constant guess)
+        sc = adg.Solver(3, N, "euler", [m, m, m], cfl=args.cfl, initial_guess="cerk")
+        Qc, clockc, tc, _, pc, cc = run(sc, args.steps, args.warmup)
+        errc = float(torch.linalg.vector_norm(Qc - Q64) / torch.linalg.vector_norm(Q64))
+        variants["cerk_guess"] = {"value": dofs / (tc / args.steps * 1e-3),
+                                  "ms_per_step": round(tc / args.steps, 4), "predict_ms": round(pc, 4),
+                                  "picard_iters": max(1, N - 2),
+                                  "rel_l2_vs_constant_guess_after_steps": errc,
+                                  "steps_compared": args.warmup + args.steps}
+        log(f"cerk guess: {tc / args.steps:.3f} ms/step (predict {pc:.3f}), rel L2 vs constant guess {errc:.2e}")
+        del sc, Qc
+
     if not args.no_elastic:
         variants["elastic_c3"] = elastic_c3(log)
         variants["ck_vs_picard_c3"] = ck_compare(log, "c3")

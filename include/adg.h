@@ -86,6 +86,23 @@ typedef int adg_status;
 #define ADG_FP64 0
 #define ADG_MIXED_FP32 1
 
+/* Initial guess of the predictor's Picard iteration (Sec. 3.3; Sec. 5.2 names
+ * a continuous extension Runge-Kutta (CERK) guess as the alternative).
+ *  ADG_GUESS_CONSTANT  q^0 = u^n at every time node (the default; with
+ *                      N + 1 passes the predictor is of order N + 1).
+ *  ADG_GUESS_CERK      q^0 = the classical four-stage Runge-Kutta method's
+ *                      continuous extension of uniform order three on the
+ *                      cell-local ODE dq/dt = R(q, t) of the predictor (the
+ *                      cell's derivatives, non-conservative product, sources
+ *                      and point sources; no face terms), taken at the time
+ *                      nodes; its error is O(dt^4) instead of O(dt), so
+ *                      N - 2 passes reach the order of N + 1 passes from the
+ *                      constant guess.  Built for the FP64 predictor of the
+ *                      built-in PDEs that are not linear in Q (Euler);
+ *                      elsewhere UNSUPPORTED. */
+#define ADG_GUESS_CONSTANT 0
+#define ADG_GUESS_CERK 1
+
 typedef struct {
   int dim;          /* 2 or 3 */
   int order;        /* polynomial degree N >= 1 (built range: adg_max_order) */
@@ -95,8 +112,9 @@ typedef struct {
   double lo[3];     /* domain lower corner */
   double hi[3];     /* domain upper corner */
   double cfl;       /* CFL_N of Eq. (7), 0 < cfl; the paper requires < 1 */
-  int picard_iters; /* fixed number of Picard iterations; 0 selects N+1 */
-  int reserved;
+  int picard_iters; /* fixed number of Picard iterations; 0 selects N+1
+                       (ADG_GUESS_CONSTANT) or max(1, N-2) (ADG_GUESS_CERK) */
+  int initial_guess; /* ADG_GUESS_* (the first Picard iterate) */
   double gamma;     /* Euler ratio of specific heats (> 1) */
   double adv[3];    /* advection velocity */
   double kappa;     /* advection decay rate */

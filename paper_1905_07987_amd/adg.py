@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libadg.so")
 
 PDE_EULER, PDE_ELASTIC, PDE_ADVECTION = 1, 2, 3
 FP64, MIXED_FP32 = 0, 1
+GUESS_CONSTANT, GUESS_CERK = 0, 1
+_GUESS_NAMES = {"constant": GUESS_CONSTANT, "cerk": GUESS_CERK}
 STEP_NEXT_DT = 1
 
 PDE_USER = 4
@@ -35,7 +37,7 @@ class Config(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("order", C.c_int), ("pde", C.c_int), ("precision", C.c_int),
         ("cells", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-        ("cfl", C.c_double), ("picard_iters", C.c_int), ("reserved", C.c_int),
+        ("cfl", C.c_double), ("picard_iters", C.c_int), ("initial_guess", C.c_int),
         ("gamma", C.c_double), ("adv", C.c_double * 3), ("kappa", C.c_double),
         ("bc", C.c_int * 6),
         ("bc_state", (C.c_double * 16) * 6),
@@ -152,8 +154,9 @@ class Solver:
     def __init__(self, dim: int, order: int, pde="euler", cells=(16, 16, 1), lo=(0.0, 0.0, 0.0),
                  hi=(1.0, 1.0, 1.0), cfl: float = 0.9, picard_iters: int = 0, precision="fp64",
                  gamma: float = 1.4, adv=(1.0, 1.0, 1.0), kappa: float = 0.0, bc=None, bc_state=None,
-                 source: str | None = None):
+                 source: str | None = None, initial_guess="constant"):
         cfg = Config()
+        cfg.initial_guess = _GUESS_NAMES.get(initial_guess, initial_guess)
         for f, b in enumerate(bc or ()):
             cfg.bc[f] = _BC_NAMES.get(b, b)
         for f, q in (bc_state or {}).items():

@@ -57,6 +57,7 @@ struct KArgs {
   // normal flux at every face node (filled once per context)
   const double* bc_trace;
   int picard_iters;
+  int guess;  // ADG_GUESS_*: initial guess of the Picard iteration
   long long ncells;
   double lo[3], h[3], inv_h[3];  // lower corner of the domain, cell sizes
   double dt_factor;  // cfl / (dim (2N+1)) * min_d h_d

@@ -221,6 +221,12 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
   if (!(c.cfl > 0.0) || !std::isfinite(c.cfl)) return fail(ADG_ERR_INVALID_ARG, "cfl must be > 0");
   if (c.picard_iters < 0 || c.picard_iters > 64)
     return fail(ADG_ERR_INVALID_ARG, "picard_iters must be in 0..64");
+  if (c.initial_guess != ADG_GUESS_CONSTANT && c.initial_guess != ADG_GUESS_CERK)
+    return fail(ADG_ERR_INVALID_ARG, "unknown initial_guess");
+  if (c.initial_guess == ADG_GUESS_CERK &&
+      (source || c.pde != ADG_PDE_EULER || c.precision != ADG_FP64))
+    return fail(ADG_ERR_UNSUPPORTED,
+                "the CERK initial guess is built for the FP64 predictor of the Euler equations");
   if (c.pde == ADG_PDE_EULER && !(c.gamma > 1.0)) return fail(ADG_ERR_INVALID_ARG, "gamma must be > 1");
   for (int d = 0; d < 3; ++d) {
     const int blo = c.bc[2 * d], bhi = c.bc[2 * d + 1];
@@ -326,7 +332,9 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     a.inv_h[d] = 1.0 / a.h[d];
   }
   a.ncells = C;
-  a.picard_iters = c.picard_iters ? c.picard_iters : c.order + 1;
+  a.guess = c.initial_guess;
+  a.picard_iters = c.picard_iters ? c.picard_iters
+                                  : (c.initial_guess == ADG_GUESS_CERK ? (c.order > 3 ? c.order - 2 : 1) : c.order + 1);
   double hmin = a.h[0];
   for (int d = 1; d < c.dim; ++d) hmin = std::fmin(hmin, a.h[d]);
   a.dt_factor = c.cfl / (c.dim * (2.0 * c.order + 1.0)) * hmin;

@@ -196,6 +196,13 @@ struct CT {
   __device__ static constexpr R w(int j) { return R(B::w[j]); }
   __device__ static constexpr R l0(int j) { return R(B::l0[j]); }
   __device__ static constexpr R l1(int j) { return R(B::l1[j]); }
+  // weights b_s(tau_j) of the third-order continuous extension of the
+  // classical four-stage Runge-Kutta method at time node j
+  __device__ static constexpr R cerk_b(int s, int j) {
+    const double x = B::xi[j];
+    return R(s == 0 ? x - 1.5 * x * x + (2.0 / 3.0) * x * x * x
+                    : (s == 3 ? -0.5 * x * x + (2.0 / 3.0) * x * x * x : x * x - (2.0 / 3.0) * x * x * x));
+  }
 };
 
 template <class R>

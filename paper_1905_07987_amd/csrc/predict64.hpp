@@ -84,22 +84,25 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   for (int p = 0; p < NP; ++p) P[p] = params[cl * NP + p];
   const double t_n = clock[0], dt = clock[1];
 
-  // Point sources: the Ricker amplitude at the n time nodes of this step,
+  // Point sources: the Ricker amplitude at the n time nodes of this step
+  // and at the stage times 0, 1/2, 1 of the CERK guess (entries n .. n+2),
   // once per block; only blocks holding a source cell use them.
-  __shared__ double src_amp[kMaxSources * n];
+  constexpr int NA = n + 3;
+  __shared__ double src_amp[kMaxSources * NA];
   bool src_here = false;
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
-  if (src_here && tid < a.nsrc * n) {
-    const int s = tid / n, j = tid - s * n;
-    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + a.t64.xi[j] * dt);
+  if (src_here && tid < a.nsrc * NA) {
+    const int s = tid / NA, j = tid - s * NA;
+    const double tau = j < n ? a.t64.xi[j] : 0.5 * (j - n);
+    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + tau * dt);
   }
   // (made visible by the first barrier below)
   auto add_point_sources = [&](int j, double* Sv) {
     if (!src_here || !node) return;
     for (int s = 0; s < a.nsrc; ++s) {
       if (a.src[s].cell != cell) continue;
-      const double amp = src_amp[s * n + j];
+      const double amp = src_amp[s * NA + j];
       const double* wsk = a.src_w + ((long long)s * S + k) * NV;
 #pragma unroll
       for (int v = 0; v < NV; ++v) Sv[v] += amp * wsk[v];
@@ -109,23 +112,23 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   double q[n][NV];  // iterate at the n time nodes of node k; R_j replaces q_j
   double Fbar[DIM][NV], Nbar[NV], Sbar[NV], qbar[NV];  // final pass: time averages
 
-  // One LDS round for slices j0 and j1 of the current iterate (j1 == j0:
-  // one slice): the two slices of a (channel, node) share one 16-byte
-  // element, so the node threads' writes and read-backs and the line tasks
-  // all move 16 bytes per access.  FIN: only the gradients the
+  // One LDS round for two states qa and qb of the node (two time slices of
+  // the iterate, or one state twice): the two share one 16-byte element per
+  // (channel, node), so the node threads' writes and read-backs and the line
+  // tasks all move 16 bytes per access.  FIN: only the gradients the
   // non-conservative product reads (the final pass averages the fluxes and
   // differentiates their average once).
   using P2 = Pair<double>;
   P2* const lds2 = reinterpret_cast<P2*>(lds);
-  auto round = [&](auto fin_tag, int j0, int j1, double (&div0)[NV], double (&g0)[DIM][NV], double (&div1)[NV],
-                   double (&g1)[DIM][NV]) {
+  auto round = [&](auto fin_tag, const double (&qa)[NV], const double (&qb)[NV], double (&div0)[NV],
+                   double (&g0)[DIM][NV], double (&div1)[NV], double (&g1)[DIM][NV]) {
     constexpr bool FIN = decltype(fin_tag)::value;
     P2* const mine = lds2 + lc * (GN::CELL_ELEMS / 2);
     if (node) {
       if constexpr (!FIN) {
         double Fa[DIM][NV], Fb[DIM][NV];
-        PDE::fluxes(q[j0], P, a.pde, Fa);
-        PDE::fluxes(q[j1], P, a.pde, Fb);
+        PDE::fluxes(qa, P, a.pde, Fa);
+        PDE::fluxes(qb, P, a.pde, Fb);
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
 #pragma unroll
@@ -136,7 +139,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
         for (int cc = 0; cc < NGR; ++cc)
-          mine[(d * NCHD + NFL + cc) * SP + pk[d]] = P2{q[j0][C::grad_var(cc)], q[j1][C::grad_var(cc)]};
+          mine[(d * NCHD + NFL + cc) * SP + pk[d]] = P2{qa[C::grad_var(cc)], qb[C::grad_var(cc)]};
     }
     __syncthreads();
     constexpr int CH0 = FIN ? NFL : 0;
@@ -189,16 +192,17 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     __syncthreads();  // read-backs done before the next round's writes
   };
 
-  // right-hand side R = S - div F - B grad q (+ point sources of slice j)
-  auto rhs = [&](int j, const double (&div)[NV], const double (&g)[DIM][NV], double (&Rv)[NV], double (&B)[NV],
-                 double (&Sv)[NV], bool sources) {
+  // right-hand side R = S - div F - B grad q of the state qj (+ the point
+  // sources at time entry j of src_amp)
+  auto rhs = [&](const double (&qj)[NV], int j, const double (&div)[NV], const double (&g)[DIM][NV],
+                 double (&Rv)[NV], double (&B)[NV], double (&Sv)[NV], bool sources) {
     if constexpr (PDE::kHasNcp) {
-      PDE::ncp(q[j], P, a.pde, g, B);
+      PDE::ncp(qj, P, a.pde, g, B);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) B[v] = 0.0;
     }
-    PDE::source(q[j], P, a.pde, Sv);
+    PDE::source(qj, P, a.pde, Sv);
     if (sources) add_point_sources(j, Sv);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Rv[v] = Sv[v] - div[v] - B[v];
@@ -222,14 +226,44 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   };
 
   const int I = a.picard_iters;
-  // First Picard step: q^0 = u^n at every time node, so every slice has the
-  // same right-hand side apart from point sources; one round suffices.
-  {
+  int r0 = 0;  // Picard passes taken before the loop below
+  if (a.guess == ADG_GUESS_CERK) {
+    // CERK guess (READING of the paper's alternative initial guess): the
+    // cell-local ODE dq/dt = R(q, t) by the classical four-stage Runge-Kutta
+    // method, whose continuous extension of uniform order three,
+    // q(tau) = u + dt sum_s b_s(tau) k_s, is taken at the time nodes.  Each
+    // stage is one LDS round of one state; the passes that follow are
+    // ordinary Picard passes.
+#pragma unroll
+    for (int j = 0; j < n; ++j)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[j][v] = u[v];
+    double Y[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Y[v] = u[v];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], kk[NV], B[NV], Sv[NV];
+      round(std::false_type{}, Y, Y, div, g, div1, g1);
+      rhs(Y, n + (st == 0 ? 0 : (st == 3 ? 2 : 1)), div, g, kk, B, Sv, true);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        const double b = dt * T::cerk_b(st, j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[j][v] += b * kk[v];
+      }
+      const double as = st == 2 ? 1.0 : 0.5;  // Y_{s+1} = u + dt a_{s+1} k_s
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Y[v] = u[v] + dt * as * kk[v];
+    }
+  } else {
+    // First Picard step: q^0 = u^n at every time node, so every slice has
+    // the same right-hand side apart from point sources; one round suffices.
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[0][v] = u[v];
     double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], R0[NV], B[NV], Sv[NV];
-    round(std::false_type{}, 0, 0, div, g, div1, g1);
-    rhs(0, div, g, R0, B, Sv, false);
+    round(std::false_type{}, q[0], q[0], div, g, div1, g1);
+    rhs(q[0], 0, div, g, R0, B, Sv, false);
 #pragma unroll
     for (int jj = 0; jj < n; ++jj) {
       double Sp[NV];
@@ -240,17 +274,18 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int v = 0; v < NV; ++v) q[jj][v] = R0[v] + Sp[v];
     }
     update();
+    r0 = 1;
   }
-  for (int r = 1; r < I; ++r) {
+  for (int r = r0; r < I; ++r) {
 #pragma unroll
     for (int j = 0; j < n; j += 2) {
       const int j1 = j + 1 < n ? j + 1 : j;
       double div0[NV], g0[DIM][NV], div1[NV], g1[DIM][NV], Rv[NV], B[NV], Sv[NV];
-      round(std::false_type{}, j, j1, div0, g0, div1, g1);
-      rhs(j, div0, g0, Rv, B, Sv, true);
+      round(std::false_type{}, q[j], q[j1], div0, g0, div1, g1);
+      rhs(q[j], j, div0, g0, Rv, B, Sv, true);
       if (j1 != j) {
         double Rw[NV];
-        rhs(j1, div1, g1, Rw, B, Sv, true);
+        rhs(q[j1], j1, div1, g1, Rw, B, Sv, true);
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[j1][v] = Rw[v];
       }
@@ -289,7 +324,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     double div[NV], g[DIM][NV], Rv[NV], B[NV], Sv[NV];
     if constexpr (PDE::kHasNcp) {
       double div1[NV], g1[DIM][NV];
-      round(std::true_type{}, j, j, div, g, div1, g1);
+      round(std::true_type{}, q[j], q[j], div, g, div1, g1);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -300,7 +335,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     }
     double Fl[DIM][NV];
     PDE::fluxes(q[j], P, a.pde, Fl);
-    rhs(j, div, g, Rv, B, Sv, true);
+    rhs(q[j], j, div, g, Rv, B, Sv, true);
     const double wj = T::w(j);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
