@@ -56,18 +56,19 @@ def euler_flux_flops(dim: int) -> int:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the FP64 predictor's source: its layout struct, its kernel body
-    and the Euler terms it inlines."""
+    """Hash of the FP64 predictor's source: its file (layout struct and kernel
+    body), the line derivative and tables it inlines, and the Euler terms."""
     csrc = os.path.join(ROOT, "paper_1905_07987_amd", "csrc")
     k = open(os.path.join(csrc, "kernels.hpp")).read()
-    a = k.index("struct GeoA2 {")
+    a = k.index("struct CT {")
     b = k.index("};", a)
-    c = k.index("// y = s D x along one line of n nodes.")  # line_deriv, then the kernel
-    d = k.index("// Kernel A for PDEs linear in Q", c)
+    c = k.index("// y = s D x along one line of n nodes.")  # line_deriv
+    d = k.index("// Kernel A, a lane pair per node", c)
     pde = open(os.path.join(csrc, "pde.hpp")).read()
     e = pde.index("struct Euler {")
     f = pde.index("\n};", e)
     h = hashlib.sha256()
+    h.update(open(os.path.join(csrc, "predict64.hpp")).read().encode())
     h.update(k[a:b].encode())
     h.update(k[c:d].encode())
     h.update(pde[e:f].encode())
@@ -438,7 +439,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cells", type=int, default=64)
     ap.add_argument("--order", type=int, default=5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the C4 adjoint gradient")
@@ -523,7 +524,7 @@ def main():
     traffic = read_traffic("c2")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": traffic, "kernel": "predict_kernel_pair<Euler<3>,5,double>",
+                "traffic": traffic, "kernel": "predict_kernel_n64<Euler<3>,5>",
                 "flops_per_launch": flops_launch, "ms_per_launch": round(pred_ms, 4)}
 
     variants = {"correct_kernel_ms": round(corr_ms, 4)}
@@ -538,6 +539,17 @@ def main():
                                   "rel_l2_vs_fp64_after_steps": err,
                                   "steps_compared": args.warmup + args.steps}
         log(f"mixed fp32: {t32 / args.steps:.3f} ms/step, {v32:.3e} DoF/s, rel L2 vs fp64 {err:.2e}")
+
+    if not args.no_mixed and args.precision == "fp64":
+        sb = adg.Solver(3, N, "euler", [m, m, m], precision="bf16x3", cfl=args.cfl)
+        Qb, clockb, tb, _, pb, cb = run(sb, args.steps, args.warmup)
+        errb = float(torch.linalg.vector_norm(Qb - Q64) / torch.linalg.vector_norm(Q64))
+        variants["mixed_bf16x3"] = {"value": dofs / (tb / args.steps * 1e-3),
+                                    "ms_per_step": round(tb / args.steps, 4), "predict_ms": round(pb, 4),
+                                    "rel_l2_vs_fp64_after_steps": errb,
+                                    "steps_compared": args.warmup + args.steps}
+        log(f"mixed bf16x3: {tb / args.steps:.3f} ms/step (predict {pb:.3f}), rel L2 vs fp64 {errb:.2e}")
+        del sb, Qb
 
     if args.precision == "fp64":
         # the CERK initial guess with N - 2 Picard passes (same order as
@@ -572,7 +584,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "DoF-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-predictor/f64-update",
+        "dtype": {"fp64": "f64", "fp32": "f32-predictor/f64-update",
+                  "bf16x3": "bf16x3-mfma-predictor/f64-update"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"c2: 3-D Euler, N={N}, {m}^3 periodic cells, seeded 8-mode Fourier "
                                f"state, CFL_N {args.cfl}, {args.precision}",

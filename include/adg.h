@@ -85,6 +85,12 @@ typedef int adg_status;
  * state, traces and clock are always stored in float64. */
 #define ADG_FP64 0
 #define ADG_MIXED_FP32 1
+/* FP32 predictor whose derivative contractions of the Picard passes run in
+ * split BF16 on the matrix cores: each float operand is the exact sum of
+ * three BF16 terms, the six partial products of size >= 2^-16 are
+ * accumulated in FP32 (v_mfma_f32_16x16x32_bf16).  Built for the PDEs that
+ * are not linear in Q (Euler); elsewhere UNSUPPORTED. */
+#define ADG_MIXED_BF16X3 2
 
 /* Initial guess of the predictor's Picard iteration (Sec. 3.3; Sec. 5.2 names
  * a continuous extension Runge-Kutta (CERK) guess as the alternative).
@@ -107,7 +113,7 @@ typedef struct {
   int dim;          /* 2 or 3 */
   int order;        /* polynomial degree N >= 1 (built range: adg_max_order) */
   int pde;          /* ADG_PDE_* */
-  int precision;    /* ADG_FP64 or ADG_MIXED_FP32 */
+  int precision;    /* ADG_FP64, ADG_MIXED_FP32 or ADG_MIXED_BF16X3 */
   int cells[3];     /* cells per axis (cells[2] ignored for dim 2) */
   double lo[3];     /* domain lower corner */
   double hi[3];     /* domain upper corner */

@@ -17,14 +17,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libadg.so")
 
 PDE_EULER, PDE_ELASTIC, PDE_ADVECTION = 1, 2, 3
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 GUESS_CONSTANT, GUESS_CERK = 0, 1
 _GUESS_NAMES = {"constant": GUESS_CONSTANT, "cerk": GUESS_CERK}
 STEP_NEXT_DT = 1
 
 PDE_USER = 4
 _PDE_NAMES = {"euler": PDE_EULER, "elastic": PDE_ELASTIC, "advection": PDE_ADVECTION, "user": PDE_USER}
-_PREC_NAMES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32}
+_PREC_NAMES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3,
+               "mixed_bf16x3": MIXED_BF16X3}
 
 
 class AdgError(RuntimeError):

@@ -216,8 +216,10 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
   if (c.order < 1) return fail(ADG_ERR_INVALID_ARG, "order must be >= 1");
   if (source ? c.pde != ADG_PDE_USER : pde_nvar(c.pde, c.dim) == 0)
     return fail(ADG_ERR_INVALID_ARG, source ? "adg_create_user needs pde = ADG_PDE_USER" : "unknown pde");
-  if (c.precision != ADG_FP64 && c.precision != ADG_MIXED_FP32)
+  if (c.precision != ADG_FP64 && c.precision != ADG_MIXED_FP32 && c.precision != ADG_MIXED_BF16X3)
     return fail(ADG_ERR_INVALID_ARG, "unknown precision");
+  if (c.precision == ADG_MIXED_BF16X3 && (source || c.pde != ADG_PDE_EULER))
+    return fail(ADG_ERR_UNSUPPORTED, "the split-BF16 predictor is built for the Euler equations");
   if (!(c.cfl > 0.0) || !std::isfinite(c.cfl)) return fail(ADG_ERR_INVALID_ARG, "cfl must be > 0");
   if (c.picard_iters < 0 || c.picard_iters > 64)
     return fail(ADG_ERR_INVALID_ARG, "picard_iters must be in 0..64");

@@ -96,7 +96,7 @@ struct alignas(2 * sizeof(R)) Pair {
   R x, y;
 };
 
-template <class PDE, int N, class R>
+template <class PDE, int N, class R, bool MF = false>
 struct GeoA1 {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
@@ -106,7 +106,9 @@ struct GeoA1 {
   static constexpr int by_threads = G::S >= 256 ? 1 : 256 / G::S;
   static constexpr int by_lds = cmax(1, (64 * 1024) / (CELL_ELEMS * (int)sizeof(R)));
   static constexpr int CPB = cmin(by_threads, by_lds);
-  static constexpr int BLOCK = CPB * G::S;
+  // MF (split-BF16 MFMA line derivatives): matrix instructions read every
+  // lane of a wave, so the block is padded to whole waves
+  static constexpr int BLOCK = MF ? (CPB * G::S + 63) / 64 * 64 : CPB * G::S;
   static constexpr int ELEMS = CPB * CELL_ELEMS;
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
   // Occupancy target (waves per SIMD) handed to the register allocator:
@@ -279,17 +281,106 @@ __device__ __forceinline__ double ricker(double f0, double t0, double amp, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Split-BF16 line derivatives on the matrix cores (ADG_MIXED_BF16X3).
+//
+// A float is the exact sum of three BF16 terms h + m + l (8 significant bits
+// each).  The product of D and x keeps the six partial products whose size
+// is at least 2^-16 of the whole, hh, hm, mh, hl, mm, lh (the three dropped
+// ones are below 2^-24), each a BF16 x BF16 product accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16: rows i = output node (n of 16 used), columns =
+// 16 (line, slice) pairs, K = (partial product, input node), one product per
+// 8-entry group of K, so two instructions cover the six.
+// ---------------------------------------------------------------------------
+typedef __bf16 adg_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float adg_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16x3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = static_cast<__bf16>(x);
+  const float r1 = x - static_cast<float>(h);  // exact
+  m = static_cast<__bf16>(r1);
+  l = static_cast<__bf16>(r1 - static_cast<float>(m));  // exact: at most 8 bits left
+}
+
+// part of the matrix (A) and of the data (B) in partial product p = 0..5
+__device__ __forceinline__ constexpr int bf_apart(int p) { return p == 2 || p == 4 ? 1 : (p == 5 ? 2 : 0); }
+__device__ __forceinline__ constexpr int bf_bpart(int p) { return p == 1 || p == 4 ? 1 : (p == 3 ? 2 : 0); }
+
+// The A operands of the two instructions for this lane: D's split parts,
+// row i = lane % 16, K group g = lane / 16 holds partial product 4 s + g.
+template <int n>
+__device__ __forceinline__ void bf16x3_matrix(adg_bf16x8 (&A)[2]) {
+  const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    const int p = 4 * st + g;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      __bf16 part[3] = {static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f)};
+      if (p < 6 && i < n && m < n) split_bf16x3(float(BasisConst<n>::D[i][m]), part[0], part[1], part[2]);
+      A[st][m] = p < 6 ? part[bf_apart(p < 6 ? p : 0)] : static_cast<__bf16>(0.0f);
+    }
+  }
+}
+
+// Differentiate, in place, NLINES lines of n two-slice elements: line t of
+// the list starts at row_of(t) (a Pair<float> pointer, stride 1 along the
+// line) and is scaled by scale_of(t).  Every wave of the block takes tiles of
+// 16 (line, slice) columns in turn; all 64 lanes of a wave execute the
+// matrix instructions.
+template <int n, class RowOf, class ScaleOf>
+__device__ __forceinline__ void bf16x3_line_derivs(int NLINES, RowOf row_of, ScaleOf scale_of, int nwaves,
+                                                   const adg_bf16x8 (&A)[2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, g = lane >> 4;
+  const int ntiles = (2 * NLINES + 15) / 16;
+  for (int tile = wave; tile < ntiles; tile += nwaves) {
+    const int c = tile * 16 + col;  // (line, slice) column, slice fastest
+    const int t = c >> 1, sl = c & 1;
+    const bool valid = t < NLINES;
+    float* xp = valid ? reinterpret_cast<float*>(row_of(t)) + sl : nullptr;
+    float x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = (valid && m < n) ? xp[2 * m] : 0.0f;
+    __bf16 xs[3][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) split_bf16x3(x[m], xs[0][m], xs[1][m], xs[2][m]);
+    adg_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int p = 4 * st + g;
+      const int bp = bf_bpart(p < 6 ? p : 0);
+      adg_bf16x8 B;
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        B[m] = p < 6 ? (bp == 0 ? xs[0][m] : (bp == 1 ? xs[1][m] : xs[2][m])) : static_cast<__bf16>(0.0f);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[st], B, acc, 0, 0, 0);
+    }
+    // lane (g, col) holds output nodes i = 4 g + r of column col
+    if (valid) {
+      const float s = scale_of(t);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        if (i < n) xp[2 * i] = acc[r] * s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel A, one thread per node (used for the FP32 predictor).
 // ---------------------------------------------------------------------------
-template <class PDE, int N, class R>
-__global__ void __launch_bounds__((GeoA1<PDE, N, R>::BLOCK), (GeoA1<PDE, N, R>::MIN_WAVES))
+template <class PDE, int N, class R, bool MF = false>
+__global__ void __launch_bounds__((GeoA1<PDE, N, R, MF>::BLOCK), (GeoA1<PDE, N, R, MF>::MIN_WAVES))
 predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ params,
                const double* __restrict__ clock, double* Qout, double* __restrict__ traces) {
+  // MF: the derivative contractions of the Picard passes in split BF16 on
+  // the matrix cores (ADG_MIXED_BF16X3), everything else as in FP32.
   // Q and Qout may be the same array (in-place step): each element is read
   // once at the start and written once at the end by the same thread.
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
-  using GA = GeoA1<PDE, N, R>;
+  using GA = GeoA1<PDE, N, R, MF>;
   using T = CT<R, G::n>;
   using P2 = Pair<R>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
@@ -300,7 +391,10 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
   R* const lds = reinterpret_cast<R*>(lds2);
 
   const int tid = threadIdx.x;
-  const int lc = tid / S, k = tid - lc * S;
+  // lanes past the block's nodes (a block padded to whole waves) only take
+  // part in the line derivatives
+  const bool node = !MF || tid < CPB * S;
+  const int lc = node ? tid / S : 0, k = node ? tid - lc * S : 0;
   int pk[DIM];  // this node's slot in the LDS rows of each direction
   {
     const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
@@ -310,7 +404,7 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
   }
   const long long cell0 = (long long)xcd_block(blockIdx.x, a.nblocks) * CPB;
   const long long cell = cell0 + lc;
-  const bool active = cell < a.ncells;
+  const bool active = node && cell < a.ncells;
   const long long cl = active ? cell : a.ncells - 1;  // clamp loads of the ragged tail
 
   double u64[NV];
@@ -341,6 +435,8 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
   // (made visible by the first barrier below)
 
   P2* const mine = lds2 + lc * (GA::CELL_ELEMS / 2);  // this cell's pairs [NCH][SP]
+  adg_bf16x8 Amf[2];  // MF: this lane's split-BF16 operands of D
+  if constexpr (MF) bf16x3_matrix<n>(Amf);
   R q[n][NV];     // current iterate at the n time nodes of node k
   R Fbar[DIM][NV], Nbar[NV], Sbar[NV];  // final pass: time averages
 
@@ -387,19 +483,21 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
           }
       }
       if constexpr (USE_LDS) {
+        if (node) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          if constexpr (!FIN) {
+          for (int d = 0; d < DIM; ++d) {
+            if constexpr (!FIN) {
 #pragma unroll
-            for (int c = 0; c < NFL; ++c) {
-              const int v = C::flux_var(d, c);
-              mine[(d * NCHD + c) * SP + pk[d]] = P2{Fa[d][v], two ? Fb[d][v] : R(0)};
+              for (int c = 0; c < NFL; ++c) {
+                const int v = C::flux_var(d, c);
+                mine[(d * NCHD + c) * SP + pk[d]] = P2{Fa[d][v], two ? Fb[d][v] : R(0)};
+              }
             }
-          }
 #pragma unroll
-          for (int c = 0; c < NGR; ++c) {
-            const int v = C::grad_var(c);
-            mine[(d * NCHD + NFL + c) * SP + pk[d]] = P2{q[j0][v], two ? q[j1][v] : R(0)};
+            for (int c = 0; c < NGR; ++c) {
+              const int v = C::grad_var(c);
+              mine[(d * NCHD + NFL + c) * SP + pk[d]] = P2{q[j0][v], two ? q[j1][v] : R(0)};
+            }
           }
         }
         __syncthreads();
@@ -407,6 +505,16 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
         //     both slices of every channel in place
         constexpr int CH0 = FIN ? NFL : 0;  // the final pass only needs gradients
         constexpr int CHM = (CH0 + NCHD + 1) / 2;
+        if constexpr (MF) {
+          constexpr int NCT = NCHD - CH0;
+          bf16x3_line_derivs<n>(
+              CPB * DIM * NCT * F,
+              [&](int t) {
+                const int l = t % F, ch = CH0 + (t / F) % NCT, d = (t / (F * NCT)) % DIM, c2 = t / (F * NCT * DIM);
+                return lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
+              },
+              [&](int t) { return float(inv_h[(t / (F * NCT)) % DIM]); }, BLOCK / 64, Amf);
+        } else
         for (int task = tid; task < CPB * DIM * 2 * F; task += BLOCK) {
           const int l = task % F;
           const int hf = (task / F) & 1;
@@ -557,13 +665,15 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
   R* const fin_mine = lds + lc * GA::CELL_ELEMS;
+  if (node) {
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
+    for (int d = 0; d < DIM; ++d) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
+      for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
 #pragma unroll
-    for (int c = 0; c < NFL; ++c)
-      fin_mine[d * FIN_D + (NV + c) * SP + pk[d]] = Fbar[d][C::flux_var(d, c)];
+      for (int c = 0; c < NFL; ++c)
+        fin_mine[d * FIN_D + (NV + c) * SP + pk[d]] = Fbar[d][C::flux_var(d, c)];
+    }
   }
   __syncthreads();
   for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
@@ -2091,6 +2201,15 @@ struct Launch {
       a.nblocks = blocks_a<GA>(a);
       hipLaunchKernelGGL((predict_kernel_node<PDE, N, float>), dim3(a.nblocks), dim3(GA::BLOCK), 0,
                          st, a, Q, params, clock, Qout, traces);
+    } else if (precision == ADG_MIXED_BF16X3) {
+      if constexpr (PDE::kLinear) {
+        return hipErrorNotSupported;  // refused when the context is created
+      } else {
+        using GA = GeoA1<PDE, N, float, true>;
+        a.nblocks = blocks_a<GA>(a);
+        hipLaunchKernelGGL((predict_kernel_node<PDE, N, float, true>), dim3(a.nblocks), dim3(GA::BLOCK), 0,
+                           st, a, Q, params, clock, Qout, traces);
+      }
     } else if constexpr (UseN64<PDE, N>::value) {
       using GA = GeoN64<PDE, N>;
       a.nblocks = blocks_a<GA>(a);
