@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ADER-DG DoF-updates/s per step, FP64 vs mixed at stated L2 error; adjoint s/grad"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (= FP64 matrix) peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -522,9 +523,16 @@ def main():
     flops_launch = flops_cell * m ** 3
     achieved = flops_launch / (pred_ms * 1e-3) / 1e12
     traffic = read_traffic("c2")
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": traffic, "kernel": "predict_kernel_n64<Euler<3>,5>",
+    # the FP32 and split-BF16 predictors compute in FP32 vector arithmetic
+    # (the latter with its derivatives on the matrix cores)
+    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    kname = {"fp64": f"predict_kernel_n64<Euler<3>,{N}>", "fp32": f"predict_kernel_node<Euler<3>,{N},float,false>",
+             "bf16x3": f"predict_kernel_node<Euler<3>,{N},float,true>"}[args.precision]
+    if args.precision != "fp64":
+        traffic = None
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": traffic, "kernel": kname,
                 "flops_per_launch": flops_launch, "ms_per_launch": round(pred_ms, 4)}
 
     variants = {"correct_kernel_ms": round(corr_ms, 4)}
