@@ -66,29 +66,45 @@ __device__ __forceinline__ int face_line_node(int d, int f, int m) {
 
 // ---------------------------------------------------------------------------
 // 1. Face projections of lam: A[c][face][v][f] = sum_m l_side(m) / w_m lam.
+// Each lam value lies on the lines of 2 DIM faces; a block stages its cells'
+// lam in LDS with contiguous loads (each value read from HBM once) and
+// writes the projections in A's order (contiguous stores).
 // ---------------------------------------------------------------------------
+template <class PDE, int N>
+struct GeoAdjP {
+  using G = Geo<PDE, N>;
+  static constexpr int CELL = G::NV * G::S;                // lam values per cell
+  static constexpr int OUT = 2 * G::DIM * G::NV * G::F;    // projections per cell
+  static constexpr int CPB = cmax(1, cmin(8, 4096 / CELL));
+  static constexpr int BLOCK = 256;
+};
+
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 adj_face_project_kernel(const KArgs a, const double* __restrict__ lam, double* __restrict__ A) {
   using G = Geo<PDE, N>;
+  using GP = GeoAdjP<PDE, N>;
   using T = CT<double, G::n>;
   constexpr int n = G::n, S = G::S, F = G::F, NV = G::NV, DIM = G::DIM;
-  const long long total = a.ncells * (2 * DIM * NV * F);
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= total) return;
-  const int f = (int)(id % F);
-  long long r = id / F;
-  const int v = (int)(r % NV);
-  r /= NV;
-  const int face = (int)(r % (2 * DIM));
-  const long long c = r / (2 * DIM);
-  const int d = face >> 1, side = face & 1;
-  const double* src = lam + (c * NV + v) * S;
-  double acc = 0.0;
+  constexpr int CELL = GP::CELL, OUT = GP::OUT, CPB = GP::CPB;
+  __shared__ double sl[CPB * CELL];
+  const long long cell0 = (long long)blockIdx.x * CPB;
+  const int here = (int)(a.ncells - cell0 < CPB ? a.ncells - cell0 : CPB);
+  const double* src = lam + cell0 * CELL;
+  for (int i = threadIdx.x; i < here * CELL; i += GP::BLOCK) sl[i] = src[i];
+  __syncthreads();
+  double* dst = A + cell0 * OUT;
+  for (int o = threadIdx.x; o < here * OUT; o += GP::BLOCK) {
+    const int c2 = o / OUT, r = o - c2 * OUT;
+    const int f = r % F, v = (r / F) % NV, face = r / (F * NV);
+    const int d = face >> 1, side = face & 1;
+    const double* row = sl + c2 * CELL + v * S;
+    double acc = 0.0;
 #pragma unroll
-  for (int m = 0; m < n; ++m)
-    acc += (side ? T::l1(m) : T::l0(m)) * (1.0 / T::w(m)) * src[face_line_node<DIM, n>(d, f, m)];
-  A[id] = acc;
+    for (int m = 0; m < n; ++m)
+      acc += (side ? T::l1(m) : T::l0(m)) * (1.0 / T::w(m)) * row[face_line_node<DIM, n>(d, f, m)];
+    dst[o] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -457,9 +473,9 @@ struct AdjLaunch {
     double* A = work;
     double* B = work + a0.ncells * face_elems;
     KArgs a = a0;
-    const long long nproj = a0.ncells * face_elems;
-    hipLaunchKernelGGL((adj_face_project_kernel<PDE, N>), dim3((unsigned)((nproj + 255) / 256)),
-                       dim3(256), 0, st, a, lam, A);
+    using GPj = GeoAdjP<PDE, N>;
+    hipLaunchKernelGGL((adj_face_project_kernel<PDE, N>), dim3((unsigned)((a0.ncells + GPj::CPB - 1) / GPj::CPB)),
+                       dim3(GPj::BLOCK), 0, st, a, lam, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.nblocks = (int)((a0.ncells + GR::CPB - 1) / GR::CPB);

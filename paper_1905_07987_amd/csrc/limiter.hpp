@@ -97,7 +97,8 @@ struct GeoLimW {
   static constexpr int P1 = VG * GL::m * ipow(GL::n, GL::DIM - 1);
   static constexpr int P2 = GL::DIM == 3 ? VG * GL::m * GL::m * GL::n : 0;
   static constexpr int RA = cmax(VG * GL::S, P2), RB = P1;
-  static constexpr int PW = RA + RB;
+  static constexpr int RN = (GL::NV - VG) * GL::S;  // nodal values of the second group
+  static constexpr int PW = RA + RB + RN;
   // columns of subcells along the last axis: one per lane
   static constexpr int LAST = ipow(GL::m, GL::DIM - 1);
   static_assert(LAST <= 64, "one column of subcells per lane");
@@ -107,7 +108,7 @@ struct GeoLimW {
 // (nodal values in A, [v][kz][ky][kx], to B, [v][kz][ky][sx]); in 3-D then
 // along y (B to A, [v][kz][sy][sx]).
 template <class PDE, int N, int NVS>
-__device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane) {
+__device__ __forceinline__ void lim_stages_wave(const double* src, double* ra, double* rb, int lane) {
   using GL = GeoLim<PDE, N>;
   using LC = LimConst<GL::n>;
   constexpr int n = GL::n, m = GL::m;
@@ -115,7 +116,7 @@ __device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane
   for (int line = lane; line < L1; line += 64) {
     double in[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k) in[k] = ra[line * n + k];
+    for (int k = 0; k < n; ++k) in[k] = src[line * n + k];
 #pragma unroll
     for (int s = 0; s < m; ++s) {
       double acc = 0.0;
@@ -144,23 +145,17 @@ __device__ __forceinline__ void lim_stages_wave(double* ra, double* rb, int lane
   }
 }
 
-// Variables V0 .. V0 + NVS - 1 of the cell at Qc ([nv][S], global) through
-// the projection: out[V0 + v][j] = the average of variable V0 + v over the
-// j-th subcell of this lane's column (subcell index lane + j m^(dim-1)), for
-// lanes below the column count.  Qold (if not null) receives a copy.
+// Variables V0 .. V0 + NVS - 1 of a cell through the projection, from
+// their nodal values at src (LDS, [v][S]): out[V0 + v][j] = the average of
+// variable V0 + v over the j-th subcell of this lane's column (subcell index
+// lane + j m^(dim-1)), for lanes below the column count.
 template <class PDE, int N, int V0, int NVS>
-__device__ __forceinline__ void lim_group_wave(const double* __restrict__ Qc, double* __restrict__ Qold, double* ra,
-                                               double* rb, int lane, double (&out)[PDE::NV][2 * N + 1]) {
+__device__ __forceinline__ void lim_group_wave(const double* src, double* ra, double* rb, int lane,
+                                               double (&out)[PDE::NV][2 * N + 1]) {
   using GL = GeoLim<PDE, N>;
   using LC = LimConst<GL::n>;
-  constexpr int n = GL::n, m = GL::m, S = GL::S;
-  for (int i = lane; i < NVS * S; i += 64) {
-    const double x = Qc[V0 * S + i];
-    ra[i] = x;
-    if (Qold) Qold[V0 * S + i] = x;
-  }
-  lim_wave_sync();
-  lim_stages_wave<PDE, N, NVS>(ra, rb, lane);
+  constexpr int n = GL::n, m = GL::m;
+  lim_stages_wave<PDE, N, NVS>(src, ra, rb, lane);
   if (lane < GeoLimW<PDE, N>::LAST) {
 #pragma unroll
     for (int v = 0; v < NVS; ++v) {
@@ -180,6 +175,19 @@ __device__ __forceinline__ void lim_group_wave(const double* __restrict__ Qc, do
   lim_wave_sync();  // the next group overwrites the stages
 }
 
+// The cell's nodal values from registers (lane k < S: node k) to the wave's
+// LDS: the first group where the projection's first stage reads it, the
+// second group in a region of its own.
+template <class PDE, int N>
+__device__ __forceinline__ void lim_stage_nodes(const double (&x)[PDE::NV], double* ra, double* rn, int lane) {
+  constexpr int S = GeoLim<PDE, N>::S, VG = GeoLimW<PDE, N>::VG;
+  if (lane < S) {
+#pragma unroll
+    for (int v = 0; v < PDE::NV; ++v) (v < VG ? ra + v * S : rn + (v - VG) * S)[lane] = x[v];
+  }
+  lim_wave_sync();
+}
+
 __device__ __forceinline__ double lim_wave_min(double x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
@@ -191,6 +199,29 @@ __device__ __forceinline__ double lim_wave_max(double x) {
   return x;
 }
 
+// The prepare and detect kernels issue every global load of a cell at once
+// (all nodal values into registers, and in detect the DMP ranges, one
+// (variable, cell) per lane) before the chain of dependent LDS stages of
+// the projection, so that a cell waits for one HBM round trip instead of
+// one per variable group and neighbour.
+template <class PDE, int N>
+struct GeoLimSeq {
+  static unsigned grid(long long ncells) {
+    return (unsigned)((ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
+  }
+};
+
+// nodal values of cell c (lane k < S: node k), zero past the grid
+template <class PDE, int N>
+__device__ __forceinline__ void lim_load_nodes(const double* __restrict__ Q, long long c, long long ncells, int lane,
+                                               double (&x)[PDE::NV]) {
+  constexpr int NV = PDE::NV, S = GeoLim<PDE, N>::S;
+  const bool ok = c < ncells && lane < S;
+  const long long cl = ok ? c : 0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = ok ? Q[(cl * NV + v) * S + lane] : 0.0;
+}
+
 // One wave per cell: u^n copied, status kept, range of the subcell
 // averages at t^n.  Block 0 clears the counters of the step.
 template <class PDE, int N>
@@ -199,7 +230,7 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
                    const uint8_t* __restrict__ status, const LimWork w) {
   using GL = GeoLim<PDE, N>;
   using GW = GeoLimW<PDE, N>;
-  constexpr int NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
+  constexpr int NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m;
   __shared__ double buf[GW::WPB][GW::PW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (blockIdx.x == 0 && tid < 4) w.counters[tid] = 0;
@@ -207,8 +238,14 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   if (c >= a.ncells) return;
   double* ra = buf[wv];
   double* rb = ra + GW::RA;
+  double* rn = rb + GW::RB;
   const uint8_t st = status[c];
+  double x[NV];
+  lim_load_nodes<PDE, N>(Q, c, a.ncells, lane, x);
   if (lane == 0) w.st_prev[c] = st;
+  if (lane < S)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w.Qold[(c * NV + v) * S + lane] = x[v];
   double lo[NV], hi[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -216,18 +253,18 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
     hi[v] = -INFINITY;
   }
   if (st >= 2) {
-    for (int i = lane; i < NV * S; i += 64) w.Qold[c * NV * S + i] = Q[c * NV * S + i];
     for (int s = lane; s < NS; s += 64)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double x = sub_in[(c * NV + v) * NS + s];
-        lo[v] = fmin(lo[v], x);
-        hi[v] = fmax(hi[v], x);
+        const double y = sub_in[(c * NV + v) * NS + s];
+        lo[v] = fmin(lo[v], y);
+        hi[v] = fmax(hi[v], y);
       }
   } else {
+    lim_stage_nodes<PDE, N>(x, ra, rn, lane);
     double q[NV][m];
-    lim_group_wave<PDE, N, 0, GW::VG>(Q + c * NV * S, w.Qold + c * NV * S, ra, rb, lane, q);
-    lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(Q + c * NV * S, w.Qold + c * NV * S, ra, rb, lane, q);
+    lim_group_wave<PDE, N, 0, GW::VG>(ra, ra, rb, lane, q);
+    lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(rn, ra, rb, lane, q);
     if (lane < GW::LAST)
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -247,46 +284,61 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   }
 }
 
+// The DMP ranges of cell c and its face neighbours, one (cell, variable)
+// per lane: lane v 8 + j holds (lo, hi) of variable v of cell j (j = 0 the
+// cell itself, 1 .. 2 dim its face neighbours; an empty range past a
+// non-periodic boundary and on the spare lanes).
+template <class PDE, int N>
+__device__ __forceinline__ void lim_load_ranges(const KArgs& a, const double* lohi, long long c, int lane,
+                                                double& lo, double& hi) {
+  constexpr int DIM = PDE::DIM, NV = PDE::NV;
+  static_assert(NV * 8 <= 64 && 2 * DIM + 1 <= 8, "one lane per (variable, cell)");
+  const int v = lane >> 3, j = lane & 7;
+  long long o = -1;
+  if (c < a.ncells && v < NV && j <= 2 * DIM)
+    o = j == 0 ? c : lim_neighbour<DIM>(a, c, (j - 1) >> 1, ((j - 1) & 1) ? 1 : -1);
+  lo = INFINITY;
+  hi = -INFINITY;
+  if (o >= 0) {
+    lo = lohi[(o * NV + v) * 2];
+    hi = lohi[(o * NV + v) * 2 + 1];
+  }
+}
+
 // One wave per cell: is the candidate troubled?
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) {
   using GL = GeoLim<PDE, N>;
   using GW = GeoLimW<PDE, N>;
-  constexpr int DIM = GL::DIM, NV = GL::NV, S = GL::S, NS = GL::NS, m = GL::m, n = GL::n;
+  constexpr int NV = GL::NV, S = GL::S, m = GL::m;
   __shared__ double buf[GW::WPB][GW::PW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const long long c = (long long)blockIdx.x * GW::WPB + wv;
   if (c >= a.ncells) return;
   double* ra = buf[wv];
   double* rb = ra + GW::RA;
+  double* rn = rb + GW::RB;
+  double x[NV], rlo, rhi;
+  lim_load_nodes<PDE, N>(Q, c, a.ncells, lane, x);
+  lim_load_ranges<PDE, N>(a, w.lohi, c, lane, rlo, rhi);
+  bool bad = lane < S && !PDE::admissible(x, x, a.pde);
+  lim_stage_nodes<PDE, N>(x, ra, rn, lane);
   // DMP range: the cell's and its face neighbours' subcell averages at t^n
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    rlo = fmin(rlo, __shfl_xor(rlo, off, 64));
+    rhi = fmax(rhi, __shfl_xor(rhi, off, 64));
+  }
   double lo[NV], hi[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    lo[v] = w.lohi[(c * NV + v) * 2];
-    hi[v] = w.lohi[(c * NV + v) * 2 + 1];
-  }
-  for (int d = 0; d < DIM; ++d)
-    for (int sd = -1; sd <= 1; sd += 2) {
-      const long long o = lim_neighbour<DIM>(a, c, d, sd);
-      if (o < 0) continue;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        lo[v] = fmin(lo[v], w.lohi[(o * NV + v) * 2]);
-        hi[v] = fmax(hi[v], w.lohi[(o * NV + v) * 2 + 1]);
-      }
-    }
-  bool bad = false;
-  for (int k = lane; k < S; k += 64) {
-    double q[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = Q[(c * NV + v) * S + k];
-    bad = bad || !PDE::admissible(q, q, a.pde);
+    lo[v] = __shfl(rlo, v * 8, 64);
+    hi[v] = __shfl(rhi, v * 8, 64);
   }
   double qv[NV][m];
-  lim_group_wave<PDE, N, 0, GW::VG>(Q + c * NV * S, nullptr, ra, rb, lane, qv);
-  lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(Q + c * NV * S, nullptr, ra, rb, lane, qv);
+  lim_group_wave<PDE, N, 0, GW::VG>(ra, ra, rb, lane, qv);
+  lim_group_wave<PDE, N, GW::VG, NV - GW::VG>(rn, ra, rb, lane, qv);
   if (lane < GW::LAST) {
 #pragma unroll
     for (int j = 0; j < m; ++j) {
@@ -765,7 +817,7 @@ struct LimLaunch {
   // prepare; the caller's DG step follows
   static hipError_t before(const KArgs& a, const double* Q, const double* sub_in, const uint8_t* status,
                            const LimWork& w, hipStream_t st) {
-    const unsigned grid = (unsigned)((a.ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
+    const unsigned grid = GeoLimSeq<PDE, N>::grid(a.ncells);
     hipLaunchKernelGGL((lim_prepare_kernel<PDE, N>), dim3(grid), dim3(64 * GeoLimW<PDE, N>::WPB), 0, st, a, Q,
                        sub_in, status, w);
     return hipGetLastError();
@@ -774,7 +826,7 @@ struct LimLaunch {
   static hipError_t after(const KArgs& a, double* Q, double* clock, const double* traces,
                           const double* sub_in, double* sub_out, uint8_t* status, const LimWork& w,
                           int next_dt, hipStream_t st) {
-    const unsigned grid = (unsigned)((a.ncells + GeoLimW<PDE, N>::WPB - 1) / GeoLimW<PDE, N>::WPB);
+    const unsigned grid = GeoLimSeq<PDE, N>::grid(a.ncells);
     hipLaunchKernelGGL((lim_detect_kernel<PDE, N>), dim3(grid), dim3(64 * GeoLimW<PDE, N>::WPB), 0, st, a, Q, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
