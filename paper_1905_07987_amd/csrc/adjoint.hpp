@@ -75,7 +75,7 @@ struct GeoAdjP {
   using G = Geo<PDE, N>;
   static constexpr int CELL = G::NV * G::S;                // lam values per cell
   static constexpr int OUT = 2 * G::DIM * G::NV * G::F;    // projections per cell
-  static constexpr int CPB = cmax(1, cmin(8, 4096 / CELL));
+  static constexpr int CPB = cmax(1, cmin(8, 1152 / CELL));
   static constexpr int BLOCK = 256;
 };
 
@@ -93,17 +93,18 @@ adj_face_project_kernel(const KArgs a, const double* __restrict__ lam, double* _
   const double* src = lam + cell0 * CELL;
   for (int i = threadIdx.x; i < here * CELL; i += GP::BLOCK) sl[i] = src[i];
   __syncthreads();
-  double* dst = A + cell0 * OUT;
-  for (int o = threadIdx.x; o < here * OUT; o += GP::BLOCK) {
-    const int c2 = o / OUT, r = o - c2 * OUT;
-    const int f = r % F, v = (r / F) % NV, face = r / (F * NV);
-    const int d = face >> 1, side = face & 1;
-    const double* row = sl + c2 * CELL + v * S;
-    double acc = 0.0;
+  for (int c2 = 0; c2 < here; ++c2) {
+    double* dst = A + (cell0 + c2) * OUT;
+    for (int r = threadIdx.x; r < OUT; r += GP::BLOCK) {
+      const int f = r % F, v = (r / F) % NV, face = r / (F * NV);
+      const int d = face >> 1, side = face & 1;
+      const double* row = sl + c2 * CELL + v * S;
+      double acc = 0.0;
 #pragma unroll
-    for (int m = 0; m < n; ++m)
-      acc += (side ? T::l1(m) : T::l0(m)) * (1.0 / T::w(m)) * row[face_line_node<DIM, n>(d, f, m)];
-    dst[o] = acc;
+      for (int m = 0; m < n; ++m)
+        acc += (side ? T::l1(m) : T::l0(m)) * (1.0 / T::w(m)) * row[face_line_node<DIM, n>(d, f, m)];
+      dst[r] = acc;
+    }
   }
 }
 
