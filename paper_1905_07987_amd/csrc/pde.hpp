@@ -72,6 +72,25 @@ struct Euler {
     }
   }
 
+  // F_d alone (the same arithmetic as fluxes() for that direction): kernels
+  // that store the fluxes one direction at a time keep fewer values live
+  template <class R>
+  __device__ static __forceinline__ void flux_dir(const R* Q, const R*, const PdeConsts& pc, int d, R* F) {
+    const R gm1 = R(pc.gamma) - R(1);
+    const R irho = R(1) / Q[0];
+    R jj = R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) jj += Q[1 + a] * Q[1 + a];
+    const R p = gm1 * (Q[DIM + 1] - R(0.5) * jj * irho);
+    const R Ep = Q[DIM + 1] + p;
+    const R ud = Q[1 + d] * irho;
+    F[0] = Q[1 + d];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) F[1 + a] = ud * Q[1 + a];
+    F[1 + d] += p;
+    F[DIM + 1] = ud * Ep;
+  }
+
   template <class R>
   __device__ static __forceinline__ void ncp(const R*, const R*, const PdeConsts&,
                                              const R (*)[NV], R* B) {

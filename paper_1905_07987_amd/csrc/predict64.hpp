@@ -44,6 +44,14 @@ struct GeoN64 {
   static constexpr int MIN_WAVES = cmax(1, cmin(3, LDS_BLOCKS * (BLOCK / 64) / 4));
 };
 
+// PDEs that provide flux_dir(Q, P, pc, d, F), the flux of one direction
+template <class... T>
+using n64_void_t = void;
+template <class PDE, class = void>
+struct HasFluxDir : std::false_type {};
+template <class PDE>
+struct HasFluxDir<PDE, n64_void_t<decltype(&PDE::template flux_dir<double>)>> : std::true_type {};
+
 template <class PDE, int N>
 __global__ void __launch_bounds__((GeoN64<PDE, N>::BLOCK), (GeoN64<PDE, N>::MIN_WAVES))
 predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ params,
@@ -77,9 +85,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int d = 0; d < DIM; ++d) pk[d] = GN::G::line_of(d, kx, ky, kz) * LS + kd[d];
   }
 
-  double u[NV], P[NP > 0 ? NP : 1];
+  // u^n is read from Q where it is used (an L2 hit after the first read;
+  // Q is only written at the end, by this thread) rather than kept in
+  // registers through the Picard loop
+  auto load_u = [&](double (&uu)[NV]) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
+    for (int v = 0; v < NV; ++v) uu[v] = Q[(cl * NV + v) * S + k];
+  };
+  double P[NP > 0 ? NP : 1];
 #pragma unroll
   for (int p = 0; p < NP; ++p) P[p] = params[cl * NP + p];
   const double t_n = clock[0], dt = clock[1];
@@ -126,14 +139,27 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     P2* const mine = lds2 + lc * (GN::CELL_ELEMS / 2);
     if (node) {
       if constexpr (!FIN) {
-        double Fa[DIM][NV], Fb[DIM][NV];
-        PDE::fluxes(qa, P, a.pde, Fa);
-        PDE::fluxes(qb, P, a.pde, Fb);
+        if constexpr (HasFluxDir<PDE>::value) {
+          // one direction at a time (fewer values live)
 #pragma unroll
-        for (int d = 0; d < DIM; ++d)
+          for (int d = 0; d < DIM; ++d) {
+            double Fa[NV], Fb[NV];
+            PDE::flux_dir(qa, P, a.pde, d, Fa);
+            PDE::flux_dir(qb, P, a.pde, d, Fb);
 #pragma unroll
-          for (int cc = 0; cc < NFL; ++cc)
-            mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[d][C::flux_var(d, cc)], Fb[d][C::flux_var(d, cc)]};
+            for (int cc = 0; cc < NFL; ++cc)
+              mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[C::flux_var(d, cc)], Fb[C::flux_var(d, cc)]};
+          }
+        } else {
+          double Fa[DIM][NV], Fb[DIM][NV];
+          PDE::fluxes(qa, P, a.pde, Fa);
+          PDE::fluxes(qb, P, a.pde, Fb);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int cc = 0; cc < NFL; ++cc)
+              mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[d][C::flux_var(d, cc)], Fb[d][C::flux_var(d, cc)]};
+        }
       }
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
@@ -145,12 +171,19 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     constexpr int CH0 = FIN ? NFL : 0;
     constexpr int NCT = NCHD - CH0;
     constexpr int NT = CPB * DIM * NCT * F;
-    for (int task = tid; task < NT; task += BLOCK) {
+    // Whole tasks (both slices of a line) while every lane has one; the rest
+    // split by slice, one slice per lane, so the last round costs half a task.
+    constexpr int NWHOLE = NT / BLOCK * BLOCK;
+    auto row_of = [&](int task, int& d) {
       const int l = task % F;
       const int ch = CH0 + (task / F) % NCT;
-      const int d = (task / (F * NCT)) % DIM;
+      d = (task / (F * NCT)) % DIM;
       const int c2 = task / (F * NCT * DIM);
-      P2* row = lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * LS;
+      return lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * LS;
+    };
+    for (int task = tid; task < NWHOLE; task += BLOCK) {
+      int d;
+      P2* row = row_of(task, d);
       double x0[n], x1[n], y0[n], y1[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) {
@@ -162,6 +195,16 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       line_deriv<double, n>(x1, y1, a.inv_h[d]);
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+    }
+    for (int h = tid; h < 2 * (NT - NWHOLE); h += BLOCK) {
+      int d;
+      double* half = reinterpret_cast<double*>(row_of(NWHOLE + (h >> 1), d)) + (h & 1);
+      double x[n], y[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) x[m] = half[2 * m];
+      line_deriv<double, n>(x, y, a.inv_h[d]);
+#pragma unroll
+      for (int i = 0; i < n; ++i) half[2 * i] = y[i];
     }
     __syncthreads();
 #pragma unroll
@@ -210,6 +253,8 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
 
   // q^{r+1}_i = u + dt sum_j KW_ij R_j, R_j held in q[j]
   auto update = [&]() {
+    double u[NV];
+    load_u(u);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double t[n];
@@ -234,13 +279,12 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     // q(tau) = u + dt sum_s b_s(tau) k_s, is taken at the time nodes.  Each
     // stage is one LDS round of one state; the passes that follow are
     // ordinary Picard passes.
+    double Y[NV];
+    load_u(Y);
 #pragma unroll
     for (int j = 0; j < n; ++j)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) q[j][v] = u[v];
-    double Y[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Y[v] = u[v];
+      for (int v = 0; v < NV; ++v) q[j][v] = Y[v];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], kk[NV], B[NV], Sv[NV];
@@ -253,14 +297,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         for (int v = 0; v < NV; ++v) q[j][v] += b * kk[v];
       }
       const double as = st == 2 ? 1.0 : 0.5;  // Y_{s+1} = u + dt a_{s+1} k_s
+      load_u(Y);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Y[v] = u[v] + dt * as * kk[v];
+      for (int v = 0; v < NV; ++v) Y[v] += dt * as * kk[v];
     }
   } else {
     // First Picard step: q^0 = u^n at every time node, so every slice has
     // the same right-hand side apart from point sources; one round suffices.
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q[0][v] = u[v];
+    load_u(q[0]);
     double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], R0[NV], B[NV], Sv[NV];
     round(std::false_type{}, q[0], q[0], div, g, div1, g1);
     rhs(q[0], 0, div, g, R0, B, Sv, false);
@@ -333,8 +377,6 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         for (int d = 0; d < DIM; ++d) g[d][v] = 0.0;
       }
     }
-    double Fl[DIM][NV];
-    PDE::fluxes(q[j], P, a.pde, Fl);
     rhs(q[j], j, div, g, Rv, B, Sv, true);
     const double wj = T::w(j);
 #pragma unroll
@@ -342,8 +384,22 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       if constexpr (PDE::kHasNcp) qbar[v] += wj * q[j][v];
       Nbar[v] += wj * B[v];
       Sbar[v] += wj * Sv[v];
+    }
+    if constexpr (HasFluxDir<PDE>::value) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) Fbar[d][v] += wj * Fl[d][v];
+      for (int d = 0; d < DIM; ++d) {
+        double Fl[NV];
+        PDE::flux_dir(q[j], P, a.pde, d, Fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[d][v] += wj * Fl[v];
+      }
+    } else {
+      double Fl[DIM][NV];
+      PDE::fluxes(q[j], P, a.pde, Fl);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fbar[d][v] += wj * Fl[d][v];
     }
   }
 
