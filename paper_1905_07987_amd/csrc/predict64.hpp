@@ -18,6 +18,10 @@
 
 namespace adg {
 
+#ifndef N64_SINGLE_WAVES
+#define N64_SINGLE_WAVES 4
+#endif
+
 template <class PDE, int N>
 struct GeoN64 {
   using G = Geo<PDE, N>;
@@ -32,16 +36,34 @@ struct GeoN64 {
   // banks for the 16-byte accesses, and the smaller rows let three blocks
   // share a compute unit.
   static constexpr int LS = n == 6 ? 6 : G::LS, SP = F * LS;
-  static constexpr int ITER_ELEMS = 2 * C::NCH * SP;           // two slices of one cell, paired
-  static constexpr int FIN_ELEMS = DIM * (NV + C::NFLUX) * SP;  // final phase, all directions
+  // PAIR: two time slices per LDS round in 16-byte elements.  A 3-D cell of
+  // 4^3 nodes is one wave, which needs few registers; there LDS bounds the
+  // waves per CU, so the rounds take one slice (8-byte elements) and the
+  // final phase one direction at a time: half and a third of the LDS, twice
+  // the waves per CU.
+  static constexpr bool PAIR = !(DIM == 3 && n == 4 && !PDE::kHasNcp && NV <= 5);
+  static constexpr bool FINDIR = !PAIR;
+  static constexpr int ITER_ELEMS = (PAIR ? 2 : 1) * C::NCH * SP;
+  static constexpr int FIN_ELEMS = (FINDIR ? 1 : DIM) * (NV + C::NFLUX) * SP;
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
   static constexpr int ELEMS = CPB * CELL_ELEMS;
+  // The Ricker amplitudes of the point sources (n + 3 time entries per
+  // source) live in the slots past the n points of each line (LS > n), which
+  // no round and no final phase touches, where there are enough of them;
+  // else in an array of their own.
+  static constexpr int NAMP = kMaxSources * (n + 3);
+  static constexpr bool AMP_IN_PAD = !PAIR && CPB == 1 && (LS - n) * F * (CELL_ELEMS / SP) >= NAMP;
+  // Single-slice geometry: the rows the final phase leaves free hold each
+  // node's time-averaged source S-bar through the final phase (fewer
+  // registers live there)
+  static constexpr bool STASH = FINDIR && CPB == 1 && CELL_ELEMS - FIN_ELEMS >= NV * BLOCK;
   static constexpr bool fits = ELEMS * 8 <= 80 * 1024 && BLOCK <= 256;
   // Waves per SIMD the register allocator aims at: as many as the blocks
-  // whose LDS fits a compute unit (160 KiB) provide, at most 3 (<= 168
+  // whose LDS fits a compute unit (160 KiB) provide, at most WMAX (3: <= 168
   // registers per lane; fewer spill).
-  static constexpr int LDS_BLOCKS = (156 * 1024) / (ELEMS * 8);
-  static constexpr int MIN_WAVES = cmax(1, cmin(3, LDS_BLOCKS * (BLOCK / 64) / 4));
+  static constexpr int WMAX = PAIR ? 3 : N64_SINGLE_WAVES;
+  static constexpr int LDS_BLOCKS = (156 * 1024) / (ELEMS * 8 + (AMP_IN_PAD ? 0 : NAMP * 8));
+  static constexpr int MIN_WAVES = cmax(1, cmin(WMAX, LDS_BLOCKS * (BLOCK / 64) / 4));
 };
 
 // PDEs that provide flux_dir(Q, P, pc, d, F), the flux of one direction
@@ -101,21 +123,30 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // and at the stage times 0, 1/2, 1 of the CERK guess (entries n .. n+2),
   // once per block; only blocks holding a source cell use them.
   constexpr int NA = n + 3;
-  __shared__ double src_amp[kMaxSources * NA];
+  __shared__ double src_amp_own[GN::AMP_IN_PAD ? 1 : kMaxSources * NA];
+  auto src_amp = [&](int e) -> double& {
+    if constexpr (GN::AMP_IN_PAD) {
+      constexpr int PADL = LS - n;  // free slots per line
+      const int r = e / (F * PADL), l = (e / PADL) % F, o = e % PADL;
+      return lds[r * SP + l * LS + n + o];
+    } else {
+      return src_amp_own[e];
+    }
+  };
   bool src_here = false;
   for (int s = 0; s < a.nsrc; ++s)
     src_here = src_here || (a.src[s].cell >= cell0 && a.src[s].cell < cell0 + CPB);
   if (src_here && tid < a.nsrc * NA) {
     const int s = tid / NA, j = tid - s * NA;
     const double tau = j < n ? a.t64.xi[j] : 0.5 * (j - n);
-    src_amp[tid] = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + tau * dt);
+    src_amp(tid) = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + tau * dt);
   }
   // (made visible by the first barrier below)
   auto add_point_sources = [&](int j, double* Sv) {
     if (!src_here || !node) return;
     for (int s = 0; s < a.nsrc; ++s) {
       if (a.src[s].cell != cell) continue;
-      const double amp = src_amp[s * NA + j];
+      const double amp = src_amp(s * NA + j);
       const double* wsk = a.src_w + ((long long)s * S + k) * NV;
 #pragma unroll
       for (int v = 0; v < NV; ++v) Sv[v] += amp * wsk[v];
@@ -133,9 +164,77 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // differentiates their average once).
   using P2 = Pair<double>;
   P2* const lds2 = reinterpret_cast<P2*>(lds);
+  // Single-slice geometry (!PAIR): the same round for qa alone, 8-byte
+  // elements (qb, div1 and g1 are not used).
+  auto round1 = [&](auto fin_tag, const double (&qa)[NV], double (&div0)[NV], double (&g0)[DIM][NV]) {
+    constexpr bool FIN = decltype(fin_tag)::value;
+    double* const mine = lds + lc * GN::CELL_ELEMS;
+    if (node) {
+      if constexpr (!FIN) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          double Fa[NV];
+          if constexpr (HasFluxDir<PDE>::value) {
+            PDE::flux_dir(qa, P, a.pde, d, Fa);
+          } else {
+            double Fall[DIM][NV];
+            PDE::fluxes(qa, P, a.pde, Fall);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fa[v] = Fall[d][v];
+          }
+#pragma unroll
+          for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * SP + pk[d]] = Fa[C::flux_var(d, cc)];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = qa[C::grad_var(cc)];
+    }
+    __syncthreads();
+    constexpr int CH0 = FIN ? NFL : 0;
+    constexpr int NCT = NCHD - CH0;
+    for (int task = tid; task < CPB * DIM * NCT * F; task += BLOCK) {
+      const int l = task % F;
+      const int ch = CH0 + (task / F) % NCT;
+      const int d = (task / (F * NCT)) % DIM;
+      const int c2 = task / (F * NCT * DIM);
+      double* row = lds + c2 * GN::CELL_ELEMS + (d * NCHD + ch) * SP + l * LS;
+      double x[n], y[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) x[m] = row[m];
+      line_deriv<double, n>(x, y, a.inv_h[d]);
+#pragma unroll
+      for (int i = 0; i < n; ++i) row[i] = y[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      div0[v] = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) g0[d][v] = 0.0;
+    }
+    if (node) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if constexpr (!FIN) {
+#pragma unroll
+          for (int cc = 0; cc < NFL; ++cc) div0[C::flux_var(d, cc)] += mine[(d * NCHD + cc) * SP + pk[d]];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+      }
+    }
+    __syncthreads();  // read-backs done before the next round's writes
+  };
+
   auto round = [&](auto fin_tag, const double (&qa)[NV], const double (&qb)[NV], double (&div0)[NV],
                    double (&g0)[DIM][NV], double (&div1)[NV], double (&g1)[DIM][NV]) {
     constexpr bool FIN = decltype(fin_tag)::value;
+    if constexpr (!GN::PAIR) {
+      round1(fin_tag, qa, div0, g0);
+      return;
+    }
     P2* const mine = lds2 + lc * (GN::CELL_ELEMS / 2);
     if (node) {
       if constexpr (!FIN) {
@@ -320,10 +419,11 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     update();
     r0 = 1;
   }
+  constexpr int SLICES = GN::PAIR ? 2 : 1;  // time slices per LDS round
   for (int r = r0; r < I; ++r) {
 #pragma unroll
-    for (int j = 0; j < n; j += 2) {
-      const int j1 = j + 1 < n ? j + 1 : j;
+    for (int j = 0; j < n; j += SLICES) {
+      const int j1 = j + SLICES - 1 < n ? j + SLICES - 1 : j;
       double div0[NV], g0[DIM][NV], div1[NV], g1[DIM][NV], Rv[NV], B[NV], Sv[NV];
       round(std::false_type{}, q[j], q[j1], div0, g0, div1, g1);
       rhs(q[j], j, div0, g0, Rv, B, Sv, true);
@@ -344,6 +444,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // non-conservative product the final pass needs no LDS round, so qbar goes
   // to its rows of the final phase at once (fewer registers live).
   constexpr int FIN_D = (NV + NFL) * SP;
+  constexpr int NDG = GN::FINDIR ? DIM : 1;  // direction groups of the final phase
+  constexpr int DPG = DIM / NDG;             // directions per group
+  auto fin_off = [](int d) { return GN::FINDIR ? 0 : d * FIN_D; };
   double* const fin_mine = lds + lc * GN::CELL_ELEMS;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -356,7 +459,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int j = 0; j < n; ++j)
 #pragma unroll
       for (int v = 0; v < NV; ++v) qbar[v] += T::w(j) * q[j][v];
-    if (node) {
+    if (node && !GN::FINDIR) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
@@ -385,7 +488,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       Nbar[v] += wj * B[v];
       Sbar[v] += wj * Sv[v];
     }
-    if constexpr (HasFluxDir<PDE>::value) {
+    if constexpr (GN::FINDIR) {
+      // Fbar_d is formed direction by direction in the final phase below
+    } else if constexpr (HasFluxDir<PDE>::value) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         double Fl[NV];
@@ -403,94 +508,131 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     }
   }
 
-  // Volume term and face projection, all directions at once: direction d's
-  // region of the cell's LDS holds qbar (NV rows) and the nonzero components
-  // of Fbar_d (NFL rows) in d's line-major layout.
+  // Volume term and face projection, all directions at once (or one at a
+  // time, FINDIR): direction d's region of the cell's LDS holds qbar (NV
+  // rows) and the nonzero components of Fbar_d (NFL rows) in d's layout.
   if constexpr (PDE::kHasNcp) __syncthreads();  // the final pass's rounds are done
-  if (node) {
+  double* const stash = lds + GN::FIN_ELEMS;  // GN::STASH: [NV][BLOCK], untouched by the final phase
+  if constexpr (GN::STASH) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if constexpr (PDE::kHasNcp) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) fin_mine[d * FIN_D + v * SP + pk[d]] = qbar[v];
-      }
-#pragma unroll
-      for (int cc = 0; cc < NFL; ++cc) fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
-    }
+    for (int v = 0; v < NV; ++v) stash[v * BLOCK + tid] = Sbar[v];
   }
-  __syncthreads();
-  for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
-    // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
-    const int l = task % F;
-    const int kind = (task / F) % (NFL + 1);
-    const int dt_ = (task / (F * (NFL + 1))) % DIM;
-    const int c2 = task / (F * (NFL + 1) * DIM);
-    const long long tcell = cell0 + c2;
-    const bool tact = tcell < a.ncells;
+  double divF[NV];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (d != dt_) continue;
-      double* rows = lds + c2 * GN::CELL_ELEMS + d * FIN_D + l * LS;
-      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-      if (kind == 0) {
+  for (int v = 0; v < NV; ++v) divF[v] = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double e0 = 0.0, e1 = 0.0;
+  for (int dg = 0; dg < NDG; ++dg) {
+    if (dg > 0) __syncthreads();  // the previous direction's read-backs are done
+    if constexpr (GN::FINDIR) {
+      // Fbar_d = sum_j w_j F_d(q_j) for this group's direction only (the
+      // iterate is still in registers): fewer values live than all of Fbar
 #pragma unroll
-          for (int m = 0; m < n; ++m) {
-            const double x = rows[v * SP + m];
-            e0 += T::l0(m) * x;
-            e1 += T::l1(m) * x;
+      for (int d = dg * DPG; d < (dg + 1) * DPG; ++d) {
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          double Fl[NV];
+          if constexpr (HasFluxDir<PDE>::value) {
+            PDE::flux_dir(q[j], P, a.pde, d, Fl);
+          } else {
+            double Fall[DIM][NV];
+            PDE::fluxes(q[j], P, a.pde, Fall);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fl[v] = Fall[d][v];
           }
-          if (tact) {
-            tr[(0 * NV + v) * F + l] = e0;  // face 2d,   state
-            tr[(2 * NV + v) * F + l] = e1;  // face 2d+1, state
-          }
-        }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          if (!PDE::flux_nonzero(d, v) && tact) {
-            tr[(1 * NV + v) * F + l] = 0.0;
-            tr[(3 * NV + v) * F + l] = 0.0;
-          }
-        }
-      } else {
-        // normal-flux traces; derivative of Fbar_d in place
-#pragma unroll
-        for (int cc = 0; cc < NFL; ++cc) {
-          if (cc != kind - 1) continue;
-          const int v = C::flux_var(d, cc);
-          double x[n], y[n];
-#pragma unroll
-          for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
-          double e0 = 0.0, e1 = 0.0;
-#pragma unroll
-          for (int m = 0; m < n; ++m) {
-            e0 += T::l0(m) * x[m];
-            e1 += T::l1(m) * x[m];
-          }
-          if (tact) {
-            tr[(1 * NV + v) * F + l] = e0;
-            tr[(3 * NV + v) * F + l] = e1;
-          }
-          line_deriv<double, n>(x, y, a.inv_h[d]);
-#pragma unroll
-          for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
+          for (int v = 0; v < NV; ++v) Fbar[d][v] += T::w(j) * Fl[v];
         }
       }
     }
+    if (node) {
+#pragma unroll
+      for (int d = dg * DPG; d < (dg + 1) * DPG; ++d) {
+        if constexpr (PDE::kHasNcp || GN::FINDIR) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) fin_mine[fin_off(d) + v * SP + pk[d]] = qbar[v];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NFL; ++cc)
+          fin_mine[fin_off(d) + (NV + cc) * SP + pk[d]] = Fbar[d][C::flux_var(d, cc)];
+      }
+    }
+    __syncthreads();
+    for (int task = tid; task < CPB * DPG * F * (NFL + 1); task += BLOCK) {
+      // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
+      const int l = task % F;
+      const int kind = (task / F) % (NFL + 1);
+      const int dt_ = dg * DPG + (task / (F * (NFL + 1))) % DPG;
+      const int c2 = task / (F * (NFL + 1) * DPG);
+      const long long tcell = cell0 + c2;
+      const bool tact = tcell < a.ncells;
+#pragma unroll
+      for (int d = dg * DPG; d < (dg + 1) * DPG; ++d) {
+        if (d != dt_) continue;
+        double* rows = lds + c2 * GN::CELL_ELEMS + fin_off(d) + l * LS;
+        double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
+        if (kind == 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double e0 = 0.0, e1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < n; ++m) {
+              const double x = rows[v * SP + m];
+              e0 += T::l0(m) * x;
+              e1 += T::l1(m) * x;
+            }
+            if (tact) {
+              tr[(0 * NV + v) * F + l] = e0;  // face 2d,   state
+              tr[(2 * NV + v) * F + l] = e1;  // face 2d+1, state
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            if (!PDE::flux_nonzero(d, v) && tact) {
+              tr[(1 * NV + v) * F + l] = 0.0;
+              tr[(3 * NV + v) * F + l] = 0.0;
+            }
+          }
+        } else {
+          // normal-flux traces; derivative of Fbar_d in place
+#pragma unroll
+          for (int cc = 0; cc < NFL; ++cc) {
+            if (cc != kind - 1) continue;
+            const int v = C::flux_var(d, cc);
+            double x[n], y[n];
+#pragma unroll
+            for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
+            double e0 = 0.0, e1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < n; ++m) {
+              e0 += T::l0(m) * x[m];
+              e1 += T::l1(m) * x[m];
+            }
+            if (tact) {
+              tr[(1 * NV + v) * F + l] = e0;
+              tr[(3 * NV + v) * F + l] = e1;
+            }
+            line_deriv<double, n>(x, y, a.inv_h[d]);
+#pragma unroll
+            for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int d = dg * DPG; d < (dg + 1) * DPG; ++d)
+#pragma unroll
+        for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[fin_off(d) + (NV + cc) * SP + pk[d]];
+    }
   }
-  __syncthreads();
   if (active) {
-    double divF[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) divF[v] = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-#pragma unroll
-      for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += fin_mine[d * FIN_D + (NV + cc) * SP + pk[d]];
     // u^n again from memory (not kept in registers through the final pass;
     // Q is only written here, by this thread)
+    if constexpr (GN::STASH) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sbar[v] = stash[v * BLOCK + tid];
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double un = Q[(cell * NV + v) * S + k];
