@@ -201,6 +201,29 @@ def test_step_parity(case):
     assert max(per) <= TOL, per
 
 
+@pytest.mark.parametrize("dim,order,cells", [(3, 3, [4, 3, 3]), (3, 5, [3, 2, 2]), (2, 3, [7, 5])])
+def test_euler_point_source_parity(dim, order, cells):
+    """A Ricker energy source in Euler cells through the FP64 node predictor
+    (slice pairs at N = 5 and in 2-D; one slice per round, amplitudes in the
+    rows' padding, at 3-D N = 3) against the oracle."""
+    say("euler point source", dim, order, cells)
+    x = (0.55, 0.4, 0.6)[:dim]
+    w = [0.0] * (dim + 1) + [1.0]
+    src = dict(x=x, w=w, f0=4.0, t0=0.02, amp=0.05)
+    s, P = pair(dim, order, "euler", cells, cfl=0.5, sources=[src])
+    s.set_point_sources([dict(x=src["x"], weight=src["w"], f0=src["f0"], t0=src["t0"], amp=src["amp"])])
+    Q0 = inputs.smooth_euler_state(O.node_coords(P), 64)
+    Qg, _ = run_gpu(s, Q0, None, 4)
+    Qo, _ = O.run(P, Q0, steps=4)
+    e = rel_l2(Qg, Qo)
+    say(f"  rel L2 {e:.2e}")
+    assert np.isfinite(Qo).all() and e <= TOL
+    # the source is felt
+    Pn = O.problem(dim, order, O.EULER, cells, cfl=0.5)
+    assert rel_l2(O.run(Pn, Q0, steps=4)[0], Qo) > 1e-5
+    s.close()
+
+
 def test_elastic_source_receivers_parity():
     """Elastic N=4 on a layered, perturbed material with a Ricker point source;
     receivers sampled after every step."""
