@@ -1681,7 +1681,10 @@ template <class PDE, int N>
 struct GeoB {
   using G = Geo<PDE, N>;
   static constexpr int FL_PER_CELL = 2 * G::DIM * G::NV * G::F;  // doubles
-  static constexpr int by_threads = G::S >= 512 ? 1 : 512 / G::S;
+  // cells of 128 nodes or more one per block (C2, N = 5: 2.54 -> 2.44 ms per
+  // launch against two per block), smaller ones up to 512 threads (N = 3:
+  // 3.01 ms, against 3.07 and 3.16 ms with 128- and 256-thread blocks)
+  static constexpr int by_threads = G::S >= 128 ? 1 : 512 / G::S;
   static constexpr int by_lds = cmax(1, (48 * 1024) / (FL_PER_CELL * 8));
   // at least one full wave per block
   static constexpr int CPB = cmax(cmin(by_threads, by_lds), (64 + G::S - 1) / G::S);
