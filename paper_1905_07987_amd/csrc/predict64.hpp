@@ -225,7 +225,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
       }
     }
-    __syncthreads();  // read-backs done before the next round's writes
+    // No barrier here: a node thread reads back only its own slots and the
+    // next round's writes go to the same slots of the same thread; the final
+    // phase, which uses another layout, starts with a barrier.
   };
 
   auto round = [&](auto fin_tag, const double (&qa)[NV], const double (&qb)[NV], double (&div0)[NV],
@@ -331,7 +333,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         }
       }
     }
-    __syncthreads();  // read-backs done before the next round's writes
+    // No barrier here: a node thread reads back only its own slots and the
+    // next round's writes go to the same slots of the same thread; the final
+    // phase, which uses another layout, starts with a barrier.
   };
 
   // right-hand side R = S - div F - B grad q of the state qj (+ the point
@@ -443,6 +447,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // final iterate): time averages of q, F, B grad q and S.  Without a
   // non-conservative product the final pass needs no LDS round, so qbar goes
   // to its rows of the final phase at once (fewer registers live).
+  __syncthreads();  // every read-back of the last round is done
   constexpr int FIN_D = (NV + NFL) * SP;
   constexpr int NDG = GN::FINDIR ? DIM : 1;  // direction groups of the final phase
   constexpr int DPG = DIM / NDG;             // directions per group
