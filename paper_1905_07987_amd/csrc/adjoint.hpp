@@ -388,6 +388,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
     }
 
   // ---- face traces of qbar = t into hat (for the Rusanov parameter derivative) ----
+  Op::sync();  // the forward sweep's last read-backs are done
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
   Op::sync();  // also: every read of hat above is done
@@ -451,6 +452,7 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
     for (int v = 0; v < NV; ++v) lam[(cell * NV + v) * S + k] += lu[v];
   }
   if constexpr (NP > 0) {
+    Op::sync();  // the reverse sweep's last read-backs are done
 #pragma unroll
     for (int p = 0; p < NP; ++p) mine[k * NP + p] = gp[p];
     Op::sync();

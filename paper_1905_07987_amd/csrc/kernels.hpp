@@ -609,7 +609,8 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
           }
         }
       }
-      if constexpr (USE_LDS) __syncthreads();
+      // no barrier after the read-backs: a node thread reads back and next
+      // writes only its own slots (the final phase starts with a barrier)
     }
   };
 
@@ -665,6 +666,7 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
   for (int v = 0; v < NV; ++v) divF[v] = R(0);
   R* const fin_mine = lds + lc * GA::CELL_ELEMS;
+  __syncthreads();  // every read-back of the passes is done
   if (node) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -1394,7 +1396,9 @@ struct LinOp {
     PDE::source(t, P, a.pde, Sv);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
-    sync();  // rows free for the next writes
+    // No barrier here: a thread reads back only its own slots, which only it
+    // writes in the next application; a caller that uses the rows otherwise
+    // next calls sync() first.
   }
 
   // mu = L^T nu at this node (FP64; the PDE's transposes): the flux part
@@ -1484,7 +1488,7 @@ struct LinOp {
 #pragma unroll
       for (int cc = 0; cc < NF; ++cc) gq[d][C::grad_var(cc)] = mine[(NCH + d * NGR + cc) * SP + pk[d]];
     }
-    sync();  // rows free for the next writes
+    // no barrier here (see apply)
   }
 };
 
@@ -1593,6 +1597,7 @@ __device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double
 
   // face traces: qhat = trace of qbar, Fhat_d = F_d(qhat); one task per
   // (cell, direction, line) extrapolates every quantity to both ends
+  Op::sync();  // the operator's last read-backs are done
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
   Op::sync();
