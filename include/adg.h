@@ -88,8 +88,12 @@ typedef int adg_status;
 /* FP32 predictor whose derivative contractions of the Picard passes run in
  * split BF16 on the matrix cores: each float operand is the exact sum of
  * three BF16 terms, the six partial products of size >= 2^-16 are
- * accumulated in FP32 (v_mfma_f32_16x16x32_bf16).  Built for the PDEs that
- * are not linear in Q (Euler); elsewhere UNSUPPORTED. */
+ * accumulated in FP32 (v_mfma_f32_16x16x32_bf16).  Built for the
+ * built-in Euler PDEs; elsewhere UNSUPPORTED.  Its error is that of
+ * ADG_MIXED_FP32, and on MI355X it runs about 5x slower than ADG_MIXED_FP32
+ * (a 6-point contraction fills a 16x16x32 tile poorly and the splits cost
+ * as much vector work as the FP32 contraction): a measured alternative, not
+ * the recommended mixed-precision form. */
 #define ADG_MIXED_BF16X3 2
 
 /* Initial guess of the predictor's Picard iteration (Sec. 3.3; Sec. 5.2 names

@@ -6,14 +6,16 @@
 // the time operator are the same for every lane: they are compile-time
 // constants and live in scalar registers, and the Picard update needs no
 // exchange between lanes.  A cell of n^3 <= 256 nodes is one block of at most
-// four waves, so with <= 256 registers per lane two blocks share a compute
-// unit and one block's barriers are covered by the other's work.
+// four waves; several blocks share a compute unit (three at n = 6, where the
+// LDS rows and 168 registers per lane set the bound) so that one block's
+// barriers are covered by the others' work.
 //
-// Spatial derivatives go through LDS one time slice at a time: the node
-// threads write the fluxes (and the quantities the non-conservative product
-// differentiates) of slice j into line-major rows, one thread per
-// (direction, channel, line) differentiates its line in place, and the node
-// threads read their derivatives back, two slices per round.
+// Spatial derivatives go through LDS: the node threads write the fluxes (and
+// the quantities the non-conservative product differentiates) of two time
+// slices as one 16-byte element per (channel, node) into line-major rows
+// (one slice in 8-byte elements for 3-D cells of 4^3 nodes, whose waves are
+// bounded by LDS), one thread per (direction, channel, line) differentiates
+// its line in place, and the node threads read their derivatives back.
 #pragma once
 
 namespace adg {
