@@ -55,6 +55,10 @@ struct Geo {
 
 // Derivative channels per direction: the nonzero flux components, then the
 // quantities whose gradient feeds the non-conservative product.
+// a * b + c with one rounding, in the precision of the operands
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class PDE>
 struct Chan {
   static constexpr int nflux(int d) {
@@ -75,6 +79,12 @@ struct Chan {
   static constexpr int grad_var(int c) {
     for (int v = 0; v < PDE::NV; ++v)
       if (PDE::grad_needed(v) && c-- == 0) return v;
+    return -1;
+  }
+  // the first direction whose flux has a nonzero component v (-1: none)
+  static constexpr int first_flux_dir(int v) {
+    for (int d = 0; d < PDE::DIM; ++d)
+      if (PDE::flux_nonzero(d, v)) return d;
     return -1;
   }
   static constexpr int NCHD = nflux(0) + ngrad();  // channels per direction
@@ -513,7 +523,7 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
                 const int l = t % F, ch = CH0 + (t / F) % NCT, d = (t / (F * NCT)) % DIM, c2 = t / (F * NCT * DIM);
                 return lds2 + c2 * (GA::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * G::LS;
               },
-              [&](int t) { return float(inv_h[(t / (F * NCT)) % DIM]); }, BLOCK / 64, Amf);
+              [&](int) { return 1.0f; }, BLOCK / 64, Amf);
         } else
         for (int task = tid; task < CPB * DIM * 2 * F; task += BLOCK) {
           const int l = task % F;
@@ -521,7 +531,6 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
           const int d = (task / (2 * F)) % DIM;
           const int c2 = task / (2 * F * DIM);
           P2* row = lds2 + c2 * (GA::CELL_ELEMS / 2) + d * NCHD * SP + l * G::LS;
-          const R s = inv_h[d];
           const int cb = hf ? CHM : CH0, ce = hf ? NCHD : CHM;
           for (int c = cb; c < ce; ++c) {
             P2 x[n];
@@ -535,39 +544,43 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
                 y0 += T::D(i, m) * x[m].x;
                 y1 += T::D(i, m) * x[m].y;
               }
-              row[c * SP + i] = P2{y0 * s, y1 * s};
+              row[c * SP + i] = P2{y0, y1};
             }
           }
         }
         __syncthreads();
       }
-      // (3) right-hand sides of slices j0, j1 at this node
+      // (3) right-hand sides of slices j0, j1 at this node; the line tasks
+      // leave the 1/h of each direction to this read-back, whose sums start
+      // from the first direction's values
       R divA[NV], divB[NV], gA[DIM][NV], gB[DIM][NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        divA[v] = divB[v] = R(0);
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int d = 0; d < DIM; ++d) gA[d][v] = gB[d][v] = R(0);
-      }
       if constexpr (USE_LDS) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-          if constexpr (!FIN) {
+          const R ih = inv_h[d];
 #pragma unroll
-            for (int c = 0; c < NFL; ++c) {
-              const P2 t = mine[(d * NCHD + c) * SP + pk[d]];
-              divA[C::flux_var(d, c)] += t.x;
-              divB[C::flux_var(d, c)] += t.y;
-            }
+          for (int c = 0; c < NFL; ++c) {
+            if constexpr (FIN) break;
+            const int v = C::flux_var(d, c);
+            const P2 t = mine[(d * NCHD + c) * SP + pk[d]];
+            divA[v] = C::first_flux_dir(v) == d ? t.x * ih : fma_r(t.x, ih, divA[v]);
+            divB[v] = C::first_flux_dir(v) == d ? t.y * ih : fma_r(t.y, ih, divB[v]);
           }
 #pragma unroll
           for (int c = 0; c < NGR; ++c) {
             const P2 t = mine[(d * NCHD + NFL + c) * SP + pk[d]];
-            gA[d][C::grad_var(c)] = t.x;
-            gB[d][C::grad_var(c)] = t.y;
+            gA[d][C::grad_var(c)] = t.x * ih;
+            gB[d][C::grad_var(c)] = t.y * ih;
           }
         }
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (!USE_LDS || FIN || C::first_flux_dir(v) < 0) divA[v] = divB[v] = R(0);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (h == 1 && !two) break;
@@ -594,6 +607,12 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[jj][v] = Rv[v] + Sp[v];
           }
+        } else if constexpr (KIND == 1 && !PDE::kHasNcp && !PDE::kHasSource) {
+          // R_j = -div F (+ the point sources, added to R_j itself) in the
+          // place of q_j, which is no longer needed
+#pragma unroll
+          for (int v = 0; v < NV; ++v) q[j][v] = -(h ? divB[v] : divA[v]);
+          add_point_sources(j, q[j]);
         } else {
           add_point_sources(j, Sv);
           if constexpr (KIND == 1) {

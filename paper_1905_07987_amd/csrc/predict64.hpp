@@ -101,9 +101,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   const bool active = node && cell < a.ncells;
   const long long cl = cell < a.ncells ? cell : a.ncells - 1;  // clamp loads of the ragged tail
 
-  int pk[DIM];  // this node's slot in the LDS rows of each direction
+  // this node's slot in the LDS rows of each direction; idle lanes take
+  // node 0 of cell 0, so that every lane reads back valid slots (the writes
+  // stay with the node lanes) and the read-back sums need no zero start
+  int pk[DIM];
+  const int lcr = node ? lc : 0;
   {
-    const int kx = k % n, ky = (k / n) % n, kz = DIM == 3 ? k / (n * n) : 0;
+    const int kr = node ? k : 0;
+    const int kx = kr % n, ky = (kr / n) % n, kz = DIM == 3 ? kr / (n * n) : 0;
     const int kd[3] = {kx, ky, kz};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) pk[d] = GN::G::line_of(d, kx, ky, kz) * LS + kd[d];
@@ -205,31 +210,35 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       double x[n], y[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) x[m] = row[m];
-      line_deriv<double, n>(x, y, a.inv_h[d]);
+      line_deriv<double, n>(x, y, 1.0);
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i] = y[i];
     }
     __syncthreads();
+    const double* const rmine = lds + lcr * GN::CELL_ELEMS;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      div0[v] = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double ih = a.inv_h[d];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) g0[d][v] = 0.0;
-    }
-    if (node) {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        if constexpr (!FIN) {
-#pragma unroll
-          for (int cc = 0; cc < NFL; ++cc) div0[C::flux_var(d, cc)] += mine[(d * NCHD + cc) * SP + pk[d]];
-        }
-#pragma unroll
-        for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+      for (int cc = 0; cc < NFL; ++cc) {
+        if constexpr (FIN) break;
+        const int v = C::flux_var(d, cc);
+        const double t = rmine[(d * NCHD + cc) * SP + pk[d]];
+        div0[v] = C::first_flux_dir(v) == d ? t * ih : fma_r(t, ih, div0[v]);
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) g0[d][v] = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = rmine[(d * NCHD + NFL + cc) * SP + pk[d]] * ih;
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (FIN || C::first_flux_dir(v) < 0) div0[v] = 0.0;
     // No barrier here: a node thread reads back only its own slots and the
-    // next round's writes go to the same slots of the same thread; the final
-    // phase, which uses another layout, starts with a barrier.
+    // next round's writes go to the same slots of the same thread (an idle
+    // lane's read of node 0's slots may see either round's values; its sums
+    // are never used); the final phase, which uses another layout, starts
+    // with a barrier.
   };
 
   auto round = [&](auto fin_tag, const double (&qa)[NV], const double (&qb)[NV], double (&div0)[NV],
@@ -294,8 +303,8 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         x0[m] = t.x;
         x1[m] = t.y;
       }
-      line_deriv<double, n>(x0, y0, a.inv_h[d]);
-      line_deriv<double, n>(x1, y1, a.inv_h[d]);
+      line_deriv<double, n>(x0, y0, 1.0);
+      line_deriv<double, n>(x1, y1, 1.0);
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
     }
@@ -305,45 +314,61 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       double x[n], y[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) x[m] = half[2 * m];
-      line_deriv<double, n>(x, y, a.inv_h[d]);
+      line_deriv<double, n>(x, y, 1.0);
 #pragma unroll
       for (int i = 0; i < n; ++i) half[2 * i] = y[i];
     }
     __syncthreads();
+    const P2* const rmine = lds2 + lcr * (GN::CELL_ELEMS / 2);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      div0[v] = div1[v] = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double ih = a.inv_h[d];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) g0[d][v] = g1[d][v] = 0.0;
-    }
-    if (node) {
+      for (int cc = 0; cc < NFL; ++cc) {
+        if constexpr (FIN) break;
+        const int v = C::flux_var(d, cc);
+        const P2 t = rmine[(d * NCHD + cc) * SP + pk[d]];
+        div0[v] = C::first_flux_dir(v) == d ? t.x * ih : fma_r(t.x, ih, div0[v]);
+        div1[v] = C::first_flux_dir(v) == d ? t.y * ih : fma_r(t.y, ih, div1[v]);
+      }
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        if constexpr (!FIN) {
+      for (int v = 0; v < NV; ++v) g0[d][v] = g1[d][v] = 0.0;
 #pragma unroll
-          for (int cc = 0; cc < NFL; ++cc) {
-            const P2 t = mine[(d * NCHD + cc) * SP + pk[d]];
-            div0[C::flux_var(d, cc)] += t.x;
-            div1[C::flux_var(d, cc)] += t.y;
-          }
-        }
-#pragma unroll
-        for (int cc = 0; cc < NGR; ++cc) {
-          const P2 t = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
-          g0[d][C::grad_var(cc)] = t.x;
-          g1[d][C::grad_var(cc)] = t.y;
-        }
+      for (int cc = 0; cc < NGR; ++cc) {
+        const P2 t = rmine[(d * NCHD + NFL + cc) * SP + pk[d]];
+        g0[d][C::grad_var(cc)] = t.x * ih;
+        g1[d][C::grad_var(cc)] = t.y * ih;
       }
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (FIN || C::first_flux_dir(v) < 0) div0[v] = div1[v] = 0.0;
     // No barrier here: a node thread reads back only its own slots and the
-    // next round's writes go to the same slots of the same thread; the final
-    // phase, which uses another layout, starts with a barrier.
+    // next round's writes go to the same slots of the same thread (an idle
+    // lane's read of node 0's slots may see either round's values; its sums
+    // are never used); the final phase, which uses another layout, starts
+    // with a barrier.
   };
 
   // right-hand side R = S - div F - B grad q of the state qj (+ the point
   // sources at time entry j of src_amp)
   auto rhs = [&](const double (&qj)[NV], int j, const double (&div)[NV], const double (&g)[DIM][NV],
                  double (&Rv)[NV], double (&B)[NV], double (&Sv)[NV], bool sources) {
+    if constexpr (!PDE::kHasNcp && !PDE::kHasSource) {
+      // R = -div F, plus the point sources where the block has one (S
+      // holds them for the final pass's average)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Rv[v] = -div[v];
+        B[v] = Sv[v] = 0.0;
+      }
+      if (sources && src_here && node) {
+        add_point_sources(j, Sv);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Rv[v] += Sv[v];
+      }
+      return;
+    }
     if constexpr (PDE::kHasNcp) {
       PDE::ncp(qj, P, a.pde, g, B);
     } else {
@@ -415,12 +440,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     rhs(q[0], 0, div, g, R0, B, Sv, false);
 #pragma unroll
     for (int jj = 0; jj < n; ++jj) {
-      double Sp[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Sp[v] = 0.0;
-      add_point_sources(jj, Sp);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) q[jj][v] = R0[v] + Sp[v];
+      for (int v = 0; v < NV; ++v) q[jj][v] = R0[v];
+      add_point_sources(jj, q[jj]);
     }
     update();
     r0 = 1;
