@@ -1387,34 +1387,47 @@ struct LinOp {
       R x[n], y[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) x[m] = row[m * st];
-      line_deriv<R, n>(x, y, inv_h[d]);
+      line_deriv<R, n>(x, y, R(1));
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i * st] = y[i];
     });
     sync();
+    // the 1/h of each direction is applied here; the divergence starts at
+    // the first direction with a flux in v
     R divF[NV], B[NV], Sv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      divF[v] = R(0);
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int d = 0; d < DIM; ++d) g[d][v] = R(0);
-    }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      const R ih = inv_h[d];
 #pragma unroll
-      for (int cc = 0; cc < NFL; ++cc) divF[C::flux_var(d, cc)] += mine[(d * NCHD + cc) * SP + pk[d]];
+      for (int cc = 0; cc < NFL; ++cc) {
+        const int v = C::flux_var(d, cc);
+        const R x = mine[(d * NCHD + cc) * SP + pk[d]];
+        divF[v] = C::first_flux_dir(v) == d ? x * ih : fma_r(x, ih, divF[v]);
+      }
 #pragma unroll
-      for (int cc = 0; cc < NGR; ++cc) g[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]];
+      for (int cc = 0; cc < NGR; ++cc) g[d][C::grad_var(cc)] = mine[(d * NCHD + NFL + cc) * SP + pk[d]] * ih;
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (C::first_flux_dir(v) < 0) divF[v] = R(0);
     if constexpr (PDE::kHasNcp) {
       PDE::ncp(t, P, a.pde, g, B);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) B[v] = R(0);
     }
-    PDE::source(t, P, a.pde, Sv);
+    if constexpr (PDE::kHasSource) {
+      PDE::source(t, P, a.pde, Sv);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
+      for (int v = 0; v < NV; ++v) out[v] = Sv[v] - divF[v] - B[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v] = -divF[v] - B[v];
+    }
     // No barrier here: a thread reads back only its own slots, which only it
     // writes in the next application; a caller that uses the rows otherwise
     // next calls sync() first.
