@@ -149,16 +149,22 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     src_amp(tid) = ricker(a.src[s].f0, a.src[s].t0, a.src[s].amp, t_n + tau * dt);
   }
   // (made visible by the first barrier below)
-  auto add_point_sources = [&](int j, double* Sv) {
+  auto add_point_sources = [&](int j, double* Sv, double sgn = 1.0) {
     if (!src_here || !node) return;
     for (int s = 0; s < a.nsrc; ++s) {
       if (a.src[s].cell != cell) continue;
       const double amp = src_amp(s * NA + j);
       const double* wsk = a.src_w + ((long long)s * S + k) * NV;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Sv[v] += amp * wsk[v];
+      for (int v = 0; v < NV; ++v) Sv[v] += (sgn * amp) * wsk[v];
     }
   };
+
+  // PDEs with neither source nor non-conservative product carry -R (= div F
+  // minus the point sources) through the Picard passes; the update and the
+  // CERK stages take the sign (no negation of every right-hand side)
+  constexpr bool NEG_R = !PDE::kHasNcp && !PDE::kHasSource;
+  constexpr double RSGN = NEG_R ? -1.0 : 1.0;
 
   double q[n][NV];  // iterate at the n time nodes of node k; R_j replaces q_j
   double Fbar[DIM][NV], Nbar[NV], Sbar[NV], qbar[NV];  // final pass: time averages
@@ -293,20 +299,40 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       const int c2 = task / (F * NCT * DIM);
       return lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * LS;
     };
-    for (int task = tid; task < NWHOLE; task += BLOCK) {
-      int d;
-      P2* row = row_of(task, d);
+    auto whole = [&](P2* row, const P2 (&xr)[n]) {
       double x0[n], x1[n], y0[n], y1[n];
 #pragma unroll
       for (int m = 0; m < n; ++m) {
-        const P2 t = row[m];
-        x0[m] = t.x;
-        x1[m] = t.y;
+        x0[m] = xr[m].x;
+        x1[m] = xr[m].y;
       }
       line_deriv<double, n>(x0, y0, 1.0);
       line_deriv<double, n>(x1, y1, 1.0);
 #pragma unroll
       for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+    };
+    if constexpr (NWHOLE == 2 * BLOCK) {
+      // two whole tasks per lane: both lines are loaded before either is
+      // differentiated
+      int d;
+      P2* ra = row_of(tid, d);
+      P2* rb = row_of(tid + BLOCK, d);
+      P2 xa[n], xb[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) xa[m] = ra[m];
+#pragma unroll
+      for (int m = 0; m < n; ++m) xb[m] = rb[m];
+      whole(ra, xa);
+      whole(rb, xb);
+    } else {
+      for (int task = tid; task < NWHOLE; task += BLOCK) {
+        int d;
+        P2* row = row_of(task, d);
+        P2 xr[n];
+#pragma unroll
+        for (int m = 0; m < n; ++m) xr[m] = row[m];
+        whole(row, xr);
+      }
     }
     for (int h = tid; h < 2 * (NT - NWHOLE); h += BLOCK) {
       int d;
@@ -354,18 +380,18 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // sources at time entry j of src_amp)
   auto rhs = [&](const double (&qj)[NV], int j, const double (&div)[NV], const double (&g)[DIM][NV],
                  double (&Rv)[NV], double (&B)[NV], double (&Sv)[NV], bool sources) {
-    if constexpr (!PDE::kHasNcp && !PDE::kHasSource) {
-      // R = -div F, plus the point sources where the block has one (S
+    if constexpr (NEG_R) {
+      // -R = div F, minus the point sources where the block has one (S
       // holds them for the final pass's average)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Rv[v] = -div[v];
+        Rv[v] = div[v];
         B[v] = Sv[v] = 0.0;
       }
       if (sources && src_here && node) {
         add_point_sources(j, Sv);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Rv[v] += Sv[v];
+        for (int v = 0; v < NV; ++v) Rv[v] -= Sv[v];
       }
       return;
     }
@@ -396,7 +422,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         t[i] = s;
       }
 #pragma unroll
-      for (int i = 0; i < n; ++i) q[i][v] = u[v] + dt * t[i];
+      for (int i = 0; i < n; ++i) q[i][v] = u[v] + (RSGN * dt) * t[i];
     }
   };
 
@@ -422,14 +448,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       rhs(Y, n + (st == 0 ? 0 : (st == 3 ? 2 : 1)), div, g, kk, B, Sv, true);
 #pragma unroll
       for (int j = 0; j < n; ++j) {
-        const double b = dt * T::cerk_b(st, j);
+        const double b = (RSGN * dt) * T::cerk_b(st, j);
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[j][v] += b * kk[v];
       }
       const double as = st == 2 ? 1.0 : 0.5;  // Y_{s+1} = u + dt a_{s+1} k_s
       load_u(Y);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Y[v] += dt * as * kk[v];
+      for (int v = 0; v < NV; ++v) Y[v] += (RSGN * dt) * as * kk[v];
     }
   } else {
     // First Picard step: q^0 = u^n at every time node, so every slice has
@@ -442,7 +468,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     for (int jj = 0; jj < n; ++jj) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[jj][v] = R0[v];
-      add_point_sources(jj, q[jj]);
+      add_point_sources(jj, q[jj], RSGN);
     }
     update();
     r0 = 1;
