@@ -58,13 +58,16 @@ def euler_flux_flops(dim: int) -> int:
 
 def kernel_source_hash() -> str:
     """Hash of the FP64 predictor's source: its file (layout struct and kernel
-    body), the line derivative and tables it inlines, and the Euler terms."""
+    body), the line derivative, tables, fma helper and channel map it inlines,
+    and the Euler terms."""
     csrc = os.path.join(ROOT, "paper_1905_07987_amd", "csrc")
     k = open(os.path.join(csrc, "kernels.hpp")).read()
     a = k.index("struct CT {")
     b = k.index("};", a)
     c = k.index("// y = s D x along one line of n nodes.")  # line_deriv
     d = k.index("// Kernel A, a lane pair per node", c)
+    g0 = k.index("// a * b + c with one rounding")  # fma_r and Chan
+    g1 = k.index("\n};", k.index("struct Chan {"))
     pde = open(os.path.join(csrc, "pde.hpp")).read()
     e = pde.index("struct Euler {")
     f = pde.index("\n};", e)
@@ -72,6 +75,7 @@ def kernel_source_hash() -> str:
     h.update(open(os.path.join(csrc, "predict64.hpp")).read().encode())
     h.update(k[a:b].encode())
     h.update(k[c:d].encode())
+    h.update(k[g0:g1].encode())
     h.update(pde[e:f].encode())
     return h.hexdigest()[:16]
 

@@ -33,11 +33,22 @@ struct GeoN64 {
   static constexpr int CPB = S >= 64 ? 1 : 64 / S;
   static constexpr int LANES = CPB * S;
   static constexpr int BLOCK = (LANES + 63) / 64 * 64;
-  // Line stride of the LDS rows: the odd stride of Geo, except n = 6, where
-  // rows of 6 two-slice elements (96 bytes apart) already fall into distinct
-  // banks for the 16-byte accesses, and the smaller rows let three blocks
-  // share a compute unit.
-  static constexpr int LS = n == 6 ? 6 : G::LS, SP = F * LS;
+  // LDS rows: line-major with the odd line stride of Geo in general (a
+  // line's points contiguous, lines LS elements apart).  For 3-D n = 6 the
+  // odd stride leaves room for only two blocks per compute unit, and
+  // unpadded line-major rows (6 elements per line) give the line tasks'
+  // 16-byte accesses two-way bank conflicts (gfx950 serves such an access
+  // 16 lanes at a time, conflict-free when their 16-byte units differ
+  // mod 16).  There (PM) the rows are position-major: point m of line l at
+  // l + F m in the final phase, and in the Picard rounds position-major
+  // across all of a round's rows at once (GPM, below): row r, line l,
+  // point m at F r + l + EI m, EI = F times the rows, so that consecutive
+  // line tasks touch consecutive units, also across row boundaries.
+  static constexpr bool PM = n == 6 && DIM == 3;
+  static constexpr int LS = PM ? 1 : (n == 6 ? 6 : G::LS);  // elements between lines
+  static constexpr int ES = PM ? F : 1;                      // elements between a line's points
+  static constexpr int SP = PM ? n * F : F * LS;
+  __host__ __device__ static constexpr int slot(int line, int pos) { return line * LS + pos * ES; }
   // PAIR: two time slices per LDS round in 16-byte elements.  A 3-D cell of
   // 4^3 nodes is one wave, which needs few registers; there LDS bounds the
   // waves per CU, so the rounds take one slice (8-byte elements) and the
@@ -45,6 +56,10 @@ struct GeoN64 {
   // the waves per CU.
   static constexpr bool PAIR = !(DIM == 3 && n == 4 && !PDE::kHasNcp && NV <= 5);
   static constexpr bool FINDIR = !PAIR;
+  // Picard rounds' rows: RS elements between rows, EI between a line's points
+  static constexpr bool GPM = PM && PAIR;
+  static constexpr int EI = GPM ? C::NCH * F : ES, RS = GPM ? F : SP;
+  __host__ __device__ static constexpr int islot(int line, int pos) { return GPM ? line + pos * EI : slot(line, pos); }
   static constexpr int ITER_ELEMS = (PAIR ? 2 : 1) * C::NCH * SP;
   static constexpr int FIN_ELEMS = (FINDIR ? 1 : DIM) * (NV + C::NFLUX) * SP;
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
@@ -54,7 +69,7 @@ struct GeoN64 {
   // no round and no final phase touches, where there are enough of them;
   // else in an array of their own.
   static constexpr int NAMP = kMaxSources * (n + 3);
-  static constexpr bool AMP_IN_PAD = !PAIR && CPB == 1 && (LS - n) * F * (CELL_ELEMS / SP) >= NAMP;
+  static constexpr bool AMP_IN_PAD = !PM && !PAIR && CPB == 1 && (LS - n) * F * (CELL_ELEMS / SP) >= NAMP;
   // Single-slice geometry: the rows the final phase leaves free hold each
   // node's time-averaged source S-bar through the final phase (fewer
   // registers live there)
@@ -86,7 +101,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   using C = Chan<PDE>;
   using T = CT<double, GN::n>;
   constexpr int n = GN::n, S = GN::S, F = GN::F, NV = GN::NV, NP = PDE::NP, DIM = GN::DIM;
-  constexpr int CPB = GN::CPB, BLOCK = GN::BLOCK, SP = GN::SP, LS = GN::LS;
+  constexpr int CPB = GN::CPB, BLOCK = GN::BLOCK, SP = GN::SP, LS = GN::LS, ES = GN::ES, RS = GN::RS, EI = GN::EI;
   constexpr int NCHD = C::NCHD, NFL = C::NFLUX, NGR = C::ngrad();
   static_assert(C::uniform(), "flux sparsity must be the same in every direction");
   static_assert(GN::fits, "predictor block exceeds its LDS or thread budget");
@@ -104,14 +119,17 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
   // this node's slot in the LDS rows of each direction; idle lanes take
   // node 0 of cell 0, so that every lane reads back valid slots (the writes
   // stay with the node lanes) and the read-back sums need no zero start
-  int pk[DIM];
+  int pk[DIM], pki[DIM];  // final phase's rows, Picard rounds' rows
   const int lcr = node ? lc : 0;
   {
     const int kr = node ? k : 0;
     const int kx = kr % n, ky = (kr / n) % n, kz = DIM == 3 ? kr / (n * n) : 0;
     const int kd[3] = {kx, ky, kz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) pk[d] = GN::G::line_of(d, kx, ky, kz) * LS + kd[d];
+    for (int d = 0; d < DIM; ++d) {
+      pk[d] = GN::slot(GN::G::line_of(d, kx, ky, kz), kd[d]);
+      pki[d] = GN::islot(GN::G::line_of(d, kx, ky, kz), kd[d]);
+    }
   }
 
   // u^n is read from Q where it is used (an L2 hit after the first read;
@@ -196,13 +214,13 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
             for (int v = 0; v < NV; ++v) Fa[v] = Fall[d][v];
           }
 #pragma unroll
-          for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * SP + pk[d]] = Fa[C::flux_var(d, cc)];
+          for (int cc = 0; cc < NFL; ++cc) mine[(d * NCHD + cc) * RS + pki[d]] = Fa[C::flux_var(d, cc)];
         }
       }
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
-        for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * SP + pk[d]] = qa[C::grad_var(cc)];
+        for (int cc = 0; cc < NGR; ++cc) mine[(d * NCHD + NFL + cc) * RS + pki[d]] = qa[C::grad_var(cc)];
     }
     __syncthreads();
     constexpr int CH0 = FIN ? NFL : 0;
@@ -212,13 +230,13 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       const int ch = CH0 + (task / F) % NCT;
       const int d = (task / (F * NCT)) % DIM;
       const int c2 = task / (F * NCT * DIM);
-      double* row = lds + c2 * GN::CELL_ELEMS + (d * NCHD + ch) * SP + l * LS;
+      double* row = lds + c2 * GN::CELL_ELEMS + (d * NCHD + ch) * RS + GN::islot(l, 0);
       double x[n], y[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) x[m] = row[m];
+      for (int m = 0; m < n; ++m) x[m] = row[m * EI];
       line_deriv<double, n>(x, y, 1.0);
 #pragma unroll
-      for (int i = 0; i < n; ++i) row[i] = y[i];
+      for (int i = 0; i < n; ++i) row[i * EI] = y[i];
     }
     __syncthreads();
     const double* const rmine = lds + lcr * GN::CELL_ELEMS;
@@ -229,13 +247,13 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int cc = 0; cc < NFL; ++cc) {
         if constexpr (FIN) break;
         const int v = C::flux_var(d, cc);
-        const double t = rmine[(d * NCHD + cc) * SP + pk[d]];
+        const double t = rmine[(d * NCHD + cc) * RS + pki[d]];
         div0[v] = C::first_flux_dir(v) == d ? t * ih : fma_r(t, ih, div0[v]);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) g0[d][v] = 0.0;
 #pragma unroll
-      for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = rmine[(d * NCHD + NFL + cc) * SP + pk[d]] * ih;
+      for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = rmine[(d * NCHD + NFL + cc) * RS + pki[d]] * ih;
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -266,7 +284,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
             PDE::flux_dir(qb, P, a.pde, d, Fb);
 #pragma unroll
             for (int cc = 0; cc < NFL; ++cc)
-              mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[C::flux_var(d, cc)], Fb[C::flux_var(d, cc)]};
+              mine[(d * NCHD + cc) * RS + pki[d]] = P2{Fa[C::flux_var(d, cc)], Fb[C::flux_var(d, cc)]};
           }
         } else {
           double Fa[DIM][NV], Fb[DIM][NV];
@@ -276,14 +294,14 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
           for (int d = 0; d < DIM; ++d)
 #pragma unroll
             for (int cc = 0; cc < NFL; ++cc)
-              mine[(d * NCHD + cc) * SP + pk[d]] = P2{Fa[d][C::flux_var(d, cc)], Fb[d][C::flux_var(d, cc)]};
+              mine[(d * NCHD + cc) * RS + pki[d]] = P2{Fa[d][C::flux_var(d, cc)], Fb[d][C::flux_var(d, cc)]};
         }
       }
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
 #pragma unroll
         for (int cc = 0; cc < NGR; ++cc)
-          mine[(d * NCHD + NFL + cc) * SP + pk[d]] = P2{qa[C::grad_var(cc)], qb[C::grad_var(cc)]};
+          mine[(d * NCHD + NFL + cc) * RS + pki[d]] = P2{qa[C::grad_var(cc)], qb[C::grad_var(cc)]};
     }
     __syncthreads();
     constexpr int CH0 = FIN ? NFL : 0;
@@ -297,7 +315,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       const int ch = CH0 + (task / F) % NCT;
       d = (task / (F * NCT)) % DIM;
       const int c2 = task / (F * NCT * DIM);
-      return lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * SP + l * LS;
+      return lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * RS + GN::islot(l, 0);
     };
     auto whole = [&](P2* row, const P2 (&xr)[n]) {
       double x0[n], x1[n], y0[n], y1[n];
@@ -309,7 +327,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       line_deriv<double, n>(x0, y0, 1.0);
       line_deriv<double, n>(x1, y1, 1.0);
 #pragma unroll
-      for (int i = 0; i < n; ++i) row[i] = P2{y0[i], y1[i]};
+      for (int i = 0; i < n; ++i) row[i * EI] = P2{y0[i], y1[i]};
     };
     if constexpr (NWHOLE == 2 * BLOCK) {
       // two whole tasks per lane: both lines are loaded before either is
@@ -319,9 +337,9 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       P2* rb = row_of(tid + BLOCK, d);
       P2 xa[n], xb[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) xa[m] = ra[m];
+      for (int m = 0; m < n; ++m) xa[m] = ra[m * EI];
 #pragma unroll
-      for (int m = 0; m < n; ++m) xb[m] = rb[m];
+      for (int m = 0; m < n; ++m) xb[m] = rb[m * EI];
       whole(ra, xa);
       whole(rb, xb);
     } else {
@@ -330,7 +348,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
         P2* row = row_of(task, d);
         P2 xr[n];
 #pragma unroll
-        for (int m = 0; m < n; ++m) xr[m] = row[m];
+        for (int m = 0; m < n; ++m) xr[m] = row[m * EI];
         whole(row, xr);
       }
     }
@@ -339,10 +357,10 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       double* half = reinterpret_cast<double*>(row_of(NWHOLE + (h >> 1), d)) + (h & 1);
       double x[n], y[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) x[m] = half[2 * m];
+      for (int m = 0; m < n; ++m) x[m] = half[2 * m * EI];
       line_deriv<double, n>(x, y, 1.0);
 #pragma unroll
-      for (int i = 0; i < n; ++i) half[2 * i] = y[i];
+      for (int i = 0; i < n; ++i) half[2 * i * EI] = y[i];
     }
     __syncthreads();
     const P2* const rmine = lds2 + lcr * (GN::CELL_ELEMS / 2);
@@ -353,7 +371,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int cc = 0; cc < NFL; ++cc) {
         if constexpr (FIN) break;
         const int v = C::flux_var(d, cc);
-        const P2 t = rmine[(d * NCHD + cc) * SP + pk[d]];
+        const P2 t = rmine[(d * NCHD + cc) * RS + pki[d]];
         div0[v] = C::first_flux_dir(v) == d ? t.x * ih : fma_r(t.x, ih, div0[v]);
         div1[v] = C::first_flux_dir(v) == d ? t.y * ih : fma_r(t.y, ih, div1[v]);
       }
@@ -361,7 +379,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int v = 0; v < NV; ++v) g0[d][v] = g1[d][v] = 0.0;
 #pragma unroll
       for (int cc = 0; cc < NGR; ++cc) {
-        const P2 t = rmine[(d * NCHD + NFL + cc) * SP + pk[d]];
+        const P2 t = rmine[(d * NCHD + NFL + cc) * RS + pki[d]];
         g0[d][C::grad_var(cc)] = t.x * ih;
         g1[d][C::grad_var(cc)] = t.y * ih;
       }
@@ -623,7 +641,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
 #pragma unroll
       for (int d = dg * DPG; d < (dg + 1) * DPG; ++d) {
         if (d != dt_) continue;
-        double* rows = lds + c2 * GN::CELL_ELEMS + fin_off(d) + l * LS;
+        double* rows = lds + c2 * GN::CELL_ELEMS + fin_off(d) + GN::slot(l, 0);
         double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
         if (kind == 0) {
 #pragma unroll
@@ -631,7 +649,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
             double e0 = 0.0, e1 = 0.0;
 #pragma unroll
             for (int m = 0; m < n; ++m) {
-              const double x = rows[v * SP + m];
+              const double x = rows[v * SP + m * ES];
               e0 += T::l0(m) * x;
               e1 += T::l1(m) * x;
             }
@@ -655,7 +673,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
             const int v = C::flux_var(d, cc);
             double x[n], y[n];
 #pragma unroll
-            for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
+            for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m * ES];
             double e0 = 0.0, e1 = 0.0;
 #pragma unroll
             for (int m = 0; m < n; ++m) {
@@ -668,7 +686,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
             }
             line_deriv<double, n>(x, y, a.inv_h[d]);
 #pragma unroll
-            for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i] = y[i];
+            for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i * ES] = y[i];
           }
         }
       }
