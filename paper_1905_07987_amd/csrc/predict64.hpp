@@ -58,9 +58,11 @@ struct GeoN64 {
   static constexpr bool FINDIR = !PAIR;
   // Picard rounds' rows: RS elements between rows, EI between a line's points
   static constexpr bool GPM = PM && PAIR;
-  static constexpr int EI = GPM ? C::NCH * F : ES, RS = GPM ? F : SP;
+  // (EI one more than the rows' elements: EI = 13 mod 16 spreads a line's
+  // points over distinct banks)
+  static constexpr int EI = GPM ? C::NCH * F + 1 : ES, RS = GPM ? F : SP;
   __host__ __device__ static constexpr int islot(int line, int pos) { return GPM ? line + pos * EI : slot(line, pos); }
-  static constexpr int ITER_ELEMS = (PAIR ? 2 : 1) * C::NCH * SP;
+  static constexpr int ITER_ELEMS = GPM ? 2 * n * EI : (PAIR ? 2 : 1) * C::NCH * SP;
   static constexpr int FIN_ELEMS = (FINDIR ? 1 : DIM) * (NV + C::NFLUX) * SP;
   static constexpr int CELL_ELEMS = cmax(ITER_ELEMS, FIN_ELEMS);
   static constexpr int ELEMS = CPB * CELL_ELEMS;
@@ -82,6 +84,23 @@ struct GeoN64 {
   static constexpr int LDS_BLOCKS = (156 * 1024) / (ELEMS * 8 + (AMP_IN_PAD ? 0 : NAMP * 8));
   static constexpr int MIN_WAVES = cmax(1, cmin(WMAX, LDS_BLOCKS * (BLOCK / 64) / 4));
 };
+
+// Line numbering of the Picard rounds' rows for 3-D n = 6 (GPM): a
+// permutation of each direction's 36 lines, chosen by a search over the
+// node threads' 16-lane access groups (lane k = kx + 6 ky + 36 kz) so that,
+// with EI = 541, their 16-byte units fall on distinct banks as far as
+// possible (x: 15 cycles per 14 groups, y: 20, z: 18, against 28, 26 and
+// 18 with the natural numbering and EI = 540).  Any permutation is correct:
+// a line task differentiates whichever line its index names.
+static __constant__ const signed char kN64LinePerm[3][36] = {
+    {11, 29, 25, 17, 15, 7, 3, 5, 22, 8, 4, 2, 26, 32, 12, 30, 9, 27, 23, 34, 16, 21, 35, 1, 24, 10, 6, 18, 20, 0, 28, 14, 31, 33, 13, 19},
+    {30, 21, 28, 13, 19, 20, 5, 18, 10, 27, 3, 32, 35, 11, 9, 2, 33, 26, 17, 25, 24, 0, 7, 31, 1, 8, 15, 22, 29, 23, 4, 34, 16, 12, 14, 6},
+    {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33, 34, 35}};
+template <bool GPM>
+__device__ __forceinline__ int n64_line_perm(int d, int line) {
+  if constexpr (GPM) return kN64LinePerm[d][line];
+  return line;
+}
 
 // PDEs that provide flux_dir(Q, P, pc, d, F), the flux of one direction
 template <class... T>
@@ -128,7 +147,7 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       pk[d] = GN::slot(GN::G::line_of(d, kx, ky, kz), kd[d]);
-      pki[d] = GN::islot(GN::G::line_of(d, kx, ky, kz), kd[d]);
+      pki[d] = GN::islot(n64_line_perm<GN::GPM>(d, GN::G::line_of(d, kx, ky, kz)), kd[d]);
     }
   }
 
