@@ -649,65 +649,53 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       }
     }
     __syncthreads();
-    for (int task = tid; task < CPB * DPG * F * (NFL + 1); task += BLOCK) {
-      // task kind 0: qbar traces of line l; kind 1 + cc: flux channel cc
+    // One task per (cell, direction of the group, quantity v, line l): the
+    // traces of qbar_v and of the normal flux Fbar_{d,v} at both faces of
+    // the line, and the derivative of Fbar_{d,v} along it, in place.  The
+    // direction and the quantity are runtime indices, so every task takes
+    // the same code path and a wave runs one task body per pass.
+    for (int task = tid; task < CPB * DPG * NV * F; task += BLOCK) {
       const int l = task % F;
-      const int kind = (task / F) % (NFL + 1);
-      const int dt_ = dg * DPG + (task / (F * (NFL + 1))) % DPG;
-      const int c2 = task / (F * (NFL + 1) * DPG);
+      const int v = (task / F) % NV;
+      const int d = dg * DPG + (task / (F * NV)) % DPG;
+      const int c2 = task / (F * NV * DPG);
       const long long tcell = cell0 + c2;
       const bool tact = tcell < a.ncells;
+      double* rows = lds + c2 * GN::CELL_ELEMS + fin_off(d) + GN::slot(l, 0);
+      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F + v * F + l;
+      double e0 = 0.0, e1 = 0.0;
 #pragma unroll
-      for (int d = dg * DPG; d < (dg + 1) * DPG; ++d) {
-        if (d != dt_) continue;
-        double* rows = lds + c2 * GN::CELL_ELEMS + fin_off(d) + GN::slot(l, 0);
-        double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-        if (kind == 0) {
+      for (int m = 0; m < n; ++m) {
+        const double x = rows[v * SP + m * ES];
+        e0 += T::l0(m) * x;
+        e1 += T::l1(m) * x;
+      }
+      // the flux row of v in d's layout (-1: F_d has no component v)
+      int cc = -1;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            double e0 = 0.0, e1 = 0.0;
+      for (int dd = dg * DPG; dd < (dg + 1) * DPG; ++dd)
 #pragma unroll
-            for (int m = 0; m < n; ++m) {
-              const double x = rows[v * SP + m * ES];
-              e0 += T::l0(m) * x;
-              e1 += T::l1(m) * x;
-            }
-            if (tact) {
-              tr[(0 * NV + v) * F + l] = e0;  // face 2d,   state
-              tr[(2 * NV + v) * F + l] = e1;  // face 2d+1, state
-            }
-          }
+        for (int c = 0; c < NFL; ++c)
+          if (dd == d && C::flux_var(dd, c) == v) cc = c;
+      double f0 = 0.0, f1 = 0.0;
+      if (cc >= 0) {
+        double x[n], y[n];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            if (!PDE::flux_nonzero(d, v) && tact) {
-              tr[(1 * NV + v) * F + l] = 0.0;
-              tr[(3 * NV + v) * F + l] = 0.0;
-            }
-          }
-        } else {
-          // normal-flux traces; derivative of Fbar_d in place
+        for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m * ES];
 #pragma unroll
-          for (int cc = 0; cc < NFL; ++cc) {
-            if (cc != kind - 1) continue;
-            const int v = C::flux_var(d, cc);
-            double x[n], y[n];
-#pragma unroll
-            for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m * ES];
-            double e0 = 0.0, e1 = 0.0;
-#pragma unroll
-            for (int m = 0; m < n; ++m) {
-              e0 += T::l0(m) * x[m];
-              e1 += T::l1(m) * x[m];
-            }
-            if (tact) {
-              tr[(1 * NV + v) * F + l] = e0;
-              tr[(3 * NV + v) * F + l] = e1;
-            }
-            line_deriv<double, n>(x, y, a.inv_h[d]);
-#pragma unroll
-            for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i * ES] = y[i];
-          }
+        for (int m = 0; m < n; ++m) {
+          f0 += T::l0(m) * x[m];
+          f1 += T::l1(m) * x[m];
         }
+        line_deriv<double, n>(x, y, a.inv_h[d]);
+#pragma unroll
+        for (int i = 0; i < n; ++i) rows[(NV + cc) * SP + i * ES] = y[i];
+      }
+      if (tact) {
+        tr[0 * NV * F] = e0;  // face 2d,   state
+        tr[1 * NV * F] = f0;  // face 2d,   normal flux
+        tr[2 * NV * F] = e1;  // face 2d+1, state
+        tr[3 * NV * F] = f1;  // face 2d+1, normal flux
       }
     }
     __syncthreads();
