@@ -697,71 +697,57 @@ predict_kernel_node(const KArgs a, const double* Q, const double* __restrict__ p
     }
   }
   __syncthreads();
-  for (int task = tid; task < CPB * DIM * F * (NFL + 1); task += BLOCK) {
-    // task kind 0: qbar traces of line l; kind 1 + c: flux channel c
+  // one task per (cell, direction, quantity v, line l), runtime indices, one
+  // code path: traces of qbar_v and Fbar_{d,v}, derivative of Fbar_{d,v}
+  for (int task = tid; task < CPB * DIM * NV * F; task += BLOCK) {
     const int l = task % F;
-    const int kind = (task / F) % (NFL + 1);
-    const int dt_ = (task / (F * (NFL + 1))) % DIM;
-    const int c2 = task / (F * (NFL + 1) * DIM);
+    const int v = (task / F) % NV;
+    const int d = (task / (F * NV)) % DIM;
+    const int c2 = task / (F * NV * DIM);
     const long long tcell = cell0 + c2;
     const bool tact = tcell < a.ncells;
+    R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + l * G::LS;
+    double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F + v * F + l;
+    R e0 = R(0), e1 = R(0);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (d != dt_) continue;
-      R* rows = lds + c2 * GA::CELL_ELEMS + d * FIN_D + l * G::LS;
-      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
-      if (kind == 0) {
-        // qbar traces at both ends
+    for (int m = 0; m < n; ++m) {
+      const R x = rows[v * SP + m];
+      e0 += T::l0(m) * x;
+      e1 += T::l1(m) * x;
+    }
+    int cc = -1;  // the flux row of v in d's layout (-1: F_d has no component v)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          R e0 = R(0), e1 = R(0);
+    for (int dd = 0; dd < DIM; ++dd)
 #pragma unroll
-          for (int m = 0; m < n; ++m) {
-            const R x = rows[v * SP + m];
-            e0 += T::l0(m) * x;
-            e1 += T::l1(m) * x;
-          }
-          if (tact) {
-            tr[(0 * NV + v) * F + l] = double(e0);  // face 2d,   state
-            tr[(2 * NV + v) * F + l] = double(e1);  // face 2d+1, state
-          }
-        }
+      for (int c = 0; c < NFL; ++c)
+        if (dd == d && C::flux_var(dd, c) == v) cc = c;
+    R f0 = R(0), f1 = R(0);
+    if (cc >= 0) {
+      R x[n];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          if (!PDE::flux_nonzero(d, v) && tact) {
-            tr[(1 * NV + v) * F + l] = 0.0;
-            tr[(3 * NV + v) * F + l] = 0.0;
-          }
-        }
-      } else {
-        // normal-flux traces; derivative of Fbar_d in place
+      for (int m = 0; m < n; ++m) x[m] = rows[(NV + cc) * SP + m];
 #pragma unroll
-        for (int c = 0; c < NFL; ++c) {
-          if (c != kind - 1) continue;
-          const int v = C::flux_var(d, c);
-          R x[n];
-#pragma unroll
-          for (int m = 0; m < n; ++m) x[m] = rows[(NV + c) * SP + m];
-          R e0 = R(0), e1 = R(0);
-#pragma unroll
-          for (int m = 0; m < n; ++m) {
-            e0 += T::l0(m) * x[m];
-            e1 += T::l1(m) * x[m];
-          }
-          if (tact) {
-            tr[(1 * NV + v) * F + l] = double(e0);
-            tr[(3 * NV + v) * F + l] = double(e1);
-          }
-          const R s = inv_h[d];
-#pragma unroll
-          for (int i = 0; i < n; ++i) {
-            R y = R(0);
-#pragma unroll
-            for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
-            rows[(NV + c) * SP + i] = y * s;
-          }
-        }
+      for (int m = 0; m < n; ++m) {
+        f0 += T::l0(m) * x[m];
+        f1 += T::l1(m) * x[m];
       }
+      R s = inv_h[0];  // 1/h of direction d (a select chain: inv_h stays in registers)
+#pragma unroll
+      for (int dd = 1; dd < DIM; ++dd)
+        if (d == dd) s = inv_h[dd];
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        R y = R(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) y += T::D(i, m) * x[m];
+        rows[(NV + cc) * SP + i] = y * s;
+      }
+    }
+    if (tact) {
+      tr[0 * NV * F] = double(e0);  // face 2d,   state
+      tr[1 * NV * F] = double(f0);  // face 2d,   normal flux
+      tr[2 * NV * F] = double(e1);  // face 2d+1, state
+      tr[3 * NV * F] = double(f1);  // face 2d+1, normal flux
     }
   }
   __syncthreads();
@@ -1633,44 +1619,50 @@ __device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double
 #pragma unroll
   for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
   Op::sync();
+  // (the direction is a runtime index: every task takes the same code path)
   Op::template cell_tasks<DIM * F>(tid, [&](int c2, int task) {
     const int l = task % F;
-    const int dt_ = task / F;
+    const int d = task / F;
     const long long tcell = cell0 + c2;
     if (tcell >= a.ncells) return;
-    const R* rows = lds + c2 * GL::CELL_ELEMS;
+    const R* rows = lds + c2 * GL::CELL_ELEMS + line_node<G>(d, l, 0);
+    const int st = line_node<G>(d, 0, 1) - line_node<G>(d, 0, 0);  // node stride along d
     R e0[NV], e1[NV], Pt[NP > 0 ? NP : 1];
 #pragma unroll
     for (int p = 0; p < NP; ++p) Pt[p] = R(params[tcell * NP + p]);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (d != dt_) continue;
+    for (int v = 0; v < NV; ++v) {
+      R s0 = R(0), s1 = R(0);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R s0 = R(0), s1 = R(0);
-#pragma unroll
-        for (int m = 0; m < n; ++m) {
-          const R x = rows[v * S + line_node<G>(d, l, m)];
-          s0 += T::l0(m) * x;
-          s1 += T::l1(m) * x;
-        }
-        e0[v] = s0;
-        e1[v] = s1;
+      for (int m = 0; m < n; ++m) {
+        const R x = rows[v * S + m * st];
+        s0 += T::l0(m) * x;
+        s1 += T::l1(m) * x;
       }
-      double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
+      e0[v] = s0;
+      e1[v] = s1;
+    }
+    double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        tr[(0 * NV + v) * F + l] = double(e0[v]);  // face 2d,   state
-        tr[(2 * NV + v) * F + l] = double(e1[v]);  // face 2d+1, state
-      }
-      if (a.flux_traces) {
+    for (int v = 0; v < NV; ++v) {
+      tr[(0 * NV + v) * F + l] = double(e0[v]);  // face 2d,   state
+      tr[(2 * NV + v) * F + l] = double(e1[v]);  // face 2d+1, state
+    }
+    if (a.flux_traces) {
+      // F_d at both faces (all directions' fluxes, d's picked by a select
+      // chain so that Fa stays in registers)
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
         R Fa[DIM][NV];
-        PDE::fluxes(e0, Pt, a.pde, Fa);
+        PDE::fluxes(side ? e1 : e0, Pt, a.pde, Fa);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) tr[(1 * NV + v) * F + l] = double(Fa[d][v]);  // face 2d
-        PDE::fluxes(e1, Pt, a.pde, Fa);
+        for (int v = 0; v < NV; ++v) {
+          R fv = Fa[0][v];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) tr[(3 * NV + v) * F + l] = double(Fa[d][v]);  // face 2d+1
+          for (int dd = 1; dd < DIM; ++dd)
+            if (d == dd) fv = Fa[dd][v];
+          tr[((side ? 3 : 1) * NV + v) * F + l] = double(fv);
+        }
       }
     }
   });
