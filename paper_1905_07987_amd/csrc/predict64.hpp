@@ -413,6 +413,70 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     // with a barrier.
   };
 
+  // One LDS round of a single state in the two-slice rows (the first pass
+  // from the constant guess, the CERK stages): the first slice of each
+  // element only, one slice per line task, half the LDS traffic and line
+  // work of a round of two states.  (Single-slice geometry: round1.)
+  auto round_one = [&](const double (&qa)[NV], double (&div0)[NV], double (&g0)[DIM][NV]) {
+    if constexpr (!GN::PAIR) {
+      round1(std::false_type{}, qa, div0, g0);
+      return;
+    }
+    double* const mine1 = reinterpret_cast<double*>(lds2 + lc * (GN::CELL_ELEMS / 2));
+    if (node) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        double Fa[NV];
+        if constexpr (HasFluxDir<PDE>::value) {
+          PDE::flux_dir(qa, P, a.pde, d, Fa);
+        } else {
+          double Fall[DIM][NV];
+          PDE::fluxes(qa, P, a.pde, Fall);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fa[v] = Fall[d][v];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NFL; ++cc) mine1[2 * ((d * NCHD + cc) * RS + pki[d])] = Fa[C::flux_var(d, cc)];
+#pragma unroll
+        for (int cc = 0; cc < NGR; ++cc) mine1[2 * ((d * NCHD + NFL + cc) * RS + pki[d])] = qa[C::grad_var(cc)];
+      }
+    }
+    __syncthreads();
+    for (int task = tid; task < CPB * DIM * NCHD * F; task += BLOCK) {
+      const int l = task % F;
+      const int ch = (task / F) % NCHD;
+      const int d = (task / (F * NCHD)) % DIM;
+      const int c2 = task / (F * NCHD * DIM);
+      double* half = reinterpret_cast<double*>(lds2 + c2 * (GN::CELL_ELEMS / 2) + (d * NCHD + ch) * RS + GN::islot(l, 0));
+      double x[n], y[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) x[m] = half[2 * m * EI];
+      line_deriv<double, n>(x, y, 1.0);
+#pragma unroll
+      for (int i = 0; i < n; ++i) half[2 * i * EI] = y[i];
+    }
+    __syncthreads();
+    const double* const rmine1 = reinterpret_cast<const double*>(lds2 + lcr * (GN::CELL_ELEMS / 2));
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double ih = a.inv_h[d];
+#pragma unroll
+      for (int cc = 0; cc < NFL; ++cc) {
+        const int v = C::flux_var(d, cc);
+        const double t = rmine1[2 * ((d * NCHD + cc) * RS + pki[d])];
+        div0[v] = C::first_flux_dir(v) == d ? t * ih : fma_r(t, ih, div0[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) g0[d][v] = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NGR; ++cc) g0[d][C::grad_var(cc)] = rmine1[2 * ((d * NCHD + NFL + cc) * RS + pki[d])] * ih;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (C::first_flux_dir(v) < 0) div0[v] = 0.0;
+    // (no barrier after the read-backs, as in round)
+  };
+
   // right-hand side R = S - div F - B grad q of the state qj (+ the point
   // sources at time entry j of src_amp)
   auto rhs = [&](const double (&qj)[NV], int j, const double (&div)[NV], const double (&g)[DIM][NV],
@@ -480,8 +544,8 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
       for (int v = 0; v < NV; ++v) q[j][v] = Y[v];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
-      double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], kk[NV], B[NV], Sv[NV];
-      round(std::false_type{}, Y, Y, div, g, div1, g1);
+      double div[NV], g[DIM][NV], kk[NV], B[NV], Sv[NV];
+      round_one(Y, div, g);
       rhs(Y, n + (st == 0 ? 0 : (st == 3 ? 2 : 1)), div, g, kk, B, Sv, true);
 #pragma unroll
       for (int j = 0; j < n; ++j) {
@@ -498,8 +562,8 @@ predict_kernel_n64(const KArgs a, const double* Q, const double* __restrict__ pa
     // First Picard step: q^0 = u^n at every time node, so every slice has
     // the same right-hand side apart from point sources; one round suffices.
     load_u(q[0]);
-    double div[NV], g[DIM][NV], div1[NV], g1[DIM][NV], R0[NV], B[NV], Sv[NV];
-    round(std::false_type{}, q[0], q[0], div, g, div1, g1);
+    double div[NV], g[DIM][NV], R0[NV], B[NV], Sv[NV];
+    round_one(q[0], div, g);
     rhs(q[0], 0, div, g, R0, B, Sv, false);
 #pragma unroll
     for (int jj = 0; jj < n; ++jj) {
