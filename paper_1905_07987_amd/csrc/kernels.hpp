@@ -53,12 +53,12 @@ struct Geo {
   }
 };
 
-// Derivative channels per direction: the nonzero flux components, then the
-// quantities whose gradient feeds the non-conservative product.
 // a * b + c with one rounding, in the precision of the operands
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Derivative channels per direction: the nonzero flux components, then the
+// quantities whose gradient feeds the non-conservative product.
 template <class PDE>
 struct Chan {
   static constexpr int nflux(int d) {
