@@ -194,8 +194,9 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True
     """C4: seconds per gradient of the seismogram misfit of the 3-D elastic
     workload (N=3, 32^3 cells, 200 steps, 16 receivers) with respect to the
     per-cell (rho, cp, cs) and the initial state: forward run with
-    checkpoints every `every` steps, then per segment the recomputation and
-    the adjoint steps (autograd Function over the library's adjoint)."""
+    checkpoints every `every` steps, then per segment the recomputation
+    (keeping what each step's adjoint reads) and the adjoint steps (autograd
+    Function over the library's adjoint)."""
     import torch
     from paper_1905_07987_amd import adg, inputs
     from paper_1905_07987_amd.autograd import seismograms
@@ -239,8 +240,8 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True
         J, gu, gm = grad_once(every)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        # the same gradient keeping every state (no recomputation; 200 states
-        # of the 151 MB C4 state fit in HBM)
+        # the same gradient with a checkpoint at every step (segments of one
+        # step: no state is advanced twice except to keep the adjoint's inputs)
         t1 = time.perf_counter()
         J1, _, gm1 = grad_once(1)
         torch.cuda.synchronize()
@@ -252,10 +253,13 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True
     lam = torch.randn(s.state_shape, dtype=torch.float64, device="cuda")
     g = torch.zeros_like(params)
     ck = torch.tensor([0.0, dt], dtype=torch.float64, device="cuda")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    keep = torch.empty(s.keep_size(), dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     reps = 10
     for _ in range(2):
         s.step_adjoint(Q, params, ck, lam, g)
+        s.step_keep(Q, params, ck.clone(), keep)
+        s.step_adjoint_kept(params, ck, keep, lam, g)
     ev[0].record(stream)
     for _ in range(reps):
         s.step(Q, params, ck.clone(), next_dt=False)
@@ -263,20 +267,30 @@ def adjoint_c4(log, steps: int | None = None, every: int = 15, grad: bool = True
     for _ in range(reps):
         s.step_adjoint(Q, params, ck, lam, g)
     ev[2].record(stream)
+    for _ in range(reps):
+        s.step_keep(Q, params, ck.clone(), keep)
+    ev[3].record(stream)
+    for _ in range(reps):
+        s.step_adjoint_kept(params, ck, keep, lam, g)
+    ev[4].record(stream)
     torch.cuda.synchronize()
     fwd_ms = ev[0].elapsed_time(ev[1]) / reps
     adj_ms = ev[1].elapsed_time(ev[2]) / reps
+    fwdk_ms = ev[2].elapsed_time(ev[3]) / reps
+    adjk_ms = ev[3].elapsed_time(ev[4]) / reps
     nseg = -(-steps // every)
     res = {"s_per_grad": round(el, 4) if grad else None,
-           "s_per_grad_all_states_kept": round(el_all, 4) if grad else None,
-           "all_states_gradient_bitwise_equal": same, "steps": steps, "checkpoint_every": every,
+           "s_per_grad_checkpoint_every_step": round(el_all, 4) if grad else None,
+           "every_step_gradient_bitwise_equal": same, "steps": steps, "checkpoint_every": every,
            "checkpoints": nseg, "forward_step_ms": round(fwd_ms, 4),
-           "adjoint_step_ms": round(adj_ms, 4), "J": float(J) if grad else None,
+           "adjoint_step_ms": round(adj_ms, 4),
+           "forward_step_keeping_ms": round(fwdk_ms, 4), "adjoint_step_from_kept_ms": round(adjk_ms, 4),
+           "J": float(J) if grad else None,
            "grad_norm_params": float(torch.linalg.vector_norm(gm)) if grad else None,
            "workload": "c4: 3-D elastic, N=3, 32^3 cells, 16 receivers, Ricker source, "
                        "misfit vs a +-5% perturbed material, FP64, dt frozen"}
     log(f"adjoint c4: {el if grad else float('nan'):.3f} s/grad (fwd step {fwd_ms:.3f} ms, "
-        f"adjoint step {adj_ms:.3f} ms)")
+        f"adjoint step {adj_ms:.3f} ms; keeping / from kept: {fwdk_ms:.3f} / {adjk_ms:.3f} ms)")
     return res
 
 

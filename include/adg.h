@@ -447,6 +447,35 @@ adg_status adg_sample_receivers(adg_ctx* ctx, const double* Q, double* out, void
 adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
                             const double* clock, double* lam, double* gparams, void* stream);
 
+/* The same adjoint step without recomputing the forward predictor: a
+ * reverse sweep that keeps, per step, what the step's adjoint reads of the
+ * forward predictor (the Horner iterates of the linear predictor's time
+ * average, Sec. 3.3 / Eq. 5 in its polynomial form, in the channels whose
+ * gradient the non-conservative product reads, and the time average itself)
+ * needs neither u^n nor the forward sweep inside the adjoint step.
+ *
+ * adg_keep_size: *n <- doubles of one step's keep buffer ([C][slots][S]).
+ * adg_step_keep: one FP64 step of adg_step (flags 0: the step size in clock
+ *   is kept) that also writes the step's keep buffer (device, caller-owned,
+ *   *n doubles; overwritten).
+ * adg_run_keep: adg_run of nsteps steps (no receivers; fused corrector/
+ *   predictor kernels where built, after adg_run_reserve) that writes step
+ *   n's keep buffer at keeps + n *n (device, caller-owned, nsteps *n
+ *   doubles); the states and buffers equal those of nsteps adg_step_keep.
+ * adg_step_adjoint_kept: adg_step_adjoint of that step from its keep buffer
+ *   (device, read only) instead of Q; lam, gparams, clock as there.  The
+ *   result equals adg_step_adjoint's (the same arithmetic on the same
+ *   values).
+ * Available where adg_step_adjoint is, for ADG_FP64 contexts; otherwise
+ * ADG_ERR_UNSUPPORTED; a NULL buffer is ADG_ERR_INVALID_ARG. */
+adg_status adg_keep_size(const adg_ctx* ctx, long long* n);
+adg_status adg_step_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, double* keep,
+                         void* stream);
+adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps, double* keeps,
+                        void* stream);
+adg_status adg_step_adjoint_kept(adg_ctx* ctx, const double* params, const double* clock,
+                                 const double* keep, double* lam, double* gparams, void* stream);
+
 /* Transpose of adg_sample_receivers: lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v]
  * for every receiver r (device lamrec [n][nvar], lam [C][nvar][S]).
  * Receivers in the same cell add in receiver order (deterministic). */

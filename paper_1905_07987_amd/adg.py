@@ -95,6 +95,10 @@ def lib():
         L.adg_set_receivers.argtypes = [vp, C.c_int, dp]
         L.adg_sample_receivers.argtypes = [vp, vp, vp, vp]
         L.adg_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.adg_keep_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.adg_step_keep.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.adg_run_keep.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.adg_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_sample_receivers_adjoint.argtypes = [vp, vp, vp, vp]
         L.adg_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
         L.adg_step_limited.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
@@ -120,6 +124,7 @@ EXPORTED = ("adg_last_error", "adg_max_order", "adg_basis_tables", "adg_create",
             "adg_correct",
             "adg_check_admissible", "adg_set_point_sources", "adg_set_receivers",
             "adg_sample_receivers", "adg_step_adjoint", "adg_sample_receivers_adjoint",
+            "adg_keep_size", "adg_step_keep", "adg_run_keep", "adg_step_adjoint_kept",
             "adg_limiter_tables", "adg_limiter_reserve", "adg_step_limited")
 
 
@@ -365,6 +370,45 @@ class Solver:
                                       self._dev(clock, (2,), torch.float64, "clock"),
                                       self._dev(lam, self.state_shape, torch.float64, "lam"), gp,
                                       _stream(stream)))
+
+    def keep_size(self) -> int:
+        """Doubles of one step's keep buffer (adg_step_keep / adg_step_adjoint_kept)."""
+        n = C.c_longlong(0)
+        _check(lib().adg_keep_size(self._ctx, C.byref(n)))
+        return int(n.value)
+
+    def step_keep(self, Q, params, clock, keep, stream=None):
+        """One FP64 step (dt held fixed) that also writes into keep [keep_size()]
+        what the step's adjoint reads of its forward predictor."""
+        import torch
+        _check(lib().adg_step_keep(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"),
+                                   self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
+                                   self._dev(keep, (self.keep_size(),), torch.float64, "keep"), _stream(stream)))
+
+    def run_keep(self, Q, params, clock, nsteps: int, keeps, stream=None):
+        """run() of nsteps steps (no receivers) that writes step n's keep buffer
+        into keeps[n] (keeps: [nsteps, keep_size()] float64)."""
+        import torch
+        if not self._run_ready:
+            self.reserve_run()
+        _check(lib().adg_run_keep(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"), self._params(params),
+                                  self._dev(clock, (2,), torch.float64, "clock"), int(nsteps),
+                                  self._dev(keeps, (nsteps, self.keep_size()), torch.float64, "keeps"),
+                                  _stream(stream)))
+
+    def step_adjoint_kept(self, params, clock, keep, lam, gparams=None, stream=None):
+        """step_adjoint of the step that wrote keep (step_keep), without u^n."""
+        import torch
+        gp = C.c_void_p()
+        if self.nparam > 0:
+            if gparams is None:
+                raise ValueError("this PDE needs a parameter-gradient array [ncells, nparam]")
+            gp = self._dev(gparams, (self.ncells, self.nparam), torch.float64, "gparams")
+        _check(lib().adg_step_adjoint_kept(self._ctx, self._params(params),
+                                           self._dev(clock, (2,), torch.float64, "clock"),
+                                           self._dev(keep, (self.keep_size(),), torch.float64, "keep"),
+                                           self._dev(lam, self.state_shape, torch.float64, "lam"), gp,
+                                           _stream(stream)))
 
     def sample_receivers_adjoint(self, lamrec, lam, stream=None):
         """lam += transpose of receiver sampling applied to lamrec [nrec, nvar]."""

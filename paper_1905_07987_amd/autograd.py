@@ -3,12 +3,14 @@
 ``seismograms(solver, u0, params, dt, steps)`` runs ``steps`` FP64 steps of
 the solver's PDE from ``u0`` with the step size held fixed and returns the
 receiver samples after every step, ``[steps, nrec, nvar]``.  Its backward is
-the library's hand-written discrete adjoint (``adg_step_adjoint`` and
+the library's hand-written discrete adjoint (``adg_step_adjoint_kept`` and
 ``adg_sample_receivers_adjoint``), run in reverse over the steps with
 time-step checkpointing: the forward pass keeps the state every ``every``
-steps; the backward pass recomputes the states of one segment from its
-checkpoint, then runs the adjoint steps of that segment backwards.  Memory:
-ceil(steps / every) checkpoints plus ``every`` segment states.
+steps; the backward pass recomputes one segment from its checkpoint with
+``adg_run_keep``, which keeps per step what that step's adjoint reads of
+its forward predictor, then runs the adjoint steps of that segment
+backwards from those buffers.  Memory: ceil(steps / every) checkpoints plus
+``every`` keep buffers (``Solver.keep_size()`` doubles each).
 
 Gradients flow to ``u0`` and ``params``.  The step size is not
 differentiated (it is an input, as in a run with a frozen dt).  Available
@@ -69,20 +71,20 @@ class _SeismogramRun(torch.autograd.Function):
         ts = _time_nodes(ctx.t0, dt, steps)
         clocks = torch.tensor([[ts[n], dt] for n in range(steps)], dtype=torch.float64, device=dev)
         nseg = math.ceil(steps / every)
+        keep_n = s.keep_size()
         for seg in reversed(range(nseg)):
             n0, n1 = seg * every, min(steps, (seg + 1) * every)
-            # recompute u^{n0} .. u^{n1-1} from the checkpoint
+            # recompute steps n0 .. n1-1 from the checkpoint, keeping what
+            # each step's adjoint reads
             Q = ctx.ckpts[seg].clone()
             clock = clocks[n0].clone()
-            states = [ctx.ckpts[seg]]
-            for n in range(n0, n1 - 1):
-                s.step(Q, prm, clock, next_dt=False)
-                states.append(Q.clone())
+            keeps = torch.empty((n1 - n0, keep_n), dtype=torch.float64, device=dev)
+            s.run_keep(Q, prm, clock, n1 - n0, keeps)
             for n in reversed(range(n0, n1)):
                 # out[n] samples u^{n+1}; the step n maps u^n to u^{n+1}
                 s.sample_receivers_adjoint(gout[n], lam)
-                s.step_adjoint(states[n - n0], prm, clocks[n], lam, g)
-            del states, Q
+                s.step_adjoint_kept(prm, clocks[n], keeps[n - n0], lam, g)
+            del keeps, Q
         gu0 = lam
         gp = g if ctx.has_params else None
         return gu0, gp, None, None, None, None, None

@@ -83,6 +83,11 @@ struct KArgs {
   // reduction slots (workspace, zero between uses): kSlots words, each on
   // its own 64-byte line
   unsigned long long* slots;
+  // the forward quantities of one step that its discrete adjoint reads
+  // (linear-PDE predictor, FP64): written by the forward step when set, read
+  // by the adjoint step instead of recomputing them; [C][keep slots][S]
+  // doubles (see adg_keep_size).  Null in every other launch.
+  double* keep;
 };
 
 // Workspace of a step with the a-posteriori subcell limiter (owned by the
@@ -133,6 +138,8 @@ struct KernelSet {
                           double* sub_out, uint8_t* status, const LimWork&, int next_dt, hipStream_t);
   // the flux half of KArgs::bc_trace from its state half (inflow faces)
   hipError_t (*bc_flux)(const KArgs&, double* bc_trace, hipStream_t);
+  // doubles per node of KArgs::keep (0 where the adjoint is not built)
+  int keep_slots;
 };
 
 // Registries implemented by the per-PDE translation units; return nullptr if

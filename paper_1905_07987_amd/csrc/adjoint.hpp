@@ -317,11 +317,15 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
 
   const double t_n = clock[0], dt = clock[1];
   const int I = a.picard_iters;
+  // a.keep: the forward step's quantities (Horner's iterates' gradient
+  // channels and qbar) were kept by that step; Q is not read
+  using KG = KeepGeo<PDE, N>;
+  const double* const keep = a.keep ? a.keep + cl * (long long)(KG::SLOTS * S) + k : nullptr;
   double P[NPX], u[NV], inv_h[3];
 #pragma unroll
   for (int p = 0; p < NPX; ++p) P[p] = p < NP ? params[cl * NP + p] : 0.0;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Q[(cl * NV + v) * S + k];
+  for (int v = 0; v < NV; ++v) u[v] = keep ? 0.0 : Q[(cl * NV + v) * S + k];
 #pragma unroll
   for (int d = 0; d < 3; ++d) inv_h[d] = a.inv_h[d];
 
@@ -354,22 +358,29 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
   // ---- forward sweep: t_k, keeping the gradient quantities of t_{k+1} ----
   double fwv[IMAX][NGX];
   double t[NV];
-  {
+  if (keep) {
+#pragma unroll
+    for (int kk = 0; kk < IMAX; ++kk)
+#pragma unroll
+      for (int c = 0; c < NGX; ++c) fwv[kk][c] = c < NGR && kk < I ? keep[(kk * KG::NGR + c) * S] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] = keep[(KG::QBAR + v) * S];
+  } else {
     const double cI = a.lin_c[I];
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v] = cI * u[v];
-  }
 #pragma unroll
-  for (int kk = IMAX - 1; kk >= 0; --kk) {
-    if (kk < I) {
+    for (int kk = IMAX - 1; kk >= 0; --kk) {
+      if (kk < I) {
 #pragma unroll
-      for (int c = 0; c < NGX; ++c) fwv[kk][c] = c < NGR ? t[C::grad_var(c)] : 0.0;
-      double Lt[NV], g[DIM][NV];
-      Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
-      const double ck = a.lin_c[kk];
+        for (int c = 0; c < NGX; ++c) fwv[kk][c] = c < NGR ? t[C::grad_var(c)] : 0.0;
+        double Lt[NV], g[DIM][NV];
+        Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
+        const double ck = a.lin_c[kk];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
-      add_sources(kk + 1, dt, t);
+        for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
+        add_sources(kk + 1, dt, t);
+      }
     }
   }
 

@@ -856,15 +856,12 @@ adg_status adg_run_reserve(adg_ctx* ctx) {
   return ADG_OK;
 }
 
-adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
-                   double* rec_out, void* stream) {
-  adg_status st = check_state(ctx, Q, params);
-  if (st) return st;
-  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
-  if (nsteps < 0) return fail(ADG_ERR_INVALID_ARG, "nsteps must be >= 0");
-  if (rec_out && ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
-  if (nsteps == 0) return ADG_OK;
-  hipStream_t s = (hipStream_t)stream;
+// nsteps fixed-dt steps (fused corrector/predictor kernels where built and
+// nsteps > 1; the caller has checked adg_run_reserve then).  rec_out: the
+// receiver samples after every step, or null.  keeps: step n's kept
+// quantities for its adjoint at keeps + n keep_n, or null.
+static hipError_t run_steps(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                            double* rec_out, double* keeps, long long keep_n, hipStream_t s) {
   const long long rec_stride = (long long)ctx->nrec * ctx->nv;
   auto sample = [&](int n) -> hipError_t {
     if (!rec_out) return hipSuccess;
@@ -872,12 +869,16 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
                        ctx->d_rec_w, rec_out + n * rec_stride, ctx->nrec, ctx->nv, ctx->S);
     return hipGetLastError();
   };
-  const bool fused = run_fuses(ctx) && nsteps > 1;
-  if (fused && !ctx->traces2) return fail(ADG_ERR_STATE, "adg_run needs adg_run_reserve first (fused steps)");
+  auto predict = [&](int n) -> hipError_t {  // the (unfused) predictor of step n
+    if (!keeps) return k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);
+    KArgs a = ctx->args;
+    a.keep = keeps + n * keep_n;
+    return ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
+  };
   hipError_t e = hipSuccess;
-  if (!fused) {
+  if (!(run_fuses(ctx) && nsteps > 1)) {
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-      e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);
+      e = predict(n);
       if (e == hipSuccess) e = k_correct(ctx, Q, params, clock, 0, s);
       if (e == hipSuccess) e = sample(n);
     }
@@ -886,8 +887,9 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
     a.nrec = rec_out ? ctx->nrec : 0;
     a.rec_cell = ctx->d_rec_cell;
     a.rec_w = ctx->d_rec_w;
-    e = k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);  // predictor of the first step
+    e = predict(0);  // predictor of the first step
     for (int n = 0; n + 1 < nsteps && e == hipSuccess; ++n) {
+      a.keep = keeps ? keeps + (n + 1) * keep_n : nullptr;  // the fused predictor is step n + 1's
       e = ctx->ks->step_fused(a, ctx->cfg.precision, Q, params, clock, ctx->traces, ctx->traces2,
                               rec_out ? rec_out + n * rec_stride : nullptr, s);
       std::swap(ctx->traces, ctx->traces2);  // the newest traces are the workspace
@@ -896,6 +898,20 @@ adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock,
     if (e == hipSuccess) e = sample(nsteps - 1);
   }
   ctx->traces_ready = false;
+  return e;
+}
+
+adg_status adg_run(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                   double* rec_out, void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (nsteps < 0) return fail(ADG_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (rec_out && ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
+  if (nsteps == 0) return ADG_OK;
+  if (run_fuses(ctx) && nsteps > 1 && !ctx->traces2)
+    return fail(ADG_ERR_STATE, "adg_run needs adg_run_reserve first (fused steps)");
+  hipError_t e = run_steps(ctx, Q, params, clock, nsteps, rec_out, nullptr, 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "run launch");
   return ADG_OK;
 }
@@ -927,6 +943,78 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
     return fail(ADG_ERR_UNSUPPORTED, "the adjoint supports at most order + 1 Picard iterations");
   hipError_t e = ctx->ks->adjoint(ctx->args, Q, params, clock, lam, gparams, ctx->traces,
                                   (hipStream_t)stream);
+  ctx->traces_ready = false;  // the adjoint reuses the trace workspace
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return ADG_OK;
+}
+
+// the checks of adg_step_adjoint for the kept-quantity pair below
+static adg_status check_keep(adg_ctx* ctx, const void* keep) {
+  if (!keep) return fail(ADG_ERR_INVALID_ARG, "null keep buffer");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->args.bc[f] != ADG_BC_PERIODIC) return fail(ADG_ERR_UNSUPPORTED, "the adjoint needs a periodic mesh");
+  if (ctx->user || !ctx->ks || !ctx->ks->adjoint || ctx->ks->keep_slots <= 0)
+    return fail(ADG_ERR_UNSUPPORTED, "the adjoint is built for the PDEs linear in Q (elastic, advection)");
+  if (ctx->cfg.precision != ADG_FP64) return fail(ADG_ERR_UNSUPPORTED, "the adjoint is that of the FP64 step");
+  if (ctx->args.picard_iters > ctx->cfg.order + 1)
+    return fail(ADG_ERR_UNSUPPORTED, "the adjoint supports at most order + 1 Picard iterations");
+  return ADG_OK;
+}
+
+adg_status adg_keep_size(const adg_ctx* ctx, long long* n) {
+  if (!ctx || !n) return fail(ADG_ERR_INVALID_ARG, "null context or output");
+  if (ctx->user || !ctx->ks || !ctx->ks->adjoint || ctx->ks->keep_slots <= 0)
+    return fail(ADG_ERR_UNSUPPORTED, "the adjoint is built for the PDEs linear in Q (elastic, advection)");
+  *n = ctx->C * (long long)ctx->S * ctx->ks->keep_slots;
+  return ADG_OK;
+}
+
+adg_status adg_step_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, double* keep,
+                         void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  st = check_keep(ctx, keep);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  KArgs a = ctx->args;
+  a.keep = keep;
+  hipError_t e = ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "predict launch");
+  ctx->traces_ready = true;
+  e = k_correct(ctx, Q, params, clock, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "correct launch");
+  return ADG_OK;
+}
+
+adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps, double* keeps,
+                        void* stream) {
+  adg_status st = check_state(ctx, Q, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (nsteps < 0) return fail(ADG_ERR_INVALID_ARG, "nsteps must be >= 0");
+  st = check_keep(ctx, keeps);
+  if (st) return st;
+  if (nsteps == 0) return ADG_OK;
+  if (run_fuses(ctx) && nsteps > 1 && !ctx->traces2)
+    return fail(ADG_ERR_STATE, "adg_run_keep needs adg_run_reserve first (fused steps)");
+  const long long keep_n = ctx->C * (long long)ctx->S * ctx->ks->keep_slots;
+  hipError_t e = run_steps(ctx, Q, params, clock, nsteps, nullptr, keeps, keep_n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "run launch");
+  return ADG_OK;
+}
+
+adg_status adg_step_adjoint_kept(adg_ctx* ctx, const double* params, const double* clock,
+                                 const double* keep, double* lam, double* gparams, void* stream) {
+  adg_status st = check_state(ctx, lam, params);
+  if (st) return st;
+  if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
+  if (ctx->np > 0 && !gparams) return fail(ADG_ERR_INVALID_ARG, "null parameter gradient");
+  st = check_keep(ctx, keep);
+  if (st) return st;
+  KArgs a = ctx->args;
+  a.keep = const_cast<double*>(keep);  // read only by the adjoint kernels
+  hipError_t e = ctx->ks->adjoint(a, nullptr, params, clock, lam, gparams, ctx->traces, (hipStream_t)stream);
   ctx->traces_ready = false;  // the adjoint reuses the trace workspace
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return ADG_OK;

@@ -1536,10 +1536,21 @@ __device__ inline void lin_source_weights(const KArgs& a, int s, double t_n, dou
   }
 }
 
+// Slots per node of KArgs::keep: for k < n (the adjoint's most Picard
+// iterations), the channels of Horner's iterate t_{k+1} whose gradient the
+// non-conservative product reads; then all of t_0 = qbar.
+template <class PDE, int N>
+struct KeepGeo {
+  static constexpr int NGR = Chan<PDE>::ngrad(), IMAX = N + 1;
+  static constexpr int QBAR = IMAX * NGR;       // first slot of qbar
+  static constexpr int SLOTS = QBAR + PDE::NV;
+};
+
 // The linear predictor for the CPB cells of a block from cell0 on: this
 // thread's node starts from u64 (with its cell's parameters P); the face
 // traces go to traces and u + dt vol to Qout (active nodes only).  t_n is
-// the start of the step (point sources), dt64 its size.
+// the start of the step (point sources), dt64 its size.  With a.keep set
+// (FP64), the quantities the step's adjoint reads go there too.
 template <class PDE, int N, class R>
 __device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double (*src_e)[kMaxLin + 1],
                                                   int tid, long long cell0, const double (&u64)[PDE::NV],
@@ -1596,13 +1607,24 @@ __device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v] = cI * u[v];
   }
+  using KG = KeepGeo<PDE, N>;
+  constexpr bool KEEP = std::is_same<R, double>::value;
+  double* const keep = KEEP && a.keep && active ? a.keep + cell * (long long)(KG::SLOTS * S) + k : nullptr;
   for (int kk = I - 1; kk >= 0; --kk) {
+    if (keep && kk < KG::IMAX) {
+#pragma unroll
+      for (int c = 0; c < KG::NGR; ++c) keep[(kk * KG::NGR + c) * S] = double(t[Chan<PDE>::grad_var(c)]);
+    }
     R Lt[NV], g[DIM][NV];
     Op::apply(a, lds, mine, pk, tid, t, P, inv_h, Lt, g);
     const R ck = R(a.lin_c[kk]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v] = ck * u[v] + dt * Lt[v];
     add_sources(kk + 1, dt, t);
+  }
+  if (keep) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) keep[(KG::QBAR + v) * S] = double(t[v]);
   }
 
   // volume term
@@ -2335,7 +2357,8 @@ struct Launch {
   static const KernelSet* set() {
     static const KernelSet ks = {GP::BLOCK, GP::CPB, GB::CPB,
                                  &predict, &correct, &stable_dt, &admissible, adjoint_entry(),
-                                 step_fused_entry(), lim_before_entry(), lim_after_entry(), &bc_flux};
+                                 step_fused_entry(), lim_before_entry(), lim_after_entry(), &bc_flux,
+                                 GeoAdjL<PDE, N>::supported ? KeepGeo<PDE, N>::SLOTS : 0};
     return &ks;
   }
 };
