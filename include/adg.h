@@ -454,18 +454,24 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
  * gradient the non-conservative product reads, and the time average itself)
  * needs neither u^n nor the forward sweep inside the adjoint step.
  *
- * adg_keep_size: *n <- doubles of one step's keep buffer ([C][slots][S]).
+ * adg_keep_size: *n <- doubles of one step's keep buffer ([C][slots][S]
+ *   per-node quantities, then the step's face traces in the layout of
+ *   adg_predict's traces, trace_elems of adg_info).
  * adg_step_keep: one FP64 step of adg_step (flags 0: the step size in clock
  *   is kept) that also writes the step's keep buffer (device, caller-owned,
- *   *n doubles; overwritten).
+ *   *n doubles; overwritten).  Its face traces go to the keep buffer, not
+ *   to the context's workspace (a following adg_correct needs a new
+ *   adg_predict).
  * adg_run_keep: adg_run of nsteps steps (no receivers; fused corrector/
  *   predictor kernels where built, after adg_run_reserve) that writes step
  *   n's keep buffer at keeps + n *n (device, caller-owned, nsteps *n
  *   doubles); the states and buffers equal those of nsteps adg_step_keep.
  * adg_step_adjoint_kept: adg_step_adjoint of that step from its keep buffer
- *   (device, read only) instead of Q; lam, gparams, clock as there.  The
- *   result equals adg_step_adjoint's (the same arithmetic on the same
- *   values).
+ *   (device, read only) instead of Q; lam, gparams, clock as there.  lam
+ *   equals adg_step_adjoint's (the same arithmetic on the same values);
+ *   gparams equals it to rounding (the Rusanov flux's two transposes run
+ *   as one pass over the faces, on the kept traces, and its compiled
+ *   products may round differently).
  * Available where adg_step_adjoint is, for ADG_FP64 contexts; otherwise
  * ADG_ERR_UNSUPPORTED; a NULL buffer is ADG_ERR_INVALID_ARG. */
 adg_status adg_keep_size(const adg_ctx* ctx, long long* n);

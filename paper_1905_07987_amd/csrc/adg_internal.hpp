@@ -121,7 +121,8 @@ struct KernelSet {
                            uint8_t* troubled, int32_t* count, hipStream_t);
   // Discrete adjoint of one FP64 step (nullptr where not built: PDEs that
   // are not linear in Q, orders whose kernel does not fit).  work holds
-  // 2 C 2dim nvar F doubles (the trace workspace).
+  // 2 C 2dim nvar F + C nparam doubles (the trace workspace).  With
+  // KArgs::keep (a kept forward step) Q is not read.
   hipError_t (*adjoint)(const KArgs&, const double* Q, const double* params, const double* clock,
                         double* lam, double* gparams, double* work, hipStream_t);
   // Corrector of step n and predictor of step n + 1 in one kernel (the

@@ -24,16 +24,23 @@
 // A and B of [C][2 dim][NV][F] doubles (face = 2 d + side, side 1 = high):
 //  1. adj_face_project_kernel: A = sum_m l_side(m) / w_m lam(line f, m), the
 //     face projections of lam that the surface integral's transpose needs.
-//  2. adj_rusanov_kernel<false>: B = adjoint of each cell's own face traces
-//     (state trace plus folded flux trace) from the fluctuation adjoints of
-//     both cells of the face.
+//  2. adj_rusanov_kernel<true, false>: B = adjoint of each cell's own face
+//     traces (state trace plus folded flux trace) from the fluctuation
+//     adjoints of both cells of the face.
 //  3. adj_predict_lin_kernel: per cell, the linear predictor's Horner sweep
 //     forward from u^n (keeping the iterates' gradient quantities), then the
 //     transposes of the face projection, the volume term and the Horner
 //     steps in reverse order; lam <- lam^n, gparams += the cell's volume
 //     terms, B <- face traces of qbar (after B's adjoints have been read).
-//  4. adj_rusanov_kernel<true> (PDEs with parameters): gparams += the
+//  4. adj_rusanov_kernel<false, true> (PDEs with parameters): gparams += the
 //     Rusanov flux's parameter derivative at every face of the cell.
+// From a kept forward step (KArgs::keep: the Horner quantities and, behind
+// them, the step's face traces of qbar) the sequence is 1; then
+// adj_rusanov_kernel<true, true>, which writes B and each cell's face terms
+// of the parameter gradient (gface, C x nparam doubles behind A and B) in
+// one pass, the qbar traces being the kept ones; then 3 without the forward
+// sweep and without B's qbar traces, adding gface after the cell's volume
+// terms (the state path's order of the two sums).
 #pragma once
 
 namespace adg {
@@ -109,9 +116,11 @@ adj_face_project_kernel(const KArgs a, const double* __restrict__ lam, double* _
 }
 
 // ---------------------------------------------------------------------------
-// 2./4. Rusanov flux in reverse.  GRAD = false: B <- adjoint of the cell's own
-// face traces.  GRAD = true: gparams += the flux's parameter derivative, with
-// B holding the face traces of qbar.
+// 2./4. Rusanov flux in reverse.  OUT: B <- adjoint of the cell's own face
+// traces.  GRAD: the flux's parameter derivative, the face traces of qbar
+// read from tq (face stride tq_face doubles: NV F for B, 2 NV F for the
+// forward trace array), added to gp (GRAD only) or written to gp (OUT and
+// GRAD: the per-cell face terms that the predictor adjoint adds).
 //
 // Forward, at the face with normal e_d between L (low) and R (high):
 //   s = max(lambda*(pL), lambda*(pR)), G = (FL + FR)/2 - s (qR - qL)/2,
@@ -119,10 +128,11 @@ adj_face_project_kernel(const KArgs a, const double* __restrict__ lam, double* _
 //   flL = G - FL + Bm (into L's high face), flR = FR - G + Bm (into R's low
 //   face), each scaled by dt / h_d in the update u -= l flL / w ...
 // ---------------------------------------------------------------------------
-template <class PDE, int N, bool GRAD>
+template <class PDE, int N, bool OUT, bool GRAD>
 __global__ void __launch_bounds__(256)
 adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const double* __restrict__ clock,
-                   const double* __restrict__ A, double* __restrict__ B, double* __restrict__ gparams) {
+                   const double* __restrict__ A, const double* __restrict__ tq, int tq_face,
+                   double* __restrict__ B, double* __restrict__ gp_out) {
   using G = Geo<PDE, N>;
   using GR = GeoAdjR<PDE, N>;
   constexpr int F = G::F, NV = G::NV, NP = G::NP, DIM = G::DIM;
@@ -174,7 +184,7 @@ adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const doubl
 #pragma unroll
       for (int v = 0; v < NV; ++v) qz[v] = 0.0;
       const double sL = PDE::max_eigen(qz, pL, a.pde, d), sR = PDE::max_eigen(qz, pR, a.pde, d);
-      if constexpr (!GRAD) {
+      if constexpr (OUT) {
         const double s = fmax(sL, sR);
         double ld[NV], lF[NV], out[NV];
 #pragma unroll
@@ -203,9 +213,10 @@ adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const doubl
         double* o = B + ((c * (2 * DIM) + face) * NV) * F + f;
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v * F] = out[v];
-      } else {
-        const double* tL = B + ((cL * (2 * DIM) + 2 * d + 1) * NV) * F + f;
-        const double* tR = B + ((cR * (2 * DIM) + 2 * d + 0) * NV) * F + f;
+      }
+      if constexpr (GRAD) {
+        const double* tL = tq + (cL * (2 * DIM) + 2 * d + 1) * tq_face + f;
+        const double* tR = tq + (cR * (2 * DIM) + 2 * d + 0) * tq_face + f;
         double jump[NV], ls = 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -243,7 +254,8 @@ adj_rusanov_kernel(const KArgs a, const double* __restrict__ params, const doubl
       if (c < a.ncells) {
         double s = 0.0;
         for (int i = 0; i < TPF; ++i) s += contrib[(c2 * TPF + i) * NPX + p];
-        gparams[c * NP + p] += s;
+        if constexpr (OUT) gp_out[c * NP + p] = s;
+        else gp_out[c * NP + p] += s;
       }
     }
   }
@@ -285,7 +297,8 @@ template <class PDE, int N>
 __global__ void __launch_bounds__((GeoAdjL<PDE, N>::BLOCK), (GeoAdjL<PDE, N>::MIN_WAVES))
 adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ params,
                        const double* __restrict__ clock, double* __restrict__ lam,
-                       double* __restrict__ gparams, double* __restrict__ hat) {
+                       double* __restrict__ gparams, double* __restrict__ hat,
+                       const double* __restrict__ gface) {
   using G = Geo<PDE, N>;
   using C = Chan<PDE>;
   using GA = GeoAdjL<PDE, N>;
@@ -398,24 +411,26 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
       for (int v = 0; v < NV; ++v) tseed[v] += l * h[v * F];
     }
 
-  // ---- face traces of qbar = t into hat (for the Rusanov parameter derivative) ----
-  Op::sync();  // the forward sweep's last read-backs are done
+  // ---- face traces of qbar = t into hat (for the Rusanov parameter
+  // derivative; a kept step's are the forward step's own) ----
+  if (NP > 0 && !keep) {
+    Op::sync();  // the forward sweep's last read-backs are done
 #pragma unroll
-  for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
-  Op::sync();  // also: every read of hat above is done
-  Op::template cell_tasks<2 * DIM * NV * F>(tid, [&](int c2, int it) {
-    const int f = it % F, v = (it / F) % NV, face = it / (F * NV);
-    const int d = face >> 1, side = face & 1;
-    const long long tcell = cell0 + c2;
-    if (tcell >= a.ncells) return;
-    const double* rows = lds + c2 * GA::CELL_ELEMS;
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < n; ++m)
-      acc += (side ? T::l1(m) : T::l0(m)) * rows[v * S + face_line_node<DIM, n>(d, f, m)];
-    hat[tcell * (2 * DIM * NV * F) + (face * NV + v) * F + f] = acc;
-  });
-  Op::sync();
+    for (int v = 0; v < NV; ++v) mine[v * S + k] = t[v];
+    Op::sync();  // also: every read of hat above is done
+    Op::template cell_tasks<DIM * NV * F>(tid, [&](int c2, int it) {
+      const int f = it % F, v = (it / F) % NV, d = it / (F * NV);
+      const long long tcell = cell0 + c2;
+      if (tcell >= a.ncells) return;
+      const int st = face_line_node<DIM, n>(d, 0, 1) - face_line_node<DIM, n>(d, 0, 0);
+      double e0, e1;
+      line_ends<double, n>(lds + c2 * GA::CELL_ELEMS + v * S + face_line_node<DIM, n>(d, f, 0), st, e0, e1);
+      double* h = hat + tcell * (2 * DIM * NV * F) + v * F + f;
+      h[(2 * d) * NV * F] = e0;
+      h[(2 * d + 1) * NV * F] = e1;
+    });
+    Op::sync();
+  }
 
   // ---- volume term: mu_0 = dt L^T lam + E^T hat; parameter term at qbar ----
   double nu[NV], mu[NV], gp[NPX], lu[NV];
@@ -470,7 +485,9 @@ adj_predict_lin_kernel(const KArgs a, const double* __restrict__ Q, const double
     if (k < NP && active) {
       double s = 0.0;
       for (int i = 0; i < S; ++i) s += mine[i * NP + k];
-      gparams[cell * NP + k] += s;
+      double g = gparams[cell * NP + k] + s;
+      if (gface) g += gface[cell * NP + k];  // the face terms after the volume terms
+      gparams[cell * NP + k] = g;
     }
   }
 }
@@ -484,8 +501,13 @@ struct AdjLaunch {
   static hipError_t run(const KArgs& a0, const double* Q, const double* params, const double* clock,
                         double* lam, double* gparams, double* work, hipStream_t st) {
     constexpr long long face_elems = 2LL * G::DIM * G::NV * G::F;
+    constexpr int NP = G::NP;
     double* A = work;
     double* B = work + a0.ncells * face_elems;
+    // kept step: its face traces of qbar follow the keep buffer's node slots
+    const bool kept = a0.keep != nullptr;
+    const double* tq = kept ? a0.keep + a0.ncells * (long long)(KeepGeo<PDE, N>::SLOTS * G::S) : B;
+    double* gface = kept && NP > 0 ? work + 2 * a0.ncells * face_elems : nullptr;
     KArgs a = a0;
     using GPj = GeoAdjP<PDE, N>;
     hipLaunchKernelGGL((adj_face_project_kernel<PDE, N>), dim3((unsigned)((a0.ncells + GPj::CPB - 1) / GPj::CPB)),
@@ -493,21 +515,32 @@ struct AdjLaunch {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.nblocks = (int)((a0.ncells + GR::CPB - 1) / GR::CPB);
-    hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, false>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
-                       a, params, clock, A, B, gparams);
+    bool fused = false;
+    if constexpr (NP > 0) {
+      if (kept) {
+        hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, true, true>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
+                           a, params, clock, A, tq, (int)(2 * G::NV * G::F), B, gface);
+        fused = true;
+      }
+    }
+    if (!fused)
+      hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, true, false>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
+                         a, params, clock, A, nullptr, 0, B, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     KArgs ap = a0;
     using GL = GeoAdjL<PDE, N>;
     ap.nblocks = (int)((a0.ncells + GL::CPB - 1) / GL::CPB);
     hipLaunchKernelGGL((adj_predict_lin_kernel<PDE, N>), dim3(ap.nblocks), dim3(GL::BLOCK), 0, st, ap, Q,
-                       params, clock, lam, gparams, B);
+                       params, clock, lam, gparams, B, gface);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (G::NP > 0) {
-      hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, true>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
-                         a, params, clock, A, B, gparams);
-      e = hipGetLastError();
+    if constexpr (NP > 0) {
+      if (!kept) {
+        hipLaunchKernelGGL((adj_rusanov_kernel<PDE, N, false, true>), dim3(a.nblocks), dim3(GR::BLOCK), 0, st,
+                           a, params, clock, A, tq, (int)(G::NV * G::F), nullptr, gparams);
+        e = hipGetLastError();
+      }
     }
     return e;
   }

@@ -25,6 +25,7 @@ struct adg_ctx {
   double* traces = nullptr;  // [C][2 dim][2][nv][F]
   double* traces2 = nullptr; // the second trace array of fused runs (adg_run_reserve)
   size_t trace_elems = 0;
+  size_t trace_alloc = 0;    // doubles per trace array: also the adjoint's C x np face terms
   void* red = nullptr;       // reduction slots
   size_t red_bytes = 0;
   SourceDev* d_src = nullptr;
@@ -390,7 +391,8 @@ adg_status create_ctx(const adg_config* cfg, const char* source, adg_ctx** out) 
     }
   }
   x->trace_elems = (size_t)C * 2 * c.dim * 2 * x->nv * x->F;
-  e = hipMalloc((void**)&x->traces, x->trace_elems * sizeof(double));
+  x->trace_alloc = x->trace_elems + (ks && ks->adjoint ? (size_t)C * np : 0);
+  e = hipMalloc((void**)&x->traces, x->trace_alloc * sizeof(double));
   if (e != hipSuccess) {
     user_module_destroy(um);
     delete x;
@@ -505,7 +507,7 @@ adg_status adg_query(const adg_ctx* ctx, adg_info* info) {
   info->ncells = ctx->C;
   info->state_elems = ctx->C * ctx->nv * ctx->S;
   info->trace_elems = ctx->trace_elems;
-  info->workspace_bytes = ctx->trace_elems * sizeof(double) * (ctx->traces2 ? 2 : 1) + ctx->red_bytes +
+  info->workspace_bytes = ctx->trace_alloc * sizeof(double) * (ctx->traces2 ? 2 : 1) + ctx->red_bytes +
                           ctx->lim_bytes;
   return ADG_OK;
 }
@@ -850,18 +852,28 @@ adg_status adg_run_reserve(adg_ctx* ctx) {
     return fail(ADG_ERR_STATE, "current HIP device differs from the context's device");
   if (!run_fuses(ctx) || ctx->traces2) return ADG_OK;
   double* p = nullptr;
-  hipError_t e = hipMalloc((void**)&p, ctx->trace_elems * sizeof(double));
+  hipError_t e = hipMalloc((void**)&p, ctx->trace_alloc * sizeof(double));
   if (e != hipSuccess) return fail(ADG_ERR_NOMEM, std::string("second trace array: ") + hipGetErrorString(e));
   ctx->traces2 = p;
   return ADG_OK;
 }
 
+// a step's keep buffer: the per-node slots, then the step's face traces
+static long long keep_elems(const adg_ctx* ctx) {
+  return ctx->C * (long long)ctx->S * ctx->ks->keep_slots + (long long)ctx->trace_elems;
+}
+static double* keep_traces(const adg_ctx* ctx, double* keep) {
+  return keep + ctx->C * (long long)ctx->S * ctx->ks->keep_slots;
+}
+
 // nsteps fixed-dt steps (fused corrector/predictor kernels where built and
 // nsteps > 1; the caller has checked adg_run_reserve then).  rec_out: the
 // receiver samples after every step, or null.  keeps: step n's kept
-// quantities for its adjoint at keeps + n keep_n, or null.
+// quantities for its adjoint at keeps + n keep_n, or null; step n's traces
+// are then those of its keep buffer.
 static hipError_t run_steps(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
                             double* rec_out, double* keeps, long long keep_n, hipStream_t s) {
+  auto ktr = [&](int n) { return keep_traces(ctx, keeps + n * keep_n); };
   const long long rec_stride = (long long)ctx->nrec * ctx->nv;
   auto sample = [&](int n) -> hipError_t {
     if (!rec_out) return hipSuccess;
@@ -873,13 +885,17 @@ static hipError_t run_steps(adg_ctx* ctx, double* Q, const double* params, doubl
     if (!keeps) return k_predict(ctx, Q, params, clock, Q, ctx->traces, 0, s);
     KArgs a = ctx->args;
     a.keep = keeps + n * keep_n;
-    return ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
+    return ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, ktr(n), 0, s);
+  };
+  auto correct = [&](int n) -> hipError_t {  // the (unfused) corrector of step n
+    if (!keeps) return k_correct(ctx, Q, params, clock, 0, s);
+    return ctx->ks->correct(ctx->args, Q, params, clock, ktr(n), 0, s);
   };
   hipError_t e = hipSuccess;
   if (!(run_fuses(ctx) && nsteps > 1)) {
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
       e = predict(n);
-      if (e == hipSuccess) e = k_correct(ctx, Q, params, clock, 0, s);
+      if (e == hipSuccess) e = correct(n);
       if (e == hipSuccess) e = sample(n);
     }
   } else {
@@ -889,12 +905,16 @@ static hipError_t run_steps(adg_ctx* ctx, double* Q, const double* params, doubl
     a.rec_w = ctx->d_rec_w;
     e = predict(0);  // predictor of the first step
     for (int n = 0; n + 1 < nsteps && e == hipSuccess; ++n) {
-      a.keep = keeps ? keeps + (n + 1) * keep_n : nullptr;  // the fused predictor is step n + 1's
-      e = ctx->ks->step_fused(a, ctx->cfg.precision, Q, params, clock, ctx->traces, ctx->traces2,
-                              rec_out ? rec_out + n * rec_stride : nullptr, s);
-      std::swap(ctx->traces, ctx->traces2);  // the newest traces are the workspace
+      double* rec = rec_out ? rec_out + n * rec_stride : nullptr;
+      if (keeps) {
+        a.keep = keeps + (n + 1) * keep_n;  // the fused predictor is step n + 1's
+        e = ctx->ks->step_fused(a, ctx->cfg.precision, Q, params, clock, ktr(n), ktr(n + 1), rec, s);
+      } else {
+        e = ctx->ks->step_fused(a, ctx->cfg.precision, Q, params, clock, ctx->traces, ctx->traces2, rec, s);
+        std::swap(ctx->traces, ctx->traces2);  // the newest traces are the workspace
+      }
     }
-    if (e == hipSuccess) e = k_correct(ctx, Q, params, clock, 0, s);  // corrector of the last step
+    if (e == hipSuccess) e = correct(nsteps - 1);  // corrector of the last step
     if (e == hipSuccess) e = sample(nsteps - 1);
   }
   ctx->traces_ready = false;
@@ -965,7 +985,7 @@ adg_status adg_keep_size(const adg_ctx* ctx, long long* n) {
   if (!ctx || !n) return fail(ADG_ERR_INVALID_ARG, "null context or output");
   if (ctx->user || !ctx->ks || !ctx->ks->adjoint || ctx->ks->keep_slots <= 0)
     return fail(ADG_ERR_UNSUPPORTED, "the adjoint is built for the PDEs linear in Q (elastic, advection)");
-  *n = ctx->C * (long long)ctx->S * ctx->ks->keep_slots;
+  *n = keep_elems(ctx);
   return ADG_OK;
 }
 
@@ -979,10 +999,10 @@ adg_status adg_step_keep(adg_ctx* ctx, double* Q, const double* params, double* 
   hipStream_t s = (hipStream_t)stream;
   KArgs a = ctx->args;
   a.keep = keep;
-  hipError_t e = ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, ctx->traces, 0, s);
+  double* tr = keep_traces(ctx, keep);  // the step's traces stay in its keep buffer
+  hipError_t e = ctx->ks->predict(a, ctx->cfg.precision, Q, params, clock, Q, tr, 0, s);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
-  ctx->traces_ready = true;
-  e = k_correct(ctx, Q, params, clock, 0, s);
+  e = ctx->ks->correct(ctx->args, Q, params, clock, tr, 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
   return ADG_OK;
 }
@@ -998,7 +1018,7 @@ adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* c
   if (nsteps == 0) return ADG_OK;
   if (run_fuses(ctx) && nsteps > 1 && !ctx->traces2)
     return fail(ADG_ERR_STATE, "adg_run_keep needs adg_run_reserve first (fused steps)");
-  const long long keep_n = ctx->C * (long long)ctx->S * ctx->ks->keep_slots;
+  const long long keep_n = keep_elems(ctx);
   hipError_t e = run_steps(ctx, Q, params, clock, nsteps, nullptr, keeps, keep_n, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "run launch");
   return ADG_OK;

@@ -1536,9 +1536,28 @@ __device__ inline void lin_source_weights(const KArgs& a, int s, double t_n, dou
   }
 }
 
-// Slots per node of KArgs::keep: for k < n (the adjoint's most Picard
-// iterations), the channels of Horner's iterate t_{k+1} whose gradient the
-// non-conservative product reads; then all of t_0 = qbar.
+// The values at both ends of a line of n nodes x[m st]: e0 = sum_m l0(m) x,
+// e1 = sum_m l1(m) x (the linear predictor's face traces and, in the same
+// arithmetic, the adjoint's).
+template <class R, int n>
+__device__ __forceinline__ void line_ends(const R* __restrict__ x, int st, R& e0, R& e1) {
+  using T = CT<R, n>;
+  R s0 = R(0), s1 = R(0);
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    const R y = x[m * st];
+    s0 += T::l0(m) * y;
+    s1 += T::l1(m) * y;
+  }
+  e0 = s0;
+  e1 = s1;
+}
+
+// Slots per node of KArgs::keep ([C][SLOTS][S] doubles): for k < n (the
+// adjoint's most Picard iterations), the channels of Horner's iterate
+// t_{k+1} whose gradient the non-conservative product reads; then all of
+// t_0 = qbar.  A step's keep buffer continues with its face traces (the
+// trace array's layout), which the step's predictor writes there.
 template <class PDE, int N>
 struct KeepGeo {
   static constexpr int NGR = Chan<PDE>::ngrad(), IMAX = N + 1;
@@ -1653,17 +1672,7 @@ __device__ __forceinline__ void lin_predict_block(const KArgs& a, R* lds, double
 #pragma unroll
     for (int p = 0; p < NP; ++p) Pt[p] = R(params[tcell * NP + p]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R s0 = R(0), s1 = R(0);
-#pragma unroll
-      for (int m = 0; m < n; ++m) {
-        const R x = rows[v * S + m * st];
-        s0 += T::l0(m) * x;
-        s1 += T::l1(m) * x;
-      }
-      e0[v] = s0;
-      e1[v] = s1;
-    }
+    for (int v = 0; v < NV; ++v) line_ends<R, n>(rows + v * S, st, e0[v], e1[v]);
     double* tr = traces + ((tcell * (2 * DIM) + 2 * d) * 2) * (long long)NV * F;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

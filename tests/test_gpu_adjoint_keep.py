@@ -1,9 +1,13 @@
 """The adjoint step from a kept forward step (adg_step_keep + adg_step_adjoint_kept).
 
-The kept path must give what adg_step_adjoint gives from u^n (the same
-arithmetic on the same values: compared bitwise, and against the oracle's
-discrete adjoint to 1e-12), and adg_step_keep must leave the forward step
-itself unchanged (bitwise the state of adg_step).  Cases: elasticity with
+The kept path must give what adg_step_adjoint gives from u^n, and the
+oracle's discrete adjoint to 1e-12; adg_step_keep must leave the forward
+step itself unchanged (bitwise the state of adg_step).  lam is compared
+bitwise (the same arithmetic on the same values).  The parameter gradient
+is compared to rounding: the kept path takes the Rusanov flux's two
+transposes in one kernel, whose compiled products may round differently
+from those of the two separate kernels (measured: at most 1.8e-15 against
+entries of order 1).  Cases: elasticity with
 per-cell material at N = 1..4 (ragged last blocks), fewer Picard iterations
 than N + 1, a point source, advection in 2-D and 3-D; error paths.
 """
@@ -17,6 +21,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+GRAD_ROUNDING = 1e-14  # kept vs state path, relative to the largest entry
+
+
+def same_gradient(ga, gb):
+    return ga is None and gb is None or np.abs(ga - gb).max() <= GRAD_ROUNDING * np.abs(ga).max()
 
 
 def say(*a):
@@ -76,8 +85,9 @@ def test_kept_adjoint_elastic(N, cells):
     s, P, params, u, lam, dt = elastic(cells, N, seed=40 + N)
     Q1, Q2, c1, c2, la, ga, lb, gb = both_paths(s, u, params, lam, dt)
     assert np.array_equal(Q1, Q2) and np.array_equal(c1, c2)
-    say(f"  kept vs state path: lam max |diff| {np.abs(la - lb).max():.1e}, grad {np.abs(ga - gb).max():.1e}")
-    assert np.array_equal(la, lb) and np.array_equal(ga, gb)
+    say(f"  kept vs state path: lam max |diff| {np.abs(la - lb).max():.1e}, grad {np.abs(ga - gb).max():.1e}"
+        f" (max |grad| {np.abs(ga).max():.2e})")
+    assert np.array_equal(la, lb) and same_gradient(ga, gb)
     lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.0, lam)
     e_l, e_g = rel_l2(lb, lam_o), rel_l2(gb[:, 1:], g_o[:, 1:])
     say(f"  vs oracle: rel L2 lam {e_l:.2e}, grad(cp, cs) {e_g:.2e}")
@@ -88,7 +98,7 @@ def test_kept_adjoint_fewer_picard_iterations():
     s, P, params, u, lam, dt = elastic((3, 2, 2), 3, seed=47, picard_iters=2)
     Q1, Q2, c1, c2, la, ga, lb, gb = both_paths(s, u, params, lam, dt)
     assert np.array_equal(Q1, Q2)
-    assert np.array_equal(la, lb) and np.array_equal(ga, gb)
+    assert np.array_equal(la, lb) and same_gradient(ga, gb)
     lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.0, lam)
     assert rel_l2(lb, lam_o) <= TOL and rel_l2(gb[:, 1:], g_o[:, 1:]) <= TOL
 
@@ -99,7 +109,7 @@ def test_kept_adjoint_point_source():
     u *= 1e-3
     Q1, Q2, c1, c2, la, ga, lb, gb = both_paths(s, u, params, lam, dt, t=0.05)
     assert np.array_equal(Q1, Q2)
-    assert np.array_equal(la, lb) and np.array_equal(ga, gb)
+    assert np.array_equal(la, lb) and same_gradient(ga, gb)
     lam_o, g_o = O.step_adjoint(P, u, params, dt, 0.05, lam)
     e_l, e_g = rel_l2(lb, lam_o), rel_l2(gb[:, 1:], g_o[:, 1:])
     say(f"point source, kept: rel L2 lam {e_l:.2e}, grad {e_g:.2e}")
@@ -164,4 +174,11 @@ def test_run_keep_equals_step_keep(nsteps):
     say(f"run_keep nsteps={nsteps}: state max |diff| {float((Qa - Qb).abs().max()):.1e}")
     assert torch.equal(Qa, Qb) and torch.equal(ca, cb)
     assert torch.equal(torch.nan_to_num(ka, nan=1.5), torch.nan_to_num(kb, nan=1.5))
-    assert not torch.isnan(kb).any()  # every slot written at picard_iters = N + 1
+    # every node slot is written at picard_iters = N + 1, and every state
+    # trace behind them (the linear step leaves the flux traces unwritten)
+    F = 4 * 4  # face nodes at N = 3
+    nodes = kn - s.ncells * 6 * 2 * 9 * F
+    assert nodes > 0 and nodes % (s.ncells * P.S) == 0
+    assert not torch.isnan(kb[:, :nodes]).any()
+    tr = kb[:, nodes:].reshape(nsteps, s.ncells, 6, 2, 9, F)
+    assert not torch.isnan(tr[:, :, :, 0]).any() and torch.isnan(tr[:, :, :, 1]).all()
