@@ -462,10 +462,11 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
  *   *n doubles; overwritten).  Its face traces go to the keep buffer, not
  *   to the context's workspace (a following adg_correct needs a new
  *   adg_predict).
- * adg_run_keep: adg_run of nsteps steps (no receivers; fused corrector/
- *   predictor kernels where built, after adg_run_reserve) that writes step
- *   n's keep buffer at keeps + n *n (device, caller-owned, nsteps *n
- *   doubles); the states and buffers equal those of nsteps adg_step_keep.
+ * adg_run_keep: adg_run of nsteps steps (rec_out as there; fused
+ *   corrector/predictor kernels where built, after adg_run_reserve) that
+ *   writes step n's keep buffer at keeps + n *n (device, caller-owned,
+ *   nsteps *n doubles); the states and buffers equal those of nsteps
+ *   adg_step_keep, the samples those of adg_run.
  * adg_step_adjoint_kept: adg_step_adjoint of that step from its keep buffer
  *   (device, read only) instead of Q; lam, gparams, clock as there.  lam
  *   equals adg_step_adjoint's (the same arithmetic on the same values);
@@ -477,8 +478,8 @@ adg_status adg_step_adjoint(adg_ctx* ctx, const double* Q, const double* params,
 adg_status adg_keep_size(const adg_ctx* ctx, long long* n);
 adg_status adg_step_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, double* keep,
                          void* stream);
-adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps, double* keeps,
-                        void* stream);
+adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                        double* rec_out, double* keeps, void* stream);
 adg_status adg_step_adjoint_kept(adg_ctx* ctx, const double* params, const double* clock,
                                  const double* keep, double* lam, double* gparams, void* stream);
 

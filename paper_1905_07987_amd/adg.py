@@ -97,7 +97,7 @@ def lib():
         L.adg_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_keep_size.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.adg_step_keep.argtypes = [vp, vp, vp, vp, vp, vp]
-        L.adg_run_keep.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+        L.adg_run_keep.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.adg_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.adg_sample_receivers_adjoint.argtypes = [vp, vp, vp, vp]
         L.adg_limiter_tables.argtypes = [C.c_int, dp, dp, dp]
@@ -385,14 +385,17 @@ class Solver:
                                    self._params(params), self._dev(clock, (2,), torch.float64, "clock"),
                                    self._dev(keep, (self.keep_size(),), torch.float64, "keep"), _stream(stream)))
 
-    def run_keep(self, Q, params, clock, nsteps: int, keeps, stream=None):
-        """run() of nsteps steps (no receivers) that writes step n's keep buffer
-        into keeps[n] (keeps: [nsteps, keep_size()] float64)."""
+    def run_keep(self, Q, params, clock, nsteps: int, keeps, rec_out=None, stream=None):
+        """run() of nsteps steps that also writes step n's keep buffer into
+        keeps[n] (keeps: [nsteps, keep_size()] float64); rec_out as in run()."""
         import torch
         if not self._run_ready:
             self.reserve_run()
+        ro = None
+        if rec_out is not None:
+            ro = self._dev(rec_out, (nsteps, self.nrec, self.nvar), torch.float64, "rec_out")
         _check(lib().adg_run_keep(self._ctx, self._dev(Q, self.state_shape, torch.float64, "Q"), self._params(params),
-                                  self._dev(clock, (2,), torch.float64, "clock"), int(nsteps),
+                                  self._dev(clock, (2,), torch.float64, "clock"), int(nsteps), ro,
                                   self._dev(keeps, (nsteps, self.keep_size()), torch.float64, "keeps"),
                                   _stream(stream)))
 

@@ -9,8 +9,13 @@ time-step checkpointing: the forward pass keeps the state every ``every``
 steps; the backward pass recomputes one segment from its checkpoint with
 ``adg_run_keep``, which keeps per step what that step's adjoint reads of
 its forward predictor, then runs the adjoint steps of that segment
-backwards from those buffers.  Memory: ceil(steps / every) checkpoints plus
-``every`` keep buffers (``Solver.keep_size()`` doubles each).
+backwards from those buffers.  The forward pass runs its last segment with
+``adg_run_keep`` already, so that the backward pass starts without a
+recomputation; the segments are laid out from the end (the first one takes
+the remainder of ``steps`` / ``every``), so that this kept segment is a
+whole one.  Memory: ceil(steps / every) checkpoints plus ``every``
+keep buffers (``Solver.keep_size()`` doubles each), the latter held from
+the forward pass on.
 
 Gradients flow to ``u0`` and ``params``.  The step size is not
 differentiated (it is an input, as in a run with a frozen dt).  Available
@@ -23,6 +28,13 @@ import math
 import torch
 
 from . import adg
+
+
+def _segments(steps: int, every: int):
+    """Checkpoint segment bounds [0, b_1, ..., steps]: segments of ``every``
+    steps counted from the end, the first one the remainder."""
+    nseg = math.ceil(steps / every)
+    return [0] + [steps - (nseg - k) * every for k in range(1, nseg)] + [steps]
 
 
 def _time_nodes(t0: float, dt: float, steps: int):
@@ -48,14 +60,23 @@ class _SeismogramRun(torch.autograd.Function):
         clock = torch.tensor([t0, dt], dtype=torch.float64, device=Q.device)
         out = torch.empty((steps, solver.nrec, solver.nvar), dtype=torch.float64, device=Q.device)
         ckpts = [Q.clone()]
-        for n0 in range(0, steps, every):
+        last_keeps = None
+        bounds = _segments(steps, every)
+        nseg = len(bounds) - 1
+        for seg in range(nseg):
             # one checkpoint segment (fused corrector/predictor kernels where built)
-            n1 = min(steps, n0 + every)
-            solver.run(Q, prm, clock, n1 - n0, out[n0:n1])
-            if n1 < steps:
-                ckpts.append(Q.clone())
+            n0, n1 = bounds[seg], bounds[seg + 1]
+            if seg + 1 < nseg:
+                solver.run(Q, prm, clock, n1 - n0, out[n0:n1])
+                # (the last segment's start state is not needed: it is kept)
+                ckpts.append(Q.clone() if seg + 2 < nseg else None)
+            else:
+                # the last segment keeps what its adjoint steps read
+                last_keeps = torch.empty((n1 - n0, solver.keep_size()), dtype=torch.float64, device=Q.device)
+                solver.run_keep(Q, prm, clock, n1 - n0, last_keeps, out[n0:n1])
         ctx.solver, ctx.t0, ctx.dt, ctx.steps, ctx.every = solver, t0, dt, steps, every
         ctx.ckpts = ckpts
+        ctx.last_keeps = last_keeps
         ctx.prm = prm
         ctx.has_params = params is not None
         return out
@@ -63,6 +84,8 @@ class _SeismogramRun(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         s, dt, steps, every = ctx.solver, ctx.dt, ctx.steps, ctx.every
+        if ctx.ckpts is None:
+            raise RuntimeError("the checkpointed adjoint runs once per forward pass (it consumes its checkpoints)")
         prm = ctx.prm
         dev = ctx.ckpts[0].device
         gout = gout.detach().to(torch.float64).contiguous()
@@ -70,21 +93,29 @@ class _SeismogramRun(torch.autograd.Function):
         g = torch.zeros_like(prm) if (prm is not None and s.nparam > 0) else None
         ts = _time_nodes(ctx.t0, dt, steps)
         clocks = torch.tensor([[ts[n], dt] for n in range(steps)], dtype=torch.float64, device=dev)
-        nseg = math.ceil(steps / every)
+        bounds = _segments(steps, every)
+        nseg = len(bounds) - 1
         keep_n = s.keep_size()
         for seg in reversed(range(nseg)):
-            n0, n1 = seg * every, min(steps, (seg + 1) * every)
-            # recompute steps n0 .. n1-1 from the checkpoint, keeping what
-            # each step's adjoint reads
-            Q = ctx.ckpts[seg].clone()
-            clock = clocks[n0].clone()
-            keeps = torch.empty((n1 - n0, keep_n), dtype=torch.float64, device=dev)
-            s.run_keep(Q, prm, clock, n1 - n0, keeps)
+            n0, n1 = bounds[seg], bounds[seg + 1]
+            if seg == nseg - 1 and ctx.last_keeps is not None:
+                keeps, ctx.last_keeps = ctx.last_keeps, None  # kept by the forward pass
+            else:
+                # recompute steps n0 .. n1-1 from the checkpoint (advanced in
+                # place: it is not needed again), keeping what each step's
+                # adjoint reads
+                Q = ctx.ckpts[seg]
+                clock = clocks[n0].clone()
+                keeps = torch.empty((n1 - n0, keep_n), dtype=torch.float64, device=dev)
+                s.run_keep(Q, prm, clock, n1 - n0, keeps)
+                del Q
+            ctx.ckpts[seg] = None
             for n in reversed(range(n0, n1)):
                 # out[n] samples u^{n+1}; the step n maps u^n to u^{n+1}
                 s.sample_receivers_adjoint(gout[n], lam)
                 s.step_adjoint_kept(prm, clocks[n], keeps[n - n0], lam, g)
-            del keeps, Q
+            del keeps
+        ctx.ckpts = None
         gu0 = lam
         gp = g if ctx.has_params else None
         return gu0, gp, None, None, None, None, None

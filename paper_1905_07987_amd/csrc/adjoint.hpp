@@ -61,7 +61,7 @@ struct GeoAdjR {
   using G = Geo<PDE, N>;
   static constexpr int TPF = 2 * G::DIM * G::F;  // tasks per cell
   static constexpr int CPB = TPF >= 256 ? 1 : 256 / TPF;
-  static constexpr int BLOCK = 256;
+  static constexpr int BLOCK = cmin(256, (CPB * TPF + 63) / 64 * 64);  // no idle wave
 };
 
 // face node f of the faces normal to d, position m along d -> node index

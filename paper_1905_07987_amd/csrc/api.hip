@@ -159,19 +159,25 @@ __global__ void sample_kernel(const double* __restrict__ Q, const long long* __r
 }
 
 // lam[c_r][v][k] += Phi_k(xi_r) lamrec[r][v], the transpose of sample_kernel.
-// One block walks the receivers in order and thread i always owns the same
-// (v, k), so receivers that share a cell add in a fixed order.
+// One thread per (receiver, quantity, node); the thread of the first
+// receiver in a cell adds, in receiver order, the terms of every receiver of
+// that cell (a fixed order of the sums; the others return).
 __global__ void sample_adjoint_kernel(const double* __restrict__ lamrec,
                                       const long long* __restrict__ rcell,
                                       const double* __restrict__ rw, double* __restrict__ lam,
                                       int nrec, int nv, int S) {
-  for (int r = 0; r < nrec; ++r) {
-    const long long c = rcell[r];
-    for (int i = threadIdx.x; i < nv * S; i += blockDim.x) {
-      const int v = i / S, k = i - v * S;
-      lam[(c * nv + v) * S + k] += rw[(long long)r * S + k] * lamrec[(long long)r * nv + v];
-    }
-  }
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)nrec * nv * S) return;
+  const int r = (int)(i / ((long long)nv * S));
+  const int j = (int)(i - (long long)r * nv * S), v = j / S, k = j - v * S;
+  const long long c = rcell[r];
+  for (int q = 0; q < r; ++q)
+    if (rcell[q] == c) return;  // an earlier receiver's thread owns this cell
+  double* x = lam + (c * nv + v) * S + k;
+  double acc = *x;
+  for (int q = r; q < nrec; ++q)
+    if (rcell[q] == c) acc += rw[(long long)q * S + k] * lamrec[(long long)q * nv + v];
+  *x = acc;
 }
 
 }  // namespace
@@ -942,7 +948,9 @@ adg_status adg_sample_receivers_adjoint(adg_ctx* ctx, const double* lamrec, doub
   if (st) return st;
   if (ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
   if (!lamrec) return fail(ADG_ERR_INVALID_ARG, "null receiver adjoint");
-  hipLaunchKernelGGL(sample_adjoint_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, lamrec,
+  const long long nthreads = (long long)ctx->nrec * ctx->nv * ctx->S;
+  hipLaunchKernelGGL(sample_adjoint_kernel, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, lamrec,
                      ctx->d_rec_cell, ctx->d_rec_w, lam, ctx->nrec, ctx->nv, ctx->S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "sample adjoint launch");
@@ -1007,19 +1015,20 @@ adg_status adg_step_keep(adg_ctx* ctx, double* Q, const double* params, double* 
   return ADG_OK;
 }
 
-adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps, double* keeps,
-                        void* stream) {
+adg_status adg_run_keep(adg_ctx* ctx, double* Q, const double* params, double* clock, int nsteps,
+                        double* rec_out, double* keeps, void* stream) {
   adg_status st = check_state(ctx, Q, params);
   if (st) return st;
   if (!clock) return fail(ADG_ERR_INVALID_ARG, "null clock");
   if (nsteps < 0) return fail(ADG_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (rec_out && ctx->nrec == 0) return fail(ADG_ERR_STATE, "no receivers set");
   st = check_keep(ctx, keeps);
   if (st) return st;
   if (nsteps == 0) return ADG_OK;
   if (run_fuses(ctx) && nsteps > 1 && !ctx->traces2)
     return fail(ADG_ERR_STATE, "adg_run_keep needs adg_run_reserve first (fused steps)");
   const long long keep_n = keep_elems(ctx);
-  hipError_t e = run_steps(ctx, Q, params, clock, nsteps, nullptr, keeps, keep_n, (hipStream_t)stream);
+  hipError_t e = run_steps(ctx, Q, params, clock, nsteps, rec_out, keeps, keep_n, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "run launch");
   return ADG_OK;
 }

@@ -217,6 +217,17 @@ def test_misfit_gradient_is_the_same_for_every_checkpoint_interval():
         assert J1 == res[0][0] and torch.equal(gu, res[0][1]) and torch.equal(gm, res[0][2])
 
 
+def test_checkpointed_adjoint_runs_once():
+    """The backward pass consumes its checkpoints and the forward pass's kept
+    last segment: a second backward through the same graph is an error, not
+    a wrong gradient."""
+    s, P, params, u0, dt, steps, rec, data, cellsr = misfit_case()
+    J, u, m = gpu_misfit(s, u0, params, dt, steps, data, cellsr, every=4)
+    J.backward(retain_graph=True)
+    with pytest.raises(RuntimeError, match="once per forward"):
+        J.backward()
+
+
 def test_misfit_gradient_finite_differences_on_gpu():
     """Central differences of the GPU misfit at the largest-gradient entries."""
     s, P, params, u0, dt, steps, rec, data, cellsr = misfit_case(seed=7)

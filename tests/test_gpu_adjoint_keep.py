@@ -157,9 +157,11 @@ def test_keep_error_paths():
 @pytest.mark.parametrize("nsteps", [1, 4])
 def test_run_keep_equals_step_keep(nsteps):
     """adg_run_keep (fused corrector/predictor kernels for nsteps > 1) writes
-    the same keep buffers and reaches the same state as nsteps adg_step_keep."""
+    the same keep buffers and reaches the same state as nsteps adg_step_keep,
+    and its receiver samples are adg_run's (two receivers share a cell)."""
     src = [dict(x=(700.0, 900.0, 400.0), w=[0.0] * 6 + [0.3, -0.2, 1.0], f0=5.0, t0=0.1, amp=1e7)]
     s, P, params, u, lam, dt = elastic((4, 3, 3), 3, seed=49, sources=src)
+    s.set_receivers(np.array([[300.0, 400.0, 200.0], [1700.0, 1100.0, 900.0], [320.0, 410.0, 260.0]]))
     u *= 1e-3
     prm = dev(params)
     kn = s.keep_size()
@@ -169,10 +171,16 @@ def test_run_keep_equals_step_keep(nsteps):
         s.step_keep(Qa, prm, ca, ka[n])
     Qb, cb = dev(u), dev([0.02, dt])
     kb = torch.full((nsteps, kn), float("nan"), dtype=torch.float64, device="cuda")
-    s.run_keep(Qb, prm, cb, nsteps, kb)
+    rb = torch.full((nsteps, 3, 9), float("nan"), dtype=torch.float64, device="cuda")
+    s.run_keep(Qb, prm, cb, nsteps, kb, rb)
+    # the samples are those of run()
+    Qc, cc = dev(u), dev([0.02, dt])
+    rc = torch.full((nsteps, 3, 9), float("nan"), dtype=torch.float64, device="cuda")
+    s.run(Qc, prm, cc, nsteps, rc)
     torch.cuda.synchronize()
     say(f"run_keep nsteps={nsteps}: state max |diff| {float((Qa - Qb).abs().max()):.1e}")
-    assert torch.equal(Qa, Qb) and torch.equal(ca, cb)
+    assert torch.equal(Qa, Qb) and torch.equal(ca, cb) and torch.equal(Qb, Qc)
+    assert torch.equal(rb, rc)
     assert torch.equal(torch.nan_to_num(ka, nan=1.5), torch.nan_to_num(kb, nan=1.5))
     # every node slot is written at picard_iters = N + 1, and every state
     # trace behind them (the linear step leaves the flux traces unwritten)

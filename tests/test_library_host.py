@@ -75,3 +75,16 @@ def test_bad_limiter_order_is_an_error():
     assert e.value.status == -1
     with pytest.raises(adg.AdgError):
         adg.limiter_tables(-1)
+
+
+def test_checkpoint_segments():
+    """The checkpointed adjoint's segments: whole segments of `every` steps
+    counted from the end (the forward pass keeps the last one), the first
+    one the remainder; they tile 0..steps."""
+    from paper_1905_07987_amd.autograd import _segments
+    for steps, every in [(200, 15), (6, 4), (6, 6), (6, 1), (7, 3), (1, 1), (5, 10), (30, 15)]:
+        b = _segments(steps, every)
+        lens = [b[i + 1] - b[i] for i in range(len(b) - 1)]
+        assert b[0] == 0 and b[-1] == steps and len(lens) == -(-steps // every)
+        assert all(0 < n <= every for n in lens) and all(n == every for n in lens[1:])
+    assert _segments(200, 15)[:3] == [0, 5, 20]
