@@ -172,7 +172,10 @@ typedef struct {
   int face_nodes;        /* n^(dim-1) */
   long long ncells;      /* C */
   long long state_elems; /* C * nvar * S */
-  size_t workspace_bytes; /* device bytes the context holds: face traces,
+  size_t workspace_bytes; /* device bytes the context holds: face traces
+                            (each trace array also holding C * nparam
+                            doubles for the adjoint where it is built; the
+                            second array once adg_run_reserve has run),
                             reduction slots, and the limiter workspace once
                             adg_limiter_reserve has run */
   size_t trace_elems;    /* C * 2 dim * 2 * nvar * face_nodes */

@@ -173,7 +173,9 @@ def test_run_needs_its_reserved_trace_array():
     assert L.adg_run_reserve(s._ctx) == 0 and L.adg_run_reserve(s._ctx) == 0
     info1 = adg.Info()
     assert L.adg_query(s._ctx, info1) == 0
-    assert info1.workspace_bytes - info0.workspace_bytes == info0.trace_elems * 8
+    # one more trace array, which (like the first) also holds the adjoint's
+    # per-cell face terms of the parameter gradient (ncells x nparam)
+    assert info1.workspace_bytes - info0.workspace_bytes == (info0.trace_elems + info0.ncells * info0.nparam) * 8
     assert L.adg_run(s._ctx, Q.data_ptr(), prm.data_ptr(), clock.data_ptr(), 3, None, None) == 0
     torch.cuda.synchronize()
     s.close()
