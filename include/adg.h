@@ -288,6 +288,7 @@ adg_status adg_read_clock_host(const double* clock, double* host, void* stream);
  * size).
  * Does not test for non-finite values: that is adg_check_admissible. */
 #define ADG_STEP_NEXT_DT 1
+#define ADG_STEP_REUSE_RANGES 2  /* adg_step_limited only (see there) */
 adg_status adg_step(adg_ctx* ctx, double* Q, const double* params, double* clock, int flags,
                     void* stream);
 
@@ -357,7 +358,7 @@ adg_status adg_correct(adg_ctx* ctx, double* Q, const double* params, double* cl
 
 /* Allocates the workspace of adg_step_limited on the context's device (a
  * copy of u^n and the FV face fluxes, 1 + 2 dim / (order + 1) state arrays,
- * plus 16 nvar + 10 bytes per cell, and the limiter tables), once; later
+ * plus 32 nvar + 10 bytes per cell, and the limiter tables), once; later
  * calls do nothing.  Synchronous; the step itself then allocates nothing.
  * Errors: INVALID_ARG (null context; limiter tables not constructible),
  * UNSUPPORTED where adg_step_limited is not built (not Euler, an order
@@ -398,6 +399,16 @@ adg_status adg_limiter_reserve(adg_ctx* ctx);
  * workspace comes from adg_limiter_reserve (STATE without it).  Calls on
  * one context must not overlap.  No allocation and no host synchronisation,
  * so the status values are not checked: the caller keeps them in 0..3.
+ * flags ADG_STEP_REUSE_RANGES: the caller's Q, status and sub_in are
+ * exactly what the previous adg_step_limited on this context left in Q,
+ * status and sub_out (a run of limited steps with nothing else touching
+ * them).  The call then takes the t^n range of every cell with status 0
+ * from the subcell averages the previous call computed for its candidate
+ * (which is that cell's u^n) instead of projecting u^n again, and stores
+ * its own candidate's ranges for the next call; results are bitwise those
+ * without the flag.  The stored ranges are used only if the previous call
+ * on the context set the flag too; a state changed in between with the
+ * flag set gives wrong ranges.
  * Errors: INVALID_ARG (null arrays, sub_in == sub_out, unknown flags),
  * UNSUPPORTED (not Euler, an order above the limit, inflow faces, run-time
  * PDEs), STATE (no workspace reserved), HIP (launches). */

@@ -21,6 +21,7 @@ FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 GUESS_CONSTANT, GUESS_CERK = 0, 1
 _GUESS_NAMES = {"constant": GUESS_CONSTANT, "cerk": GUESS_CERK}
 STEP_NEXT_DT = 1
+STEP_REUSE_RANGES = 2
 
 PDE_USER = 4
 _PDE_NAMES = {"euler": PDE_EULER, "elastic": PDE_ELASTIC, "advection": PDE_ADVECTION, "user": PDE_USER}
@@ -307,11 +308,15 @@ class Solver:
         self._limiter_ready = True
 
     def step_limited(self, Q, clock, sub_in, sub_out, status, counts=None, next_dt: bool = True,
-                     stream=None):
+                     reuse_ranges: bool = False, stream=None):
         """One step with the a-posteriori subcell limiter (Euler): Q, status
         (uint8 [ncells]) in place; sub_in / sub_out (subcell_shape) the FV
         data before and after the step (distinct tensors, swapped by the
-        caller each step); counts (int32 [3]) or None."""
+        caller each step); counts (int32 [3]) or None.  reuse_ranges: Q,
+        status and sub_in are what the previous step_limited left (a run of
+        limited steps); the t^n ranges of DG cells are then taken from that
+        step's candidate (ADG_STEP_REUSE_RANGES), with bitwise the same
+        results."""
         import torch
         if not self._limiter_ready:
             self.reserve_limiter()
@@ -322,7 +327,7 @@ class Solver:
             self._dev(sub_in, self.subcell_shape, torch.float64, "sub_in"),
             self._dev(sub_out, self.subcell_shape, torch.float64, "sub_out"),
             self._dev(status, (self.ncells,), torch.uint8, "status"), cnt,
-            STEP_NEXT_DT if next_dt else 0, _stream(stream)))
+            (STEP_NEXT_DT if next_dt else 0) | (STEP_REUSE_RANGES if reuse_ranges else 0), _stream(stream)))
 
     def check_admissible(self, Q, params, troubled, count, stream=None):
         import torch

@@ -98,6 +98,9 @@ struct LimWork {
   uint8_t* st_prev;   // [C]          status at the start of the step
   uint8_t* trb;       // [C]          troubled flags of this step
   double* lohi;       // [C][nv][2]   range of the subcell averages at t^n
+  double* lohi_next;  // [C][nv][2]   range of the candidate's subcell averages (detect)
+  int reuse;          // prepare takes lohi_next of DG cells (status 0) instead of projecting
+  int store_next;     // detect writes lohi_next
   int* fv_list;       // [C]
   int* y_list;        // [C]
   int* counters;      // [4]: troubled cells, FV cells, DG cells with FV faces

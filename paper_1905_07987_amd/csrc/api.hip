@@ -40,6 +40,7 @@ struct adg_ctx {
   LimWork lim{};
   void* lim_block = nullptr;
   size_t lim_bytes = 0;  // size of lim_block
+  bool lim_ranges_stored = false;  // the last adg_step_limited stored its candidate's ranges
   double* d_bc_state = nullptr;  // [6][2][nvar][F] outside traces of inflow faces
   void* scratch = nullptr;       // this device's copy of the static scratch array
 };
@@ -655,9 +656,9 @@ adg_status adg_limiter_reserve(adg_ctx* ctx) {
     // one allocation, each array on a 256-byte boundary
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t ntab = (size_t)3 * m * n;
-    const size_t sz[9] = {up(ntab * 8), up((size_t)C * nv * S * 8), up((size_t)C), up((size_t)C),
-                          up((size_t)C * nv * 2 * 8), up((size_t)C * 4), up((size_t)C * 4), up(4 * 4),
-                          up((size_t)C * 2 * ctx->dim * nv * ctx->F * 8)};
+    const size_t sz[10] = {up(ntab * 8), up((size_t)C * nv * S * 8), up((size_t)C), up((size_t)C),
+                           up((size_t)C * nv * 2 * 8), up((size_t)C * 4), up((size_t)C * 4), up(4 * 4),
+                           up((size_t)C * 2 * ctx->dim * nv * ctx->F * 8), up((size_t)C * nv * 2 * 8)};
     size_t total = 0;
     for (size_t b : sz) total += b;
     void* blk = nullptr;
@@ -682,8 +683,10 @@ adg_status adg_limiter_reserve(adg_ctx* ctx) {
     w.fv_list = (int*)p;        p += sz[5];
     w.y_list = (int*)p;         p += sz[6];
     w.counters = (int*)p;       p += sz[7];
-    w.gfv = (double*)p;
+    w.gfv = (double*)p;         p += sz[8];
+    w.lohi_next = (double*)p;
     ctx->lim_block = blk;
+    ctx->lim_ranges_stored = false;
     ctx->lim_bytes = total;
   }
   return ADG_OK;
@@ -702,19 +705,27 @@ adg_status adg_step_limited(adg_ctx* ctx, double* Q, double* clock, const double
   if (st) return st;
   if (!clock || !sub_in || !sub_out || !status) return fail(ADG_ERR_INVALID_ARG, "null argument");
   if (sub_in == sub_out) return fail(ADG_ERR_INVALID_ARG, "sub_in and sub_out must be different arrays");
-  if (flags & ~ADG_STEP_NEXT_DT) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
+  if (flags & ~(ADG_STEP_NEXT_DT | ADG_STEP_REUSE_RANGES)) return fail(ADG_ERR_INVALID_ARG, "unknown flags");
   if (!ctx->lim_block) return fail(ADG_ERR_STATE, "adg_step_limited needs adg_limiter_reserve first");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = ctx->ks->lim_before(ctx->args, Q, sub_in, status, ctx->lim, s);
+  // ranges of the previous call's candidate: taken only if that call stored
+  // them and this one says its state continues from there
+  const bool reuse_flag = (flags & ADG_STEP_REUSE_RANGES) != 0;
+  LimWork w = ctx->lim;
+  w.reuse = reuse_flag && ctx->lim_ranges_stored ? 1 : 0;
+  w.store_next = reuse_flag ? 1 : 0;
+  ctx->lim_ranges_stored = false;
+  hipError_t e = ctx->ks->lim_before(ctx->args, Q, sub_in, status, w, s);
   if (e != hipSuccess) return hip_fail(e, "limiter prepare launch");
   e = k_predict(ctx, Q, nullptr, clock, Q, ctx->traces, 0, s);
   if (e != hipSuccess) return hip_fail(e, "predict launch");
   ctx->traces_ready = true;
   e = k_correct(ctx, Q, nullptr, clock, 0, s);
   if (e != hipSuccess) return hip_fail(e, "correct launch");
-  e = ctx->ks->lim_after(ctx->args, Q, clock, ctx->traces, sub_in, sub_out, status, ctx->lim,
+  e = ctx->ks->lim_after(ctx->args, Q, clock, ctx->traces, sub_in, sub_out, status, w,
                          (flags & ADG_STEP_NEXT_DT) ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "limiter launch");
+  ctx->lim_ranges_stored = reuse_flag;
   if (counts) ADG_HIP(hipMemcpyAsync(counts, ctx->lim.counters, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   return ADG_OK;
 }

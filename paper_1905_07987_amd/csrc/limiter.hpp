@@ -223,7 +223,9 @@ __device__ __forceinline__ void lim_load_nodes(const double* __restrict__ Q, lon
 }
 
 // One wave per cell: u^n copied, status kept, range of the subcell
-// averages at t^n.  Block 0 clears the counters of the step.
+// averages at t^n (w.reuse: for a DG cell of status 0, whose u^n is the
+// previous step's candidate, the range that step's detect stored).  Block 0
+// clears the counters of the step.
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __restrict__ sub_in,
@@ -251,6 +253,13 @@ lim_prepare_kernel(const KArgs a, const double* __restrict__ Q, const double* __
   for (int v = 0; v < NV; ++v) {
     lo[v] = INFINITY;
     hi[v] = -INFINITY;
+  }
+  if (w.reuse && st == 0) {
+    if (lane < NV) {
+      w.lohi[(c * NV + lane) * 2] = w.lohi_next[(c * NV + lane) * 2];
+      w.lohi[(c * NV + lane) * 2 + 1] = w.lohi_next[(c * NV + lane) * 2 + 1];
+    }
+    return;
   }
   if (st >= 2) {
     for (int s = lane; s < NS; s += 64)
@@ -305,7 +314,9 @@ __device__ __forceinline__ void lim_load_ranges(const KArgs& a, const double* lo
   }
 }
 
-// One wave per cell: is the candidate troubled?
+// One wave per cell: is the candidate troubled?  (w.store_next: also the
+// range of the candidate's subcell averages, as prepare computes it, for
+// the next step's prepare.)
 template <class PDE, int N>
 __global__ void __launch_bounds__(256)
 lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) {
@@ -350,6 +361,30 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
       for (int v = 0; v < NV; ++v) {
         const double delta = fmax(1e-4, 1e-3 * (hi[v] - lo[v]));
         bad = bad || !(q[v] >= lo[v] - delta && q[v] <= hi[v] + delta);
+      }
+    }
+  }
+  if (w.store_next) {
+    double l2[NV], h2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      l2[v] = INFINITY;
+      h2[v] = -INFINITY;
+    }
+    if (lane < GW::LAST)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+          l2[v] = fmin(l2[v], qv[v][j]);
+          h2[v] = fmax(h2[v], qv[v][j]);
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double l = lim_wave_min(l2[v]), h = lim_wave_max(h2[v]);
+      if (lane == 0) {
+        w.lohi_next[(c * NV + v) * 2] = l;
+        w.lohi_next[(c * NV + v) * 2 + 1] = h;
       }
     }
   }

@@ -170,6 +170,38 @@ def test_planted_bad_state_and_status_stencil():
     s.close()
 
 
+@pytest.mark.parametrize("dim,cells", [(3, [12, 12, 12]), (2, [24, 20])])
+def test_reused_ranges_give_bitwise_the_same_run(dim, cells):
+    """A run of limited steps that takes its DG cells' t^n subcell ranges from
+    the previous step's candidate (ADG_STEP_REUSE_RANGES) is bitwise the run
+    that projects every cell each step: state, statuses, FV data, counts and
+    clock after every step (min and max of the same subcell averages)."""
+    say(f"limiter reused ranges {dim}-D {cells}")
+    P, s, Q, sub, st = blast_case(dim, 3, cells, [W] * (2 * dim), seed=13, radius=0.3)
+    runs = []
+    for reuse in (False, True):
+        Qg, sin, stg = dev(Q), dev(sub), dev(st, torch.uint8)
+        sout = torch.zeros_like(sin)
+        counts = torch.zeros(3, dtype=torch.int32, device="cuda")
+        clock = torch.zeros(2, dtype=torch.float64, device="cuda")
+        s.stable_dt(Qg, None, clock)
+        hist = []
+        for k in range(8):
+            s.step_limited(Qg, clock, sin, sout, stg, counts, next_dt=True, reuse_ranges=reuse)
+            sin, sout = sout, sin
+            fvm = stg >= 2
+            hist.append((Qg.clone(), stg.clone(), torch.where(fvm[:, None, None], sin, 0.0), counts.clone(),
+                         clock.clone()))
+        torch.cuda.synchronize()
+        runs.append(hist)
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert all(torch.equal(x, y) for x, y in zip(a, b)), f"step {k}"
+    c = runs[1][-1][3].cpu().tolist()
+    say(f"  8 steps bitwise equal, counts at the end {c}")
+    assert c[1] > 0 and c[2] > 0  # FV cells and DG cells with an FV face took part
+    s.close()
+
+
 def test_reflecting_box_conserves_at_a_larger_size():
     say("limiter conservation 3-D 12^3 N=3")
     cells = [12, 12, 12]
@@ -229,6 +261,10 @@ def test_limiter_errors():
     assert adg.lib().adg_step_limited(*args) == -6
     assert adg.lib().adg_limiter_reserve(s._ctx) == 0 and adg.lib().adg_limiter_reserve(s._ctx) == 0
     assert adg.lib().adg_step_limited(*args) == 0
+    # flags: unknown bits are INVALID_ARG; the range reuse is a limited-step flag only
+    bad = args[:7] + (4,) + args[8:]
+    assert adg.lib().adg_step_limited(*bad) == -1
+    assert adg.lib().adg_step(s._ctx, Q.data_ptr(), None, clk.data_ptr(), 2, None) == -1
     torch.cuda.synchronize()
     s.close()
     if adg.max_order("euler", 3) >= 4:
