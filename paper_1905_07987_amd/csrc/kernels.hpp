@@ -1752,6 +1752,26 @@ struct GeoB {
   static_assert(BLOCK >= 64 && BLOCK <= 1024, "block must hold one full wave");
 };
 
+// First cell of the corrector's logical block lb (CPB consecutive cells).
+// In 3-D meshes whose extents are multiples of 8 the blocks walk bricks of
+// 8 x 8 x 8 cells (x fastest inside a brick and from brick to brick), so a
+// cell's y and z neighbours are visited within 64 cells of it and the face
+// traces it shares with them are still in L2 (in cell order the z
+// neighbours are C0 C1 cells apart); otherwise the cells in order.
+template <int DIM, int CPB>
+__device__ __forceinline__ int corr_cell0(const KArgs& a, int lb) {
+  const int first = lb * CPB;
+  if constexpr (DIM == 3 && 8 % CPB == 0) {
+    const int C0 = a.cells[0], C1 = a.cells[1], C2 = a.cells[2];
+    if (((C0 | C1 | C2) & 7) == 0) {
+      const int o = first & 511, bi = first >> 9, nbx = C0 >> 3, nby = C1 >> 3;
+      const int bx = bi % nbx, by = (bi / nbx) % nby, bz = bi / (nbx * nby);
+      return (bx * 8 + (o & 7)) + C0 * ((by * 8 + ((o >> 3) & 7)) + C1 * (bz * 8 + (o >> 6)));
+    }
+  }
+  return first;
+}
+
 // PDEs with a boundary_values function for ADG_BC_USER faces (run-time PDEs
 // that define one)
 template <class... T>
@@ -1955,7 +1975,7 @@ correct_kernel(const KArgs a, double* __restrict__ Q, const double* __restrict__
   __shared__ double red[BLOCK];
 
   const int tid = threadIdx.x;
-  const int cell0 = xcd_block(blockIdx.x, a.nblocks) * CPB;
+  const int cell0 = corr_cell0<DIM, CPB>(a, xcd_block(blockIdx.x, a.nblocks));
   const double dt = clock[1];
   const int ncells = (int)a.ncells;
 

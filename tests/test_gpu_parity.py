@@ -154,6 +154,9 @@ def test_c1_config_parity_and_closed_form():
 STEP_CASES = {
     "euler3_N5": (dict(dim=3, order=5, pde="euler", cells=[4, 3, 3]), 3),
     "euler3_N3_ragged": (dict(dim=3, order=3, pde="euler", cells=[5, 3, 3]), 4),
+    # extents that are multiples of 8: the corrector walks 8^3-cell bricks
+    "euler3_N3_bricks": (dict(dim=3, order=3, pde="euler", cells=[16, 8, 8]), 2),
+    "euler3_N5_bricks": (dict(dim=3, order=5, pde="euler", cells=[8, 8, 16]), 2),
     "euler3_N2": (dict(dim=3, order=2, pde="euler", cells=[6, 4, 5]), 4),
     "euler2_N5": (dict(dim=2, order=5, pde="euler", cells=[9, 8]), 4),
     "advection3_N2_decay": (dict(dim=3, order=2, pde="advection", cells=[5, 4, 3], adv=(0.3, 0.5, -0.2), kappa=0.7), 4),
