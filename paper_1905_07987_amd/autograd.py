@@ -33,6 +33,8 @@ from . import adg
 def _segments(steps: int, every: int):
     """Checkpoint segment bounds [0, b_1, ..., steps]: segments of ``every``
     steps counted from the end, the first one the remainder."""
+    if steps <= 0:
+        return [0]
     nseg = math.ceil(steps / every)
     return [0] + [steps - (nseg - k) * every for k in range(1, nseg)] + [steps]
 

@@ -88,3 +88,4 @@ def test_checkpoint_segments():
         assert b[0] == 0 and b[-1] == steps and len(lens) == -(-steps // every)
         assert all(0 < n <= every for n in lens) and all(n == every for n in lens[1:])
     assert _segments(200, 15)[:3] == [0, 5, 20]
+    assert _segments(0, 4) == [0]  # no steps: no segment
