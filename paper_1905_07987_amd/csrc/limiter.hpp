@@ -379,12 +379,37 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
           l2[v] = fmin(l2[v], qv[v][j]);
           h2[v] = fmax(h2[v], qv[v][j]);
         }
+    if constexpr (2 * NV * 65 <= GW::PW) {
+      // the lanes' partial ranges through the wave's stage buffer (free once
+      // the projection is done; rows 65 apart, so the folding lanes take
+      // distinct banks), then one lane per (variable, bound) folds the 64
+      // (the minima stored negated: one max loop)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double l = lim_wave_min(l2[v]), h = lim_wave_max(h2[v]);
-      if (lane == 0) {
-        w.lohi_next[(c * NV + v) * 2] = l;
-        w.lohi_next[(c * NV + v) * 2 + 1] = h;
+      for (int v = 0; v < NV; ++v) {
+        ra[(2 * v) * 65 + lane] = -l2[v];
+        ra[(2 * v + 1) * 65 + lane] = h2[v];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < 2 * NV) {
+        const double* col = ra + lane * 65;
+        double r = col[0];
+#pragma unroll 16
+        for (int i = 1; i < 64; ++i) r = fmax(r, col[i]);
+        w.lohi_next[c * NV * 2 + lane] = (lane & 1) ? r : -r;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double l = lim_wave_min(l2[v]), h = lim_wave_max(h2[v]);
+        if (lane == 0) {
+          w.lohi_next[(c * NV + v) * 2] = l;
+          w.lohi_next[(c * NV + v) * 2 + 1] = h;
+        }
       }
     }
   }
