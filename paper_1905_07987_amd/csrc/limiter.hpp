@@ -379,7 +379,7 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
           l2[v] = fmin(l2[v], qv[v][j]);
           h2[v] = fmax(h2[v], qv[v][j]);
         }
-    if constexpr (2 * NV * 65 <= GW::PW) {
+    if constexpr (2 * NV * 71 <= GW::PW) {
       // the lanes' partial ranges through the wave's stage buffer (free once
       // the projection is done; rows 65 apart, so the folding lanes take
       // distinct banks), then one lane per (variable, bound) folds the 64
@@ -395,11 +395,23 @@ lim_detect_kernel(const KArgs a, const double* __restrict__ Q, const LimWork w) 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < 2 * NV * 6) {  // six lanes per (variable, bound), 11 values each
+        const int slot = lane / 6, part = lane - slot * 6;
+        const double* col = ra + slot * 65 + part * 11;
+        double r = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 11; ++i)
+          if (part * 11 + i < 64) r = fmax(r, col[i]);
+        ra[2 * NV * 65 + lane] = r;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (lane < 2 * NV) {
-        const double* col = ra + lane * 65;
-        double r = col[0];
-#pragma unroll 16
-        for (int i = 1; i < 64; ++i) r = fmax(r, col[i]);
+        const double* pr = ra + 2 * NV * 65 + lane * 6;
+        double r = pr[0];
+#pragma unroll
+        for (int i = 1; i < 6; ++i) r = fmax(r, pr[i]);
         w.lohi_next[c * NV * 2 + lane] = (lane & 1) ? r : -r;
       }
     } else {
